@@ -1,0 +1,188 @@
+/*
+ * ifa.h -- C ABI of libifa.so, the MI355X (gfx950) brute-force gapless scan.
+ *
+ * The library implements the brute-force mode of IndelFreeAligner (Methods,
+ * "Algorithm Design"): every query is tested, forward and reverse complement,
+ * against every start position of a reference that is streamed in contig by
+ * contig, and every window whose Hamming distance is at most the query's
+ * threshold is reported. Thresholds may go up to the full query length
+ * (Abstract; "Mismatch Tolerance Scalability"). Reference Ns are counted apart
+ * from substitutions (Methods, "Algorithm Design"; "SIMD Optimization").
+ * Device memory does not grow with the total reference size (Methods,
+ * "Memory Management").
+ *
+ * Definition computed for query j (length L, threshold k, N threshold maxN),
+ * strand s and every window [p, p + L) lying wholly inside one contig:
+ *   n_ref = number of window positions holding a reference non-ACGT byte;
+ *   IFA_N_SEPARATE (default):
+ *     m   = positions where the reference base is A/C/G/T and differs from
+ *           the query base (a query non-ACGT byte differs from every A/C/G/T);
+ *     hit iff m <= min(k, L) and n_ref <= min(maxN, L);
+ *   IFA_N_AS_MISMATCH:
+ *     m   = positions where either side is non-ACGT or the bases differ;
+ *     hit iff m <= min(k, L).
+ * Strand 0 compares the query itself, strand 1 its reverse complement, both
+ * against the forward reference; pos is the 0-based leftmost forward
+ * coordinate of the window in its contig. Bytes are case-insensitive; every
+ * byte other than A/C/G/T/a/c/g/t is N.
+ *
+ * General conventions
+ *   - Every entry point returns an ifa_status; a failed call changes nothing
+ *     (all or nothing) and leaves a message for ifa_last_error.
+ *   - Input buffers belong to the caller and may be reused as soon as the
+ *     call returns: the library packs what it needs into its own pinned host
+ *     memory before returning. Output arrays belong to the caller. The
+ *     context, its device memory and its pinned memory belong to the library.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - All pointers in this header are host pointers.
+ */
+#ifndef IFA_H
+#define IFA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IFA_ABI_VERSION 1u
+#define IFA_MAX_QUERY_LEN 256u
+
+typedef struct ifa_ctx ifa_ctx;
+
+typedef enum {
+    IFA_OK = 0,
+    IFA_E_INVALID = 1,   /* bad argument */
+    IFA_E_NOMEM = 2,     /* host or device allocation failed */
+    IFA_E_DEVICE = 3,    /* HIP runtime error */
+    IFA_E_STATE = 4,     /* call not allowed in the context's current state */
+    IFA_E_TOO_LONG = 5   /* query longer than IFA_MAX_QUERY_LEN, or empty */
+} ifa_status;
+
+enum { IFA_N_SEPARATE = 0, IFA_N_AS_MISMATCH = 1 };
+enum { IFA_SINK_RECORDS = 0, IFA_SINK_COUNT_DIGEST = 1 };
+enum { IFA_STRAND_FWD = 1, IFA_STRAND_RC = 2, IFA_STRAND_BOTH = 3 };
+
+typedef struct {
+    uint32_t abi_version;   /* must equal IFA_ABI_VERSION */
+    int32_t device;         /* HIP device ordinal */
+    uint64_t chunk_bases;   /* bases per device chunk; multiple of 32 in
+                               [4096, 2^31]; fixes the device footprint */
+    uint64_t hit_capacity;  /* hit records per device hit buffer; 0 = auto
+                               (2^22). A full buffer never loses hits: the
+                               chunk is re-scanned in halves, and a buffer
+                               grows only if the 32 windows of one plane word
+                               x every query strand alone overflow it */
+    uint32_t strands;       /* IFA_STRAND_* */
+    uint32_t n_policy;      /* IFA_N_SEPARATE | IFA_N_AS_MISMATCH */
+    uint32_t sink;          /* IFA_SINK_RECORDS | IFA_SINK_COUNT_DIGEST */
+    uint32_t host_threads;  /* packing threads; 0 = hardware concurrency */
+} ifa_config;
+
+/* One reported window (16 bytes). strand: 0 = +, 1 = - (reverse complement). */
+typedef struct {
+    uint32_t query;         /* index of the query in the last ifa_load_queries */
+    uint32_t contig;        /* global contig ordinal, in stream order from 0 */
+    uint32_t pos;           /* 0-based leftmost forward coordinate in the contig */
+    uint8_t strand;
+    uint8_t n_ref;          /* reference non-ACGT bases in the window */
+    uint16_t mismatches;    /* m as defined above */
+} ifa_hit;
+
+/* Counters since ifa_create (or the last ifa_reset_stats). */
+typedef struct {
+    uint64_t bases;          /* reference bases submitted for scanning */
+    uint64_t chunks;         /* chunk scans submitted */
+    uint64_t kernel_launches;/* scan kernel launches, overflow re-scans included */
+    uint64_t rescans;        /* re-scans caused by a full hit buffer */
+    uint64_t hits;           /* hits found */
+    double kernel_ms;        /* summed scan-kernel time, HIP events on the
+                                compute stream around each launch */
+    double h2d_ms;           /* summed host-to-device copy time of chunks */
+    double pack_ms;          /* host wall time spent packing contigs */
+} ifa_stats;
+
+/* Fill *cfg with the defaults: device 0, 2^30-base chunks, automatic hit
+ * capacity, both strands, IFA_N_SEPARATE, records sink, all host threads. */
+void ifa_config_default(ifa_config *cfg);
+
+/* Create a context on cfg->device (cfg NULL = defaults). Allocates the fixed
+ * device footprint: two chunk buffers of 0.5 byte per base plus hit buffers.
+ * Errors: IFA_E_INVALID (bad config), IFA_E_DEVICE, IFA_E_NOMEM. */
+ifa_status ifa_create(const ifa_config *cfg, ifa_ctx **out);
+
+/* Load the query set, once before scanning (Methods, "Memory Management": the
+ * query set is loaded once). n queries; seq[i] points to len[i] bytes;
+ * max_subs[i] >= 0 (values above len[i] act as len[i]); max_n NULL means
+ * floor(len[i] / 4) for every query (the 25% soft-clip default of Methods,
+ * "Algorithm Design"), else max_n[i] >= 0.
+ * Errors: IFA_E_TOO_LONG (len 0 or > IFA_MAX_QUERY_LEN), IFA_E_INVALID
+ * (negative threshold, NULL pointer), IFA_E_STATE (chunks or hits still
+ * pending: call ifa_collect_hits first). Resets count+digest statistics. */
+ifa_status ifa_load_queries(ifa_ctx *ctx, uint32_t n, const uint8_t *const *seq,
+                            const uint32_t *len, const int32_t *max_subs,
+                            const int32_t *max_n);
+
+/* Stream n_contigs contigs (seq[i] -> len[i] bytes, len[i] < 2^32) into the
+ * scan. Contigs take global ordinals in call order; *first_ordinal (may be
+ * NULL) receives the first one. Empty or short contigs take an ordinal and
+ * yield no windows. Contigs are packed to 2-bit planes on host threads and
+ * scanned asynchronously as device chunks fill; a contig longer than the room
+ * left in a chunk continues in the next chunk, which repeats its last
+ * IFA_MAX_QUERY_LEN - 1 bases so that every window is tested exactly once.
+ * Errors: IFA_E_STATE (no queries loaded), IFA_E_INVALID, IFA_E_DEVICE. */
+ifa_status ifa_scan_chunk(ifa_ctx *ctx, uint32_t n_contigs, const uint8_t *const *seq,
+                          const uint64_t *len, uint32_t *first_ordinal);
+
+/* Wait for every submitted scan and hand out the hits found so far in
+ * reference order: (contig, pos, strand, query) ascending (Results, "Accuracy
+ * Validation": output follows the reference stream). Writes at most cap
+ * records to out; *n_written gets the count written and *n_remaining (may be
+ * NULL) the count still held; call again to drain the rest. With the
+ * count+digest sink no records exist and both counts are 0. */
+ifa_status ifa_collect_hits(ifa_ctx *ctx, ifa_hit *out, uint64_t cap, uint64_t *n_written,
+                            uint64_t *n_remaining);
+
+/* Release everything the context owns. NULL-safe. */
+void ifa_destroy(ifa_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none). The string belongs to
+ * the context and lives until its next call. */
+const char *ifa_last_error(const ifa_ctx *ctx);
+
+/* Count+digest sink: waits for every submitted scan, then writes for each
+ * loaded query the number of hits and the wrapping 64-bit sum over its hits of
+ *   mix64(((contig << 32) | pos) ^ (aux << 45)),
+ *   aux = strand | (mismatches << 1) | (n_ref << 10),
+ * mix64 being the SplitMix64 output finaliser (shifts 30, 27, 31; multipliers
+ * 0xBF58476D1CE4E5B9, 0x94D049BB133111EB). count and digest are arrays of the
+ * loaded query count. Errors: IFA_E_STATE (records sink or no queries). */
+ifa_status ifa_query_stats(ifa_ctx *ctx, uint64_t *count, uint64_t *digest);
+
+/* Device-resident reference: pack contigs into device chunks that stay in
+ * device memory (one chunk buffer per chunk_bases of reference) so that
+ * later query sets can be scanned without copying the reference again.
+ * Ordinals come from the same counter as ifa_scan_chunk. Errors: IFA_E_NOMEM
+ * when device memory runs out (what was loaded before the call stays). */
+ifa_status ifa_ref_load(ifa_ctx *ctx, uint32_t n_contigs, const uint8_t *const *seq,
+                        const uint64_t *len, uint32_t *first_ordinal);
+
+/* Scan every resident chunk with the loaded queries; hits are collected as
+ * for ifa_scan_chunk. Errors: IFA_E_STATE (no queries or no resident chunk). */
+ifa_status ifa_scan_resident(ifa_ctx *ctx);
+
+/* Free the resident reference. Errors: IFA_E_STATE while scans are pending. */
+ifa_status ifa_ref_release(ifa_ctx *ctx);
+
+/* Resident reference size: bases (*bases) in *chunks device chunks. */
+ifa_status ifa_ref_info(const ifa_ctx *ctx, uint64_t *bases, uint32_t *chunks);
+
+/* Counters (see ifa_stats). ifa_get_stats waits for submitted work first. */
+ifa_status ifa_get_stats(ifa_ctx *ctx, ifa_stats *out);
+ifa_status ifa_reset_stats(ifa_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IFA_H */

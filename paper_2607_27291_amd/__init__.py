@@ -1,0 +1,309 @@
+"""MI355X (gfx950) brute-force gapless scan of IndelFreeAligner.
+
+Thin ctypes binding over libifa.so: each function below marshals arguments to
+the C entry point of the same name in include/ifa.h. All compute runs in the
+library's HIP kernels; there is no CPU fallback, and loading fails loudly when
+the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+__all__ = [
+    "IfaError", "HIT_DTYPE", "lib", "ifa_config_default", "ifa_create", "ifa_destroy",
+    "ifa_load_queries", "ifa_scan_chunk", "ifa_collect_hits", "ifa_last_error",
+    "ifa_query_stats", "ifa_ref_load", "ifa_scan_resident", "ifa_ref_release", "ifa_ref_info",
+    "ifa_get_stats", "ifa_reset_stats", "Scanner", "collect_all",
+]
+
+IFA_ABI_VERSION = 1
+IFA_MAX_QUERY_LEN = 256
+IFA_N_SEPARATE, IFA_N_AS_MISMATCH = 0, 1
+IFA_SINK_RECORDS, IFA_SINK_COUNT_DIGEST = 0, 1
+IFA_STRAND_FWD, IFA_STRAND_RC, IFA_STRAND_BOTH = 1, 2, 3
+
+STATUS = {0: "IFA_OK", 1: "IFA_E_INVALID", 2: "IFA_E_NOMEM", 3: "IFA_E_DEVICE",
+          4: "IFA_E_STATE", 5: "IFA_E_TOO_LONG"}
+
+HIT_DTYPE = np.dtype([("query", "<u4"), ("contig", "<u4"), ("pos", "<u4"), ("strand", "u1"),
+                      ("n_ref", "u1"), ("mismatches", "<u2")])
+
+
+class IfaConfig(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("chunk_bases", ctypes.c_uint64), ("hit_capacity", ctypes.c_uint64),
+                ("strands", ctypes.c_uint32), ("n_policy", ctypes.c_uint32),
+                ("sink", ctypes.c_uint32), ("host_threads", ctypes.c_uint32)]
+
+
+class IfaStats(ctypes.Structure):
+    _fields_ = [("bases", ctypes.c_uint64), ("chunks", ctypes.c_uint64),
+                ("kernel_launches", ctypes.c_uint64), ("rescans", ctypes.c_uint64),
+                ("hits", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
+                ("h2d_ms", ctypes.c_double), ("pack_ms", ctypes.c_double)]
+
+
+class IfaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libifa.so; raises if it was not built (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            raise ImportError(f"{_build.LIB} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(_build.LIB)
+        vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+        st = ctypes.c_int
+        L.ifa_config_default.argtypes = [ctypes.POINTER(IfaConfig)]
+        L.ifa_config_default.restype = None
+        L.ifa_create.argtypes = [ctypes.POINTER(IfaConfig), ctypes.POINTER(vp)]
+        L.ifa_create.restype = st
+        L.ifa_destroy.argtypes = [vp]
+        L.ifa_destroy.restype = None
+        L.ifa_last_error.argtypes = [vp]
+        L.ifa_last_error.restype = ctypes.c_char_p
+        L.ifa_load_queries.argtypes = [vp, u32, vp, vp, vp, vp]
+        L.ifa_load_queries.restype = st
+        L.ifa_scan_chunk.argtypes = [vp, u32, vp, vp, ctypes.POINTER(u32)]
+        L.ifa_scan_chunk.restype = st
+        L.ifa_collect_hits.argtypes = [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.ifa_collect_hits.restype = st
+        L.ifa_query_stats.argtypes = [vp, vp, vp]
+        L.ifa_query_stats.restype = st
+        L.ifa_ref_load.argtypes = [vp, u32, vp, vp, ctypes.POINTER(u32)]
+        L.ifa_ref_load.restype = st
+        L.ifa_scan_resident.argtypes = [vp]
+        L.ifa_scan_resident.restype = st
+        L.ifa_ref_release.argtypes = [vp]
+        L.ifa_ref_release.restype = st
+        L.ifa_ref_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u32)]
+        L.ifa_ref_info.restype = st
+        L.ifa_get_stats.argtypes = [vp, ctypes.POINTER(IfaStats)]
+        L.ifa_get_stats.restype = st
+        L.ifa_reset_stats.argtypes = [vp]
+        L.ifa_reset_stats.restype = st
+        _lib = L
+    return _lib
+
+
+def _check(ctx, status):
+    if status != 0:
+        msg = lib().ifa_last_error(ctx) if ctx else b""
+        raise IfaError(status, (msg or b"").decode(errors="replace"))
+
+
+def _bytes(x) -> bytes:
+    if isinstance(x, (bytes, bytearray)):
+        return bytes(x)
+    if isinstance(x, str):
+        return x.encode()
+    return np.ascontiguousarray(x, dtype=np.uint8).tobytes()
+
+
+class _SeqArray:
+    """Pointer + length arrays over a list of byte sequences (kept alive)."""
+
+    def __init__(self, seqs, len_dtype):
+        self.keep = []
+        ptrs, lens = [], []
+        for s in seqs:
+            if isinstance(s, np.ndarray):
+                a = np.ascontiguousarray(s, dtype=np.uint8)
+            else:
+                a = np.frombuffer(_bytes(s), dtype=np.uint8)
+            self.keep.append(a)
+            ptrs.append(a.ctypes.data if a.size else None)
+            lens.append(a.size)
+        n = len(ptrs)
+        self.n = n
+        self.ptrs = (ctypes.c_void_p * max(n, 1))(*ptrs)
+        self.lens = np.array(lens or [0], dtype=len_dtype)
+
+
+def _contig_arrays(contigs):
+    if hasattr(contigs, "pointer_array"):
+        ptrs, lens = contigs.pointer_array()
+        return ptrs, lens, contigs.n_contigs, contigs
+    sa = _SeqArray(contigs, np.uint64)
+    return sa.ptrs, sa.lens, sa.n, sa
+
+
+# --------------------------------------------------------------------------
+# the C entry points, one to one
+# --------------------------------------------------------------------------
+
+def ifa_config_default() -> IfaConfig:
+    cfg = IfaConfig()
+    lib().ifa_config_default(ctypes.byref(cfg))
+    return cfg
+
+
+def ifa_create(cfg: IfaConfig | None = None) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    st = lib().ifa_create(ctypes.byref(cfg) if cfg is not None else None, ctypes.byref(ctx))
+    if st != 0:
+        raise IfaError(st, "ifa_create failed")
+    return ctx
+
+
+def ifa_destroy(ctx):
+    lib().ifa_destroy(ctx)
+
+
+def ifa_last_error(ctx) -> str:
+    return (lib().ifa_last_error(ctx) or b"").decode(errors="replace")
+
+
+def ifa_load_queries(ctx, queries, max_subs, max_n=None):
+    sa = _SeqArray(queries, np.uint32)
+    ks = np.ascontiguousarray(list(max_subs) or [0], dtype=np.int32)
+    mn = None if max_n is None else np.ascontiguousarray(list(max_n) or [0], dtype=np.int32)
+    if len(ks) < sa.n or (mn is not None and len(mn) < sa.n):
+        raise ValueError("one threshold per query is required")
+    _check(ctx, lib().ifa_load_queries(ctx, sa.n, sa.ptrs, sa.lens.ctypes.data, ks.ctypes.data,
+                                       None if mn is None else mn.ctypes.data))
+
+
+def ifa_scan_chunk(ctx, contigs) -> int:
+    ptrs, lens, n, keep = _contig_arrays(contigs)
+    first = ctypes.c_uint32()
+    _check(ctx, lib().ifa_scan_chunk(ctx, n, ptrs, lens.ctypes.data, ctypes.byref(first)))
+    del keep
+    return first.value
+
+
+def ifa_collect_hits(ctx, cap: int):
+    """One call: returns (hits array of at most cap records, n_remaining)."""
+    out = np.zeros(max(cap, 1), dtype=HIT_DTYPE)
+    nw = ctypes.c_uint64()
+    nr = ctypes.c_uint64()
+    _check(ctx, lib().ifa_collect_hits(ctx, out.ctypes.data, cap, ctypes.byref(nw),
+                                       ctypes.byref(nr)))
+    return out[:nw.value].copy(), nr.value
+
+
+def ifa_query_stats(ctx, n_queries: int):
+    cnt = np.zeros(max(n_queries, 1), dtype=np.uint64)
+    dig = np.zeros(max(n_queries, 1), dtype=np.uint64)
+    _check(ctx, lib().ifa_query_stats(ctx, cnt.ctypes.data, dig.ctypes.data))
+    return cnt[:n_queries], dig[:n_queries]
+
+
+def ifa_ref_load(ctx, contigs) -> int:
+    ptrs, lens, n, keep = _contig_arrays(contigs)
+    first = ctypes.c_uint32()
+    _check(ctx, lib().ifa_ref_load(ctx, n, ptrs, lens.ctypes.data, ctypes.byref(first)))
+    del keep
+    return first.value
+
+
+def ifa_scan_resident(ctx):
+    _check(ctx, lib().ifa_scan_resident(ctx))
+
+
+def ifa_ref_release(ctx):
+    _check(ctx, lib().ifa_ref_release(ctx))
+
+
+def ifa_ref_info(ctx):
+    b = ctypes.c_uint64()
+    c = ctypes.c_uint32()
+    _check(ctx, lib().ifa_ref_info(ctx, ctypes.byref(b), ctypes.byref(c)))
+    return b.value, c.value
+
+
+def ifa_get_stats(ctx) -> dict:
+    s = IfaStats()
+    _check(ctx, lib().ifa_get_stats(ctx, ctypes.byref(s)))
+    return {k: getattr(s, k) for k, _ in IfaStats._fields_}
+
+
+def ifa_reset_stats(ctx):
+    _check(ctx, lib().ifa_reset_stats(ctx))
+
+
+def collect_all(ctx, batch: int = 1 << 20) -> np.ndarray:
+    """Drain every held hit (two-call pattern over ifa_collect_hits)."""
+    parts = []
+    while True:
+        h, rem = ifa_collect_hits(ctx, batch)
+        parts.append(h)
+        if rem == 0:
+            break
+    return np.concatenate(parts) if len(parts) > 1 else parts[0]
+
+
+class Scanner:
+    """Owns one context; convenience over the entry points above."""
+
+    def __init__(self, *, device=0, chunk_bases=1 << 30, hit_capacity=0,
+                 strands=IFA_STRAND_BOTH, n_policy=IFA_N_SEPARATE, sink=IFA_SINK_RECORDS,
+                 host_threads=0):
+        cfg = ifa_config_default()
+        cfg.device = device
+        cfg.chunk_bases = chunk_bases
+        cfg.hit_capacity = hit_capacity
+        cfg.strands = strands
+        cfg.n_policy = n_policy
+        cfg.sink = sink
+        cfg.host_threads = host_threads
+        self.ctx = ifa_create(cfg)
+        self.n_queries = 0
+
+    def close(self):
+        if self.ctx:
+            ifa_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_queries(self, queries, max_subs, max_n=None):
+        ifa_load_queries(self.ctx, queries, max_subs, max_n)
+        self.n_queries = len(queries)
+
+    def scan_chunk(self, contigs) -> int:
+        return ifa_scan_chunk(self.ctx, contigs)
+
+    def collect(self) -> np.ndarray:
+        return collect_all(self.ctx)
+
+    def query_stats(self):
+        return ifa_query_stats(self.ctx, self.n_queries)
+
+    def ref_load(self, contigs) -> int:
+        return ifa_ref_load(self.ctx, contigs)
+
+    def scan_resident(self):
+        ifa_scan_resident(self.ctx)
+
+    def stats(self) -> dict:
+        return ifa_get_stats(self.ctx)
+
+    def scan(self, queries, contigs, max_subs, max_n=None) -> np.ndarray:
+        """Load queries, stream contigs, return every hit in reference order."""
+        self.load_queries(queries, max_subs, max_n)
+        self.scan_chunk(contigs)
+        return self.collect()

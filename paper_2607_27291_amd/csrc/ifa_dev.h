@@ -1,0 +1,72 @@
+// ifa_dev.h -- data layouts shared by the host runtime and the gfx950 kernels.
+//
+// Reference chunk in device memory: four bit planes of `plane_words` uint32
+// words each, stored one after another (hi, lo, nm, em). Base x of the chunk
+// is bit (x & 31) of word (x >> 5) in every plane:
+//   hi, lo : 2-bit base code A=00 C=01 G=10 T=11 (hi bit, lo bit); N is 00
+//   nm     : 1 where the base is N (any non-ACGT byte)
+//   em     : 1 at the last base of every contig piece, so a window is inside
+//            one piece iff no em bit falls on its first L-1 positions
+// Words past the chunk end hold hi = lo = 0 and nm = em = all ones, and at
+// least IFA_PAD_WORDS such words follow the last data word.
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace ifa {
+
+constexpr uint32_t kMaxLen = 256;          // longest query
+constexpr uint32_t kCarry = kMaxLen - 1;   // bases repeated at a split
+constexpr uint32_t kPadWords = 16;         // > (31 + kMaxLen) / 32 + 1
+constexpr uint32_t kMaxQWords = kMaxLen / 32;
+
+enum Sink : uint32_t { kSinkRecords = 0, kSinkCountDigest = 1 };
+enum Policy : uint32_t { kNSeparate = 0, kNAsMismatch = 1 };
+
+// One contig piece inside a chunk.
+struct Piece {
+    uint64_t start;       // chunk-local offset of the first base
+    uint64_t len;         // bases
+    uint64_t contig_off;  // contig coordinate of the first base
+    uint32_t contig;      // global contig ordinal
+    uint32_t pad;
+};
+static_assert(sizeof(Piece) == 32, "Piece layout");
+
+// One (query, strand) entry. Its packed words live at qwords[woff ...]:
+// for word t (bases 32t .. 32t+31 of the strand sequence) the three words
+// hi, lo, qn at woff + 3t + {0, 1, 2}; bits at or past L are zero.
+struct QSDesc {
+    uint32_t qid;         // caller's query index
+    uint16_t len;         // L
+    uint8_t strand;       // 0 forward, 1 reverse complement
+    uint8_t nw;           // ceil(L / 32)
+    uint16_t k;           // min(maxSubs, L)
+    uint16_t maxn;        // min(maxN, L)
+    uint32_t woff;
+};
+static_assert(sizeof(QSDesc) == 16, "QSDesc layout");
+
+struct ScanArgs {
+    const uint32_t *hi, *lo, *nm, *em;
+    uint64_t chunk_len;       // bases in the chunk
+    uint32_t own_from;        // a window is owned only if its last base >= own_from
+    uint32_t w_begin, w_end;  // window-start words [w_begin, w_end) to scan
+    uint32_t lmax;            // longest L among qs
+    const QSDesc *qs;
+    uint32_t n_qs;
+    uint32_t policy;
+    const uint32_t *qwords;
+    const Piece *pieces;
+    uint32_t n_pieces;
+    uint32_t sink;
+    // records sink
+    uint4 *hits;
+    unsigned long long *hit_count;
+    unsigned long long hit_cap;
+    // count+digest sink, indexed by qid
+    unsigned long long *q_count;
+    unsigned long long *q_digest;
+};
+
+}  // namespace ifa

@@ -1,0 +1,997 @@
+// ifa_runtime.cpp -- host runtime of libifa.so (the C ABI in include/ifa.h).
+//
+// Streaming architecture (Methods, "Algorithm Design" and "Memory
+// Management"): contigs arrive on the fly; the host packs them into 2-bit
+// planes in pinned staging buffers; full chunks are copied to one of two
+// device chunk buffers and scanned while the host packs the next one. Device
+// memory is fixed at creation (two chunk buffers, two hit buffers), so it does
+// not depend on the total reference size nor on the largest contig: a contig
+// that does not fit is split, and the next chunk repeats its last kCarry bases.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/ifa.h"
+#include "ifa_dev.h"
+
+namespace ifa {
+hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
+}  // namespace ifa
+
+using namespace ifa;
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+struct Failure {
+    ifa_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(ifa_status st, const std::string &msg) { throw Failure{st, msg}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) {
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            fail(IFA_E_NOMEM, std::string(what) + ": " + hipGetErrorString(e));
+        fail(IFA_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// byte -> base code: A 0, C 1, G 2, T 3, anything else 4
+struct CodeTable {
+    uint8_t c[256];
+    CodeTable()
+    {
+        std::memset(c, 4, sizeof c);
+        c['A'] = c['a'] = 0;
+        c['C'] = c['c'] = 1;
+        c['G'] = c['g'] = 2;
+        c['T'] = c['t'] = 3;
+    }
+};
+const CodeTable kCode;
+
+void parallel_for(unsigned threads, size_t n, const std::function<void(size_t)> &fn)
+{
+    if (n == 0) return;
+    unsigned t = std::max(1u, std::min<unsigned>(threads, (unsigned)n));
+    if (t == 1) {
+        for (size_t i = 0; i < n; i++) fn(i);
+        return;
+    }
+    std::atomic<size_t> next{0};
+    auto body = [&]() {
+        for (;;) {
+            size_t i = next.fetch_add(1);
+            if (i >= n) break;
+            fn(i);
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(t - 1);
+    for (unsigned i = 1; i < t; i++) th.emplace_back(body);
+    body();
+    for (auto &x : th) x.join();
+}
+
+// ---------------------------------------------------------------------------
+// pinned / device buffers
+// ---------------------------------------------------------------------------
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count, const char *what)
+    {
+        release();
+        if (count == 0) count = 1;
+        hip_check(hipMalloc((void **)&p, count * sizeof(T)), what);
+        n = count;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~DevBuf() { release(); }
+};
+
+template <class T>
+struct HostBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    void alloc(size_t count, const char *what)
+    {
+        release();
+        if (count == 0) count = 1;
+        hip_check(hipHostMalloc((void **)&p, count * sizeof(T), hipHostMallocDefault), what);
+        n = count;
+    }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    ~HostBuf() { release(); }
+};
+
+// ---------------------------------------------------------------------------
+// host staging chunk
+// ---------------------------------------------------------------------------
+
+// A pending copy of contig bytes into the staging planes.
+struct PackTask {
+    const uint8_t *src;
+    uint64_t dst;     // chunk-local base offset
+    uint64_t n;
+};
+
+struct Staging {
+    HostBuf<uint32_t> planes;       // 4 * plane_words
+    std::vector<Piece> pieces;
+    std::vector<PackTask> tasks;    // not yet packed
+    uint64_t len = 0;               // bases used
+    uint32_t own_from = 0;
+    uint64_t packed_to = 0;         // bases [0, packed_to) are packed
+    hipEvent_t copied = nullptr;    // H2D from this staging finished
+    bool copy_pending = false;
+};
+
+// Device chunk: planes + piece table, either a stream slot or resident.
+struct DevChunk {
+    DevBuf<uint32_t> planes;      // 4 planes of `stride` words each
+    DevBuf<Piece> pieces;
+    uint64_t stride = 0;
+    uint64_t len = 0;
+    uint32_t own_from = 0;
+    uint32_t n_pieces = 0;
+    hipEvent_t free_ev = nullptr;   // last kernel reading it finished
+};
+
+// A submitted scan of one device chunk whose hits are not yet retired.
+struct Job {
+    DevChunk *chunk = nullptr;
+    int hitbuf = 0;
+    hipEvent_t k0 = nullptr, k1 = nullptr;  // kernel start / stop
+    hipEvent_t done = nullptr;              // hit count copied to the host
+    bool active = false;
+};
+
+}  // namespace
+
+struct ifa_ctx {
+    ifa_config cfg{};
+    std::string err;
+    unsigned threads = 1;
+    uint64_t plane_words = 0;
+
+    hipStream_t copy_s = nullptr, comp_s = nullptr;
+
+    // queries
+    bool have_queries = false;
+    uint32_t n_queries = 0;
+    uint32_t lmax = 0;
+    std::vector<QSDesc> h_qs;
+    std::vector<uint32_t> h_qwords;
+    DevBuf<QSDesc> d_qs;
+    DevBuf<uint32_t> d_qwords;
+    DevBuf<unsigned long long> d_qcount, d_qdigest;
+
+    // streaming
+    Staging stage[2];
+    int cur = 0;                      // staging being filled
+    DevChunk slot[2];
+    uint64_t chunk_seq = 0;           // chunks submitted to stream slots
+    uint32_t next_ordinal = 0;
+
+    // hits
+    DevBuf<uint4> d_hits[2];
+    DevBuf<unsigned long long> d_hitcount;   // [2]
+    HostBuf<unsigned long long> h_hitcount;  // [2]
+    uint64_t hit_cap = 0;             // configured records per hit buffer
+    uint64_t buf_cap[2] = {0, 0};     // current records per hit buffer
+    Job jobs[2];
+    uint64_t job_seq = 0;
+    std::vector<ifa_hit> hits;        // retired, not yet handed out
+    bool hits_sorted = true;
+    uint64_t drain_pos = 0;
+
+    // resident reference
+    std::vector<std::unique_ptr<DevChunk>> resident;
+    uint64_t resident_bases = 0;
+
+    // stats
+    ifa_stats st{};
+    hipEvent_t h2d0 = nullptr, h2d1 = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> h2d_pending;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// packing
+// ---------------------------------------------------------------------------
+
+uint32_t *plane(ifa_ctx *c, Staging &s, int k) { return s.planes.p + (size_t)k * c->plane_words; }
+
+// Pack bases [dst, dst + n) of the chunk from src. Words are written whole,
+// except the first word, whose bits below `dst` are kept (they belong to bases
+// packed earlier).
+void pack_range(ifa_ctx *c, Staging &s, uint64_t dst, const uint8_t *src, uint64_t n,
+                bool keep_low)
+{
+    uint32_t *H = plane(c, s, 0), *Lo = plane(c, s, 1), *N = plane(c, s, 2);
+    uint64_t x = dst, end = dst + n;
+    while (x < end) {
+        uint64_t w = x >> 5;
+        uint32_t b0 = (uint32_t)(x & 31);
+        uint64_t wend = std::min<uint64_t>(end, (w + 1) << 5);
+        uint32_t h = 0, l = 0, nn = 0;
+        const uint8_t *p = src + (x - dst);
+        uint32_t cnt = (uint32_t)(wend - x);
+        for (uint32_t i = 0; i < cnt; i++) {
+            uint32_t code = kCode.c[p[i]];
+            uint32_t bit = 1u << (b0 + i);
+            if (code == 4) {
+                nn |= bit;
+            } else {
+                if (code & 2) h |= bit;
+                if (code & 1) l |= bit;
+            }
+        }
+        if (b0 != 0 && keep_low) {
+            uint32_t keep = (1u << b0) - 1u;
+            H[w] = (H[w] & keep) | h;
+            Lo[w] = (Lo[w] & keep) | l;
+            N[w] = (N[w] & keep) | nn;
+        } else {
+            H[w] = h;
+            Lo[w] = l;
+            N[w] = nn;
+        }
+        x = wend;
+    }
+}
+
+// Pack every pending task of staging s, in parallel over word-aligned spans.
+void pack_pending(ifa_ctx *c, Staging &s)
+{
+    if (s.tasks.empty()) return;
+    double t0 = now_ms();
+    // Tasks are back to back in chunk order. The first word of the whole
+    // region may hold bits packed by an earlier call; every later word is
+    // written whole by exactly one worker.
+    const uint64_t region0 = s.tasks.front().dst;
+    const uint64_t region1 = s.tasks.back().dst + s.tasks.back().n;
+    const uint64_t span = 1ull << 20;   // bases per work item (multiple of 32)
+    const uint64_t a0 = region0 & ~31ull;
+    const size_t items = (size_t)((region1 - a0 + span - 1) / span);
+    std::vector<PackTask> &T = s.tasks;
+    parallel_for(c->threads, items, [&](size_t it) {
+        uint64_t lo = std::max(region0, a0 + (uint64_t)it * span);
+        uint64_t hi = std::min(region1, a0 + (uint64_t)(it + 1) * span);
+        if (lo >= hi) return;
+        // first task overlapping [lo, hi)
+        size_t k = (size_t)(std::upper_bound(T.begin(), T.end(), lo,
+                                             [](uint64_t v, const PackTask &t) {
+                                                 return v < t.dst;
+                                             }) - T.begin());
+        if (k > 0) k--;
+        for (; k < T.size() && T[k].dst < hi; k++) {
+            uint64_t s0 = std::max(lo, T[k].dst), s1 = std::min(hi, T[k].dst + T[k].n);
+            if (s0 >= s1) continue;
+            // keep earlier bits only in the very first word of the region;
+            // bits of a word shared by two tasks are packed in task order by
+            // this same worker
+            bool keep = (s0 == region0) || (s0 != lo);
+            pack_range(c, s, s0, T[k].src + (s0 - T[k].dst), s1 - s0, keep);
+        }
+    });
+    s.packed_to = region1;
+    s.tasks.clear();
+    c->st.pack_ms += now_ms() - t0;
+}
+
+// Finish the staging chunk: piece-end marks and padding words.
+void seal(ifa_ctx *c, Staging &s)
+{
+    uint32_t *H = plane(c, s, 0), *Lo = plane(c, s, 1), *N = plane(c, s, 2), *E = plane(c, s, 3);
+    const uint64_t used_words = (s.len + 31) >> 5;
+    std::memset(E, 0, used_words * sizeof(uint32_t));
+    for (const Piece &p : s.pieces) {
+        uint64_t last = p.start + p.len - 1;
+        E[last >> 5] |= 1u << (last & 31);
+    }
+    if (s.len & 31) {
+        uint64_t w = s.len >> 5;
+        uint32_t tail = ~((1u << (s.len & 31)) - 1u);
+        H[w] &= ~tail;
+        Lo[w] &= ~tail;
+        N[w] |= tail;
+        E[w] |= tail;
+    }
+    for (uint64_t w = used_words; w < used_words + kPadWords; w++) {
+        H[w] = 0;
+        Lo[w] = 0;
+        N[w] = 0xffffffffu;
+        E[w] = 0xffffffffu;
+    }
+}
+
+uint64_t words_with_pad(uint64_t len) { return ((len + 31) >> 5) + kPadWords; }
+
+// ---------------------------------------------------------------------------
+// jobs: launch and retire
+// ---------------------------------------------------------------------------
+
+ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
+{
+    ScanArgs a{};
+    a.hi = ch.planes.p;
+    a.lo = ch.planes.p + ch.stride;
+    a.nm = ch.planes.p + 2 * ch.stride;
+    a.em = ch.planes.p + 3 * ch.stride;
+    a.chunk_len = ch.len;
+    a.own_from = ch.own_from;
+    a.w_begin = 0;
+    a.w_end = (uint32_t)((ch.len + 31) >> 5);
+    a.lmax = c->lmax;
+    a.qs = c->d_qs.p;
+    a.n_qs = (uint32_t)c->h_qs.size();
+    a.policy = c->cfg.n_policy;
+    a.qwords = c->d_qwords.p;
+    a.pieces = ch.pieces.p;
+    a.n_pieces = ch.n_pieces;
+    a.sink = c->cfg.sink;
+    a.hits = c->d_hits[hb].p;
+    a.hit_count = c->d_hitcount.p + hb;
+    a.hit_cap = c->buf_cap[hb];
+    a.q_count = c->d_qcount.p;
+    a.q_digest = c->d_qdigest.p;
+    return a;
+}
+
+void add_kernel_time(ifa_ctx *c, hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) c->st.kernel_ms += ms;
+}
+
+void collect_h2d_times(ifa_ctx *c)
+{
+    for (auto &pr : c->h2d_pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(pr.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess)
+            c->st.h2d_ms += ms;
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    c->h2d_pending.clear();
+}
+
+void copy_records(ifa_ctx *c, int hb, uint64_t n)
+{
+    if (n == 0) return;
+    size_t old = c->hits.size();
+    c->hits.resize(old + n);
+    hip_check(hipMemcpy(c->hits.data() + old, c->d_hits[hb].p, n * sizeof(ifa_hit),
+                        hipMemcpyDeviceToHost),
+              "copy hit records");
+    c->hits_sorted = false;
+    c->st.hits += n;
+}
+
+// Re-scan word range [w0, w1) of a chunk whose hit buffer overflowed; halves
+// the range until every part fits.
+void rescan_range(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t w1)
+{
+    ScanArgs a = make_args(c, ch, hb);
+    a.w_begin = w0;
+    a.w_end = w1;
+    hip_check(launch_clear_u64(a.hit_count, 1, c->comp_s), "clear hit counter");
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    hip_check(hipEventRecord(e0, c->comp_s), "event record");
+    hip_check(launch_scan(a, c->comp_s), "scan launch");
+    hip_check(hipEventRecord(e1, c->comp_s), "event record");
+    hip_check(hipMemcpyAsync(c->h_hitcount.p + hb, a.hit_count, sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, c->comp_s),
+              "copy hit count");
+    hip_check(hipStreamSynchronize(c->comp_s), "sync");
+    add_kernel_time(c, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->st.kernel_launches++;
+    c->st.rescans++;
+    uint64_t n = c->h_hitcount.p[hb];
+    if (n <= c->buf_cap[hb]) {
+        copy_records(c, hb, n);
+        return;
+    }
+    if (w1 - w0 <= 1) {
+        // one plane word holds 32 windows x every query strand; when those
+        // alone overflow the buffer, the buffer grows to fit them
+        c->d_hits[hb].alloc(n, "grow hit buffer");
+        c->buf_cap[hb] = n;
+        rescan_range(c, ch, hb, w0, w1);
+        return;
+    }
+    uint32_t mid = w0 + (w1 - w0) / 2;
+    rescan_range(c, ch, hb, w0, mid);
+    rescan_range(c, ch, hb, mid, w1);
+}
+
+void retire(ifa_ctx *c, Job &j)
+{
+    if (!j.active) return;
+    hip_check(hipEventSynchronize(j.done), "wait for scan");
+    add_kernel_time(c, j.k0, j.k1);
+    if (c->cfg.sink == IFA_SINK_RECORDS) {
+        uint64_t n = c->h_hitcount.p[j.hitbuf];
+        if (n <= c->buf_cap[j.hitbuf]) {
+            copy_records(c, j.hitbuf, n);
+        } else {
+            const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
+            uint32_t mid = words / 2;
+            rescan_range(c, *j.chunk, j.hitbuf, 0, mid);
+            rescan_range(c, *j.chunk, j.hitbuf, mid, words);
+        }
+    }
+    j.active = false;
+}
+
+void retire_all(ifa_ctx *c)
+{
+    // oldest first
+    uint64_t s = c->job_seq;
+    for (uint64_t i = (s >= 2 ? s - 2 : 0); i < s; i++) retire(c, c->jobs[i % 2]);
+    collect_h2d_times(c);
+}
+
+// Launch the scan of a device chunk into the next hit buffer.
+void submit_job(ifa_ctx *c, DevChunk *ch)
+{
+    Job &j = c->jobs[c->job_seq % 2];
+    retire(c, j);   // frees the hit buffer this job will use
+    j.chunk = ch;
+    j.hitbuf = (int)(c->job_seq % 2);
+    ScanArgs a = make_args(c, *ch, j.hitbuf);
+    if (!j.k0) hip_check(hipEventCreate(&j.k0), "event");
+    if (!j.k1) hip_check(hipEventCreate(&j.k1), "event");
+    if (!j.done) hip_check(hipEventCreateWithFlags(&j.done, hipEventDisableTiming), "event");
+    if (c->cfg.sink == IFA_SINK_RECORDS)
+        hip_check(launch_clear_u64(a.hit_count, 1, c->comp_s), "clear hit counter");
+    hip_check(hipEventRecord(j.k0, c->comp_s), "event record");
+    hip_check(launch_scan(a, c->comp_s), "scan launch");
+    hip_check(hipEventRecord(j.k1, c->comp_s), "event record");
+    hip_check(hipEventRecord(ch->free_ev, c->comp_s), "event record");
+    if (c->cfg.sink == IFA_SINK_RECORDS)
+        hip_check(hipMemcpyAsync(c->h_hitcount.p + j.hitbuf, a.hit_count,
+                                 sizeof(unsigned long long), hipMemcpyDeviceToHost, c->comp_s),
+                  "copy hit count");
+    hip_check(hipEventRecord(j.done, c->comp_s), "event record");
+    j.active = true;
+    c->job_seq++;
+    c->st.kernel_launches++;
+    c->st.chunks++;
+}
+
+// Copy a sealed staging chunk into a device chunk on the copy stream.
+void upload(ifa_ctx *c, Staging &s, DevChunk &d, hipStream_t stream)
+{
+    const uint64_t words = words_with_pad(s.len);
+    if (d.pieces.n < s.pieces.size() || d.pieces.p == nullptr)
+        d.pieces.alloc(std::max<size_t>(s.pieces.size(), 1024), "device piece table");
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "event");
+    hip_check(hipEventCreate(&e1), "event");
+    hip_check(hipEventRecord(e0, stream), "event record");
+    if (d.stride < words) fail(IFA_E_INVALID, "device chunk too small");
+    for (int k = 0; k < 4; k++)
+        hip_check(hipMemcpyAsync(d.planes.p + (size_t)k * d.stride,
+                                 s.planes.p + (size_t)k * c->plane_words,
+                                 words * sizeof(uint32_t), hipMemcpyHostToDevice, stream),
+                  "copy chunk planes");
+    if (!s.pieces.empty())
+        hip_check(hipMemcpyAsync(d.pieces.p, s.pieces.data(), s.pieces.size() * sizeof(Piece),
+                                 hipMemcpyHostToDevice, stream),
+                  "copy piece table");
+    hip_check(hipEventRecord(e1, stream), "event record");
+    c->h2d_pending.emplace_back(e0, e1);
+    d.len = s.len;
+    d.own_from = s.own_from;
+    d.n_pieces = (uint32_t)s.pieces.size();
+}
+
+void reset_staging(Staging &s)
+{
+    s.pieces.clear();
+    s.tasks.clear();
+    s.len = 0;
+    s.own_from = 0;
+    s.packed_to = 0;
+}
+
+// Submit the staging chunk being filled (if it holds any base) to the GPU.
+void flush_stream(ifa_ctx *c)
+{
+    Staging &s = c->stage[c->cur];
+    if (s.len == 0) {
+        reset_staging(s);
+        return;
+    }
+    pack_pending(c, s);
+    seal(c, s);
+    DevChunk &d = c->slot[c->chunk_seq % 2];
+    // The device slot is reused. Its previous scan is retired first: an
+    // overflowing hit buffer is re-scanned from this slot, so the slot must
+    // not be overwritten before that job's hits are safe on the host.
+    for (auto &j : c->jobs)
+        if (j.active && j.chunk == &d) retire(c, j);
+    hip_check(hipStreamWaitEvent(c->copy_s, d.free_ev, 0), "wait slot");
+    upload(c, s, d, c->copy_s);
+    hip_check(hipEventRecord(s.copied, c->copy_s), "event record");
+    s.copy_pending = true;
+    hip_check(hipStreamWaitEvent(c->comp_s, s.copied, 0), "wait copy");
+    c->st.bases += s.len - s.own_from;
+    submit_job(c, &d);
+    c->chunk_seq++;
+    // switch staging buffers; wait until the other one's copy has finished
+    c->cur ^= 1;
+    Staging &n = c->stage[c->cur];
+    if (n.copy_pending) {
+        hip_check(hipEventSynchronize(n.copied), "wait staging");
+        n.copy_pending = false;
+    }
+    reset_staging(n);
+}
+
+// Append contigs to the chunk stream (or, when `sink` is given, to a
+// sequence of chunks handed to `sink` as each one fills).
+void append_contigs(ifa_ctx *c, uint32_t n_contigs, const uint8_t *const *seq,
+                    const uint64_t *len, const std::function<void()> &on_full)
+{
+    const uint64_t cap = c->cfg.chunk_bases;
+    for (uint32_t i = 0; i < n_contigs; i++) {
+        const uint32_t ordinal = c->next_ordinal++;
+        const uint64_t n = len[i];
+        const uint8_t *src = seq[i];
+        uint64_t x = 0;
+        bool continuing = false;    // a piece of this contig is in an earlier chunk
+        while (x < n) {
+            Staging *s = &c->stage[c->cur];
+            if (s->len == cap) {
+                on_full();
+                s = &c->stage[c->cur];
+            }
+            uint64_t carry = 0;
+            if (continuing && s->len == 0) {
+                carry = std::min<uint64_t>(kCarry, x);
+                s->own_from = (uint32_t)carry;
+            }
+            uint64_t room = cap - s->len - carry;
+            uint64_t take = std::min(room, n - x);
+            Piece p{};
+            p.start = s->len;
+            p.len = carry + take;
+            p.contig_off = x - carry;
+            p.contig = ordinal;
+            s->pieces.push_back(p);
+            s->tasks.push_back(PackTask{src + (x - carry), s->len, carry + take});
+            s->len += carry + take;
+            x += take;
+            continuing = true;
+        }
+    }
+}
+
+// Prepare the device to run on the context's device in this thread.
+void use_device(ifa_ctx *c) { hip_check(hipSetDevice(c->cfg.device), "hipSetDevice"); }
+
+template <class F>
+ifa_status guarded(ifa_ctx *c, F &&f)
+{
+    try {
+        if (c) c->err.clear();
+        f();
+        return IFA_OK;
+    } catch (const Failure &e) {
+        if (c) c->err = e.msg;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        if (c) c->err = "host allocation failed";
+        return IFA_E_NOMEM;
+    } catch (...) {
+        if (c) c->err = "unexpected internal error";
+        return IFA_E_DEVICE;
+    }
+}
+
+bool nothing_pending(ifa_ctx *c)
+{
+    if (c->stage[c->cur].len != 0) return false;
+    for (auto &j : c->jobs)
+        if (j.active) return false;
+    return c->drain_pos >= c->hits.size();
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void ifa_config_default(ifa_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof *cfg);
+    cfg->abi_version = IFA_ABI_VERSION;
+    cfg->device = 0;
+    cfg->chunk_bases = 1ull << 30;
+    cfg->hit_capacity = 0;
+    cfg->strands = IFA_STRAND_BOTH;
+    cfg->n_policy = IFA_N_SEPARATE;
+    cfg->sink = IFA_SINK_RECORDS;
+    cfg->host_threads = 0;
+}
+
+ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
+{
+    if (!out) return IFA_E_INVALID;
+    *out = nullptr;
+    ifa_config cfg;
+    if (cfg_in) cfg = *cfg_in; else ifa_config_default(&cfg);
+    if (cfg.abi_version != IFA_ABI_VERSION || cfg.chunk_bases < 4096 ||
+        cfg.chunk_bases > (1ull << 31) || (cfg.chunk_bases & 31) || cfg.strands < 1 ||
+        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1)
+        return IFA_E_INVALID;
+    ifa_ctx *c = new (std::nothrow) ifa_ctx();
+    if (!c) return IFA_E_NOMEM;
+    c->cfg = cfg;
+    ifa_status st = guarded(nullptr, [&]() {
+        int ndev = 0;
+        hip_check(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        if (cfg.device < 0 || cfg.device >= ndev) fail(IFA_E_INVALID, "no such device");
+        use_device(c);
+        unsigned hw = std::thread::hardware_concurrency();
+        c->threads = cfg.host_threads ? cfg.host_threads : (hw ? hw : 1);
+        c->threads = std::min(c->threads, 64u);
+        c->plane_words = words_with_pad(cfg.chunk_bases);
+        hip_check(hipStreamCreateWithFlags(&c->copy_s, hipStreamNonBlocking), "stream");
+        hip_check(hipStreamCreateWithFlags(&c->comp_s, hipStreamNonBlocking), "stream");
+        for (int i = 0; i < 2; i++) {
+            c->stage[i].planes.alloc(4 * c->plane_words, "pinned staging");
+            hip_check(hipEventCreateWithFlags(&c->stage[i].copied, hipEventDisableTiming),
+                      "event");
+            c->slot[i].stride = c->plane_words;
+            c->slot[i].planes.alloc(4 * c->plane_words, "device chunk");
+            c->slot[i].pieces.alloc(1024, "device piece table");
+            hip_check(hipEventCreateWithFlags(&c->slot[i].free_ev, hipEventDisableTiming),
+                      "event");
+        }
+        uint64_t cap = cfg.hit_capacity;
+        if (cap == 0) cap = 1ull << 22;
+        c->hit_cap = cap;
+        if (cfg.sink == IFA_SINK_RECORDS) {
+            for (int i = 0; i < 2; i++) {
+                c->d_hits[i].alloc(cap, "device hit buffer");
+                c->buf_cap[i] = cap;
+            }
+        }
+        c->d_hitcount.alloc(2, "hit counters");
+        c->h_hitcount.alloc(2, "pinned hit counters");
+        hip_check(hipMemset(c->d_hitcount.p, 0, 2 * sizeof(unsigned long long)), "memset");
+        c->h_hitcount.p[0] = c->h_hitcount.p[1] = 0;
+    });
+    if (st != IFA_OK) {
+        ifa_destroy(c);
+        return st;
+    }
+    *out = c;
+    return IFA_OK;
+}
+
+void ifa_destroy(ifa_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->cfg.device);
+    if (c->comp_s) (void)hipStreamSynchronize(c->comp_s);
+    if (c->copy_s) (void)hipStreamSynchronize(c->copy_s);
+    for (auto &pr : c->h2d_pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto &j : c->jobs) {
+        if (j.k0) (void)hipEventDestroy(j.k0);
+        if (j.k1) (void)hipEventDestroy(j.k1);
+        if (j.done) (void)hipEventDestroy(j.done);
+    }
+    for (int i = 0; i < 2; i++) {
+        if (c->stage[i].copied) (void)hipEventDestroy(c->stage[i].copied);
+        if (c->slot[i].free_ev) (void)hipEventDestroy(c->slot[i].free_ev);
+    }
+    for (auto &r : c->resident)
+        if (r->free_ev) (void)hipEventDestroy(r->free_ev);
+    c->resident.clear();
+    if (c->copy_s) (void)hipStreamDestroy(c->copy_s);
+    if (c->comp_s) (void)hipStreamDestroy(c->comp_s);
+    delete c;
+}
+
+const char *ifa_last_error(const ifa_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
+                            const uint32_t *len, const int32_t *max_subs, const int32_t *max_n)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (n > 0 && (!seq || !len || !max_subs)) fail(IFA_E_INVALID, "NULL argument");
+        if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
+        for (uint32_t j = 0; j < n; j++) {
+            if (len[j] == 0 || len[j] > IFA_MAX_QUERY_LEN)
+                fail(IFA_E_TOO_LONG, "query " + std::to_string(j) + " has length " +
+                                         std::to_string(len[j]) + " (allowed 1..256)");
+            if (!seq[j]) fail(IFA_E_INVALID, "NULL query pointer");
+            if (max_subs[j] < 0) fail(IFA_E_INVALID, "negative max_subs");
+            if (max_n && max_n[j] < 0) fail(IFA_E_INVALID, "negative max_n");
+        }
+        use_device(c);
+        std::vector<QSDesc> qs;
+        std::vector<uint32_t> words;
+        uint32_t lmax = 0;
+        for (uint32_t j = 0; j < n; j++) {
+            const uint32_t L = len[j];
+            lmax = std::max(lmax, L);
+            uint8_t code[IFA_MAX_QUERY_LEN];
+            for (uint32_t i = 0; i < L; i++) code[i] = kCode.c[seq[j][i]];
+            for (uint32_t s = 0; s < 2; s++) {
+                if (!(c->cfg.strands & (1u << s))) continue;
+                QSDesc d{};
+                d.qid = j;
+                d.len = (uint16_t)L;
+                d.strand = (uint8_t)s;
+                d.nw = (uint8_t)((L + 31) / 32);
+                d.k = (uint16_t)std::min<int64_t>(max_subs[j], L);
+                int64_t mn = max_n ? max_n[j] : (int64_t)(L / 4);
+                d.maxn = (uint16_t)std::min<int64_t>(mn, L);
+                d.woff = (uint32_t)words.size();
+                words.resize(words.size() + 3u * d.nw, 0u);
+                uint32_t *W = words.data() + d.woff;
+                for (uint32_t i = 0; i < L; i++) {
+                    // strand 1: reverse complement (A<->T, C<->G, N stays N)
+                    uint32_t v = s == 0 ? code[i] : code[L - 1 - i];
+                    if (s == 1 && v < 4) v = 3 - v;
+                    uint32_t t = i >> 5, bit = 1u << (i & 31);
+                    if (v == 4) {
+                        W[3 * t + 2] |= bit;
+                    } else {
+                        if (v & 2) W[3 * t] |= bit;
+                        if (v & 1) W[3 * t + 1] |= bit;
+                    }
+                }
+                qs.push_back(d);
+            }
+        }
+        c->d_qs.alloc(std::max<size_t>(qs.size(), 1), "query table");
+        c->d_qwords.alloc(std::max<size_t>(words.size(), 1), "query words");
+        if (!qs.empty())
+            hip_check(hipMemcpy(c->d_qs.p, qs.data(), qs.size() * sizeof(QSDesc),
+                                hipMemcpyHostToDevice),
+                      "upload queries");
+        if (!words.empty())
+            hip_check(hipMemcpy(c->d_qwords.p, words.data(), words.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice),
+                      "upload query words");
+        c->d_qcount.alloc(std::max<uint32_t>(n, 1), "query counters");
+        c->d_qdigest.alloc(std::max<uint32_t>(n, 1), "query digests");
+        hip_check(hipMemset(c->d_qcount.p, 0, c->d_qcount.n * sizeof(unsigned long long)),
+                  "memset");
+        hip_check(hipMemset(c->d_qdigest.p, 0, c->d_qdigest.n * sizeof(unsigned long long)),
+                  "memset");
+        c->h_qs = std::move(qs);
+        c->h_qwords = std::move(words);
+        c->n_queries = n;
+        c->lmax = std::max<uint32_t>(lmax, 1);
+        c->have_queries = true;
+        c->hits.clear();
+        c->drain_pos = 0;
+        c->hits_sorted = true;
+    });
+}
+
+ifa_status ifa_scan_chunk(ifa_ctx *c, uint32_t n_contigs, const uint8_t *const *seq,
+                          const uint64_t *len, uint32_t *first_ordinal)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (!c->have_queries) fail(IFA_E_STATE, "no queries loaded");
+        if (n_contigs > 0 && (!seq || !len)) fail(IFA_E_INVALID, "NULL argument");
+        for (uint32_t i = 0; i < n_contigs; i++) {
+            if (len[i] >= (1ull << 32)) fail(IFA_E_INVALID, "contig longer than 2^32 - 1");
+            if (len[i] > 0 && !seq[i]) fail(IFA_E_INVALID, "NULL contig pointer");
+        }
+        use_device(c);
+        if (first_ordinal) *first_ordinal = c->next_ordinal;
+        append_contigs(c, n_contigs, seq, len, [&]() { flush_stream(c); });
+        // caller memory must not be read after return
+        pack_pending(c, c->stage[c->cur]);
+    });
+}
+
+ifa_status ifa_collect_hits(ifa_ctx *c, ifa_hit *out, uint64_t cap, uint64_t *n_written,
+                            uint64_t *n_remaining)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (cap > 0 && !out) fail(IFA_E_INVALID, "NULL output");
+        use_device(c);
+        flush_stream(c);
+        retire_all(c);
+        if (!c->hits_sorted) {
+            std::sort(c->hits.begin() + (ptrdiff_t)c->drain_pos, c->hits.end(),
+                      [](const ifa_hit &a, const ifa_hit &b) {
+                          if (a.contig != b.contig) return a.contig < b.contig;
+                          if (a.pos != b.pos) return a.pos < b.pos;
+                          if (a.strand != b.strand) return a.strand < b.strand;
+                          return a.query < b.query;
+                      });
+            c->hits_sorted = true;
+        }
+        uint64_t avail = c->hits.size() - c->drain_pos;
+        uint64_t k = std::min(avail, cap);
+        if (k) std::memcpy(out, c->hits.data() + c->drain_pos, k * sizeof(ifa_hit));
+        c->drain_pos += k;
+        if (n_written) *n_written = k;
+        if (n_remaining) *n_remaining = avail - k;
+        if (c->drain_pos >= c->hits.size()) {
+            c->hits.clear();
+            c->hits.shrink_to_fit();
+            c->drain_pos = 0;
+        }
+    });
+}
+
+ifa_status ifa_query_stats(ifa_ctx *c, uint64_t *count, uint64_t *digest)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (c->cfg.sink != IFA_SINK_COUNT_DIGEST) fail(IFA_E_STATE, "sink is not count+digest");
+        if (!c->have_queries) fail(IFA_E_STATE, "no queries loaded");
+        use_device(c);
+        flush_stream(c);
+        retire_all(c);
+        hip_check(hipStreamSynchronize(c->comp_s), "sync");
+        if (count)
+            hip_check(hipMemcpy(count, c->d_qcount.p, c->n_queries * sizeof(uint64_t),
+                                hipMemcpyDeviceToHost),
+                      "copy counts");
+        if (digest)
+            hip_check(hipMemcpy(digest, c->d_qdigest.p, c->n_queries * sizeof(uint64_t),
+                                hipMemcpyDeviceToHost),
+                      "copy digests");
+    });
+}
+
+ifa_status ifa_ref_load(ifa_ctx *c, uint32_t n_contigs, const uint8_t *const *seq,
+                        const uint64_t *len, uint32_t *first_ordinal)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (n_contigs > 0 && (!seq || !len)) fail(IFA_E_INVALID, "NULL argument");
+        for (uint32_t i = 0; i < n_contigs; i++) {
+            if (len[i] >= (1ull << 32)) fail(IFA_E_INVALID, "contig longer than 2^32 - 1");
+            if (len[i] > 0 && !seq[i]) fail(IFA_E_INVALID, "NULL contig pointer");
+        }
+        if (c->stage[c->cur].len != 0)
+            fail(IFA_E_STATE, "a streamed chunk is being filled; collect hits first");
+        use_device(c);
+        if (first_ordinal) *first_ordinal = c->next_ordinal;
+        // Build chunks in the streaming staging buffers; each full chunk goes
+        // to a new resident device chunk instead of a stream slot.
+        auto to_resident = [&]() {
+            Staging &s = c->stage[c->cur];
+            if (s.len == 0) return;
+            pack_pending(c, s);
+            seal(c, s);
+            std::unique_ptr<DevChunk> d(new DevChunk());
+            d->stride = words_with_pad(s.len);
+            d->planes.alloc(4 * d->stride, "resident chunk");
+            d->pieces.alloc(std::max<size_t>(s.pieces.size(), 1), "resident piece table");
+            hip_check(hipEventCreateWithFlags(&d->free_ev, hipEventDisableTiming), "event");
+            upload(c, s, *d, c->copy_s);
+            hip_check(hipStreamSynchronize(c->copy_s), "sync");
+            c->resident_bases += s.len - s.own_from;
+            c->resident.push_back(std::move(d));
+            reset_staging(s);
+        };
+        append_contigs(c, n_contigs, seq, len, to_resident);
+        to_resident();
+        collect_h2d_times(c);
+    });
+}
+
+ifa_status ifa_scan_resident(ifa_ctx *c)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (!c->have_queries) fail(IFA_E_STATE, "no queries loaded");
+        if (c->resident.empty()) fail(IFA_E_STATE, "no resident reference");
+        use_device(c);
+        flush_stream(c);
+        for (auto &d : c->resident) {
+            c->st.bases += d->len - d->own_from;
+            submit_job(c, d.get());
+        }
+    });
+}
+
+ifa_status ifa_ref_release(ifa_ctx *c)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        use_device(c);
+        for (auto &j : c->jobs)
+            if (j.active) fail(IFA_E_STATE, "scans pending; collect hits first");
+        hip_check(hipStreamSynchronize(c->comp_s), "sync");
+        for (auto &r : c->resident)
+            if (r->free_ev) (void)hipEventDestroy(r->free_ev);
+        c->resident.clear();
+        c->resident_bases = 0;
+    });
+}
+
+ifa_status ifa_ref_info(const ifa_ctx *c, uint64_t *bases, uint32_t *chunks)
+{
+    if (!c) return IFA_E_INVALID;
+    if (bases) *bases = c->resident_bases;
+    if (chunks) *chunks = (uint32_t)c->resident.size();
+    return IFA_OK;
+}
+
+ifa_status ifa_get_stats(ifa_ctx *c, ifa_stats *out)
+{
+    if (!c || !out) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        use_device(c);
+        retire_all(c);
+        *out = c->st;
+    });
+}
+
+ifa_status ifa_reset_stats(ifa_ctx *c)
+{
+    if (!c) return IFA_E_INVALID;
+    std::memset(&c->st, 0, sizeof c->st);
+    return IFA_OK;
+}
+
+}  // extern "C"

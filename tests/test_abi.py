@@ -1,0 +1,66 @@
+"""The C ABI library: it loads, and exports every entry point include/ifa.h
+declares. No compute call is made here (no GPU needed)."""
+import ctypes
+import os
+import re
+import subprocess
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ifa.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ifa_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_core_calls():
+    names = declared_functions()
+    for core in ("ifa_create", "ifa_load_queries", "ifa_scan_chunk", "ifa_collect_hits",
+                 "ifa_destroy"):
+        assert core in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2607_27291_amd as ifa
+    L = ifa.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", ifa._build.LIB], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (ifa_[a-z_]+)\b", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_struct_layouts_match_header():
+    import paper_2607_27291_amd as ifa
+    assert ifa.HIT_DTYPE.itemsize == 16
+    assert ctypes.sizeof(ifa.IfaConfig) == 40
+    cfg = ifa.ifa_config_default()
+    assert cfg.abi_version == ifa.IFA_ABI_VERSION
+    assert cfg.chunk_bases == 1 << 30 and cfg.strands == 3 and cfg.sink == 0
+
+
+def test_null_and_bad_arguments_are_rejected_without_a_device():
+    import paper_2607_27291_amd as ifa
+    L = ifa.lib()
+    assert L.ifa_create(None, None) == 1                      # IFA_E_INVALID
+    cfg = ifa.ifa_config_default()
+    cfg.chunk_bases = 1000                                    # not a multiple of 32 / too small
+    ctx = ctypes.c_void_p()
+    assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
+    assert not ctx.value
+    cfg = ifa.ifa_config_default()
+    cfg.abi_version = 99
+    assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
+    L.ifa_destroy(None)                                       # NULL-safe
+    assert L.ifa_load_queries(None, 0, None, None, None, None) == 1
+    assert L.ifa_scan_chunk(None, 0, None, None, None) == 1
+    assert L.ifa_collect_hits(None, None, 0, None, None) == 1
+
+
+def test_binding_names_mirror_the_c_entry_points():
+    import paper_2607_27291_amd as ifa
+    for name in declared_functions():
+        assert hasattr(ifa, name), name

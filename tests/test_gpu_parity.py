@@ -1,0 +1,269 @@
+"""Parity of the HIP scan (through the C ABI) with the oracle.
+
+Every comparison is element by element on all six record fields (query,
+contig, pos, strand, n_ref, mismatches) in reference order; the method is
+integer-only, so the bar is bit-exact. Inputs are seeded; each test prints the
+case it is about to run before touching the GPU.
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+COMP = bytes.maketrans(b"ACGTacgt", b"TGCAtgca")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rand_dna(rng, n, alphabet=b"ACGT"):
+    return bytes(rng.choice(alphabet) for _ in range(n))
+
+
+@pytest.fixture(scope="module")
+def ifa():
+    import paper_2607_27291_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def gpu_scan(ifa, queries, contigs, ks, mn=None, *, calls=1, **cfg):
+    with ifa.Scanner(**cfg) as s:
+        s.load_queries(queries, ks, mn)
+        if calls <= 1:
+            s.scan_chunk(contigs)
+        else:
+            parts = np.array_split(np.arange(len(contigs)), calls)
+            for idx in parts:
+                s.scan_chunk([contigs[i] for i in idx])
+        return s.collect()
+
+
+def assert_same(a, b, ctx=""):
+    if not np.array_equal(a, b):
+        sa = {tuple(r) for r in a.tolist()}
+        sb = {tuple(r) for r in b.tolist()}
+        raise AssertionError(f"{ctx}: gpu {len(a)} oracle {len(b)}; only gpu "
+                             f"{sorted(sa - sb)[:5]} only oracle {sorted(sb - sa)[:5]}")
+
+
+def test_c1_tiny_bit_exact(ifa, orc):
+    import synth
+    w = synth.c1_tiny()
+    say("c1_tiny: 1 query L32 vs 10 x 100 kbp, k=3")
+    want = orc.scan(w.queries, w.ref, w.max_subs)
+    got = gpu_scan(ifa, w.queries, w.ref, w.max_subs)
+    assert_same(got, want, "c1")
+    assert len(got) == 20
+    planted = {(p.query, p.contig, p.pos, p.strand, 0, p.subs) for p in w.plants}
+    assert {tuple(r) for r in got.tolist()} == planted
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_random_small_cases(ifa, orc, policy):
+    rng = random.Random(1000 + policy)
+    for trial in range(60):
+        nc = rng.randint(0, 6)
+        contigs = []
+        for _ in range(nc):
+            n = rng.choice([0, 1, 5, 31, 32, 33, 63, 64, 65, 100, 257, 1000, 4000])
+            alpha = rng.choice([b"ACGT", b"ACGT", b"ACGTN", b"acgtNNRY"])
+            contigs.append(rand_dna(rng, n, alpha))
+        nq = rng.randint(1, 6)
+        qs = [rand_dna(rng, rng.choice([1, 2, 7, 16, 31, 32, 33, 40, 63, 64, 65, 100]),
+                       b"ACGT" if rng.random() < 0.85 else b"ACGTN") for _ in range(nq)]
+        ks = [rng.randint(0, len(q) + 1) if rng.random() < 0.5 else rng.randint(0, 3) for q in qs]
+        mn = None if rng.random() < 0.5 else [rng.randint(0, len(q)) for q in qs]
+        strands = rng.choice([1, 2, 3])
+        chunk = rng.choice([4096, 4096 + 32 * 7, 1 << 16])
+        say(f"random trial {trial} policy {policy} nq {nq} nc {nc} chunk {chunk}")
+        want = orc.scan(qs, contigs, ks, mn, strands=strands, policy=policy)
+        got = gpu_scan(ifa, qs, contigs, ks, mn, strands=strands, n_policy=policy,
+                       chunk_bases=chunk, calls=rng.choice([1, 2, 3]))
+        assert_same(got, want, f"trial {trial}")
+
+
+def test_queries_of_every_length_and_threshold(ifa, orc):
+    rng = random.Random(77)
+    contigs = [rand_dna(rng, 3000, b"ACGTN") for _ in range(3)]
+    for L in (1, 2, 3, 8, 15, 31, 32, 33, 47, 64, 95, 96, 97, 128, 150, 200, 255, 256):
+        # plant a few near copies so high-threshold and low-threshold hits exist
+        q = rand_dna(rng, L)
+        cs = []
+        for c in contigs:
+            c = bytearray(c)
+            for _ in range(3):
+                p = rng.randint(0, len(c) - L)
+                src = q if rng.random() < 0.5 else q.translate(COMP)[::-1]
+                c[p:p + L] = src
+            cs.append(bytes(c))
+        ks = [0, L // 8, L // 4, L // 2, L]
+        say(f"length {L}")
+        want = orc.scan([q] * len(ks), cs, ks)
+        got = gpu_scan(ifa, [q] * len(ks), cs, ks, chunk_bases=8192)
+        assert_same(got, want, f"L={L}")
+
+
+def test_chunk_size_and_call_split_invariance(ifa, orc):
+    import synth
+    spec = synth.c2_spec(seed=21, total=3_000_000)
+    spec.n_param = 2e-3
+    spec.median = 20_000
+    ref = synth.gen_reference(spec)
+    qs = synth.gen_queries(21, 6, 20, 60)
+    ks = [6, 8, 10, 12, 14, 16]
+    say("chunk invariance: 3 Mbp, 6 queries")
+    want = orc.scan(qs, ref, ks)
+    contigs = [ref.contig(i) for i in range(ref.n_contigs)]
+    for chunk, calls in ((4096, 1), (4096 + 32, 5), (100_000, 3), (1 << 20, 2), (1 << 30, 1)):
+        say(f"  chunk {chunk} calls {calls}")
+        got = gpu_scan(ifa, qs, contigs, ks, chunk_bases=chunk, calls=calls)
+        assert_same(got, want, f"chunk {chunk}")
+
+
+def test_contig_longer_than_chunk(ifa, orc):
+    rng = random.Random(5)
+    q = rand_dna(rng, 40)
+    big = bytearray(rand_dna(rng, 50_000, b"ACGTN"))
+    for p in range(0, 50_000 - 40, 997):       # copies straddling every chunk boundary
+        big[p:p + 40] = q
+    contigs = [rand_dna(rng, 100), bytes(big), rand_dna(rng, 10)]
+    say("contig longer than chunk")
+    want = orc.scan([q], contigs, [2])
+    got = gpu_scan(ifa, [q], contigs, [2], chunk_bases=4096)
+    assert_same(got, want, "long contig")
+    assert len(got) >= 50
+
+
+def test_overflow_rescan_gives_same_result(ifa, orc):
+    rng = random.Random(8)
+    contigs = [rand_dna(rng, 20_000) for _ in range(3)]
+    qs = [rand_dna(rng, 10), rand_dna(rng, 12)]
+    ks = [5, 6]                 # thousands of hits
+    say("overflow: hit capacity 7")
+    want = orc.scan(qs, contigs, ks)
+    assert len(want) > 1000
+    for cap in (7, 100, 1 << 20):
+        got = gpu_scan(ifa, qs, contigs, ks, hit_capacity=cap, chunk_bases=16384)
+        assert_same(got, want, f"cap {cap}")
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_count_digest_sink(ifa, orc, policy):
+    import synth
+    spec = synth.c2_spec(seed=33, total=2_000_000)
+    spec.n_param = 1e-3
+    ref = synth.gen_reference(spec)
+    qs = synth.gen_queries(33, 40, 18, 50)
+    rng = np.random.default_rng(33)
+    ks = [int(x) for x in rng.integers(0, 17, size=len(qs))]
+    say(f"count+digest policy {policy}")
+    _, cnt, dig = orc.scan(qs, ref, ks, policy=policy, stats=True, records=False)
+    with ifa.Scanner(sink=ifa.IFA_SINK_COUNT_DIGEST, n_policy=policy, chunk_bases=1 << 18) as s:
+        s.load_queries(qs, ks)
+        s.scan_chunk(ref)
+        gc, gd = s.query_stats()
+    assert np.array_equal(gc, cnt)
+    assert np.array_equal(gd, dig)
+    assert int(cnt.sum()) > 10_000
+
+
+def test_resident_reference_matches_streaming(ifa, orc):
+    import synth
+    spec = synth.c2_spec(seed=44, total=5_000_000)
+    ref = synth.gen_reference(spec)
+    rng = random.Random(44)
+    say("resident reference, two query sets")
+    with ifa.Scanner(chunk_bases=1 << 21) as s:
+        first = s.ref_load(ref)
+        assert first == 0
+        bases, chunks = ifa.ifa_ref_info(s.ctx)
+        assert bases == ref.total and chunks == 3
+        for round_ in range(2):
+            qs = [rand_dna(rng, rng.randint(18, 60)) for _ in range(5)]
+            ks = [rng.randint(2, 12) for _ in qs]
+            s.load_queries(qs, ks)
+            s.scan_resident()
+            got = s.collect()
+            want = orc.scan(qs, ref, ks)
+            assert_same(got, want, f"resident round {round_}")
+
+
+def test_error_paths(ifa):
+    say("error paths")
+    with ifa.Scanner(chunk_bases=4096) as s:
+        with pytest.raises(ifa.IfaError) as e:
+            s.load_queries([b""], [0])
+        assert e.value.status == 5
+        with pytest.raises(ifa.IfaError) as e:
+            s.load_queries([b"A" * 257], [0])
+        assert e.value.status == 5
+        with pytest.raises(ifa.IfaError) as e:
+            s.load_queries([b"ACGT"], [-1])
+        assert e.value.status == 1
+        with pytest.raises(ifa.IfaError) as e:
+            s.scan_chunk([b"ACGT"])              # no queries yet
+        assert e.value.status == 4
+        s.load_queries([b"ACGT"], [0])
+        s.scan_chunk([b"TTACGTT"])
+        with pytest.raises(ifa.IfaError) as e:
+            s.load_queries([b"ACGT"], [0])       # hits pending
+        assert e.value.status == 4
+        got = s.collect()
+        assert {tuple(r) for r in got.tolist()} == {(0, 0, 2, 0, 0, 0), (0, 0, 2, 1, 0, 0)}
+        s.load_queries([b"ACGT"], [0])           # allowed again once drained
+        assert s.scan_chunk([b"", b"ACGTACGT"]) == 1     # ordinals continue
+        got = s.collect()
+        assert {tuple(r) for r in got.tolist()} == {(0, 2, p, st, 0, 0) for p in (0, 4)
+                                                    for st in (0, 1)}
+
+
+def test_collect_in_small_batches(ifa, orc):
+    rng = random.Random(9)
+    contigs = [rand_dna(rng, 5000) for _ in range(2)]
+    qs = [rand_dna(rng, 8)]
+    want = orc.scan(qs, contigs, [3])
+    say("two-call drain")
+    with ifa.Scanner(chunk_bases=4096) as s:
+        s.load_queries(qs, [3])
+        s.scan_chunk(contigs)
+        parts = []
+        while True:
+            h, rem = ifa.ifa_collect_hits(s.ctx, 37)
+            parts.append(h)
+            if rem == 0:
+                break
+        got = np.concatenate(parts)
+    assert_same(got, want, "batched drain")
+
+
+def test_c2_scaled_full_parity(ifa, orc):
+    """The paper-scale generator at 200 Mbp: every query and threshold of the
+    configuration, full oracle comparison."""
+    import synth
+    say("c2 scaled: 200 Mbp, 10 queries, k in 0 4 8")
+    w = synth.c2_paper_scale(total=200_000_000, plants_per_query=4)
+    for k in (0, 4, 8):
+        ks = [k] * len(w.queries)
+        want = orc.scan(w.queries, w.ref, ks)
+        with ifa.Scanner() as s:
+            s.load_queries(w.queries, ks)
+            s.scan_chunk(w.ref)
+            got = s.collect()
+        assert_same(got, want, f"c2 k={k}")
+        found = {(int(r[0]), int(r[1]), int(r[2]), int(r[3])) for r in got.tolist()}
+        for p in w.plants:
+            if p.subs <= k:
+                assert (p.query, p.contig, p.pos, p.strand) in found
