@@ -40,10 +40,28 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--total", type=int, default=4_000_000_000, help="reference bases")
     ap.add_argument("--ks", default="0,4,8")
-    ap.add_argument("--cpu-sample", type=int, default=100_000_000,
+    ap.add_argument("--cpu-sample", type=int, default=250_000_000,
                     help="reference bases the oracle baseline scans per maxSubs (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="scan kernel variant (default: autotuned on the workload's queries)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a 1 GiB device copy kernel (calib_copy_kernel) 3 times, "
+                         "to scale the HBM byte counters of a profiling run")
     return ap.parse_args()
+
+
+def calib_copy():
+    import ctypes
+    from paper_2607_27291_amd import build as b
+    L = ctypes.CDLL(b.CALIB_LIB)
+    L.ifa_calib_copy.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    ms = ctypes.c_double()
+    rc = L.ifa_calib_copy(1 << 30, 3, ctypes.byref(ms))
+    if rc != 0:
+        raise RuntimeError(f"calibration copy failed: HIP error {rc}")
+    log(f"calib copy: 1 GiB read + 1 GiB write per launch, {ms.value:.3f} ms "
+        f"({2 * (1 << 30) / ms.value / 1e6:.0f} GB/s)")
 
 
 def main():
@@ -56,6 +74,8 @@ def main():
     import synth
     import paper_2607_27291_amd as ifa
 
+    if args.calib_copy:
+        calib_copy()
     ks = [int(x) for x in args.ks.split(",")]
     t0 = time.time()
     w = synth.c2_paper_scale(total=args.total)
@@ -68,6 +88,19 @@ def main():
     s.ref_load(w.ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
     log(f"resident: {bases / 1e9:.2f} Gbp in {chunks} device chunks ({time.time() - t0:.1f} s)")
+
+    # choose the kernel variant: autotuner on a 64 Mi-base calibration chunk
+    # with this workload's queries (maxSubs 4), unless one is given
+    if args.variant >= 0:
+        ifa.ifa_set_variant(s.ctx, args.variant)
+        tune = None
+    else:
+        s.load_queries(w.queries, [4] * nq)
+        chosen, ms = ifa.ifa_autotune(s.ctx, 64 << 20, 5)
+        tune = {"chosen": chosen, "ms": [round(float(x), 4) for x in ms]}
+        log(f"autotune: variant {chosen} {ifa.ifa_variant_info(chosen)}; "
+            f"ms per variant {tune['ms']}")
+    variant = ifa.ifa_get_variant(s.ctx)
 
     def step():
         found = 0
@@ -124,6 +157,7 @@ def main():
             "hits_per_step": hits // max(1, args.steps),
         },
         "kernel_only_gbpq_s": round(kernel_rate, 3),
+        "autotune": tune,
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved, 3),
@@ -131,7 +165,9 @@ def main():
             "unit": "TOP/s",
             "frac": round(achieved / peak, 4),
             "traffic": None,
-            "kernel": "scan_words_kernel",
+            "kernel": "scan_kernel",
+            "variant": variant,
+            "variant_shape": ifa.ifa_variant_info(variant),
             "kernel_ms_avg": round(kernel_ms_avg, 4),
             "launches": launches,
         },

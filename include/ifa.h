@@ -181,6 +181,28 @@ ifa_status ifa_ref_info(const ifa_ctx *ctx, uint64_t *bases, uint32_t *chunks);
 ifa_status ifa_get_stats(ifa_ctx *ctx, ifa_stats *out);
 ifa_status ifa_reset_stats(ifa_ctx *ctx);
 
+/* Kernel variants: tile shapes of the scan kernel (windows per lane, query
+ * strands per loop iteration, workgroup size). Every variant computes the
+ * same hits; they differ only in speed. */
+uint32_t ifa_variant_count(void);
+ifa_status ifa_variant_info(uint32_t v, uint32_t *windows_per_lane, uint32_t *queries_per_iter,
+                            uint32_t *workgroup);
+ifa_status ifa_set_variant(ifa_ctx *ctx, uint32_t v);
+ifa_status ifa_get_variant(const ifa_ctx *ctx, uint32_t *v);
+
+/* Autotuner: time every variant on a calibration chunk of calib_bases
+ * uniform random bases (0 = 64 Mi) with the loaded queries, median of reps
+ * launches (0 = 3), and select the fastest for this context. cache_path (may
+ * be NULL): a text file of "key variant ms" lines keyed by device
+ * architecture, query-strand count band, longest query in words and threshold
+ * band; a cached key is used without timing, a new result is appended.
+ * *chosen (may be NULL) gets the variant; ms_per_variant (may be NULL) gets
+ * ifa_variant_count() medians (-1 when taken from the cache). Hits found on
+ * the calibration chunk are discarded. Errors: IFA_E_STATE (no queries, or
+ * scans pending). */
+ifa_status ifa_autotune(ifa_ctx *ctx, uint64_t calib_bases, uint32_t reps, const char *cache_path,
+                        uint32_t *chosen, double *ms_per_variant);
+
 #ifdef __cplusplus
 }
 #endif

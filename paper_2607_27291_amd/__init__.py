@@ -18,7 +18,8 @@ __all__ = [
     "IfaError", "HIT_DTYPE", "lib", "ifa_config_default", "ifa_create", "ifa_destroy",
     "ifa_load_queries", "ifa_scan_chunk", "ifa_collect_hits", "ifa_last_error",
     "ifa_query_stats", "ifa_ref_load", "ifa_scan_resident", "ifa_ref_release", "ifa_ref_info",
-    "ifa_get_stats", "ifa_reset_stats", "Scanner", "collect_all",
+    "ifa_get_stats", "ifa_reset_stats", "ifa_variant_count", "ifa_variant_info",
+    "ifa_set_variant", "ifa_get_variant", "ifa_autotune", "Scanner", "collect_all",
 ]
 
 IFA_ABI_VERSION = 1
@@ -95,6 +96,17 @@ def lib():
         L.ifa_get_stats.restype = st
         L.ifa_reset_stats.argtypes = [vp]
         L.ifa_reset_stats.restype = st
+        L.ifa_variant_count.argtypes = []
+        L.ifa_variant_count.restype = u32
+        L.ifa_variant_info.argtypes = [u32, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                       ctypes.POINTER(u32)]
+        L.ifa_variant_info.restype = st
+        L.ifa_set_variant.argtypes = [vp, u32]
+        L.ifa_set_variant.restype = st
+        L.ifa_get_variant.argtypes = [vp, ctypes.POINTER(u32)]
+        L.ifa_get_variant.restype = st
+        L.ifa_autotune.argtypes = [vp, u64, u32, ctypes.c_char_p, ctypes.POINTER(u32), vp]
+        L.ifa_autotune.restype = st
         _lib = L
     return _lib
 
@@ -233,6 +245,39 @@ def ifa_get_stats(ctx) -> dict:
 
 def ifa_reset_stats(ctx):
     _check(ctx, lib().ifa_reset_stats(ctx))
+
+
+def ifa_variant_count() -> int:
+    return int(lib().ifa_variant_count())
+
+
+def ifa_variant_info(v: int) -> dict:
+    a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    st = lib().ifa_variant_info(v, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if st != 0:
+        raise IfaError(st, f"no variant {v}")
+    return {"windows_per_lane": a.value, "queries_per_iter": b.value, "workgroup": c.value}
+
+
+def ifa_set_variant(ctx, v: int):
+    _check(ctx, lib().ifa_set_variant(ctx, v))
+
+
+def ifa_get_variant(ctx) -> int:
+    v = ctypes.c_uint32()
+    _check(ctx, lib().ifa_get_variant(ctx, ctypes.byref(v)))
+    return v.value
+
+
+def ifa_autotune(ctx, calib_bases: int = 0, reps: int = 0, cache_path: str | None = None):
+    """Returns (chosen variant, per-variant median ms; -1 entries = cache hit)."""
+    nv = ifa_variant_count()
+    ms = np.zeros(nv, dtype=np.float64)
+    chosen = ctypes.c_uint32()
+    _check(ctx, lib().ifa_autotune(ctx, calib_bases, reps,
+                                   cache_path.encode() if cache_path else None,
+                                   ctypes.byref(chosen), ms.ctypes.data))
+    return chosen.value, ms
 
 
 def collect_all(ctx, batch: int = 1 << 20) -> np.ndarray:

@@ -42,7 +42,23 @@ def build(force=True, verbose=False):
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)
+    build_calib(verbose)
     return LIB
+
+
+CALIB_LIB = os.path.join(HERE, "libifa_calib.so")
+
+
+def build_calib(verbose=False):
+    """The copy kernel that calibrates HBM byte counters (measurement only)."""
+    tmp = CALIB_LIB + ".tmp"
+    cmd = [HIPCC, *DEVICE, "-x", "hip", *COMMON, "-shared",
+           os.path.join(CSRC, "ifa_calib.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, CALIB_LIB)
+    return CALIB_LIB
 
 
 if __name__ == "__main__":

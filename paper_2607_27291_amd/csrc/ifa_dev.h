@@ -33,9 +33,11 @@ struct Piece {
 };
 static_assert(sizeof(Piece) == 32, "Piece layout");
 
-// One (query, strand) entry. Its packed words live at qwords[woff ...]:
-// for word t (bases 32t .. 32t+31 of the strand sequence) the three words
-// hi, lo, qn at woff + 3t + {0, 1, 2}; bits at or past L are zero.
+// One (query, strand) entry, 32 bytes so a wave reads it with a single scalar
+// load. Its packed words live at qwords[woff ...]: for word t (bases 32t ..
+// 32t+31 of the strand sequence) the three words hi, lo, qn at
+// woff + 3t + {0, 1, 2}; bits at or past L are zero. Word 0 is repeated
+// inline (qh0, ql0, qn0) for the filter.
 struct QSDesc {
     uint32_t qid;         // caller's query index
     uint16_t len;         // L
@@ -44,8 +46,10 @@ struct QSDesc {
     uint16_t k;           // min(maxSubs, L)
     uint16_t maxn;        // min(maxN, L)
     uint32_t woff;
+    uint32_t qh0, ql0, qn0;
+    uint32_t thr;         // filter bound k + 32 - min(L, 32); >= 32: no filter
 };
-static_assert(sizeof(QSDesc) == 16, "QSDesc layout");
+static_assert(sizeof(QSDesc) == 32, "QSDesc layout");
 
 struct ScanArgs {
     const uint32_t *hi, *lo, *nm, *em;
@@ -60,6 +64,7 @@ struct ScanArgs {
     const Piece *pieces;
     uint32_t n_pieces;
     uint32_t sink;
+    uint32_t variant;         // kernel variant index (see kVariants)
     // records sink
     uint4 *hits;
     unsigned long long *hit_count;

@@ -27,6 +27,8 @@
 namespace ifa {
 hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
+uint32_t variant_count();
+void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg);
 }  // namespace ifa
 
 using namespace ifa;
@@ -191,6 +193,10 @@ struct ifa_ctx {
     uint64_t plane_words = 0;
 
     hipStream_t copy_s = nullptr, comp_s = nullptr;
+
+    // kernel variant (autotuner or caller's choice)
+    uint32_t variant = 0;
+    std::vector<double> tune_ms;
 
     // queries
     bool have_queries = false;
@@ -368,6 +374,7 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
+    a.variant = c->variant;
     a.hits = c->d_hits[hb].p;
     a.hit_count = c->d_hitcount.p + hb;
     a.hit_cap = c->buf_cap[hb];
@@ -642,6 +649,55 @@ bool nothing_pending(ifa_ctx *c)
     return c->drain_pos >= c->hits.size();
 }
 
+// Autotune cache key: device architecture, query-strand count band (log2),
+// longest query in words, threshold band. Tile choice depends on these.
+std::string tune_key(ifa_ctx *c)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->cfg.device) == hipSuccess) arch = prop.gcnArchName;
+    for (auto &ch : arch)
+        if (ch == ' ' || ch == '\t') ch = '_';
+    uint32_t nqs = (uint32_t)c->h_qs.size(), band = 0;
+    while ((1u << band) < nqs) band++;
+    uint32_t nw = 0, kmin = 0xffff, kmax = 0;
+    for (const QSDesc &d : c->h_qs) {
+        nw = std::max<uint32_t>(nw, d.nw);
+        kmin = std::min<uint32_t>(kmin, d.k);
+        kmax = std::max<uint32_t>(kmax, d.k);
+    }
+    return arch + "|q2^" + std::to_string(band) + "|w" + std::to_string(nw) + "|k" +
+           std::to_string(kmin / 4) + "-" + std::to_string(kmax / 4) + "|v" +
+           std::to_string(ifa::variant_count());
+}
+
+bool cache_lookup(const char *path, const std::string &key, uint32_t *v)
+{
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[400];
+        unsigned vv;
+        double ms;
+        if (std::sscanf(line, "%399s %u %lf", k, &vv, &ms) == 3 && key == k) {
+            *v = vv;
+            found = true;   // the last entry for a key wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, uint32_t v, double ms)
+{
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %u %.6f\n", key.c_str(), v, ms);
+    std::fclose(f);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -798,9 +854,20 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
                         if (v & 1) W[3 * t + 1] |= bit;
                     }
                 }
+                d.qh0 = W[0];
+                d.ql0 = W[1];
+                d.qn0 = W[2];
+                // filter bound: unmasked query bits past L may add 32 - min(L, 32)
+                d.thr = (uint32_t)d.k + 32u - std::min<uint32_t>(L, 32u);
                 qs.push_back(d);
             }
         }
+        // group strands of equal word count, then by threshold, so waves see
+        // similar early-exit behaviour in consecutive iterations
+        std::stable_sort(qs.begin(), qs.end(), [](const QSDesc &x, const QSDesc &y) {
+            if (x.nw != y.nw) return x.nw < y.nw;
+            return x.k < y.k;
+        });
         c->d_qs.alloc(std::max<size_t>(qs.size(), 1), "query table");
         c->d_qwords.alloc(std::max<size_t>(words.size(), 1), "query words");
         if (!qs.empty())
@@ -984,6 +1051,137 @@ ifa_status ifa_get_stats(ifa_ctx *c, ifa_stats *out)
         use_device(c);
         retire_all(c);
         *out = c->st;
+    });
+}
+
+uint32_t ifa_variant_count(void) { return ifa::variant_count(); }
+
+ifa_status ifa_variant_info(uint32_t v, uint32_t *windows_per_lane, uint32_t *queries_per_iter,
+                            uint32_t *workgroup)
+{
+    if (v >= ifa::variant_count()) return IFA_E_INVALID;
+    uint32_t a, b, g;
+    ifa::variant_shape(v, &a, &b, &g);
+    if (windows_per_lane) *windows_per_lane = a;
+    if (queries_per_iter) *queries_per_iter = b;
+    if (workgroup) *workgroup = g;
+    return IFA_OK;
+}
+
+ifa_status ifa_set_variant(ifa_ctx *c, uint32_t v)
+{
+    if (!c) return IFA_E_INVALID;
+    if (v >= ifa::variant_count()) {
+        c->err = "no such kernel variant";
+        return IFA_E_INVALID;
+    }
+    c->variant = v;
+    return IFA_OK;
+}
+
+ifa_status ifa_get_variant(const ifa_ctx *c, uint32_t *v)
+{
+    if (!c || !v) return IFA_E_INVALID;
+    *v = c->variant;
+    return IFA_OK;
+}
+
+ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const char *cache_path,
+                        uint32_t *chosen, double *ms_per_variant)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (!c->have_queries) fail(IFA_E_STATE, "no queries loaded");
+        if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
+        use_device(c);
+        if (calib_bases == 0) calib_bases = 64ull << 20;
+        calib_bases = std::max<uint64_t>(4096, std::min<uint64_t>(calib_bases, c->cfg.chunk_bases));
+        calib_bases &= ~31ull;
+        if (reps == 0) reps = 3;
+        const std::string key = tune_key(c);
+        const uint32_t nv = ifa::variant_count();
+        if (cache_path) {
+            uint32_t v;
+            if (cache_lookup(cache_path, key, &v) && v < nv) {
+                c->variant = v;
+                if (chosen) *chosen = v;
+                if (ms_per_variant)
+                    for (uint32_t i = 0; i < nv; i++) ms_per_variant[i] = -1.0;
+                return;
+            }
+        }
+        // calibration chunk: uniform random bases, one contig piece, no N
+        DevChunk ch;
+        ch.stride = words_with_pad(calib_bases);
+        ch.planes.alloc(4 * ch.stride, "calibration chunk");
+        ch.pieces.alloc(1, "calibration piece");
+        std::vector<uint32_t> host(4 * ch.stride, 0u);
+        uint64_t z = 0x243F6A8885A308D3ull;
+        const uint64_t used = calib_bases >> 5;
+        for (uint64_t w = 0; w < used; w++) {
+            z += 0x9E3779B97F4A7C15ull;
+            uint64_t r = z;
+            r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ull;
+            r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
+            r ^= r >> 31;
+            host[w] = (uint32_t)r;
+            host[ch.stride + w] = (uint32_t)(r >> 32);
+        }
+        uint32_t *E = host.data() + 3 * ch.stride, *N = host.data() + 2 * ch.stride;
+        E[(calib_bases - 1) >> 5] |= 1u << ((calib_bases - 1) & 31);
+        for (uint64_t w = used; w < ch.stride; w++) {
+            N[w] = 0xffffffffu;
+            E[w] = 0xffffffffu;
+        }
+        hip_check(hipMemcpy(ch.planes.p, host.data(), host.size() * sizeof(uint32_t),
+                            hipMemcpyHostToDevice),
+                  "upload calibration chunk");
+        Piece pc{};
+        pc.len = calib_bases;
+        hip_check(hipMemcpy(ch.pieces.p, &pc, sizeof pc, hipMemcpyHostToDevice), "upload piece");
+        ch.len = calib_bases;
+        ch.n_pieces = 1;
+        // hits go to a small scratch buffer; the tuner only times
+        DevBuf<uint4> scratch_hits;
+        scratch_hits.alloc(1024, "tuning hit buffer");
+        DevBuf<unsigned long long> scratch_cnt;
+        scratch_cnt.alloc(2, "tuning counter");
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "event");
+        hip_check(hipEventCreate(&e1), "event");
+        std::vector<double> ms(nv, 0.0);
+        const uint32_t saved = c->variant;
+        for (uint32_t v = 0; v < nv; v++) {
+            c->variant = v;
+            ScanArgs a = make_args(c, ch, 0);
+            a.sink = kSinkRecords;
+            a.hits = scratch_hits.p;
+            a.hit_count = scratch_cnt.p;
+            a.hit_cap = 1024;
+            hip_check(launch_scan(a, c->comp_s), "tuning launch");   // warm up
+            std::vector<float> t(reps);
+            for (uint32_t r = 0; r < reps; r++) {
+                hip_check(hipEventRecord(e0, c->comp_s), "event record");
+                hip_check(launch_scan(a, c->comp_s), "tuning launch");
+                hip_check(hipEventRecord(e1, c->comp_s), "event record");
+                hip_check(hipEventSynchronize(e1), "tuning sync");
+                hip_check(hipEventElapsedTime(&t[r], e0, e1), "event time");
+            }
+            std::sort(t.begin(), t.end());
+            ms[v] = t[reps / 2];
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->variant = saved;
+        uint32_t best = 0;
+        for (uint32_t v = 1; v < nv; v++)
+            if (ms[v] < ms[best]) best = v;
+        c->variant = best;
+        c->tune_ms = ms;
+        if (chosen) *chosen = best;
+        if (ms_per_variant)
+            for (uint32_t i = 0; i < nv; i++) ms_per_variant[i] = ms[i];
+        if (cache_path) cache_store(cache_path, key, best, ms[best]);
     });
 }
 

@@ -267,3 +267,52 @@ def test_c2_scaled_full_parity(ifa, orc):
         for p in w.plants:
             if p.subs <= k:
                 assert (p.query, p.contig, p.pos, p.strand) in found
+
+
+def test_every_kernel_variant_is_bit_exact(ifa, orc):
+    """The autotuner may pick any variant, so each must give the oracle's hits."""
+    import synth
+    spec = synth.c2_spec(seed=55, total=1_500_000)
+    spec.n_param = 3e-3
+    spec.median = 50_000
+    ref = synth.gen_reference(spec)
+    rng = random.Random(55)
+    qs = [rand_dna(rng, rng.choice([5, 18, 31, 32, 33, 50, 64, 100]),
+                   b"ACGT" if rng.random() < 0.9 else b"ACGTN") for _ in range(13)]
+    ks = [rng.randint(0, min(len(q), 12)) for q in qs]
+    want = orc.scan(qs, ref, ks)
+    _, cnt, dig = orc.scan(qs, ref, ks, stats=True, records=False)
+    for v in range(ifa.ifa_variant_count()):
+        say(f"variant {v} {ifa.ifa_variant_info(v)}")
+        with ifa.Scanner(chunk_bases=1 << 19) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries(qs, ks)
+            s.scan_chunk(ref)
+            assert_same(s.collect(), want, f"variant {v}")
+        with ifa.Scanner(chunk_bases=1 << 19, sink=ifa.IFA_SINK_COUNT_DIGEST) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries(qs, ks)
+            s.scan_chunk(ref)
+            gc, gd = s.query_stats()
+            assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), f"variant {v} stats"
+
+
+def test_autotune_chooses_a_variant_and_caches_it(ifa, orc, tmp_path):
+    rng = random.Random(66)
+    qs = [rand_dna(rng, 32) for _ in range(8)]
+    ks = [3] * 8
+    cache = str(tmp_path / "tune.txt")
+    say("autotune")
+    with ifa.Scanner(chunk_bases=1 << 22) as s:
+        s.load_queries(qs, ks)
+        v, ms = ifa.ifa_autotune(s.ctx, 1 << 22, 3, cache)
+        assert 0 <= v < ifa.ifa_variant_count()
+        assert ms[v] > 0 and ms[v] == ms[ms > 0].min()
+        assert ifa.ifa_get_variant(s.ctx) == v
+        ifa.ifa_set_variant(s.ctx, 0)
+        v2, ms2 = ifa.ifa_autotune(s.ctx, 1 << 22, 3, cache)      # cache hit
+        assert v2 == v and (ms2 == -1).all()
+        # tuning leaves no hits behind; a scan after it is exact
+        c = rand_dna(rng, 20000)
+        s.scan_chunk([c])
+        assert_same(s.collect(), orc.scan(qs, [c], ks), "after autotune")
