@@ -77,6 +77,12 @@ typedef struct {
     uint32_t n_policy;      /* IFA_N_SEPARATE | IFA_N_AS_MISMATCH */
     uint32_t sink;          /* IFA_SINK_RECORDS | IFA_SINK_COUNT_DIGEST */
     uint32_t host_threads;  /* packing threads; 0 = hardware concurrency */
+    uint32_t work_capacity; /* filter work items per list (one item per wave
+                               and batch of 32 query strands with a candidate
+                               window); 0 = auto (2^20). A full list never
+                               loses work: it grows and the filtered part of
+                               the pass runs again */
+    uint32_t reserved;      /* must be 0 */
 } ifa_config;
 
 /* One reported window (16 bytes). strand: 0 = +, 1 = - (reverse complement). */
@@ -93,13 +99,17 @@ typedef struct {
 typedef struct {
     uint64_t bases;          /* reference bases submitted for scanning */
     uint64_t chunks;         /* chunk scans submitted */
-    uint64_t kernel_launches;/* scan kernel launches, overflow re-scans included */
+    uint64_t kernel_launches;/* scan passes (filter, resolve and dense kernels of one
+                                chunk or word range), overflow re-scans included */
     uint64_t rescans;        /* re-scans caused by a full hit buffer */
     uint64_t hits;           /* hits found */
-    double kernel_ms;        /* summed scan-kernel time, HIP events on the
-                                compute stream around each launch */
+    double kernel_ms;        /* summed scan-pass time, HIP events on the compute
+                                stream around the kernels of each pass */
     double h2d_ms;           /* summed host-to-device copy time of chunks */
     double pack_ms;          /* host wall time spent packing contigs */
+    double filter_ms;        /* summed time of the filter kernel alone (the hot
+                                loop), HIP events on the compute stream */
+    uint64_t filter_launches;/* filter kernel launches */
 } ifa_stats;
 
 /* Fill *cfg with the defaults: device 0, 2^30-base chunks, automatic hit

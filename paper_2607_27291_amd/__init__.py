@@ -39,14 +39,16 @@ class IfaConfig(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_uint32), ("device", ctypes.c_int32),
                 ("chunk_bases", ctypes.c_uint64), ("hit_capacity", ctypes.c_uint64),
                 ("strands", ctypes.c_uint32), ("n_policy", ctypes.c_uint32),
-                ("sink", ctypes.c_uint32), ("host_threads", ctypes.c_uint32)]
+                ("sink", ctypes.c_uint32), ("host_threads", ctypes.c_uint32),
+                ("work_capacity", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class IfaStats(ctypes.Structure):
     _fields_ = [("bases", ctypes.c_uint64), ("chunks", ctypes.c_uint64),
                 ("kernel_launches", ctypes.c_uint64), ("rescans", ctypes.c_uint64),
                 ("hits", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
-                ("h2d_ms", ctypes.c_double), ("pack_ms", ctypes.c_double)]
+                ("h2d_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
+                ("filter_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64)]
 
 
 class IfaError(RuntimeError):
@@ -296,7 +298,7 @@ class Scanner:
 
     def __init__(self, *, device=0, chunk_bases=1 << 30, hit_capacity=0,
                  strands=IFA_STRAND_BOTH, n_policy=IFA_N_SEPARATE, sink=IFA_SINK_RECORDS,
-                 host_threads=0):
+                 host_threads=0, work_capacity=0):
         cfg = ifa_config_default()
         cfg.device = device
         cfg.chunk_bases = chunk_bases
@@ -305,6 +307,7 @@ class Scanner:
         cfg.n_policy = n_policy
         cfg.sink = sink
         cfg.host_threads = host_threads
+        cfg.work_capacity = work_capacity
         self.ctx = ifa_create(cfg)
         self.n_queries = 0
 

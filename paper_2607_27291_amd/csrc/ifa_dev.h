@@ -19,6 +19,9 @@ constexpr uint32_t kMaxLen = 256;          // longest query
 constexpr uint32_t kCarry = kMaxLen - 1;   // bases repeated at a split
 constexpr uint32_t kPadWords = 16;         // > (31 + kMaxLen) / 32 + 1
 constexpr uint32_t kMaxQWords = kMaxLen / 32;
+// count+digest accumulators are striped: query q adds into slot
+// q * kStripes + (workgroup % kStripes); the host sums the stripes
+constexpr uint32_t kStripes = 64;
 
 enum Sink : uint32_t { kSinkRecords = 0, kSinkCountDigest = 1 };
 enum Policy : uint32_t { kNSeparate = 0, kNAsMismatch = 1 };
@@ -47,9 +50,20 @@ struct QSDesc {
     uint16_t maxn;        // min(maxN, L)
     uint32_t woff;
     uint32_t qh0, ql0, qn0;
-    uint32_t thr;         // filter bound k + 32 - min(L, 32); >= 32: no filter
+    uint32_t thr;         // filter bound on the first min(L, 32) bases (= k);
+                          // >= 32: the filter cannot exclude a window
 };
 static_assert(sizeof(QSDesc) == 32, "QSDesc layout");
+
+// Work item of the sparse path: wave `wave` of the filter grid has at least
+// one candidate window for the query strands qb + j, j a set bit of `pending`.
+struct WorkItem {
+    uint32_t wave;
+    uint32_t qb;
+    uint32_t pending;
+    uint32_t pad;
+};
+static_assert(sizeof(WorkItem) == 16, "WorkItem layout");
 
 struct ScanArgs {
     const uint32_t *hi, *lo, *nm, *em;
@@ -58,7 +72,8 @@ struct ScanArgs {
     uint32_t w_begin, w_end;  // window-start words [w_begin, w_end) to scan
     uint32_t lmax;            // longest L among qs
     const QSDesc *qs;
-    uint32_t n_qs;
+    uint32_t n_qs;            // query strands; [0, n_sparse) filtered, the rest dense
+    uint32_t n_sparse;
     uint32_t policy;
     const uint32_t *qwords;
     const Piece *pieces;
@@ -69,7 +84,11 @@ struct ScanArgs {
     uint4 *hits;
     unsigned long long *hit_count;
     unsigned long long hit_cap;
-    // count+digest sink, indexed by qid
+    // sparse-path work list (filled by the filter kernel, read by resolve)
+    WorkItem *work;
+    unsigned int *work_count;
+    unsigned int work_cap;
+    // count+digest sink, kStripes slots per query (see kStripes)
     unsigned long long *q_count;
     unsigned long long *q_digest;
 };

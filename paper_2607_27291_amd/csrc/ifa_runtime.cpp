@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <functional>
@@ -25,8 +26,11 @@
 #include "ifa_dev.h"
 
 namespace ifa {
-hipError_t launch_scan(const ScanArgs &a, hipStream_t s);
+hipError_t launch_filter(const ScanArgs &a, hipStream_t s);
+hipError_t launch_resolve(const ScanArgs &a, hipStream_t s);
+hipError_t launch_dense(const ScanArgs &a, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
+hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s);
 uint32_t variant_count();
 void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg);
 }  // namespace ifa
@@ -179,7 +183,7 @@ struct DevChunk {
 struct Job {
     DevChunk *chunk = nullptr;
     int hitbuf = 0;
-    hipEvent_t k0 = nullptr, k1 = nullptr;  // kernel start / stop
+    hipEvent_t k0 = nullptr, kf = nullptr, k1 = nullptr;  // start / filter end / stop
     hipEvent_t done = nullptr;              // hit count copied to the host
     bool active = false;
 };
@@ -202,7 +206,8 @@ struct ifa_ctx {
     bool have_queries = false;
     uint32_t n_queries = 0;
     uint32_t lmax = 0;
-    std::vector<QSDesc> h_qs;
+    std::vector<QSDesc> h_qs;         // sparse strands first, then dense
+    uint32_t n_sparse = 0;
     std::vector<uint32_t> h_qwords;
     DevBuf<QSDesc> d_qs;
     DevBuf<uint32_t> d_qwords;
@@ -221,6 +226,10 @@ struct ifa_ctx {
     HostBuf<unsigned long long> h_hitcount;  // [2]
     uint64_t hit_cap = 0;             // configured records per hit buffer
     uint64_t buf_cap[2] = {0, 0};     // current records per hit buffer
+    DevBuf<WorkItem> work[2];         // sparse-path work lists, one per hit buffer
+    uint32_t work_cap[2] = {0, 0};
+    DevBuf<unsigned int> d_workcount; // [2]
+    HostBuf<unsigned int> h_workcount;
     Job jobs[2];
     uint64_t job_seq = 0;
     std::vector<ifa_hit> hits;        // retired, not yet handed out
@@ -351,6 +360,19 @@ void seal(ifa_ctx *c, Staging &s)
 
 uint64_t words_with_pad(uint64_t len) { return ((len + 31) >> 5) + kPadWords; }
 
+// P(Bin(n, p) <= k)
+double binom_cdf(uint32_t n, double p, uint32_t k)
+{
+    if (k >= n) return 1.0;
+    double term = std::pow(1.0 - p, (double)n);   // P(X = 0)
+    double acc = term;
+    for (uint32_t i = 1; i <= k; i++) {
+        term *= (double)(n - i + 1) / (double)i * p / (1.0 - p);
+        acc += term;
+    }
+    return acc;
+}
+
 // ---------------------------------------------------------------------------
 // jobs: launch and retire
 // ---------------------------------------------------------------------------
@@ -369,12 +391,16 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.lmax = c->lmax;
     a.qs = c->d_qs.p;
     a.n_qs = (uint32_t)c->h_qs.size();
+    a.n_sparse = c->n_sparse;
     a.policy = c->cfg.n_policy;
     a.qwords = c->d_qwords.p;
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
     a.variant = c->variant;
+    a.work = c->work[hb].p;
+    a.work_count = c->d_workcount.p + hb;
+    a.work_cap = c->work_cap[hb];
     a.hits = c->d_hits[hb].p;
     a.hit_count = c->d_hitcount.p + hb;
     a.hit_cap = c->buf_cap[hb];
@@ -383,10 +409,11 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     return a;
 }
 
-void add_kernel_time(ifa_ctx *c, hipEvent_t a, hipEvent_t b)
+float elapsed(hipEvent_t a, hipEvent_t b)
 {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) c->st.kernel_ms += ms;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) ms = 0.f;
+    return ms;
 }
 
 void collect_h2d_times(ifa_ctx *c)
@@ -414,29 +441,103 @@ void copy_records(ifa_ctx *c, int hb, uint64_t n)
     c->st.hits += n;
 }
 
-// Re-scan word range [w0, w1) of a chunk whose hit buffer overflowed; halves
-// the range until every part fits.
+// Timing events of one pass: t0 before the filter, t1 after it, t2 after the
+// last scan kernel.
+struct PassEvents {
+    hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
+    void create()
+    {
+        if (!t0) hip_check(hipEventCreate(&t0), "event");
+        if (!t1) hip_check(hipEventCreate(&t1), "event");
+        if (!t2) hip_check(hipEventCreate(&t2), "event");
+    }
+    void destroy()
+    {
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+        if (t2) (void)hipEventDestroy(t2);
+        t0 = t1 = t2 = nullptr;
+    }
+};
+
+// Enqueue one pass of the scan over a's word range: the sparse part (filter
+// kernel, then resolve kernel over the work list) and, if `dense`, the dense
+// kernel. Counters are cleared by kernels on the stream first.
+void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, PassEvents &ev)
+{
+    if (clear_hits && c->cfg.sink == IFA_SINK_RECORDS)
+        hip_check(launch_clear_u64(a.hit_count, 1, c->comp_s), "clear hit counter");
+    hip_check(launch_clear_u32(a.work_count, 1, c->comp_s), "clear work counter");
+    hip_check(hipEventRecord(ev.t0, c->comp_s), "event record");
+    hip_check(launch_filter(a, c->comp_s), "filter launch");
+    hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
+    hip_check(launch_resolve(a, c->comp_s), "resolve launch");
+    if (dense) hip_check(launch_dense(a, c->comp_s), "dense launch");
+    hip_check(hipEventRecord(ev.t2, c->comp_s), "event record");
+}
+
+void enqueue_count_copies(ifa_ctx *c, int hb)
+{
+    if (c->cfg.sink == IFA_SINK_RECORDS)
+        hip_check(hipMemcpyAsync(c->h_hitcount.p + hb, c->d_hitcount.p + hb,
+                                 sizeof(unsigned long long), hipMemcpyDeviceToHost, c->comp_s),
+                  "copy hit count");
+    hip_check(hipMemcpyAsync(c->h_workcount.p + hb, c->d_workcount.p + hb, sizeof(unsigned int),
+                             hipMemcpyDeviceToHost, c->comp_s),
+              "copy work count");
+}
+
+void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse)
+{
+    c->st.kernel_ms += elapsed(ev.t0, ev.t2);
+    c->st.kernel_launches++;
+    if (sparse) {
+        c->st.filter_ms += elapsed(ev.t0, ev.t1);
+        c->st.filter_launches++;
+    }
+}
+
+// After a pass whose resolve kernel found the work list too small (and so
+// did nothing), grow the list and run the sparse part again until it fits.
+// Its dense part is not repeated: it does not use the list.
+void settle_work_overflow(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t w1)
+{
+    while (c->h_workcount.p[hb] > c->work_cap[hb]) {
+        const uint64_t need = (uint64_t)c->h_workcount.p[hb];
+        const uint64_t cap = std::min<uint64_t>(need + need / 4 + 1024, 0xffffffffull);
+        c->work[hb].alloc(cap, "grow work list");
+        c->work_cap[hb] = (uint32_t)cap;
+        ScanArgs a = make_args(c, ch, hb);
+        a.w_begin = w0;
+        a.w_end = w1;
+        PassEvents ev;
+        ev.create();
+        enqueue_pass(c, a, false, false, ev);
+        enqueue_count_copies(c, hb);
+        hip_check(hipStreamSynchronize(c->comp_s), "sync");
+        add_pass_times(c, ev, true);
+        ev.destroy();
+        c->st.rescans++;
+    }
+}
+
+// Re-scan word range [w0, w1) of a chunk whose hit buffer overflowed (the
+// records of the first pass are discarded); halves the range until every
+// part fits.
 void rescan_range(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t w1)
 {
     ScanArgs a = make_args(c, ch, hb);
     a.w_begin = w0;
     a.w_end = w1;
-    hip_check(launch_clear_u64(a.hit_count, 1, c->comp_s), "clear hit counter");
-    hipEvent_t e0, e1;
-    hip_check(hipEventCreate(&e0), "event");
-    hip_check(hipEventCreate(&e1), "event");
-    hip_check(hipEventRecord(e0, c->comp_s), "event record");
-    hip_check(launch_scan(a, c->comp_s), "scan launch");
-    hip_check(hipEventRecord(e1, c->comp_s), "event record");
-    hip_check(hipMemcpyAsync(c->h_hitcount.p + hb, a.hit_count, sizeof(unsigned long long),
-                             hipMemcpyDeviceToHost, c->comp_s),
-              "copy hit count");
+    PassEvents ev;
+    ev.create();
+    enqueue_pass(c, a, true, true, ev);
+    enqueue_count_copies(c, hb);
     hip_check(hipStreamSynchronize(c->comp_s), "sync");
-    add_kernel_time(c, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c->st.kernel_launches++;
+    add_pass_times(c, ev, c->n_sparse > 0);
+    ev.destroy();
     c->st.rescans++;
+    settle_work_overflow(c, ch, hb, w0, w1);
     uint64_t n = c->h_hitcount.p[hb];
     if (n <= c->buf_cap[hb]) {
         copy_records(c, hb, n);
@@ -459,13 +560,18 @@ void retire(ifa_ctx *c, Job &j)
 {
     if (!j.active) return;
     hip_check(hipEventSynchronize(j.done), "wait for scan");
-    add_kernel_time(c, j.k0, j.k1);
+    PassEvents ev;
+    ev.t0 = j.k0;
+    ev.t1 = j.kf;
+    ev.t2 = j.k1;
+    add_pass_times(c, ev, c->n_sparse > 0);
+    const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
+    settle_work_overflow(c, *j.chunk, j.hitbuf, 0, words);
     if (c->cfg.sink == IFA_SINK_RECORDS) {
         uint64_t n = c->h_hitcount.p[j.hitbuf];
         if (n <= c->buf_cap[j.hitbuf]) {
             copy_records(c, j.hitbuf, n);
         } else {
-            const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
             uint32_t mid = words / 2;
             rescan_range(c, *j.chunk, j.hitbuf, 0, mid);
             rescan_range(c, *j.chunk, j.hitbuf, mid, words);
@@ -486,27 +592,24 @@ void retire_all(ifa_ctx *c)
 void submit_job(ifa_ctx *c, DevChunk *ch)
 {
     Job &j = c->jobs[c->job_seq % 2];
-    retire(c, j);   // frees the hit buffer this job will use
+    retire(c, j);   // frees the hit buffer and work list this job will use
     j.chunk = ch;
     j.hitbuf = (int)(c->job_seq % 2);
     ScanArgs a = make_args(c, *ch, j.hitbuf);
     if (!j.k0) hip_check(hipEventCreate(&j.k0), "event");
+    if (!j.kf) hip_check(hipEventCreate(&j.kf), "event");
     if (!j.k1) hip_check(hipEventCreate(&j.k1), "event");
     if (!j.done) hip_check(hipEventCreateWithFlags(&j.done, hipEventDisableTiming), "event");
-    if (c->cfg.sink == IFA_SINK_RECORDS)
-        hip_check(launch_clear_u64(a.hit_count, 1, c->comp_s), "clear hit counter");
-    hip_check(hipEventRecord(j.k0, c->comp_s), "event record");
-    hip_check(launch_scan(a, c->comp_s), "scan launch");
-    hip_check(hipEventRecord(j.k1, c->comp_s), "event record");
+    PassEvents ev;
+    ev.t0 = j.k0;
+    ev.t1 = j.kf;
+    ev.t2 = j.k1;
+    enqueue_pass(c, a, true, true, ev);
     hip_check(hipEventRecord(ch->free_ev, c->comp_s), "event record");
-    if (c->cfg.sink == IFA_SINK_RECORDS)
-        hip_check(hipMemcpyAsync(c->h_hitcount.p + j.hitbuf, a.hit_count,
-                                 sizeof(unsigned long long), hipMemcpyDeviceToHost, c->comp_s),
-                  "copy hit count");
+    enqueue_count_copies(c, j.hitbuf);
     hip_check(hipEventRecord(j.done, c->comp_s), "event record");
     j.active = true;
     c->job_seq++;
-    c->st.kernel_launches++;
     c->st.chunks++;
 }
 
@@ -728,7 +831,7 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
     if (cfg_in) cfg = *cfg_in; else ifa_config_default(&cfg);
     if (cfg.abi_version != IFA_ABI_VERSION || cfg.chunk_bases < 4096 ||
         cfg.chunk_bases > (1ull << 31) || (cfg.chunk_bases & 31) || cfg.strands < 1 ||
-        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1)
+        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || cfg.reserved != 0)
         return IFA_E_INVALID;
     ifa_ctx *c = new (std::nothrow) ifa_ctx();
     if (!c) return IFA_E_NOMEM;
@@ -763,6 +866,15 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
                 c->buf_cap[i] = cap;
             }
         }
+        const uint32_t wcap = cfg.work_capacity ? cfg.work_capacity : (1u << 20);
+        for (int i = 0; i < 2; i++) {
+            c->work[i].alloc(wcap, "work list");
+            c->work_cap[i] = wcap;
+        }
+        c->d_workcount.alloc(2, "work counters");
+        c->h_workcount.alloc(2, "pinned work counters");
+        hip_check(hipMemset(c->d_workcount.p, 0, 2 * sizeof(unsigned int)), "memset");
+        c->h_workcount.p[0] = c->h_workcount.p[1] = 0;
         c->d_hitcount.alloc(2, "hit counters");
         c->h_hitcount.alloc(2, "pinned hit counters");
         hip_check(hipMemset(c->d_hitcount.p, 0, 2 * sizeof(unsigned long long)), "memset");
@@ -789,6 +901,7 @@ void ifa_destroy(ifa_ctx *c)
     for (auto &j : c->jobs) {
         if (j.k0) (void)hipEventDestroy(j.k0);
         if (j.k1) (void)hipEventDestroy(j.k1);
+        if (j.kf) (void)hipEventDestroy(j.kf);
         if (j.done) (void)hipEventDestroy(j.done);
     }
     for (int i = 0; i < 2; i++) {
@@ -857,17 +970,40 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
                 d.qh0 = W[0];
                 d.ql0 = W[1];
                 d.qn0 = W[2];
-                // filter bound: unmasked query bits past L may add 32 - min(L, 32)
-                d.thr = (uint32_t)d.k + 32u - std::min<uint32_t>(L, 32u);
+                // the filter counts mismatches over the first min(L, 32) bases
+                d.thr = d.k;
                 qs.push_back(d);
             }
         }
-        // group strands of equal word count, then by threshold, so waves see
-        // similar early-exit behaviour in consecutive iterations
-        std::stable_sort(qs.begin(), qs.end(), [](const QSDesc &x, const QSDesc &y) {
-            if (x.nw != y.nw) return x.nw < y.nw;
-            return x.k < y.k;
+        // Partition: strands whose filter is expected to pass a window in most
+        // waves (P(Bin(min(L, 32), 3/4) <= k) x 1024 windows >= 1/2 for iid
+        // bases) are dense and skip the filter's work list. Sparse strands go
+        // first, sorted by L descending (the filter masks its cached slices in
+        // place as L drops), then by k.
+        std::vector<uint8_t> dense(qs.size());
+        for (size_t i = 0; i < qs.size(); i++)
+            dense[i] = qs[i].thr >= 32u ||
+                       binom_cdf(std::min<uint32_t>(qs[i].len, 32u), 0.75, qs[i].k) * 1024.0 >= 0.5;
+        std::vector<size_t> order(qs.size());
+        for (size_t i = 0; i < order.size(); i++) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+            if (dense[x] != dense[y]) return dense[x] < dense[y];
+            const QSDesc &a = qs[x], &b = qs[y];
+            if (!dense[x]) {
+                if (a.len != b.len) return a.len > b.len;
+                return a.k < b.k;
+            }
+            if (a.nw != b.nw) return a.nw < b.nw;
+            return a.k < b.k;
         });
+        std::vector<QSDesc> sorted;
+        sorted.reserve(qs.size());
+        uint32_t n_sparse = 0;
+        for (size_t i : order) {
+            sorted.push_back(qs[i]);
+            if (!dense[i]) n_sparse++;
+        }
+        qs.swap(sorted);
         c->d_qs.alloc(std::max<size_t>(qs.size(), 1), "query table");
         c->d_qwords.alloc(std::max<size_t>(words.size(), 1), "query words");
         if (!qs.empty())
@@ -878,13 +1014,14 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
             hip_check(hipMemcpy(c->d_qwords.p, words.data(), words.size() * sizeof(uint32_t),
                                 hipMemcpyHostToDevice),
                       "upload query words");
-        c->d_qcount.alloc(std::max<uint32_t>(n, 1), "query counters");
-        c->d_qdigest.alloc(std::max<uint32_t>(n, 1), "query digests");
+        c->d_qcount.alloc((size_t)std::max<uint32_t>(n, 1) * kStripes, "query counters");
+        c->d_qdigest.alloc((size_t)std::max<uint32_t>(n, 1) * kStripes, "query digests");
         hip_check(hipMemset(c->d_qcount.p, 0, c->d_qcount.n * sizeof(unsigned long long)),
                   "memset");
         hip_check(hipMemset(c->d_qdigest.p, 0, c->d_qdigest.n * sizeof(unsigned long long)),
                   "memset");
         c->h_qs = std::move(qs);
+        c->n_sparse = n_sparse;
         c->h_qwords = std::move(words);
         c->n_queries = n;
         c->lmax = std::max<uint32_t>(lmax, 1);
@@ -957,14 +1094,29 @@ ifa_status ifa_query_stats(ifa_ctx *c, uint64_t *count, uint64_t *digest)
         flush_stream(c);
         retire_all(c);
         hip_check(hipStreamSynchronize(c->comp_s), "sync");
-        if (count)
-            hip_check(hipMemcpy(count, c->d_qcount.p, c->n_queries * sizeof(uint64_t),
+        // per-query accumulators are striped over kStripes slots; sum them
+        const size_t n = (size_t)c->n_queries * kStripes;
+        std::vector<uint64_t> buf(n ? n : 1);
+        if (count) {
+            hip_check(hipMemcpy(buf.data(), c->d_qcount.p, n * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost),
                       "copy counts");
-        if (digest)
-            hip_check(hipMemcpy(digest, c->d_qdigest.p, c->n_queries * sizeof(uint64_t),
+            for (uint32_t q = 0; q < c->n_queries; q++) {
+                uint64_t acc = 0;
+                for (uint32_t k = 0; k < kStripes; k++) acc += buf[(size_t)q * kStripes + k];
+                count[q] = acc;
+            }
+        }
+        if (digest) {
+            hip_check(hipMemcpy(buf.data(), c->d_qdigest.p, n * sizeof(uint64_t),
                                 hipMemcpyDeviceToHost),
                       "copy digests");
+            for (uint32_t q = 0; q < c->n_queries; q++) {
+                uint64_t acc = 0;
+                for (uint32_t k = 0; k < kStripes; k++) acc += buf[(size_t)q * kStripes + k];
+                digest[q] = acc;
+            }
+        }
     });
 }
 
@@ -1141,11 +1293,16 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
         hip_check(hipMemcpy(ch.pieces.p, &pc, sizeof pc, hipMemcpyHostToDevice), "upload piece");
         ch.len = calib_bases;
         ch.n_pieces = 1;
-        // hits go to a small scratch buffer; the tuner only times
+        // hits go to a small scratch buffer and the work list to a scratch
+        // list; the tuner only times (a full scratch list skips the resolve)
         DevBuf<uint4> scratch_hits;
         scratch_hits.alloc(1024, "tuning hit buffer");
         DevBuf<unsigned long long> scratch_cnt;
         scratch_cnt.alloc(2, "tuning counter");
+        DevBuf<WorkItem> scratch_work;
+        scratch_work.alloc(1u << 16, "tuning work list");
+        DevBuf<unsigned int> scratch_wc;
+        scratch_wc.alloc(2, "tuning work counter");
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
@@ -1158,11 +1315,20 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
             a.hits = scratch_hits.p;
             a.hit_count = scratch_cnt.p;
             a.hit_cap = 1024;
-            hip_check(launch_scan(a, c->comp_s), "tuning launch");   // warm up
+            a.work = scratch_work.p;
+            a.work_count = scratch_wc.p;
+            a.work_cap = 1u << 16;
+            auto pass = [&]() {
+                hip_check(launch_clear_u32(a.work_count, 1, c->comp_s), "clear");
+                hip_check(launch_filter(a, c->comp_s), "tuning launch");
+                hip_check(launch_resolve(a, c->comp_s), "tuning launch");
+                hip_check(launch_dense(a, c->comp_s), "tuning launch");
+            };
+            pass();   // warm up
             std::vector<float> t(reps);
             for (uint32_t r = 0; r < reps; r++) {
                 hip_check(hipEventRecord(e0, c->comp_s), "event record");
-                hip_check(launch_scan(a, c->comp_s), "tuning launch");
+                pass();
                 hip_check(hipEventRecord(e1, c->comp_s), "event record");
                 hip_check(hipEventSynchronize(e1), "tuning sync");
                 hip_check(hipEventElapsedTime(&t[r], e0, e1), "event time");

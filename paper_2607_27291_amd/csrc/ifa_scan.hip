@@ -6,26 +6,33 @@
 // keeps per-lane substitution and N ("clip") counters, stopping once every
 // lane is past a threshold (Methods, "SIMD Optimization"). Here the reference
 // is held as 2-bit bit planes and each GPU lane owns W consecutive window
-// starts (W = 32: one plane word; W = 16: half a word):
+// starts (W = 32: one plane word; W = 16: half a word).
 //
-//   * The lane loads plane words w and w+1 and forms, once, the W funnel
+// scan_filter_kernel (the hot loop), for the query strands predicted sparse:
+//   * the lane loads plane words w and w+1 and forms, once, the W funnel
 //     shifts (v_alignbit_b32) that give each of its windows' first 32 bases
-//     as one word per plane. They are shared by every query and strand.
-//   * Filter, per query strand: the mismatches of a window's first 32 bases
-//     are popcount((qh ^ rh) | (ql ^ rl) | qn), two v_bitop3_b32 and one
-//     v_bcnt_u32_b32, folded over the lane's windows with v_min3_u32.
-//     Query bits at or past L are zero and are not masked, so those positions
-//     can add up to 32 - min(L, 32) to the count; a window can be a hit only
-//     if this count is <= thr = k + 32 - min(L, 32). When no window of the
-//     lane passes (almost always), the lane is done with this query strand:
-//     the paper's early exit, taken per 32 bases.
-//   * Reference N positions must not count in the filter; waves whose bases
-//     hold an N (rare) run the filter with the N positions masked out.
-//   * Windows that pass go to the exact test, which walks every query word
-//     and applies the N rule, piece boundaries and chunk ownership.
+//     as one word per plane; they are shared by every query and strand;
+//   * per query strand, a window's mismatches over its first min(L, 32)
+//     bases are popcount((qh ^ rh) | (ql ^ rl) | qn): two v_bitop3_b32 and
+//     one v_bcnt_u32_b32, folded over the lane's windows with v_min3_u32.
+//     Strands come sorted by L descending and the cached slices are masked in
+//     place when L drops below 32, so query bits past L (zero) never differ.
+//     A window can be a hit only if this count is <= k. When no window
+//     passes (almost always), the lane is done with this query strand: the
+//     paper's early exit, taken per 32 bases;
+//   * reference N positions must not count in the filter; waves whose bases
+//     hold an N (rare) run the filter with the N positions masked out;
+//   * a wave with a candidate window appends one work item per batch of 32
+//     query strands to a work list.
+// scan_resolve_kernel: one wave per work item re-runs the filter for the
+//   listed strands and runs the exact test on candidate lanes.
+// scan_dense_kernel: query strands predicted to have candidates in most
+//   waves skip the list; every lane resolves them directly.
+// The exact test walks every query word and applies the N rule, piece ends
+// and chunk ownership; hits go to records or to a per-query count+digest.
 //
 // Variants (template parameters, chosen by the autotuner): windows per lane
-// W, query strands per loop iteration QU, and workgroup size.
+// W, query strands per filter iteration QU, and workgroup size.
 #include <hip/hip_runtime.h>
 
 #include "ifa_dev.h"
@@ -91,43 +98,74 @@ __device__ __forceinline__ QS load_qs(const ScanArgs &a, uint32_t q)
     return d;
 }
 
-// Map a chunk position to (contig ordinal, contig coordinate) and record it.
-__device__ void emit_hit(const ScanArgs &a, const QS &d, uint64_t p, uint32_t m, uint32_t nref)
+// Hash of one hit for the count+digest sink: SplitMix64 output finaliser of
+// ((contig << 32) | pos) ^ (aux << 45), aux = strand | m << 1 | n_ref << 10.
+__device__ __forceinline__ uint64_t hit_hash(uint32_t contig, uint32_t pos, uint32_t strand,
+                                             uint32_t m, uint32_t nref)
+{
+    const uint64_t key = ((uint64_t)contig << 32) | pos;
+    const uint64_t aux = (uint64_t)strand | ((uint64_t)m << 1) | ((uint64_t)nref << 10);
+    return splitmix_fin(key ^ (aux << 45));
+}
+
+// Index of the piece holding chunk position p (pieces sorted by start).
+__device__ __forceinline__ uint32_t find_piece(const ScanArgs &a, uint64_t p)
 {
     uint32_t lo = 0, hi = a.n_pieces;
     while (hi - lo > 1) {
         uint32_t mid = (lo + hi) >> 1;
         if (a.pieces[mid].start <= p) lo = mid; else hi = mid;
     }
-    const Piece pc = a.pieces[lo];
-    const uint32_t contig = pc.contig;
-    const uint32_t pos = (uint32_t)(pc.contig_off + (p - pc.start));
-    if (a.sink == kSinkRecords) {
-        unsigned long long slot = atomicAdd(a.hit_count, 1ull);
-        if (slot < a.hit_cap) {
-            uint4 rec;
-            rec.x = d.qid;
-            rec.y = contig;
-            rec.z = pos;
-            rec.w = d.strand | (nref << 8) | (m << 16);
-            a.hits[slot] = rec;
-        }
-    } else {
-        const uint64_t key = ((uint64_t)contig << 32) | pos;
-        const uint64_t aux = (uint64_t)d.strand | ((uint64_t)m << 1) | ((uint64_t)nref << 10);
-        atomicAdd(&a.q_count[d.qid], 1ull);
-        atomicAdd(&a.q_digest[d.qid], (unsigned long long)splitmix_fin(key ^ (aux << 45)));
+    return lo;
+}
+
+__device__ __forceinline__ void write_record(const ScanArgs &a, unsigned long long slot,
+                                             const QS &d, uint32_t contig, uint32_t pos,
+                                             uint32_t m, uint32_t nref)
+{
+    if (slot < a.hit_cap) {
+        uint4 rec;
+        rec.x = d.qid;
+        rec.y = contig;
+        rec.z = pos;
+        rec.w = d.strand | (nref << 8) | (m << 16);
+        a.hits[slot] = rec;
     }
 }
 
-// Exact test of windows 32w + off .. 32w + off + W - 1 against one query strand.
+// Per-lane state: the lane's W windows start at 32w + off.
+struct Lane {
+    uint32_t w, off;
+    bool active;
+    int plain;            // -1 unknown; 1: no N, piece end, carried prefix or chunk
+                          // tail among the bases its windows can touch
+    uint32_t h0, h1, l0, l1, n0, n1;
+};
+
+__device__ __forceinline__ bool lane_is_plain(const ScanArgs &a, const Lane &ln)
+{
+    const uint64_t first = 32ull * ln.w + ln.off;
+    // windows start at first .. first + W - 1 and span up to lmax bases
+    const uint64_t last = first + 31u + a.lmax;   // >= last base touched, W <= 32
+    if (first < (uint64_t)a.own_from || last >= a.chunk_len) return false;
+    const uint32_t wlast = (uint32_t)(last >> 5);
+    uint32_t acc = 0;
+    for (uint32_t x = ln.w; x <= wlast; x++) acc |= a.nm[x] | a.em[x];
+    return acc == 0u;
+}
+
+// Exact test, any lane: one window at a time, every query word, N rule, piece
+// ends, chunk ownership and tail. Records are written here (one atomic slot
+// per hit: these lanes are rare); count+digest accumulates into cnt/dig.
 template <int W>
-__device__ __forceinline__ void exact_lane(const ScanArgs &a, const QS &d, uint32_t w,
-                                           uint32_t off)
+__device__ void exact_serial(const ScanArgs &a, const QS &d, const Lane &ln, uint32_t &cnt,
+                             uint64_t &dig)
 {
     const uint32_t L = d.len;
     const IFA_CONST uint32_t *qw = as_const(a.qwords) + d.woff;
-    for (uint32_t b = off; b < off + (uint32_t)W; b++) {
+    const uint32_t w = ln.w;
+#pragma unroll 1
+    for (uint32_t b = ln.off; b < ln.off + (uint32_t)W; b++) {
         const uint64_t p = 32ull * w + b;
         if (p + L > a.chunk_len) break;
         if (p + L - 1 < (uint64_t)a.own_from) continue;
@@ -153,81 +191,293 @@ __device__ __forceinline__ void exact_lane(const ScanArgs &a, const QS &d, uint3
         if (ends) continue;
         if (m > d.k) continue;
         if (a.policy == kNSeparate && nref > d.maxn) continue;
-        emit_hit(a, d, p, m, nref);
+        const Piece pc = a.pieces[find_piece(a, p)];
+        const uint32_t pos = (uint32_t)(pc.contig_off + (p - pc.start));
+        if (a.sink == kSinkRecords) {
+            write_record(a, atomicAdd(a.hit_count, 1ull), d, pc.contig, pos, m, nref);
+        } else {
+            cnt += 1;
+            dig += hit_hash(pc.contig, pos, d.strand, m, nref);
+        }
     }
 }
 
-// Minimum over the lane's W windows of the filter count for one query strand.
+// Exact test of a plain lane: no N, no piece end, every window owned and
+// inside the chunk, all W windows in one piece. Word 0 comes from the lane's
+// cached plane words; later query words only for windows still within k.
+// kWrite = false: count (and hash) the hits; kWrite = true: write records to
+// slots slot, slot + 1, ... in window order.
+template <int W, bool kWrite>
+__device__ void exact_plain(const ScanArgs &a, const QS &d, const Lane &ln, uint32_t contig,
+                            uint32_t pos0, uint32_t &cnt, uint64_t &dig,
+                            unsigned long long slot)
+{
+    const uint32_t L = d.len;
+    const IFA_CONST uint32_t *qw = as_const(a.qwords) + d.woff;
+    const uint32_t lmask0 = low_mask(L);
+    uint32_t h2 = 0, l2 = 0, qh1 = 0, ql1 = 0, qn1 = 0, lmask1 = 0;
+    if (d.nw >= 2) {
+        h2 = a.hi[ln.w + 2];
+        l2 = a.lo[ln.w + 2];
+        qh1 = qw[3];
+        ql1 = qw[4];
+        qn1 = qw[5];
+        lmask1 = low_mask(L - 32u);
+    }
+#pragma unroll 1
+    for (uint32_t b = 0; b < (uint32_t)W; b++) {
+        const uint32_t s = ln.off + b;
+        uint32_t diff = __builtin_amdgcn_bitop3_b32(funnel(ln.h1, ln.h0, s), d.qh, d.qn, IFA_XOR_OR);
+        diff = __builtin_amdgcn_bitop3_b32(diff, funnel(ln.l1, ln.l0, s), d.ql, IFA_OR_XOR);
+        uint32_t m = __popc(diff & lmask0);
+        if (m <= d.k && d.nw >= 2) {
+            uint32_t d1 = __builtin_amdgcn_bitop3_b32(funnel(h2, ln.h1, s), qh1, qn1, IFA_XOR_OR);
+            d1 = __builtin_amdgcn_bitop3_b32(d1, funnel(l2, ln.l1, s), ql1, IFA_OR_XOR);
+            m += __popc(d1 & lmask1);
+            for (uint32_t t = 2; t < d.nw && m <= d.k; t++) {
+                const uint32_t x = ln.w + t;
+                const uint32_t rh = funnel(a.hi[x + 1], a.hi[x], s);
+                const uint32_t rl = funnel(a.lo[x + 1], a.lo[x], s);
+                const uint32_t dt = (qw[3 * t] ^ rh) | (qw[3 * t + 1] ^ rl) | qw[3 * t + 2];
+                m += __popc(dt & low_mask(L - 32u * t));
+            }
+        }
+        if (m <= d.k) {
+            if (kWrite) {
+                write_record(a, slot, d, contig, pos0 + b, m, 0u);
+                slot++;
+            } else {
+                cnt += 1;
+                if (a.sink == kSinkCountDigest) dig += hit_hash(contig, pos0 + b, d.strand, m, 0u);
+            }
+        }
+    }
+}
+
+// One query strand against the lane's windows after the filter: exact test
+// where `cand`, then (count+digest) a wave-wide sum added once per wave to
+// stripe `stripe` of the query's accumulators. Called by all 64 lanes.
+template <int W>
+__device__ __forceinline__ void resolve(const ScanArgs &a, const QS &d, Lane &ln, bool cand,
+                                        uint32_t stripe)
+{
+    const bool mine = ln.active && cand;
+    if (!__any(mine)) return;
+    uint32_t cnt = 0;
+    uint64_t dig = 0;
+    if (mine) {
+        if (ln.plain < 0) ln.plain = lane_is_plain(a, ln) ? 1 : 0;
+        if (ln.plain) {
+            const uint64_t first = 32ull * ln.w + ln.off;
+            const Piece pc = a.pieces[find_piece(a, first)];
+            const uint32_t pos0 = (uint32_t)(pc.contig_off + (first - pc.start));
+            exact_plain<W, false>(a, d, ln, pc.contig, pos0, cnt, dig, 0ull);
+            if (a.sink == kSinkRecords && cnt) {
+                unsigned long long slot = atomicAdd(a.hit_count, (unsigned long long)cnt);
+                uint32_t c2 = 0;
+                uint64_t d2 = 0;
+                exact_plain<W, true>(a, d, ln, pc.contig, pos0, c2, d2, slot);
+            }
+        } else {
+            exact_serial<W>(a, d, ln, cnt, dig);
+        }
+    }
+    if (a.sink == kSinkCountDigest) {
+        uint32_t dlo = (uint32_t)dig, dhi = (uint32_t)(dig >> 32);
+        for (int o = 32; o >= 1; o >>= 1) {
+            const uint32_t c_o = __shfl_xor(cnt, o);
+            const uint32_t lo_o = __shfl_xor(dlo, o);
+            const uint32_t hi_o = __shfl_xor(dhi, o);
+            const uint64_t sum = ((uint64_t)dhi << 32 | dlo) + ((uint64_t)hi_o << 32 | lo_o);
+            cnt += c_o;
+            dlo = (uint32_t)sum;
+            dhi = (uint32_t)(sum >> 32);
+        }
+        if ((threadIdx.x & 63u) == 0u && cnt) {
+            const uint32_t slot = d.qid * kStripes + stripe % kStripes;
+            atomicAdd(&a.q_count[slot], (unsigned long long)cnt);
+            atomicAdd(&a.q_digest[slot], ((unsigned long long)dhi << 32) | dlo);
+        }
+    }
+}
+
+// Minimum over the lane's W windows of the filter count for one query strand
+// (hot loop: slices cached in registers).
 template <int W, bool kMaskN>
 __device__ __forceinline__ uint32_t filter_min(const uint32_t (&sh)[W], const uint32_t (&sl)[W],
-                                               const QS &d, uint32_t n0, uint32_t n1, uint32_t off)
+                                               const QS &d, const Lane &ln)
 {
     uint32_t mn = 0xffffffffu;
 #pragma unroll
     for (int b = 0; b < W; b++) {
         uint32_t diff = __builtin_amdgcn_bitop3_b32(sh[b], d.qh, d.qn, IFA_XOR_OR);
         diff = __builtin_amdgcn_bitop3_b32(diff, sl[b], d.ql, IFA_OR_XOR);
-        if (kMaskN) diff &= ~funnel(n1, n0, off + (uint32_t)b);
+        if (kMaskN) diff &= ~funnel(ln.n1, ln.n0, ln.off + (uint32_t)b);
         mn = min(mn, (uint32_t)__popc(diff));
     }
     return mn;
 }
 
-// Filter every query strand against the lane's W windows; run the exact test
-// where a window may be a hit.
+// The same filter decision formed from the lane's plane words, N positions
+// always masked (cold paths).
+template <int W>
+__device__ __forceinline__ bool filter_cand_words(const QS &d, const Lane &ln)
+{
+    if (d.thr >= 32u) return true;
+    const uint32_t lmask = low_mask(d.len);
+    uint32_t mn = 0xffffffffu;
+#pragma unroll 4
+    for (int b = 0; b < W; b++) {
+        const uint32_t s = ln.off + (uint32_t)b;
+        uint32_t diff = __builtin_amdgcn_bitop3_b32(funnel(ln.h1, ln.h0, s), d.qh, d.qn, IFA_XOR_OR);
+        diff = __builtin_amdgcn_bitop3_b32(diff, funnel(ln.l1, ln.l0, s), d.ql, IFA_OR_XOR);
+        diff &= ~funnel(ln.n1, ln.n0, s) & lmask;
+        mn = min(mn, (uint32_t)__popc(diff));
+    }
+    return mn <= d.thr;
+}
+
+// Lane state of filter-grid lane `gl` (relative to w_begin).
+template <int W>
+__device__ __forceinline__ Lane make_lane(const ScanArgs &a, uint32_t gl)
+{
+    constexpr uint32_t kLanesPerWord = 32 / W;
+    Lane ln;
+    ln.w = a.w_begin + gl / kLanesPerWord;
+    ln.off = (gl % kLanesPerWord) * (uint32_t)W;
+    ln.active = ln.w < a.w_end;
+    ln.plain = -1;
+    if (!ln.active) ln.w = a.w_begin;    // inactive lanes read valid words, report nothing
+    ln.h0 = a.hi[ln.w];
+    ln.h1 = a.hi[ln.w + 1];
+    ln.l0 = a.lo[ln.w];
+    ln.l1 = a.lo[ln.w + 1];
+    ln.n0 = a.nm[ln.w];
+    ln.n1 = a.nm[ln.w + 1];
+    return ln;
+}
+
+// Mask the cached slices to the first L bases (L < 32). Sparse strands come
+// sorted by L descending, so masks only ever shrink and can be applied in
+// place: bases past L then never differ from the zero query bits there.
+template <int W>
+__device__ __forceinline__ void mask_slices(uint32_t (&sh)[W], uint32_t (&sl)[W], uint32_t L)
+{
+    const uint32_t m = low_mask(L);
+#pragma unroll
+    for (int b = 0; b < W; b++) {
+        sh[b] &= m;
+        sl[b] &= m;
+    }
+}
+
+// Filter the sparse query strands; one work item per (wave, batch of 32
+// strands) that has a candidate window in any lane.
 template <int W, int QU, bool kMaskN>
-__device__ __forceinline__ void scan_lane(const ScanArgs &a, uint32_t w, uint32_t off,
-                                          bool active, uint32_t h0, uint32_t h1, uint32_t l0,
-                                          uint32_t l1, uint32_t n0, uint32_t n1)
+__device__ __forceinline__ void filter_lane(const ScanArgs &a, const Lane &ln, uint32_t wave)
 {
     uint32_t sh[W], sl[W];
 #pragma unroll
     for (int b = 0; b < W; b++) {
-        sh[b] = funnel(h1, h0, off + (uint32_t)b);
-        sl[b] = funnel(l1, l0, off + (uint32_t)b);
+        sh[b] = funnel(ln.h1, ln.h0, ln.off + (uint32_t)b);
+        sl[b] = funnel(ln.l1, ln.l0, ln.off + (uint32_t)b);
     }
-    const uint32_t n = a.n_qs;
-    uint32_t q = 0;
-    if (QU == 2) {
-        for (; q + 1 < n; q += 2) {
-            const QS d0 = load_qs(a, q);
-            const QS d1 = load_qs(a, q + 1);
-            const bool c0 =
-                d0.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d0, n0, n1, off) <= d0.thr;
-            const bool c1 =
-                d1.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d1, n0, n1, off) <= d1.thr;
-            if (active && c0) exact_lane<W>(a, d0, w, off);
-            if (active && c1) exact_lane<W>(a, d1, w, off);
+    uint32_t cur_len = 32;      // slices hold this many bases (wave-uniform)
+    const uint32_t n = a.n_sparse;
+    for (uint32_t qb = 0; qb < n; qb += 32) {
+        const uint32_t nb = min(32u, n - qb);
+        uint32_t pending = 0;   // wave-uniform
+        uint32_t j = 0;
+        if (QU == 2) {
+            for (; j + 1 < nb; j += 2) {
+                const QS d0 = load_qs(a, qb + j);
+                const QS d1 = load_qs(a, qb + j + 1);
+                if (d0.len < cur_len) {
+                    mask_slices<W>(sh, sl, d0.len);
+                    cur_len = d0.len;
+                }
+                const bool c0 = d0.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d0, ln) <= d0.thr;
+                if (d1.len < cur_len) {
+                    mask_slices<W>(sh, sl, d1.len);
+                    cur_len = d1.len;
+                }
+                const bool c1 = d1.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d1, ln) <= d1.thr;
+                if (__any(ln.active && c0)) pending |= 1u << j;
+                if (__any(ln.active && c1)) pending |= 2u << j;
+            }
         }
-    }
-    for (; q < n; q++) {
-        const QS d = load_qs(a, q);
-        const bool c = d.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d, n0, n1, off) <= d.thr;
-        if (active && c) exact_lane<W>(a, d, w, off);
+        for (; j < nb; j++) {
+            const QS d = load_qs(a, qb + j);
+            if (d.len < cur_len) {
+                mask_slices<W>(sh, sl, d.len);
+                cur_len = d.len;
+            }
+            const bool c = d.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d, ln) <= d.thr;
+            if (__any(ln.active && c)) pending |= 1u << j;
+        }
+        if (pending && (threadIdx.x & 63u) == 0u) {
+            const unsigned int idx = atomicAdd(a.work_count, 1u);
+            if (idx < a.work_cap) {
+                WorkItem it;
+                it.wave = wave;
+                it.qb = qb;
+                it.pending = pending;
+                it.pad = 0;
+                a.work[idx] = it;
+            }
+        }
     }
 }
 
 template <int W, int QU, int WG>
-__global__ __launch_bounds__(WG) void scan_kernel(ScanArgs a)
+__global__ __launch_bounds__(WG) void scan_filter_kernel(ScanArgs a)
 {
-    constexpr uint32_t kLanesPerWord = 32 / W;
-    const uint32_t lane = blockIdx.x * WG + threadIdx.x;
-    const uint32_t w = a.w_begin + lane / kLanesPerWord;
-    const uint32_t off = (lane % kLanesPerWord) * (uint32_t)W;
-    const bool active = w < a.w_end;
-    const uint32_t wl = active ? w : a.w_begin;
-
-    const uint32_t h0 = a.hi[wl], h1 = a.hi[wl + 1];
-    const uint32_t l0 = a.lo[wl], l1 = a.lo[wl + 1];
-    const uint32_t n0 = a.nm[wl], n1 = a.nm[wl + 1];
-
+    const uint32_t gl = blockIdx.x * WG + threadIdx.x;
+    const Lane ln = make_lane<W>(a, gl);
+    const uint32_t wave = gl >> 6;
     // Does any base the filter reads for this lane hold an N? Words w and
     // w+1 cover the first 32 bases of all of the lane's windows.
-    const bool lane_n = active && ((n0 | n1) != 0u);
+    const bool lane_n = ln.active && ((ln.n0 | ln.n1) != 0u);
     if (__any(lane_n))
-        scan_lane<W, QU, true>(a, w, off, active, h0, h1, l0, l1, n0, n1);
+        filter_lane<W, QU, true>(a, ln, wave);
     else
-        scan_lane<W, QU, false>(a, w, off, active, h0, h1, l0, l1, n0, n1);
+        filter_lane<W, QU, false>(a, ln, wave);
+}
+
+// One wave per work item (grid-stride). Does nothing when the filter kernel
+// overflowed the list: the host then grows it and runs the sparse part again.
+template <int W>
+__global__ __launch_bounds__(256) void scan_resolve_kernel(ScanArgs a)
+{
+    const unsigned int count = *a.work_count;
+    if (count > a.work_cap) return;
+    const uint32_t waves = gridDim.x * 4u;
+    const uint32_t slot = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const IFA_CONST uint32_t *work = as_const(reinterpret_cast<const uint32_t *>(a.work));
+    for (uint32_t i = slot; i < count; i += waves) {
+        const uint32_t wave = work[4u * i], qb = work[4u * i + 1];
+        uint32_t pending = work[4u * i + 2];
+        Lane ln = make_lane<W>(a, wave * 64u + (threadIdx.x & 63u));
+        while (pending) {
+            const uint32_t j = __builtin_ctz(pending);
+            pending &= pending - 1u;
+            const QS d = load_qs(a, qb + j);
+            resolve<W>(a, d, ln, filter_cand_words<W>(d, ln), wave);
+        }
+    }
+}
+
+// Dense query strands [n_sparse, n_qs): every lane resolves them directly.
+template <int W>
+__global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
+{
+    const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
+    Lane ln = make_lane<W>(a, gl);
+    const uint32_t wave = gl >> 6;
+    for (uint32_t q = a.n_sparse; q < a.n_qs; q++) {
+        const QS d = load_qs(a, q);
+        resolve<W>(a, d, ln, filter_cand_words<W>(d, ln), wave);
+    }
 }
 
 // Clears counters on the stream (a kernel, so the launch sequence can be
@@ -238,18 +488,27 @@ __global__ void clear_u64_kernel(unsigned long long *p, uint32_t n)
     if (i < n) p[i] = 0ull;
 }
 
+__global__ void clear_u32_kernel(unsigned int *p, uint32_t n)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
 // ---------------------------------------------------------------------------
 // variant table
 // ---------------------------------------------------------------------------
 
 struct VariantDesc {
-    void (*fn)(ScanArgs);
+    void (*filter)(ScanArgs);
+    void (*resolve)(ScanArgs);
+    void (*dense)(ScanArgs);
     uint32_t windows;   // W
     uint32_t qunroll;   // QU
-    uint32_t wg;        // workgroup size
+    uint32_t wg;        // filter workgroup size
 };
 
-#define IFA_V(W, QU, WG) { scan_kernel<W, QU, WG>, W, QU, WG }
+#define IFA_V(W, QU, WG) \
+    { scan_filter_kernel<W, QU, WG>, scan_resolve_kernel<W>, scan_dense_kernel<W>, W, QU, WG }
 static const VariantDesc kVariantTable[] = {
     IFA_V(32, 1, 256),   // 0: default
     IFA_V(32, 1, 64),    IFA_V(32, 1, 128),  IFA_V(32, 1, 512),
@@ -269,13 +528,44 @@ void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *w
     *wg = d.wg;
 }
 
-hipError_t launch_scan(const ScanArgs &a, hipStream_t s)
+static const VariantDesc &pick(const ScanArgs &a)
 {
-    if (a.w_end <= a.w_begin || a.n_qs == 0) return hipSuccess;
-    const VariantDesc &v = kVariantTable[a.variant < variant_count() ? a.variant : 0];
+    return kVariantTable[a.variant < variant_count() ? a.variant : 0];
+}
+
+// Filter lanes of the word range (a multiple of 64, whole waves).
+static uint64_t filter_lanes(const ScanArgs &a, const VariantDesc &v)
+{
     const uint64_t lanes = (uint64_t)(a.w_end - a.w_begin) * (32u / v.windows);
-    const uint64_t grid = (lanes + v.wg - 1) / v.wg;
-    hipLaunchKernelGGL(v.fn, dim3((uint32_t)grid), dim3(v.wg), 0, s, a);
+    return (lanes + 63) & ~63ull;
+}
+
+// Sparse part, step 1: the filter kernel fills the work list (the caller
+// clears *work_count first).
+hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
+{
+    if (a.w_end <= a.w_begin || a.n_sparse == 0) return hipSuccess;
+    const VariantDesc &v = pick(a);
+    const uint64_t lanes = filter_lanes(a, v);
+    hipLaunchKernelGGL(v.filter, dim3((uint32_t)((lanes + v.wg - 1) / v.wg)), dim3(v.wg), 0, s, a);
+    return hipGetLastError();
+}
+
+// Sparse part, step 2: resolve the work list (a fixed grid, grid-stride).
+hipError_t launch_resolve(const ScanArgs &a, hipStream_t s)
+{
+    if (a.w_end <= a.w_begin || a.n_sparse == 0) return hipSuccess;
+    hipLaunchKernelGGL(pick(a).resolve, dim3(1024), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Dense part: every lane resolves query strands [n_sparse, n_qs).
+hipError_t launch_dense(const ScanArgs &a, hipStream_t s)
+{
+    if (a.w_end <= a.w_begin || a.n_qs <= a.n_sparse) return hipSuccess;
+    const VariantDesc &v = pick(a);
+    const uint64_t lanes = filter_lanes(a, v);
+    hipLaunchKernelGGL(v.dense, dim3((uint32_t)((lanes + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -283,6 +573,13 @@ hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(clear_u64_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(clear_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     import paper_2607_27291_amd as ifa
     assert ifa.HIT_DTYPE.itemsize == 16
-    assert ctypes.sizeof(ifa.IfaConfig) == 40
+    assert ctypes.sizeof(ifa.IfaConfig) == 48
     cfg = ifa.ifa_config_default()
     assert cfg.abi_version == ifa.IFA_ABI_VERSION
     assert cfg.chunk_bases == 1 << 30 and cfg.strands == 3 and cfg.sink == 0

@@ -316,3 +316,35 @@ def test_autotune_chooses_a_variant_and_caches_it(ifa, orc, tmp_path):
         c = rand_dna(rng, 20000)
         s.scan_chunk([c])
         assert_same(s.collect(), orc.scan(qs, [c], ks), "after autotune")
+
+
+@pytest.mark.parametrize("sink", [0, 1])
+def test_dense_and_sparse_strands_with_work_list_overflow(ifa, orc, sink):
+    """A query set mixing filtered (sparse) and hit-dense strands, lengths 18-150
+    and thresholds up to L/2; a work list of 4 items forces the grow-and-rerun
+    path of the filtered part. Records and count+digest must both match."""
+    import synth
+    spec = synth.c2_spec(seed=77, total=600_000)
+    spec.n_param = 2e-3
+    spec.median = 40_000
+    ref = synth.gen_reference(spec)
+    rng = random.Random(77)
+    qs = [rand_dna(rng, rng.choice([18, 20, 24, 31, 32, 33, 40, 50, 64, 100, 150]))
+          for _ in range(24)]
+    ks = [rng.randint(0, len(q) // 2) for q in qs]
+    say(f"dense+sparse mix, sink {sink}")
+    want, cnt, dig = orc.scan(qs, ref, ks, stats=True)
+    for wcap in (4, 0):
+        with ifa.Scanner(chunk_bases=1 << 18, work_capacity=wcap, sink=sink,
+                         hit_capacity=1 << 14) as s:
+            s.load_queries(qs, ks)
+            s.scan_chunk(ref)
+            if sink == 0:
+                assert_same(s.collect(), want, f"records wcap {wcap}")
+            else:
+                gc, gd = s.query_stats()
+                assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), f"stats wcap {wcap}"
+            st = s.stats()
+            if wcap == 4:
+                assert st["rescans"] > 0
+    assert len(want) > 1000
