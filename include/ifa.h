@@ -79,7 +79,7 @@ typedef struct {
     uint32_t host_threads;  /* packing threads; 0 = hardware concurrency */
     uint32_t work_capacity; /* filter work items per list (one item per wave
                                and batch of 32 query strands with a candidate
-                               window); 0 = auto (2^20). A full list never
+                               window); 0 = auto (2^22). A full list never
                                loses work: it grows and the filtered part of
                                the pass runs again */
     uint32_t reserved;      /* must be 0 */

@@ -866,7 +866,7 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
                 c->buf_cap[i] = cap;
             }
         }
-        const uint32_t wcap = cfg.work_capacity ? cfg.work_capacity : (1u << 20);
+        const uint32_t wcap = cfg.work_capacity ? cfg.work_capacity : (1u << 22);
         for (int i = 0; i < 2; i++) {
             c->work[i].alloc(wcap, "work list");
             c->work_cap[i] = wcap;

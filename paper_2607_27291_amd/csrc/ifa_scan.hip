@@ -20,8 +20,8 @@
 //     A window can be a hit only if this count is <= k. When no window
 //     passes (almost always), the lane is done with this query strand: the
 //     paper's early exit, taken per 32 bases;
-//   * reference N positions must not count in the filter; waves whose bases
-//     hold an N (rare) run the filter with the N positions masked out;
+//   * waves whose first bases hold an N (rare) skip the filter and list
+//     every strand for the resolve kernel, which applies the N rule;
 //   * a wave with a candidate window appends one work item per batch of 32
 //     query strands to a work list.
 // scan_resolve_kernel: one wave per work item re-runs the filter for the
@@ -302,26 +302,28 @@ __device__ __forceinline__ void resolve(const ScanArgs &a, const QS &d, Lane &ln
 }
 
 // Minimum over the lane's W windows of the filter count for one query strand
-// (hot loop: slices cached in registers).
-template <int W, bool kMaskN>
+// (hot loop: slices cached in registers, already masked to the strand's first
+// min(L, 32) bases; the wave holds no N).
+template <int W>
 __device__ __forceinline__ uint32_t filter_min(const uint32_t (&sh)[W], const uint32_t (&sl)[W],
-                                               const QS &d, const Lane &ln)
+                                               const QS &d)
 {
     uint32_t mn = 0xffffffffu;
 #pragma unroll
     for (int b = 0; b < W; b++) {
         uint32_t diff = __builtin_amdgcn_bitop3_b32(sh[b], d.qh, d.qn, IFA_XOR_OR);
         diff = __builtin_amdgcn_bitop3_b32(diff, sl[b], d.ql, IFA_OR_XOR);
-        if (kMaskN) diff &= ~funnel(ln.n1, ln.n0, ln.off + (uint32_t)b);
         mn = min(mn, (uint32_t)__popc(diff));
     }
     return mn;
 }
 
-// The same filter decision formed from the lane's plane words, N positions
-// always masked (cold paths).
+// The filter decision formed from the lane's plane words (cold paths), over
+// the first min(L, 32) bases. N positions: under N_SEPARATE they are left out
+// of the count, and a window whose N count there already exceeds maxN is
+// pushed past any threshold; under N_AS_MISMATCH they are mismatches.
 template <int W>
-__device__ __forceinline__ bool filter_cand_words(const QS &d, const Lane &ln)
+__device__ __forceinline__ bool filter_cand_words(const ScanArgs &a, const QS &d, const Lane &ln)
 {
     if (d.thr >= 32u) return true;
     const uint32_t lmask = low_mask(d.len);
@@ -331,8 +333,14 @@ __device__ __forceinline__ bool filter_cand_words(const QS &d, const Lane &ln)
         const uint32_t s = ln.off + (uint32_t)b;
         uint32_t diff = __builtin_amdgcn_bitop3_b32(funnel(ln.h1, ln.h0, s), d.qh, d.qn, IFA_XOR_OR);
         diff = __builtin_amdgcn_bitop3_b32(diff, funnel(ln.l1, ln.l0, s), d.ql, IFA_OR_XOR);
-        diff &= ~funnel(ln.n1, ln.n0, s) & lmask;
-        mn = min(mn, (uint32_t)__popc(diff));
+        const uint32_t rn = funnel(ln.n1, ln.n0, s) & lmask;
+        diff &= lmask;
+        if (a.policy == kNSeparate) {
+            const uint32_t over = __popc(rn) > d.maxn ? 64u : 0u;
+            mn = min(mn, (uint32_t)__popc(diff & ~rn) + over);
+        } else {
+            mn = min(mn, (uint32_t)__popc(diff | rn));
+        }
     }
     return mn <= d.thr;
 }
@@ -373,7 +381,7 @@ __device__ __forceinline__ void mask_slices(uint32_t (&sh)[W], uint32_t (&sl)[W]
 
 // Filter the sparse query strands; one work item per (wave, batch of 32
 // strands) that has a candidate window in any lane.
-template <int W, int QU, bool kMaskN>
+template <int W, int QU>
 __device__ __forceinline__ void filter_lane(const ScanArgs &a, const Lane &ln, uint32_t wave)
 {
     uint32_t sh[W], sl[W];
@@ -396,12 +404,14 @@ __device__ __forceinline__ void filter_lane(const ScanArgs &a, const Lane &ln, u
                     mask_slices<W>(sh, sl, d0.len);
                     cur_len = d0.len;
                 }
-                const bool c0 = d0.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d0, ln) <= d0.thr;
+                const bool c0 = d0.thr >= 32u ||
+                    filter_min<W>(sh, sl, d0) <= d0.thr;
                 if (d1.len < cur_len) {
                     mask_slices<W>(sh, sl, d1.len);
                     cur_len = d1.len;
                 }
-                const bool c1 = d1.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d1, ln) <= d1.thr;
+                const bool c1 = d1.thr >= 32u ||
+                    filter_min<W>(sh, sl, d1) <= d1.thr;
                 if (__any(ln.active && c0)) pending |= 1u << j;
                 if (__any(ln.active && c1)) pending |= 2u << j;
             }
@@ -412,7 +422,8 @@ __device__ __forceinline__ void filter_lane(const ScanArgs &a, const Lane &ln, u
                 mask_slices<W>(sh, sl, d.len);
                 cur_len = d.len;
             }
-            const bool c = d.thr >= 32u || filter_min<W, kMaskN>(sh, sl, d, ln) <= d.thr;
+            const bool c = d.thr >= 32u ||
+                filter_min<W>(sh, sl, d) <= d.thr;
             if (__any(ln.active && c)) pending |= 1u << j;
         }
         if (pending && (threadIdx.x & 63u) == 0u) {
@@ -436,12 +447,29 @@ __global__ __launch_bounds__(WG) void scan_filter_kernel(ScanArgs a)
     const Lane ln = make_lane<W>(a, gl);
     const uint32_t wave = gl >> 6;
     // Does any base the filter reads for this lane hold an N? Words w and
-    // w+1 cover the first 32 bases of all of the lane's windows.
+    // w+1 cover the first 32 bases of all of the lane's windows. Such waves
+    // are rare; they skip the filter and list every strand for the resolve
+    // kernel, whose filter applies the N rule (keeping that rule out of this
+    // kernel saves ~30 VGPRs of occupancy for every other wave).
     const bool lane_n = ln.active && ((ln.n0 | ln.n1) != 0u);
-    if (__any(lane_n))
-        filter_lane<W, QU, true>(a, ln, wave);
-    else
-        filter_lane<W, QU, false>(a, ln, wave);
+    if (__any(lane_n)) {
+        if ((threadIdx.x & 63u) == 0u) {
+            for (uint32_t qb = 0; qb < a.n_sparse; qb += 32) {
+                const uint32_t nb = min(32u, a.n_sparse - qb);
+                const unsigned int idx = atomicAdd(a.work_count, 1u);
+                if (idx < a.work_cap) {
+                    WorkItem it;
+                    it.wave = wave;
+                    it.qb = qb;
+                    it.pending = nb == 32u ? 0xffffffffu : ((1u << nb) - 1u);
+                    it.pad = 0;
+                    a.work[idx] = it;
+                }
+            }
+        }
+        return;
+    }
+    filter_lane<W, QU>(a, ln, wave);
 }
 
 // One wave per work item (grid-stride). Does nothing when the filter kernel
@@ -462,7 +490,7 @@ __global__ __launch_bounds__(256) void scan_resolve_kernel(ScanArgs a)
             const uint32_t j = __builtin_ctz(pending);
             pending &= pending - 1u;
             const QS d = load_qs(a, qb + j);
-            resolve<W>(a, d, ln, filter_cand_words<W>(d, ln), wave);
+            resolve<W>(a, d, ln, filter_cand_words<W>(a, d, ln), wave);
         }
     }
 }
@@ -476,7 +504,7 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
     const uint32_t wave = gl >> 6;
     for (uint32_t q = a.n_sparse; q < a.n_qs; q++) {
         const QS d = load_qs(a, q);
-        resolve<W>(a, d, ln, filter_cand_words<W>(d, ln), wave);
+        resolve<W>(a, d, ln, filter_cand_words<W>(a, d, ln), wave);
     }
 }
 
@@ -515,6 +543,7 @@ static const VariantDesc kVariantTable[] = {
     IFA_V(32, 2, 256),   IFA_V(32, 2, 128),
     IFA_V(16, 1, 256),   IFA_V(16, 1, 128),  IFA_V(16, 1, 512),
     IFA_V(16, 2, 256),   IFA_V(16, 2, 512),
+    IFA_V(32, 2, 512),   IFA_V(16, 2, 1024),
 };
 #undef IFA_V
 
