@@ -1,13 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark: the brute-force gapless scan on one MI355X.
 
-Workload (paper-scale single pass): 10 queries of length 30-36 against a
-4 Gbp synthetic reference (lognormal contigs, median 3 Mbp; per-contig GC
-35-65%; N runs covering 1e-4), one planted copy per query per 100 Mbp, at
-maxSubs 0, 4 and 8. The reference is packed and resident in device memory
-before timing starts. One step = three full passes (one per maxSubs) of the
-10 queries over the 4 Gbp, each pass = the scan kernels, the hit drain from
-the device and the canonical sort of the records.
+Default workload (paper-scale single pass, the headline line): 10 queries of
+length 30-36 against a 4 Gbp synthetic reference (lognormal contigs, median
+3 Mbp; per-contig GC 35-65%; N runs covering 1e-4), one planted copy per query
+per 100 Mbp, at maxSubs 0, 4 and 8. The reference is packed and resident in
+device memory before timing starts. One step = three full passes (one per
+maxSubs) of the 10 queries over the 4 Gbp; each pass = the scan kernels, the
+hit drain from the device and the canonical sort of the records.
+
+Other workloads (--workload):
+  c3  batched scan: 10,000 queries, L 18-50, maxSubs 0-16 per query, against
+      1 Gbp resident, count+digest sink; one step = one pass + statistics.
+  c4  streaming: 100 queries, L 20-40, maxSubs 4, against a reference
+      generated on the fly by host threads, packed and streamed through the
+      pinned double buffer (never resident); one step = the whole reference.
+The serving loop has its own driver (serve.py).
 
 Prints one JSON line. `value` is Gbp*query/s (reference bases x queries,
 both strands inside one unit) over the timed steps, wall clock.
@@ -16,6 +24,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -38,10 +47,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--total", type=int, default=4_000_000_000, help="reference bases")
-    ap.add_argument("--ks", default="0,4,8")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"])
+    ap.add_argument("--total", type=int, default=0, help="reference bases (0 = workload default)")
+    ap.add_argument("--queries", type=int, default=0, help="query count (0 = workload default)")
+    ap.add_argument("--ks", default="0,4,8", help="c2: maxSubs values, one pass each")
     ap.add_argument("--cpu-sample", type=int, default=250_000_000,
-                    help="reference bases the oracle baseline scans per maxSubs (0 = skip)")
+                    help="c2: reference bases the oracle baseline scans per maxSubs (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1,
                     help="scan kernel variant (default: autotuned on the workload's queries)")
@@ -64,79 +75,42 @@ def calib_copy():
         f"({2 * (1 << 30) / ms.value / 1e6:.0f} GB/s)")
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is design-only)", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import synth
-    import paper_2607_27291_amd as ifa
-
-    if args.calib_copy:
-        calib_copy()
-    ks = [int(x) for x in args.ks.split(",")]
-    t0 = time.time()
-    w = synth.c2_paper_scale(total=args.total)
-    log(f"generated {w.ref.total / 1e9:.2f} Gbp in {w.ref.n_contigs} contigs, "
-        f"{len(w.plants)} planted copies ({time.time() - t0:.1f} s)")
-    nq = len(w.queries)
-
-    s = ifa.Scanner(device=0)
-    t0 = time.time()
-    s.ref_load(w.ref)
-    bases, chunks = ifa.ifa_ref_info(s.ctx)
-    log(f"resident: {bases / 1e9:.2f} Gbp in {chunks} device chunks ({time.time() - t0:.1f} s)")
-
-    # choose the kernel variant: autotuner on a 64 Mi-base calibration chunk
-    # with this workload's queries (maxSubs 4), unless one is given
+def choose_variant(ifa, s, args, queries, ks):
+    """Autotune the kernel variant on a 64 Mi-base calibration chunk with the
+    workload's queries, unless one is given."""
     if args.variant >= 0:
         ifa.ifa_set_variant(s.ctx, args.variant)
-        tune = None
-    else:
-        s.load_queries(w.queries, [4] * nq)
-        chosen, ms = ifa.ifa_autotune(s.ctx, 64 << 20, 5)
-        tune = {"chosen": chosen, "ms": [round(float(x), 4) for x in ms]}
-        log(f"autotune: variant {chosen} {ifa.ifa_variant_info(chosen)}; "
-            f"ms per variant {tune['ms']}")
-    variant = ifa.ifa_get_variant(s.ctx)
+        return None
+    s.load_queries(queries, ks)
+    chosen, ms = ifa.ifa_autotune(s.ctx, 64 << 20, 5)
+    log(f"autotune: variant {chosen} {ifa.ifa_variant_info(chosen)}; "
+        f"ms per variant {[round(float(x), 4) for x in ms]}")
+    return {"chosen": chosen, "ms": [round(float(x), 4) for x in ms]}
 
-    def step():
-        found = 0
-        for k in ks:
-            s.load_queries(w.queries, [k] * nq)
-            s.scan_resident()
-            found += len(s.collect())
-        return found
 
-    for i in range(args.warmup):
-        step()
-        log(f"warmup step {i} done")
-    ifa.ifa_get_stats(s.ctx)
-    ifa.ifa_reset_stats(s.ctx)
-    t0 = time.perf_counter()
-    hits = 0
-    for i in range(args.steps):
-        hits += step()
-        log(f"step {i} done")
-    elapsed = time.perf_counter() - t0
-    st = ifa.ifa_get_stats(s.ctx)
-
-    bpq_per_step = bases * nq * len(ks)
-    value = bpq_per_step * args.steps / elapsed / 1e9
-    ms_per_step = elapsed * 1e3 / args.steps
-    # dominant kernel: the filter (hot loop), timed alone by HIP events on the
-    # compute stream around each of its launches
+def roofline(ifa, st, ops_per_launch, variant):
     launches = max(1, st["filter_launches"])
     filter_ms_avg = st["filter_ms"] / launches
-    # algorithmic VALU ops of one launch: every window of a chunk x 2 strands x queries
-    ops_per_launch = OPS_PER_WINDOW_STRAND * 2 * nq * (bases / chunks)
-    achieved = ops_per_launch / (filter_ms_avg * 1e-3) / 1e12
+    achieved = ops_per_launch / (filter_ms_avg * 1e-3) / 1e12 if st["filter_launches"] else 0.0
     peak = PEAK_VALU_OPS / 1e12
-    kernel_rate = bpq_per_step * args.steps / (st["kernel_ms"] * 1e-3) / 1e9
+    return {
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": round(peak, 3),
+        "unit": "TOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": None,
+        "kernel": "scan_filter_kernel",
+        "variant": variant,
+        "variant_shape": ifa.ifa_variant_info(variant),
+        "kernel_ms_avg": round(filter_ms_avg, 4),
+        "launches": st["filter_launches"],
+        "pass_ms_avg": round(st["kernel_ms"] / max(1, st["kernel_launches"]), 4),
+    }
 
-    out = {
+
+def base_record(args, value, ms_per_step, config):
+    return {
         "metric": METRIC,
         "value": round(value, 3),
         "unit": "Gbp·query/s",
@@ -149,32 +123,73 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {
-            "workload": "paper-scale single pass: 10 queries L30-36 vs 4 Gbp resident, "
-                        "maxSubs 0/4/8 (one pass each per step)",
-            "reference_bases": bases,
-            "queries": nq,
-            "max_subs": ks,
-            "device_chunks": chunks,
-            "hits_per_step": hits // max(1, args.steps),
-        },
-        "kernel_only_gbpq_s": round(kernel_rate, 3),
-        "autotune": tune,
-        "roofline": {
-            "bound": "alu",
-            "achieved": round(achieved, 3),
-            "peak": round(peak, 3),
-            "unit": "TOP/s",
-            "frac": round(achieved / peak, 4),
-            "traffic": None,
-            "kernel": "scan_filter_kernel",
-            "variant": variant,
-            "variant_shape": ifa.ifa_variant_info(variant),
-            "kernel_ms_avg": round(filter_ms_avg, 4),
-            "launches": launches,
-            "pass_ms_avg": round(st["kernel_ms"] / max(1, st["kernel_launches"]), 4),
-        },
+        "config": config,
     }
+
+
+def timed_steps(ifa, s, args, step):
+    for i in range(args.warmup):
+        step()
+        log(f"warmup step {i} done")
+    ifa.ifa_get_stats(s.ctx)
+    ifa.ifa_reset_stats(s.ctx)
+    t0 = time.perf_counter()
+    res = []
+    for i in range(args.steps):
+        res.append(step())
+        log(f"step {i} done")
+    elapsed = time.perf_counter() - t0
+    return elapsed, ifa.ifa_get_stats(s.ctx), res
+
+
+# --------------------------------------------------------------------------
+# c2: paper-scale single pass (headline)
+# --------------------------------------------------------------------------
+
+def run_c2(args):
+    import synth
+    import paper_2607_27291_amd as ifa
+
+    ks = [int(x) for x in args.ks.split(",")]
+    total = args.total or 4_000_000_000
+    t0 = time.time()
+    w = synth.c2_paper_scale(total=total)
+    log(f"generated {w.ref.total / 1e9:.2f} Gbp in {w.ref.n_contigs} contigs, "
+        f"{len(w.plants)} planted copies ({time.time() - t0:.1f} s)")
+    nq = len(w.queries)
+
+    s = ifa.Scanner(device=0)
+    t0 = time.time()
+    s.ref_load(w.ref)
+    bases, chunks = ifa.ifa_ref_info(s.ctx)
+    log(f"resident: {bases / 1e9:.2f} Gbp in {chunks} device chunks ({time.time() - t0:.1f} s)")
+    tune = choose_variant(ifa, s, args, w.queries, [4] * nq)
+    variant = ifa.ifa_get_variant(s.ctx)
+
+    def step():
+        found = 0
+        for k in ks:
+            s.load_queries(w.queries, [k] * nq)
+            s.scan_resident()
+            found += len(s.collect())
+        return found
+
+    elapsed, st, res = timed_steps(ifa, s, args, step)
+    bpq_per_step = bases * nq * len(ks)
+    out = base_record(args, bpq_per_step * args.steps / elapsed / 1e9,
+                      elapsed * 1e3 / args.steps, {
+                          "workload": "paper-scale single pass: 10 queries L30-36 vs 4 Gbp "
+                                      "resident, maxSubs 0/4/8 (one pass each per step)",
+                          "reference_bases": bases,
+                          "queries": nq,
+                          "max_subs": ks,
+                          "device_chunks": chunks,
+                          "hits_per_step": sum(res) // max(1, args.steps),
+                      })
+    out["kernel_only_gbpq_s"] = round(bpq_per_step * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
+    out["autotune"] = tune
+    # algorithmic VALU ops of one filter launch: every window of a chunk x 2 strands x queries
+    out["roofline"] = roofline(ifa, st, OPS_PER_WINDOW_STRAND * 2 * nq * (bases / chunks), variant)
 
     if not args.no_cpu and args.cpu_sample > 0:
         import oracle
@@ -200,6 +215,165 @@ def main():
                       f"maxSubs {'/'.join(map(str, ks))}, {dt:.1f} s",
         }
     s.close()
+    return out
+
+
+# --------------------------------------------------------------------------
+# c3: batched scan, count+digest
+# --------------------------------------------------------------------------
+
+def run_c3(args):
+    import synth
+    import paper_2607_27291_amd as ifa
+
+    total = args.total or 1_000_000_000
+    nq = args.queries or 10_000
+    t0 = time.time()
+    w = synth.c3_batched(total=total, n_queries=nq)
+    log(f"generated {w.ref.total / 1e9:.2f} Gbp, {nq} queries ({time.time() - t0:.1f} s)")
+    s = ifa.Scanner(device=0, sink=ifa.IFA_SINK_COUNT_DIGEST)
+    s.ref_load(w.ref)
+    bases, chunks = ifa.ifa_ref_info(s.ctx)
+    tune = choose_variant(ifa, s, args, w.queries, w.max_subs)
+    variant = ifa.ifa_get_variant(s.ctx)
+
+    def step():
+        s.load_queries(w.queries, w.max_subs)
+        s.scan_resident()
+        return s.query_stats()
+
+    elapsed, st, res = timed_steps(ifa, s, args, step)
+    cnt, dig = res[-1]
+    bpq = bases * nq
+    n_sparse = ifa.ifa_sparse_count(s.ctx)
+    out = base_record(args, bpq * args.steps / elapsed / 1e9, elapsed * 1e3 / args.steps, {
+        "workload": f"batched scan: {nq} queries L18-50, maxSubs 0-16, vs "
+                    f"{bases / 1e9:.2f} Gbp resident, count+digest",
+        "reference_bases": bases,
+        "queries": nq,
+        "device_chunks": chunks,
+        "hits_per_step": int(cnt.sum()),
+        "sparse_strands": n_sparse,
+        "dense_strands": 2 * nq - n_sparse,
+    })
+    out["kernel_only_gbpq_s"] = round(bpq * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
+    out["filter_ms_per_step"] = round(st["filter_ms"] / args.steps, 3)
+    out["pass_ms_per_step"] = round(st["kernel_ms"] / args.steps, 3)
+    out["autotune"] = tune
+    # filter launches cover the sparse strands only; dense strands bypass it
+    out["roofline"] = roofline(ifa, st, OPS_PER_WINDOW_STRAND * n_sparse * (bases / chunks),
+                               variant)
+    s.close()
+    return out
+
+
+# --------------------------------------------------------------------------
+# c4: streaming from a reference generated on the fly
+# --------------------------------------------------------------------------
+
+def run_c4(args):
+    import numpy as np
+    import synth
+    import paper_2607_27291_amd as ifa
+
+    total = args.total or 100_000_000_000
+    nq = args.queries or 100
+    spec = synth.c4_spec(total=total)
+    lens = synth.contig_lengths(spec)
+    gcs = synth.contig_gc(spec, 0, len(lens))
+    qs, ks = synth.c4_queries(n=nq)
+    batch_bases = 1 << 30
+    # contig batches of about batch_bases each
+    batches, cur, acc = [], [], 0
+    for i, n in enumerate(lens):
+        cur.append(i)
+        acc += int(n)
+        if acc >= batch_bases:
+            batches.append(cur)
+            cur, acc = [], 0
+    if cur:
+        batches.append(cur)
+    threads = synth.default_threads()
+    log(f"c4: {total / 1e9:.0f} Gbp in {len(lens)} contigs, {len(batches)} batches, {nq} queries")
+
+    s = ifa.Scanner(device=0, host_threads=max(1, threads // 2))
+    tune = choose_variant(ifa, s, args, qs, ks)
+    variant = ifa.ifa_get_variant(s.ctx)
+    foot0 = ifa.ifa_device_footprint(s.ctx)
+
+    def gen_batch(b):
+        idx = batches[b]
+        blen = lens[idx]
+        offs = np.zeros(len(idx), dtype=np.uint64)
+        if len(idx) > 1:
+            offs[1:] = np.cumsum(blen)[:-1]
+        buf = np.empty(int(blen.sum()), dtype=np.uint8)
+        synth.fill_contigs(spec, idx[0], blen, gcs[idx], buf, offs, max(1, threads // 2))
+        return synth.Reference(buf, offs, blen)
+
+    gen_s = [0.0]
+
+    def step():
+        # producer thread generates batch b+1 while this thread packs and
+        # streams batch b (both release the GIL inside their C code)
+        s.load_queries(qs, ks)
+        nxt = {}
+
+        def produce(b):
+            t = time.perf_counter()
+            nxt[b] = gen_batch(b)
+            gen_s[0] += time.perf_counter() - t
+
+        th = threading.Thread(target=produce, args=(0,))
+        th.start()
+        for b in range(len(batches)):
+            th.join()
+            ref = nxt.pop(b)
+            if b + 1 < len(batches):
+                th = threading.Thread(target=produce, args=(b + 1,))
+                th.start()
+            s.scan_chunk(ref)
+        return len(s.collect())
+
+    elapsed, st, res = timed_steps(ifa, s, args, step)
+    foot1 = ifa.ifa_device_footprint(s.ctx)
+    bpq = total * nq
+    out = base_record(args, bpq * args.steps / elapsed / 1e9, elapsed * 1e3 / args.steps, {
+        "workload": f"terabase-style streaming: {nq} queries L20-40, maxSubs 4, vs "
+                    f"{total / 1e9:.0f} Gbp generated on the fly, packed on host threads and "
+                    "streamed through pinned double buffers",
+        "reference_bases": total,
+        "queries": nq,
+        "contigs": len(lens),
+        "hits_per_step": res[-1],
+    })
+    out["kernel_only_gbpq_s"] = round(bpq * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
+    out["gpu_busy_frac"] = round(st["kernel_ms"] / (elapsed * 1e3), 4)
+    out["producer_gbp_s"] = round(total * (args.steps + args.warmup) / max(gen_s[0], 1e-9) / 1e9, 3)
+    out["pack_gbp_s"] = round(st["bases"] / max(st["pack_ms"] * 1e-3, 1e-9) / 1e9, 3)
+    out["h2d_gb_s"] = round(st["bases"] / 4 / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
+    out["device_footprint_bytes"] = {"before": foot0, "after": foot1}
+    out["autotune"] = tune
+    chunk_windows = 1 << 30
+    out["roofline"] = roofline(ifa, st, OPS_PER_WINDOW_STRAND * 2 * nq * chunk_windows, variant)
+    s.close()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is design-only)", file=sys.stderr)
+        sys.exit(2)
+    if args.calib_copy:
+        calib_copy()
+    if args.workload == "c2":
+        out = run_c2(args)
+    elif args.workload == "c3":
+        out = run_c3(args)
+    else:
+        out = run_c4(args)
     print(json.dumps(out), flush=True)
 
 

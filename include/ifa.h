@@ -191,6 +191,15 @@ ifa_status ifa_ref_info(const ifa_ctx *ctx, uint64_t *bases, uint32_t *chunks);
 ifa_status ifa_get_stats(ifa_ctx *ctx, ifa_stats *out);
 ifa_status ifa_reset_stats(ifa_ctx *ctx);
 
+/* Query strands of the loaded set (*n_strands) and how many of them take the
+ * filter kernel (*n_filtered); the rest are predicted hit-dense and are
+ * resolved directly. */
+ifa_status ifa_query_partition(const ifa_ctx *ctx, uint32_t *n_strands, uint32_t *n_filtered);
+
+/* Device memory held by the context, in bytes: stream chunk buffers, hit
+ * buffers, work lists, query tables, counters and any resident reference. */
+ifa_status ifa_device_footprint(const ifa_ctx *ctx, uint64_t *bytes);
+
 /* Kernel variants: tile shapes of the scan kernel (windows per lane, query
  * strands per loop iteration, workgroup size). Every variant computes the
  * same hits; they differ only in speed. */

@@ -297,24 +297,30 @@ int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
         for (int i = 0; i < L; i++) Q->code[1][i] = (uint8_t)orc_comp(Q->code[0][L - 1 - i]);
         if (L > J.maxL) J.maxL = L;
     }
-    /* work items: ranges of window starts */
+    /* work items: ranges of window starts, small enough that every thread
+     * gets several even when there is one contig */
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    uint64_t total_bases = 0;
+    for (uint32_t c = 0; c < nc; c++) total_bases += clen[c];
+    uint64_t item = total_bases / ((uint64_t)threads * 8u);
+    if (item < 4096) item = 4096;
+    if (item > ORC_ITEM_WINDOWS) item = ORC_ITEM_WINDOWS;
     uint64_t n_items = 0;
     for (uint32_t c = 0; c < nc; c++)
-        n_items += (clen[c] + ORC_ITEM_WINDOWS - 1) / ORC_ITEM_WINDOWS;
+        n_items += (clen[c] + item - 1) / item;
     J.items = (orc_item *)malloc((n_items ? n_items : 1) * sizeof(orc_item));
     if (!J.items) goto done;
     J.n_items = 0;
     for (uint32_t c = 0; c < nc; c++) {
-        for (uint64_t p = 0; p < clen[c]; p += ORC_ITEM_WINDOWS) {
+        for (uint64_t p = 0; p < clen[c]; p += item) {
             orc_item *it = &J.items[J.n_items++];
             it->contig = c;
             it->p0 = p;
-            it->p1 = p + ORC_ITEM_WINDOWS < clen[c] ? p + ORC_ITEM_WINDOWS : clen[c];
+            it->p1 = p + item < clen[c] ? p + item : clen[c];
         }
     }
     pthread_mutex_init(&J.mu, NULL);
-    if (threads < 1) threads = 1;
-    if (threads > 256) threads = 256;
     orc_worker *W = (orc_worker *)calloc((size_t)threads, sizeof(orc_worker));
     pthread_t *th = (pthread_t *)calloc((size_t)threads, sizeof(pthread_t));
     int *started = (int *)calloc((size_t)threads, sizeof(int));

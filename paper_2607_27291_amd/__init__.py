@@ -19,7 +19,8 @@ __all__ = [
     "ifa_load_queries", "ifa_scan_chunk", "ifa_collect_hits", "ifa_last_error",
     "ifa_query_stats", "ifa_ref_load", "ifa_scan_resident", "ifa_ref_release", "ifa_ref_info",
     "ifa_get_stats", "ifa_reset_stats", "ifa_variant_count", "ifa_variant_info",
-    "ifa_set_variant", "ifa_get_variant", "ifa_autotune", "Scanner", "collect_all",
+    "ifa_set_variant", "ifa_get_variant", "ifa_autotune", "ifa_query_partition",
+    "ifa_device_footprint", "Scanner", "collect_all",
 ]
 
 IFA_ABI_VERSION = 1
@@ -109,6 +110,10 @@ def lib():
         L.ifa_get_variant.restype = st
         L.ifa_autotune.argtypes = [vp, u64, u32, ctypes.c_char_p, ctypes.POINTER(u32), vp]
         L.ifa_autotune.restype = st
+        L.ifa_query_partition.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        L.ifa_query_partition.restype = st
+        L.ifa_device_footprint.argtypes = [vp, ctypes.POINTER(u64)]
+        L.ifa_device_footprint.restype = st
         _lib = L
     return _lib
 
@@ -280,6 +285,23 @@ def ifa_autotune(ctx, calib_bases: int = 0, reps: int = 0, cache_path: str | Non
                                    cache_path.encode() if cache_path else None,
                                    ctypes.byref(chosen), ms.ctypes.data))
     return chosen.value, ms
+
+
+def ifa_query_partition(ctx):
+    """(query strands loaded, strands taking the filter kernel)."""
+    a, b = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(ctx, lib().ifa_query_partition(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def ifa_sparse_count(ctx) -> int:
+    return ifa_query_partition(ctx)[1]
+
+
+def ifa_device_footprint(ctx) -> int:
+    b = ctypes.c_uint64()
+    _check(ctx, lib().ifa_device_footprint(ctx, ctypes.byref(b)))
+    return b.value
 
 
 def collect_all(ctx, batch: int = 1 << 20) -> np.ndarray:

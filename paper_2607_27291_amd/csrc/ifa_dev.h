@@ -3,10 +3,12 @@
 // Reference chunk in device memory: four bit planes of `plane_words` uint32
 // words each, stored one after another (hi, lo, nm, em). Base x of the chunk
 // is bit (x & 31) of word (x >> 5) in every plane:
-//   hi, lo : 2-bit base code A=00 C=01 G=10 T=11 (hi bit, lo bit); N is 00
+//   hi, lo : 2-bit base code A=00 C=01 G=11 T=10 (hi bit, lo bit): bits 2
+//            and 1 of the ASCII byte; complementing a base flips hi
 //   nm     : 1 where the base is N (any non-ACGT byte)
 //   em     : 1 at the last base of every contig piece, so a window is inside
 //            one piece iff no em bit falls on its first L-1 positions
+// hi/lo bits at N positions are unspecified (readers mask them with nm).
 // Words past the chunk end hold hi = lo = 0 and nm = em = all ones, and at
 // least IFA_PAD_WORDS such words follow the last data word.
 #pragma once

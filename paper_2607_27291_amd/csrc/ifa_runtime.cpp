@@ -8,6 +8,7 @@
 // not depend on the total reference size nor on the largest contig: a contig
 // that does not fit is split, and the next chunk repeats its last kCarry bases.
 #include <hip/hip_runtime.h>
+#include <immintrin.h>
 
 #include <algorithm>
 #include <atomic>
@@ -65,16 +66,15 @@ double now_ms()
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-// byte -> base code: A 0, C 1, G 2, T 3, anything else 4
+// byte -> base code, anything other than A/C/G/T/a/c/g/t is 4 (N). The 2-bit
+// code (hi, lo) of a base is bits 2 and 1 of its ASCII byte: A=00, C=01,
+// G=11, T=10, in either case; complementing a base flips hi.
 struct CodeTable {
     uint8_t c[256];
     CodeTable()
     {
         std::memset(c, 4, sizeof c);
-        c['A'] = c['a'] = 0;
-        c['C'] = c['c'] = 1;
-        c['G'] = c['g'] = 2;
-        c['T'] = c['t'] = 3;
+        for (const char *p = "ACGTacgt"; *p; p++) c[(uint8_t)*p] = ((uint8_t)*p >> 1) & 3u;
     }
 };
 const CodeTable kCode;
@@ -254,33 +254,61 @@ namespace {
 
 uint32_t *plane(ifa_ctx *c, Staging &s, int k) { return s.planes.p + (size_t)k * c->plane_words; }
 
+// One plane word from 32 bytes: hi = bit 2 of each byte, lo = bit 1, n = 1
+// where the byte is not A/C/G/T/a/c/g/t.
+__attribute__((target("avx2"))) void pack32_avx2(const uint8_t *p, uint32_t *h, uint32_t *l,
+                                                 uint32_t *n)
+{
+    const __m256i v = _mm256_loadu_si256((const __m256i *)p);
+    *h = (uint32_t)_mm256_movemask_epi8(_mm256_slli_epi16(v, 5));
+    *l = (uint32_t)_mm256_movemask_epi8(_mm256_slli_epi16(v, 6));
+    const __m256i f = _mm256_or_si256(v, _mm256_set1_epi8(0x20));   // fold case
+    __m256i ok = _mm256_cmpeq_epi8(f, _mm256_set1_epi8('a'));
+    ok = _mm256_or_si256(ok, _mm256_cmpeq_epi8(f, _mm256_set1_epi8('c')));
+    ok = _mm256_or_si256(ok, _mm256_cmpeq_epi8(f, _mm256_set1_epi8('g')));
+    ok = _mm256_or_si256(ok, _mm256_cmpeq_epi8(f, _mm256_set1_epi8('t')));
+    *n = ~(uint32_t)_mm256_movemask_epi8(ok);
+}
+
+void pack32_scalar(const uint8_t *p, uint32_t cnt, uint32_t b0, uint32_t *h, uint32_t *l,
+                   uint32_t *n)
+{
+    uint32_t hh = 0, ll = 0, nn = 0;
+    for (uint32_t i = 0; i < cnt; i++) {
+        const uint32_t b = p[i], bit = 1u << (b0 + i);
+        if (kCode.c[b] == 4) nn |= bit;
+        if (b & 4u) hh |= bit;
+        if (b & 2u) ll |= bit;
+    }
+    *h = hh;
+    *l = ll;
+    *n = nn;
+}
+
+const bool kHaveAvx2 = __builtin_cpu_supports("avx2");
+
 // Pack bases [dst, dst + n) of the chunk from src. Words are written whole,
-// except the first word, whose bits below `dst` are kept (they belong to bases
-// packed earlier).
+// except the first word, whose bits below `dst` are kept when keep_low (they
+// belong to bases packed earlier). hi/lo bits at N positions are whatever the
+// byte holds: every reader masks N positions with the N plane.
 void pack_range(ifa_ctx *c, Staging &s, uint64_t dst, const uint8_t *src, uint64_t n,
                 bool keep_low)
 {
     uint32_t *H = plane(c, s, 0), *Lo = plane(c, s, 1), *N = plane(c, s, 2);
     uint64_t x = dst, end = dst + n;
     while (x < end) {
-        uint64_t w = x >> 5;
-        uint32_t b0 = (uint32_t)(x & 31);
-        uint64_t wend = std::min<uint64_t>(end, (w + 1) << 5);
-        uint32_t h = 0, l = 0, nn = 0;
+        const uint64_t w = x >> 5;
+        const uint32_t b0 = (uint32_t)(x & 31);
+        const uint64_t wend = std::min<uint64_t>(end, (w + 1) << 5);
         const uint8_t *p = src + (x - dst);
-        uint32_t cnt = (uint32_t)(wend - x);
-        for (uint32_t i = 0; i < cnt; i++) {
-            uint32_t code = kCode.c[p[i]];
-            uint32_t bit = 1u << (b0 + i);
-            if (code == 4) {
-                nn |= bit;
-            } else {
-                if (code & 2) h |= bit;
-                if (code & 1) l |= bit;
-            }
-        }
+        const uint32_t cnt = (uint32_t)(wend - x);
+        uint32_t h, l, nn;
+        if (cnt == 32 && kHaveAvx2)
+            pack32_avx2(p, &h, &l, &nn);
+        else
+            pack32_scalar(p, cnt, b0, &h, &l, &nn);
         if (b0 != 0 && keep_low) {
-            uint32_t keep = (1u << b0) - 1u;
+            const uint32_t keep = (1u << b0) - 1u;
             H[w] = (H[w] & keep) | h;
             Lo[w] = (Lo[w] & keep) | l;
             N[w] = (N[w] & keep) | nn;
@@ -956,9 +984,10 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
                 words.resize(words.size() + 3u * d.nw, 0u);
                 uint32_t *W = words.data() + d.woff;
                 for (uint32_t i = 0; i < L; i++) {
-                    // strand 1: reverse complement (A<->T, C<->G, N stays N)
+                    // strand 1: reverse complement; complementing flips the
+                    // hi bit of the code (A<->T, C<->G), N stays N
                     uint32_t v = s == 0 ? code[i] : code[L - 1 - i];
-                    if (s == 1 && v < 4) v = 3 - v;
+                    if (s == 1 && v < 4) v ^= 2u;
                     uint32_t t = i >> 5, bit = 1u << (i & 31);
                     if (v == 4) {
                         W[3 * t + 2] |= bit;
@@ -1349,6 +1378,31 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
             for (uint32_t i = 0; i < nv; i++) ms_per_variant[i] = ms[i];
         if (cache_path) cache_store(cache_path, key, best, ms[best]);
     });
+}
+
+ifa_status ifa_query_partition(const ifa_ctx *c, uint32_t *n_strands, uint32_t *n_filtered)
+{
+    if (!c) return IFA_E_INVALID;
+    if (n_strands) *n_strands = (uint32_t)c->h_qs.size();
+    if (n_filtered) *n_filtered = c->n_sparse;
+    return IFA_OK;
+}
+
+ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
+{
+    if (!c || !bytes) return IFA_E_INVALID;
+    uint64_t b = 0;
+    for (int i = 0; i < 2; i++) {
+        b += c->slot[i].planes.n * sizeof(uint32_t) + c->slot[i].pieces.n * sizeof(Piece);
+        b += c->d_hits[i].n * sizeof(uint4) + c->work[i].n * sizeof(WorkItem);
+    }
+    b += c->d_hitcount.n * sizeof(unsigned long long) + c->d_workcount.n * sizeof(unsigned int);
+    b += c->d_qs.n * sizeof(QSDesc) + c->d_qwords.n * sizeof(uint32_t);
+    b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
+    for (const auto &r : c->resident)
+        b += r->planes.n * sizeof(uint32_t) + r->pieces.n * sizeof(Piece);
+    *bytes = b;
+    return IFA_OK;
 }
 
 ifa_status ifa_reset_stats(ifa_ctx *c)

@@ -142,9 +142,12 @@ static void fill_range(const syn_spec *sp, uint64_t c, uint64_t clen, double gc,
 {
     if (x0 >= clen) return;
     if (x0 + n > clen) n = clen - x0;
-    const uint32_t thr = (uint32_t)(gc * 32768.0 + 0.5);
-    static const uint8_t at[2] = { 'A', 'T' };
-    static const uint8_t cg[2] = { 'C', 'G' };
+    /* 8 random bits per base: the low 7 against the GC fraction (so GC is
+     * quantised to 1/128), the top bit picks G/C or A/T */
+    const uint32_t thr = (uint32_t)(gc * 128.0 + 0.5);
+    uint8_t table[256];
+    for (uint32_t u = 0; u < 256; u++)
+        table[u] = (u & 0x7Fu) < thr ? ((u >> 7) ? 'G' : 'C') : ((u >> 7) ? 'T' : 'A');
     uint64_t x = x0, end = x0 + n;
     while (x < end) {
         uint64_t blk = x / SYN_BLOCK;
@@ -152,17 +155,37 @@ static void fill_range(const syn_spec *sp, uint64_t c, uint64_t clen, double gc,
         uint64_t bend = bstart + SYN_BLOCK;
         if (bend > end) bend = end;
         syn_rng r = { syn_key(sp->seed, 3, c, blk) };
-        /* skip draws for the part of the block before x: 4 bases per draw */
-        uint64_t skip = (x - bstart) / 4;
+        /* skip draws for the part of the block before x: 8 bases per draw */
+        uint64_t skip = (x - bstart) / 8;
         r.s += skip * SYN_GAMMA;
-        uint64_t pos = bstart + skip * 4;
+        uint64_t pos = bstart + skip * 8;
+        if (pos < x || bend - pos < 8) {
+            /* ragged head or tail: base by base */
+            while (pos < bend) {
+                uint64_t v = syn_next(&r);
+                for (int j = 0; j < 8 && pos < bend; j++, pos++)
+                    if (pos >= x) out[pos - x0] = table[(v >> (8 * j)) & 0xFFu];
+            }
+        }
+        /* whole draws */
+        uint8_t *o = out + (pos - x0);
+        while (pos + 8 <= bend) {
+            uint64_t v = syn_next(&r);
+            o[0] = table[v & 0xFF];
+            o[1] = table[(v >> 8) & 0xFF];
+            o[2] = table[(v >> 16) & 0xFF];
+            o[3] = table[(v >> 24) & 0xFF];
+            o[4] = table[(v >> 32) & 0xFF];
+            o[5] = table[(v >> 40) & 0xFF];
+            o[6] = table[(v >> 48) & 0xFF];
+            o[7] = table[v >> 56];
+            o += 8;
+            pos += 8;
+        }
         while (pos < bend) {
             uint64_t v = syn_next(&r);
-            for (int j = 0; j < 4 && pos < bend; j++, pos++) {
-                uint32_t u = (uint32_t)(v >> (16 * j)) & 0xFFFFu;
-                uint32_t u15 = u & 0x7FFFu, sel = u >> 15;
-                if (pos >= x) out[pos - x0] = (u15 < thr) ? cg[sel] : at[sel];
-            }
+            for (int j = 0; j < 8 && pos < bend; j++, pos++)
+                out[pos - x0] = table[(v >> (8 * j)) & 0xFFu];
         }
         if (sp->n_mode == 1) {
             syn_rng rn = { syn_key(sp->seed, 4, c, blk) };
