@@ -15,7 +15,10 @@ Other workloads (--workload):
   c4  streaming: 100 queries, L 20-40, maxSubs 4, against a reference
       generated on the fly by host threads, packed and streamed through the
       pinned double buffer (never resident); one step = the whole reference.
-The serving loop has its own driver (serve.py).
+  c5  serving loop: Poisson arrivals (200/s) of query sets of 1-1000
+      queries (log-uniform), L 18-150, maxSubs 0-L/4, against 16 Gbp
+      resident; continuous batching versus serial first-in-first-out scans
+      over the same trace, plus a run at 70% of the measured capacity.
 
 Prints one JSON line. `value` is Gbp*query/s (reference bases x queries,
 both strands inside one unit) over the timed steps, wall clock.
@@ -47,7 +50,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--requests", type=int, default=50, help="c5: requests in the trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="c5: Poisson arrivals per second")
+    ap.add_argument("--chunk-bases", type=int, default=1 << 28, help="c5: resident chunk size")
     ap.add_argument("--total", type=int, default=0, help="reference bases (0 = workload default)")
     ap.add_argument("--queries", type=int, default=0, help="query count (0 = workload default)")
     ap.add_argument("--ks", default="0,4,8", help="c2: maxSubs values, one pass each")
@@ -360,6 +366,61 @@ def run_c4(args):
     return out
 
 
+# --------------------------------------------------------------------------
+# c5: serving loop
+# --------------------------------------------------------------------------
+
+def run_c5(args):
+    import synth
+    import paper_2607_27291_amd as ifa
+    from paper_2607_27291_amd import serve
+
+    total = args.total or 16_000_000_000
+    t0 = time.time()
+    ref = synth.gen_reference(synth.c5_spec(total=total))
+    log(f"generated {ref.total / 1e9:.1f} Gbp ({time.time() - t0:.1f} s)")
+    s = ifa.Scanner(device=0, chunk_bases=args.chunk_bases)
+    s.ref_load(ref)
+    bases, chunks = ifa.ifa_ref_info(s.ctx)
+    del ref
+    log(f"resident: {bases / 1e9:.1f} Gbp in {chunks} chunks")
+    trace = synth.c5_trace(n_requests=args.requests, rate=args.rate)
+    if args.variant >= 0:
+        ifa.ifa_set_variant(s.ctx, args.variant)
+    variant = ifa.ifa_get_variant(s.ctx)
+    res = {}
+    for mode in ("batch", "serial"):
+        log(f"replaying {len(trace)} requests, {mode}")
+        res[mode] = serve.replay(s, trace, mode=mode, log=log)
+    # sub-saturation run: arrivals at 70% of the capacity measured above
+    mean_q = sum(len(r[1]) for r in trace) / len(trace)
+    cap_req_s = res["batch"]["gbpq_per_s"] * 1e9 / (mean_q * bases)
+    rate2 = 0.7 * cap_req_s
+    trace2 = synth.c5_trace(n_requests=args.requests, rate=rate2)
+    log(f"replaying {len(trace2)} requests at {rate2:.3f}/s (70% of capacity), batch")
+    res["batch_70pct"] = serve.replay(s, trace2, mode="batch", log=log)
+    b = res["batch"]
+    out = base_record(args, b["gbpq_per_s"], b["makespan_s"] * 1e3, {
+        "workload": f"serving loop: Poisson arrivals {args.rate:g}/s, {args.requests} requests of "
+                    "1-1000 queries (log-uniform), L18-150, maxSubs 0-L/4, vs "
+                    f"{bases / 1e9:.0f} Gbp resident in {chunks} chunks, continuous batching",
+        "reference_bases": bases,
+        "requests": args.requests,
+        "queries": b["queries"],
+        "variant": variant,
+    })
+    out["steps"] = 1
+    out["warmup"] = 0
+    out["serving"] = {
+        k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()
+            if kk not in ("latencies_s", "hits", "hit_records")}
+        for k, v in res.items()
+    }
+    out["serving"]["batch_70pct"]["rate_per_s"] = round(rate2, 4)
+    s.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -372,8 +433,10 @@ def main():
         out = run_c2(args)
     elif args.workload == "c3":
         out = run_c3(args)
-    else:
+    elif args.workload == "c4":
         out = run_c4(args)
+    else:
+        out = run_c5(args)
     print(json.dumps(out), flush=True)
 
 

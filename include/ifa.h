@@ -222,6 +222,68 @@ ifa_status ifa_get_variant(const ifa_ctx *ctx, uint32_t *v);
 ifa_status ifa_autotune(ifa_ctx *ctx, uint64_t calib_bases, uint32_t reps, const char *cache_path,
                         uint32_t *chosen, double *ms_per_variant);
 
+/* ------------------------------------------------------------------------
+ * Serving loop: continuous batching over a device-resident reference.
+ *
+ * Query sets ("requests") arrive at any time through ifa_server_submit. Each
+ * ifa_server_step scans one resident chunk, the one under a rotating cursor,
+ * with the query strands of every admitted request together, so the work of
+ * concurrent requests shares the same kernel launches. A request admitted at
+ * a step completes after one full revolution over the resident chunks; its
+ * hits are exactly those of a plain scan of that query set alone (same
+ * records, same reference order). Admission keeps the admitted query count
+ * under max_active_queries and the admitted requests' expected hits (iid-base
+ * binomial model) under hit_budget records; a request alone is always
+ * admitted. A server borrows its context: the context must hold a resident
+ * reference (ifa_ref_load), use the records sink, and must not be used for
+ * other scans while the server exists.
+ * ------------------------------------------------------------------------ */
+typedef struct ifa_server ifa_server;
+
+typedef struct {
+    uint32_t max_active_queries;  /* default 4096 */
+    uint32_t reserved;            /* must be 0 */
+    uint64_t hit_budget;          /* default 2^26 records */
+} ifa_server_config;
+
+typedef struct {
+    uint32_t pending;         /* submitted, not yet admitted */
+    uint32_t active;          /* admitted, scanning */
+    uint32_t active_queries;
+    uint32_t done_waiting;    /* completed, hits not yet taken */
+    uint64_t steps;
+    uint64_t completed;
+    double step_ms;           /* host wall time inside steps */
+    uint32_t cursor;          /* next resident chunk */
+    uint32_t chunks;          /* resident chunks */
+} ifa_server_stats;
+
+void ifa_server_config_default(ifa_server_config *cfg);
+ifa_status ifa_server_create(ifa_ctx *ctx, const ifa_server_config *cfg, ifa_server **out);
+void ifa_server_destroy(ifa_server *srv);   /* NULL-safe; pending requests are dropped */
+
+/* Queue a request of n queries (same arguments as ifa_load_queries). Hits
+ * report query indices within the request. *request_id (may be NULL) gets
+ * its id (ids count up from 1). */
+ifa_status ifa_server_submit(ifa_server *srv, uint32_t n, const uint8_t *const *seq,
+                             const uint32_t *len, const int32_t *max_subs, const int32_t *max_n,
+                             uint64_t *request_id);
+
+/* Admit what fits, then scan the chunk under the cursor for every admitted
+ * request and advance the cursor. Blocks until the chunk's hits are routed.
+ * Does nothing when no request is admitted. */
+ifa_status ifa_server_step(ifa_server *srv, uint32_t *n_active, uint32_t *n_done_waiting);
+
+/* The oldest completed request not yet taken: *request_id (0 if none) and
+ * its hit count. */
+ifa_status ifa_server_poll(ifa_server *srv, uint64_t *request_id, uint64_t *n_hits);
+
+/* Copy the hits of the request ifa_server_poll returned (cap >= its hit
+ * count) in reference order, and release it. */
+ifa_status ifa_server_take(ifa_server *srv, uint64_t request_id, ifa_hit *out, uint64_t cap);
+
+ifa_status ifa_server_info(const ifa_server *srv, ifa_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

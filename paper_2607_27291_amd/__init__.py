@@ -20,7 +20,9 @@ __all__ = [
     "ifa_query_stats", "ifa_ref_load", "ifa_scan_resident", "ifa_ref_release", "ifa_ref_info",
     "ifa_get_stats", "ifa_reset_stats", "ifa_variant_count", "ifa_variant_info",
     "ifa_set_variant", "ifa_get_variant", "ifa_autotune", "ifa_query_partition",
-    "ifa_device_footprint", "Scanner", "collect_all",
+    "ifa_device_footprint", "ifa_server_config_default", "ifa_server_create",
+    "ifa_server_destroy", "ifa_server_submit", "ifa_server_step", "ifa_server_poll",
+    "ifa_server_take", "ifa_server_info", "Scanner", "Server", "collect_all",
 ]
 
 IFA_ABI_VERSION = 1
@@ -50,6 +52,19 @@ class IfaStats(ctypes.Structure):
                 ("hits", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
                 ("h2d_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
                 ("filter_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64)]
+
+
+class IfaServerConfig(ctypes.Structure):
+    _fields_ = [("max_active_queries", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("hit_budget", ctypes.c_uint64)]
+
+
+class IfaServerStats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_uint32), ("active", ctypes.c_uint32),
+                ("active_queries", ctypes.c_uint32), ("done_waiting", ctypes.c_uint32),
+                ("steps", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("step_ms", ctypes.c_double), ("cursor", ctypes.c_uint32),
+                ("chunks", ctypes.c_uint32)]
 
 
 class IfaError(RuntimeError):
@@ -114,6 +129,22 @@ def lib():
         L.ifa_query_partition.restype = st
         L.ifa_device_footprint.argtypes = [vp, ctypes.POINTER(u64)]
         L.ifa_device_footprint.restype = st
+        L.ifa_server_config_default.argtypes = [ctypes.POINTER(IfaServerConfig)]
+        L.ifa_server_config_default.restype = None
+        L.ifa_server_create.argtypes = [vp, ctypes.POINTER(IfaServerConfig), ctypes.POINTER(vp)]
+        L.ifa_server_create.restype = st
+        L.ifa_server_destroy.argtypes = [vp]
+        L.ifa_server_destroy.restype = None
+        L.ifa_server_submit.argtypes = [vp, u32, vp, vp, vp, vp, ctypes.POINTER(u64)]
+        L.ifa_server_submit.restype = st
+        L.ifa_server_step.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32)]
+        L.ifa_server_step.restype = st
+        L.ifa_server_poll.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.ifa_server_poll.restype = st
+        L.ifa_server_take.argtypes = [vp, u64, vp, u64]
+        L.ifa_server_take.restype = st
+        L.ifa_server_info.argtypes = [vp, ctypes.POINTER(IfaServerStats)]
+        L.ifa_server_info.restype = st
         _lib = L
     return _lib
 
@@ -304,6 +335,98 @@ def ifa_device_footprint(ctx) -> int:
     return b.value
 
 
+def ifa_server_config_default() -> IfaServerConfig:
+    cfg = IfaServerConfig()
+    lib().ifa_server_config_default(ctypes.byref(cfg))
+    return cfg
+
+
+def ifa_server_create(ctx, cfg: IfaServerConfig | None = None):
+    srv = ctypes.c_void_p()
+    _check(ctx, lib().ifa_server_create(ctx, ctypes.byref(cfg) if cfg is not None else None,
+                                        ctypes.byref(srv)))
+    return srv
+
+
+def ifa_server_destroy(srv):
+    lib().ifa_server_destroy(srv)
+
+
+def ifa_server_submit(srv, ctx, queries, max_subs, max_n=None) -> int:
+    sa = _SeqArray(queries, np.uint32)
+    ks = np.ascontiguousarray(list(max_subs) or [0], dtype=np.int32)
+    mn = None if max_n is None else np.ascontiguousarray(list(max_n) or [0], dtype=np.int32)
+    rid = ctypes.c_uint64()
+    _check(ctx, lib().ifa_server_submit(srv, sa.n, sa.ptrs, sa.lens.ctypes.data, ks.ctypes.data,
+                                        None if mn is None else mn.ctypes.data,
+                                        ctypes.byref(rid)))
+    return rid.value
+
+
+def ifa_server_step(srv, ctx):
+    a, d = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(ctx, lib().ifa_server_step(srv, ctypes.byref(a), ctypes.byref(d)))
+    return a.value, d.value
+
+
+def ifa_server_poll(srv, ctx):
+    rid, n = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(ctx, lib().ifa_server_poll(srv, ctypes.byref(rid), ctypes.byref(n)))
+    return rid.value, n.value
+
+
+def ifa_server_take(srv, ctx, request_id: int, n_hits: int) -> np.ndarray:
+    out = np.zeros(max(n_hits, 1), dtype=HIT_DTYPE)
+    _check(ctx, lib().ifa_server_take(srv, request_id, out.ctypes.data, n_hits))
+    return out[:n_hits]
+
+
+def ifa_server_info(srv) -> dict:
+    st = IfaServerStats()
+    lib().ifa_server_info(srv, ctypes.byref(st))
+    return {k: getattr(st, k) for k, _ in IfaServerStats._fields_}
+
+
+class Server:
+    """Continuous-batching server over a Scanner's resident reference."""
+
+    def __init__(self, scanner, max_active_queries=4096, hit_budget=1 << 26):
+        self.scanner = scanner
+        cfg = ifa_server_config_default()
+        cfg.max_active_queries = max_active_queries
+        cfg.hit_budget = hit_budget
+        self.srv = ifa_server_create(scanner.ctx, cfg)
+
+    def close(self):
+        if self.srv:
+            ifa_server_destroy(self.srv)
+            self.srv = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, queries, max_subs, max_n=None) -> int:
+        return ifa_server_submit(self.srv, self.scanner.ctx, queries, max_subs, max_n)
+
+    def step(self):
+        return ifa_server_step(self.srv, self.scanner.ctx)
+
+    def completed(self):
+        """Take every completed request: list of (request_id, hits)."""
+        out = []
+        while True:
+            rid, n = ifa_server_poll(self.srv, self.scanner.ctx)
+            if rid == 0:
+                return out
+            out.append((rid, ifa_server_take(self.srv, self.scanner.ctx, rid, n)))
+
+    def info(self) -> dict:
+        return ifa_server_info(self.srv)
+
+
 def collect_all(ctx, batch: int = 1 << 20) -> np.ndarray:
     """Drain every held hit (two-call pattern over ifa_collect_hits)."""
     parts = []
@@ -368,6 +491,9 @@ class Scanner:
 
     def scan_resident(self):
         ifa_scan_resident(self.ctx)
+
+    def resident_bases(self) -> int:
+        return ifa_ref_info(self.ctx)[0]
 
     def stats(self) -> dict:
         return ifa_get_stats(self.ctx)

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <functional>
 #include <memory>
 #include <new>
@@ -780,6 +781,134 @@ bool nothing_pending(ifa_ctx *c)
     return c->drain_pos >= c->hits.size();
 }
 
+// ---------------------------------------------------------------------------
+// query tables
+// ---------------------------------------------------------------------------
+
+void validate_queries(uint32_t n, const uint8_t *const *seq, const uint32_t *len,
+                      const int32_t *max_subs, const int32_t *max_n)
+{
+    if (n > 0 && (!seq || !len || !max_subs)) fail(IFA_E_INVALID, "NULL argument");
+    for (uint32_t j = 0; j < n; j++) {
+        if (len[j] == 0 || len[j] > IFA_MAX_QUERY_LEN)
+            fail(IFA_E_TOO_LONG, "query " + std::to_string(j) + " has length " +
+                                     std::to_string(len[j]) + " (allowed 1..256)");
+        if (!seq[j]) fail(IFA_E_INVALID, "NULL query pointer");
+        if (max_subs[j] < 0) fail(IFA_E_INVALID, "negative max_subs");
+        if (max_n && max_n[j] < 0) fail(IFA_E_INVALID, "negative max_n");
+    }
+}
+
+// Pack every selected strand of n queries into descriptors and plane words,
+// appending to qs / words; query j gets qid qid_base + j.
+void pack_query_strands(uint32_t strands, uint32_t n, const uint8_t *const *seq,
+                        const uint32_t *len, const int32_t *max_subs, const int32_t *max_n,
+                        uint32_t qid_base, std::vector<QSDesc> &qs, std::vector<uint32_t> &words,
+                        uint32_t &lmax)
+{
+    for (uint32_t j = 0; j < n; j++) {
+        const uint32_t L = len[j];
+        lmax = std::max(lmax, L);
+        uint8_t code[IFA_MAX_QUERY_LEN];
+        for (uint32_t i = 0; i < L; i++) code[i] = kCode.c[seq[j][i]];
+        for (uint32_t s = 0; s < 2; s++) {
+            if (!(strands & (1u << s))) continue;
+            QSDesc d{};
+            d.qid = qid_base + j;
+            d.len = (uint16_t)L;
+            d.strand = (uint8_t)s;
+            d.nw = (uint8_t)((L + 31) / 32);
+            d.k = (uint16_t)std::min<int64_t>(max_subs[j], L);
+            int64_t mn = max_n ? max_n[j] : (int64_t)(L / 4);
+            d.maxn = (uint16_t)std::min<int64_t>(mn, L);
+            d.woff = (uint32_t)words.size();
+            words.resize(words.size() + 3u * d.nw, 0u);
+            uint32_t *W = words.data() + d.woff;
+            for (uint32_t i = 0; i < L; i++) {
+                // strand 1: reverse complement; complementing flips the hi
+                // bit of the code (A<->T, C<->G), N stays N
+                uint32_t v = s == 0 ? code[i] : code[L - 1 - i];
+                if (s == 1 && v < 4) v ^= 2u;
+                uint32_t t = i >> 5, bit = 1u << (i & 31);
+                if (v == 4) {
+                    W[3 * t + 2] |= bit;
+                } else {
+                    if (v & 2) W[3 * t] |= bit;
+                    if (v & 1) W[3 * t + 1] |= bit;
+                }
+            }
+            d.qh0 = W[0];
+            d.ql0 = W[1];
+            d.qn0 = W[2];
+            // the filter counts mismatches over the first min(L, 32) bases
+            d.thr = d.k;
+            qs.push_back(d);
+        }
+    }
+}
+
+// Make qs / words the context's query table. Partition: strands whose filter
+// is expected to pass a window in most waves (P(Bin(min(L, 32), 3/4) <= k) x
+// 1024 windows >= 1/2 for iid bases) are dense and skip the filter's work
+// list. Sparse strands go first, then dense ones; each group sorted by L
+// descending (the kernels mask their cached slices in place as L drops),
+// then by k. n_queries sizes the
+// count+digest accumulators, which this resets.
+void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t> &&words,
+                     uint32_t n_queries, uint32_t lmax)
+{
+    std::vector<uint8_t> dense(qs.size());
+    for (size_t i = 0; i < qs.size(); i++)
+        dense[i] = qs[i].thr >= 32u ||
+                   binom_cdf(std::min<uint32_t>(qs[i].len, 32u), 0.75, qs[i].k) * 1024.0 >= 0.5;
+    std::vector<size_t> order(qs.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+        if (dense[x] != dense[y]) return dense[x] < dense[y];
+        const QSDesc &a = qs[x], &b = qs[y];
+        if (a.len != b.len) return a.len > b.len;
+        return a.k < b.k;
+    });
+    std::vector<QSDesc> sorted;
+    sorted.reserve(qs.size());
+    uint32_t n_sparse = 0;
+    for (size_t i : order) {
+        sorted.push_back(qs[i]);
+        if (!dense[i]) n_sparse++;
+    }
+    qs.swap(sorted);
+    if (c->d_qs.n < qs.size() || !c->d_qs.p)
+        c->d_qs.alloc(std::max<size_t>(qs.size(), 1), "query table");
+    if (c->d_qwords.n < words.size() || !c->d_qwords.p)
+        c->d_qwords.alloc(std::max<size_t>(words.size(), 1), "query words");
+    if (!qs.empty())
+        hip_check(hipMemcpy(c->d_qs.p, qs.data(), qs.size() * sizeof(QSDesc),
+                            hipMemcpyHostToDevice),
+                  "upload queries");
+    if (!words.empty())
+        hip_check(hipMemcpy(c->d_qwords.p, words.data(), words.size() * sizeof(uint32_t),
+                            hipMemcpyHostToDevice),
+                  "upload query words");
+    if (c->cfg.sink == IFA_SINK_COUNT_DIGEST) {
+        const size_t need = (size_t)std::max<uint32_t>(n_queries, 1) * kStripes;
+        if (c->d_qcount.n < need) {
+            c->d_qcount.alloc(need, "query counters");
+            c->d_qdigest.alloc(need, "query digests");
+        }
+        hip_check(hipMemset(c->d_qcount.p, 0, need * sizeof(unsigned long long)), "memset");
+        hip_check(hipMemset(c->d_qdigest.p, 0, need * sizeof(unsigned long long)), "memset");
+    }
+    c->h_qs = std::move(qs);
+    c->n_sparse = n_sparse;
+    c->h_qwords = std::move(words);
+    c->n_queries = n_queries;
+    c->lmax = std::max<uint32_t>(lmax, 1);
+    c->have_queries = true;
+    c->hits.clear();
+    c->drain_pos = 0;
+    c->hits_sorted = true;
+}
+
 // Autotune cache key: device architecture, query-strand count band (log2),
 // longest query in words, threshold band. Tile choice depends on these.
 std::string tune_key(ifa_ctx *c)
@@ -951,113 +1080,14 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
 {
     if (!c) return IFA_E_INVALID;
     return guarded(c, [&]() {
-        if (n > 0 && (!seq || !len || !max_subs)) fail(IFA_E_INVALID, "NULL argument");
         if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
-        for (uint32_t j = 0; j < n; j++) {
-            if (len[j] == 0 || len[j] > IFA_MAX_QUERY_LEN)
-                fail(IFA_E_TOO_LONG, "query " + std::to_string(j) + " has length " +
-                                         std::to_string(len[j]) + " (allowed 1..256)");
-            if (!seq[j]) fail(IFA_E_INVALID, "NULL query pointer");
-            if (max_subs[j] < 0) fail(IFA_E_INVALID, "negative max_subs");
-            if (max_n && max_n[j] < 0) fail(IFA_E_INVALID, "negative max_n");
-        }
+        validate_queries(n, seq, len, max_subs, max_n);
         use_device(c);
         std::vector<QSDesc> qs;
         std::vector<uint32_t> words;
         uint32_t lmax = 0;
-        for (uint32_t j = 0; j < n; j++) {
-            const uint32_t L = len[j];
-            lmax = std::max(lmax, L);
-            uint8_t code[IFA_MAX_QUERY_LEN];
-            for (uint32_t i = 0; i < L; i++) code[i] = kCode.c[seq[j][i]];
-            for (uint32_t s = 0; s < 2; s++) {
-                if (!(c->cfg.strands & (1u << s))) continue;
-                QSDesc d{};
-                d.qid = j;
-                d.len = (uint16_t)L;
-                d.strand = (uint8_t)s;
-                d.nw = (uint8_t)((L + 31) / 32);
-                d.k = (uint16_t)std::min<int64_t>(max_subs[j], L);
-                int64_t mn = max_n ? max_n[j] : (int64_t)(L / 4);
-                d.maxn = (uint16_t)std::min<int64_t>(mn, L);
-                d.woff = (uint32_t)words.size();
-                words.resize(words.size() + 3u * d.nw, 0u);
-                uint32_t *W = words.data() + d.woff;
-                for (uint32_t i = 0; i < L; i++) {
-                    // strand 1: reverse complement; complementing flips the
-                    // hi bit of the code (A<->T, C<->G), N stays N
-                    uint32_t v = s == 0 ? code[i] : code[L - 1 - i];
-                    if (s == 1 && v < 4) v ^= 2u;
-                    uint32_t t = i >> 5, bit = 1u << (i & 31);
-                    if (v == 4) {
-                        W[3 * t + 2] |= bit;
-                    } else {
-                        if (v & 2) W[3 * t] |= bit;
-                        if (v & 1) W[3 * t + 1] |= bit;
-                    }
-                }
-                d.qh0 = W[0];
-                d.ql0 = W[1];
-                d.qn0 = W[2];
-                // the filter counts mismatches over the first min(L, 32) bases
-                d.thr = d.k;
-                qs.push_back(d);
-            }
-        }
-        // Partition: strands whose filter is expected to pass a window in most
-        // waves (P(Bin(min(L, 32), 3/4) <= k) x 1024 windows >= 1/2 for iid
-        // bases) are dense and skip the filter's work list. Sparse strands go
-        // first, sorted by L descending (the filter masks its cached slices in
-        // place as L drops), then by k.
-        std::vector<uint8_t> dense(qs.size());
-        for (size_t i = 0; i < qs.size(); i++)
-            dense[i] = qs[i].thr >= 32u ||
-                       binom_cdf(std::min<uint32_t>(qs[i].len, 32u), 0.75, qs[i].k) * 1024.0 >= 0.5;
-        std::vector<size_t> order(qs.size());
-        for (size_t i = 0; i < order.size(); i++) order[i] = i;
-        std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-            if (dense[x] != dense[y]) return dense[x] < dense[y];
-            const QSDesc &a = qs[x], &b = qs[y];
-            if (!dense[x]) {
-                if (a.len != b.len) return a.len > b.len;
-                return a.k < b.k;
-            }
-            if (a.nw != b.nw) return a.nw < b.nw;
-            return a.k < b.k;
-        });
-        std::vector<QSDesc> sorted;
-        sorted.reserve(qs.size());
-        uint32_t n_sparse = 0;
-        for (size_t i : order) {
-            sorted.push_back(qs[i]);
-            if (!dense[i]) n_sparse++;
-        }
-        qs.swap(sorted);
-        c->d_qs.alloc(std::max<size_t>(qs.size(), 1), "query table");
-        c->d_qwords.alloc(std::max<size_t>(words.size(), 1), "query words");
-        if (!qs.empty())
-            hip_check(hipMemcpy(c->d_qs.p, qs.data(), qs.size() * sizeof(QSDesc),
-                                hipMemcpyHostToDevice),
-                      "upload queries");
-        if (!words.empty())
-            hip_check(hipMemcpy(c->d_qwords.p, words.data(), words.size() * sizeof(uint32_t),
-                                hipMemcpyHostToDevice),
-                      "upload query words");
-        c->d_qcount.alloc((size_t)std::max<uint32_t>(n, 1) * kStripes, "query counters");
-        c->d_qdigest.alloc((size_t)std::max<uint32_t>(n, 1) * kStripes, "query digests");
-        hip_check(hipMemset(c->d_qcount.p, 0, c->d_qcount.n * sizeof(unsigned long long)),
-                  "memset");
-        hip_check(hipMemset(c->d_qdigest.p, 0, c->d_qdigest.n * sizeof(unsigned long long)),
-                  "memset");
-        c->h_qs = std::move(qs);
-        c->n_sparse = n_sparse;
-        c->h_qwords = std::move(words);
-        c->n_queries = n;
-        c->lmax = std::max<uint32_t>(lmax, 1);
-        c->have_queries = true;
-        c->hits.clear();
-        c->drain_pos = 0;
-        c->hits_sorted = true;
+        pack_query_strands(c->cfg.strands, n, seq, len, max_subs, max_n, 0, qs, words, lmax);
+        install_queries(c, std::move(qs), std::move(words), n, lmax);
     });
 }
 
@@ -1409,6 +1439,264 @@ ifa_status ifa_reset_stats(ifa_ctx *c)
 {
     if (!c) return IFA_E_INVALID;
     std::memset(&c->st, 0, sizeof c->st);
+    return IFA_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving loop: continuous batching over a device-resident reference
+// ===========================================================================
+//
+// Requests (query sets with their own thresholds) arrive at any time. A step
+// scans one resident chunk, the one under a rotating cursor, with the union
+// of the query strands of every admitted request, so the work of different
+// requests overlaps in the same kernels. A request admitted at step s sees
+// the chunks s, s+1, ... (mod the chunk count) and completes after one full
+// revolution; its hits are then sorted into reference order. Admission keeps
+// the active query count under a cap (bounding step time) and the expected
+// hits of the active requests under a record budget (device and host memory
+// for hits); a request alone on the server is always admitted.
+
+namespace {
+
+struct SrvRequest {
+    uint64_t id = 0;
+    uint32_t n_queries = 0;
+    std::vector<QSDesc> qs;           // qid = query index within the request
+    std::vector<uint32_t> words;
+    uint32_t lmax = 0;
+    uint32_t chunks_left = 0;
+    uint64_t est_hits = 0;
+    std::vector<ifa_hit> hits;
+};
+
+}  // namespace
+
+struct ifa_server {
+    ifa_ctx *ctx = nullptr;
+    uint32_t max_active_queries = 0;
+    uint64_t hit_budget = 0;
+    std::deque<std::unique_ptr<SrvRequest>> pending;
+    std::vector<std::unique_ptr<SrvRequest>> active;
+    std::deque<std::unique_ptr<SrvRequest>> done;
+    uint32_t active_queries = 0;
+    uint64_t active_est_hits = 0;
+    uint32_t cursor = 0;
+    uint64_t next_id = 1;
+    uint64_t steps = 0;
+    uint64_t completed = 0;
+    double step_ms = 0.0;
+};
+
+namespace {
+
+// Expected hits of a query set against `bases` reference bases for iid
+// uniform bases (each base matches with probability 1/4).
+uint64_t expected_hits(const SrvRequest &r, uint64_t bases)
+{
+    double e = 0.0;
+    for (const QSDesc &d : r.qs) e += (double)bases * binom_cdf(d.len, 0.75, d.k);
+    return (uint64_t)(e + 1.0);
+}
+
+void server_admit(ifa_server *S)
+{
+    while (!S->pending.empty()) {
+        SrvRequest &r = *S->pending.front();
+        const bool alone = S->active.empty();
+        if (!alone && (S->active_queries + r.n_queries > S->max_active_queries ||
+                       S->active_est_hits + r.est_hits > S->hit_budget))
+            break;
+        r.chunks_left = (uint32_t)S->ctx->resident.size();
+        S->active_queries += r.n_queries;
+        S->active_est_hits += r.est_hits;
+        S->active.push_back(std::move(S->pending.front()));
+        S->pending.pop_front();
+    }
+}
+
+void server_step(ifa_server *S)
+{
+    ifa_ctx *c = S->ctx;
+    server_admit(S);
+    if (S->active.empty()) return;
+    const double t0 = now_ms();
+    // one query table for every active request: qid = slot base + local index
+    std::vector<QSDesc> qs;
+    std::vector<uint32_t> words;
+    std::vector<uint32_t> owner;      // global qid -> index into active
+    std::vector<uint32_t> base;       // per active request: first global qid
+    uint32_t lmax = 0;
+    for (size_t i = 0; i < S->active.size(); i++) {
+        const SrvRequest &r = *S->active[i];
+        const uint32_t qb = (uint32_t)owner.size();
+        const uint32_t wb = (uint32_t)words.size();
+        base.push_back(qb);
+        for (QSDesc d : r.qs) {
+            d.qid += qb;
+            d.woff += wb;
+            qs.push_back(d);
+        }
+        words.insert(words.end(), r.words.begin(), r.words.end());
+        owner.insert(owner.end(), r.n_queries, (uint32_t)i);
+        lmax = std::max(lmax, r.lmax);
+    }
+    install_queries(c, std::move(qs), std::move(words), (uint32_t)owner.size(), lmax);
+    DevChunk *ch = c->resident[S->cursor].get();
+    c->st.bases += ch->len - ch->own_from;
+    submit_job(c, ch);
+    retire_all(c);
+    // route the chunk's hits to their requests
+    for (const ifa_hit &h : c->hits) {
+        const uint32_t i = owner[h.query];
+        ifa_hit local = h;
+        local.query = h.query - base[i];
+        S->active[i]->hits.push_back(local);
+    }
+    c->hits.clear();
+    c->drain_pos = 0;
+    c->hits_sorted = true;
+    S->cursor = (S->cursor + 1) % (uint32_t)c->resident.size();
+    S->steps++;
+    // requests that have seen every chunk are complete
+    std::vector<std::unique_ptr<SrvRequest>> still;
+    for (auto &rp : S->active) {
+        if (--rp->chunks_left == 0) {
+            std::sort(rp->hits.begin(), rp->hits.end(), [](const ifa_hit &a, const ifa_hit &b) {
+                if (a.contig != b.contig) return a.contig < b.contig;
+                if (a.pos != b.pos) return a.pos < b.pos;
+                if (a.strand != b.strand) return a.strand < b.strand;
+                return a.query < b.query;
+            });
+            S->active_queries -= rp->n_queries;
+            S->active_est_hits -= rp->est_hits;
+            S->completed++;
+            S->done.push_back(std::move(rp));
+        } else {
+            still.push_back(std::move(rp));
+        }
+    }
+    S->active.swap(still);
+    S->step_ms += now_ms() - t0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ifa_server_config_default(ifa_server_config *cfg)
+{
+    if (!cfg) return;
+    cfg->max_active_queries = 4096;
+    cfg->reserved = 0;
+    cfg->hit_budget = 1ull << 26;
+}
+
+ifa_status ifa_server_create(ifa_ctx *c, const ifa_server_config *cfg_in, ifa_server **out)
+{
+    if (!c || !out) return IFA_E_INVALID;
+    *out = nullptr;
+    return guarded(c, [&]() {
+        if (c->resident.empty()) fail(IFA_E_STATE, "no resident reference: call ifa_ref_load");
+        if (c->cfg.sink != IFA_SINK_RECORDS) fail(IFA_E_STATE, "serving needs the records sink");
+        if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
+        ifa_server_config cfg;
+        if (cfg_in) cfg = *cfg_in; else ifa_server_config_default(&cfg);
+        if (cfg.max_active_queries == 0 || cfg.hit_budget == 0 || cfg.reserved != 0)
+            fail(IFA_E_INVALID, "bad server config");
+        ifa_server *S = new ifa_server();
+        S->ctx = c;
+        S->max_active_queries = cfg.max_active_queries;
+        S->hit_budget = cfg.hit_budget;
+        *out = S;
+    });
+}
+
+void ifa_server_destroy(ifa_server *S)
+{
+    if (!S) return;
+    if (S->ctx) {
+        (void)hipSetDevice(S->ctx->cfg.device);
+        if (S->ctx->comp_s) (void)hipStreamSynchronize(S->ctx->comp_s);
+    }
+    delete S;
+}
+
+ifa_status ifa_server_submit(ifa_server *S, uint32_t n, const uint8_t *const *seq,
+                             const uint32_t *len, const int32_t *max_subs, const int32_t *max_n,
+                             uint64_t *request_id)
+{
+    if (!S) return IFA_E_INVALID;
+    ifa_ctx *c = S->ctx;
+    return guarded(c, [&]() {
+        if (n == 0) fail(IFA_E_INVALID, "empty request");
+        validate_queries(n, seq, len, max_subs, max_n);
+        std::unique_ptr<SrvRequest> r(new SrvRequest());
+        r->id = S->next_id++;
+        r->n_queries = n;
+        pack_query_strands(c->cfg.strands, n, seq, len, max_subs, max_n, 0, r->qs, r->words,
+                           r->lmax);
+        r->est_hits = expected_hits(*r, c->resident_bases);
+        if (request_id) *request_id = r->id;
+        S->pending.push_back(std::move(r));
+    });
+}
+
+ifa_status ifa_server_step(ifa_server *S, uint32_t *n_active, uint32_t *n_done_waiting)
+{
+    if (!S) return IFA_E_INVALID;
+    ifa_ctx *c = S->ctx;
+    return guarded(c, [&]() {
+        use_device(c);
+        server_step(S);
+        if (n_active) *n_active = (uint32_t)S->active.size();
+        if (n_done_waiting) *n_done_waiting = (uint32_t)S->done.size();
+    });
+}
+
+ifa_status ifa_server_poll(ifa_server *S, uint64_t *request_id, uint64_t *n_hits)
+{
+    if (!S || !request_id) return IFA_E_INVALID;
+    if (S->done.empty()) {
+        *request_id = 0;
+        if (n_hits) *n_hits = 0;
+        return IFA_OK;
+    }
+    *request_id = S->done.front()->id;
+    if (n_hits) *n_hits = S->done.front()->hits.size();
+    return IFA_OK;
+}
+
+ifa_status ifa_server_take(ifa_server *S, uint64_t request_id, ifa_hit *out, uint64_t cap)
+{
+    if (!S) return IFA_E_INVALID;
+    ifa_ctx *c = S->ctx;
+    return guarded(c, [&]() {
+        if (S->done.empty() || S->done.front()->id != request_id)
+            fail(IFA_E_STATE, "request is not the next completed one (call ifa_server_poll)");
+        SrvRequest &r = *S->done.front();
+        if (cap < r.hits.size()) fail(IFA_E_INVALID, "output array too small");
+        if (!r.hits.empty()) {
+            if (!out) fail(IFA_E_INVALID, "NULL output");
+            std::memcpy(out, r.hits.data(), r.hits.size() * sizeof(ifa_hit));
+        }
+        S->done.pop_front();
+    });
+}
+
+ifa_status ifa_server_info(const ifa_server *S, ifa_server_stats *out)
+{
+    if (!S || !out) return IFA_E_INVALID;
+    out->pending = (uint32_t)S->pending.size();
+    out->active = (uint32_t)S->active.size();
+    out->active_queries = S->active_queries;
+    out->done_waiting = (uint32_t)S->done.size();
+    out->steps = S->steps;
+    out->completed = S->completed;
+    out->step_ms = S->step_ms;
+    out->cursor = S->cursor;
+    out->chunks = (uint32_t)S->ctx->resident.size();
     return IFA_OK;
 }
 

@@ -254,6 +254,29 @@ __device__ void exact_plain(const ScanArgs &a, const QS &d, const Lane &ln, uint
     }
 }
 
+// Sum cnt / dig over the wave and add them once, to stripe `stripe` of the
+// query's count+digest accumulators. Called by all 64 lanes.
+__device__ __forceinline__ void wave_add_stats(const ScanArgs &a, const QS &d, uint32_t cnt,
+                                               uint64_t dig, uint32_t stripe)
+{
+    if (!__any(cnt != 0u)) return;
+    uint32_t dlo = (uint32_t)dig, dhi = (uint32_t)(dig >> 32);
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t c_o = __shfl_xor(cnt, o);
+        const uint32_t lo_o = __shfl_xor(dlo, o);
+        const uint32_t hi_o = __shfl_xor(dhi, o);
+        const uint64_t sum = ((uint64_t)dhi << 32 | dlo) + ((uint64_t)hi_o << 32 | lo_o);
+        cnt += c_o;
+        dlo = (uint32_t)sum;
+        dhi = (uint32_t)(sum >> 32);
+    }
+    if ((threadIdx.x & 63u) == 0u) {
+        const uint32_t slot = d.qid * kStripes + stripe % kStripes;
+        atomicAdd(&a.q_count[slot], (unsigned long long)cnt);
+        atomicAdd(&a.q_digest[slot], ((unsigned long long)dhi << 32) | dlo);
+    }
+}
+
 // One query strand against the lane's windows after the filter: exact test
 // where `cand`, then (count+digest) a wave-wide sum added once per wave to
 // stripe `stripe` of the query's accumulators. Called by all 64 lanes.
@@ -282,23 +305,7 @@ __device__ __forceinline__ void resolve(const ScanArgs &a, const QS &d, Lane &ln
             exact_serial<W>(a, d, ln, cnt, dig);
         }
     }
-    if (a.sink == kSinkCountDigest) {
-        uint32_t dlo = (uint32_t)dig, dhi = (uint32_t)(dig >> 32);
-        for (int o = 32; o >= 1; o >>= 1) {
-            const uint32_t c_o = __shfl_xor(cnt, o);
-            const uint32_t lo_o = __shfl_xor(dlo, o);
-            const uint32_t hi_o = __shfl_xor(dhi, o);
-            const uint64_t sum = ((uint64_t)dhi << 32 | dlo) + ((uint64_t)hi_o << 32 | lo_o);
-            cnt += c_o;
-            dlo = (uint32_t)sum;
-            dhi = (uint32_t)(sum >> 32);
-        }
-        if ((threadIdx.x & 63u) == 0u && cnt) {
-            const uint32_t slot = d.qid * kStripes + stripe % kStripes;
-            atomicAdd(&a.q_count[slot], (unsigned long long)cnt);
-            atomicAdd(&a.q_digest[slot], ((unsigned long long)dhi << 32) | dlo);
-        }
-    }
+    if (a.sink == kSinkCountDigest) wave_add_stats(a, d, cnt, dig, stripe);
 }
 
 // Minimum over the lane's W windows of the filter count for one query strand
@@ -495,16 +502,118 @@ __global__ __launch_bounds__(256) void scan_resolve_kernel(ScanArgs a)
     }
 }
 
-// Dense query strands [n_sparse, n_qs): every lane resolves them directly.
+// Dense query strands [n_sparse, n_qs): strands whose first-word filter
+// passes windows in most waves (short queries with high k, long queries with
+// k >= 16). Each lane counts its W windows' mismatches word by word, all
+// windows at once; after each 32-base word the wave stops with this strand
+// once no window of any lane is still within k (the paper's early exit, per
+// word). Windows within k after the last word are hits; plain lanes emit them
+// here. Other lanes (N, piece end, carried prefix, chunk tail) are left to
+// scan_dense_cold_kernel, so that their code does not weigh on this loop's
+// registers. Dense strands come sorted by L descending so the cached word-0
+// slices can be masked in place.
+template <int W>
+__device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, Lane &ln,
+                                             const uint32_t (&sh)[W], const uint32_t (&sl)[W],
+                                             uint32_t wave)
+{
+    if (ln.plain < 0) ln.plain = (ln.active && lane_is_plain(a, ln)) ? 1 : 0;
+    const bool plain = ln.plain == 1;
+    uint32_t m[W];
+    uint32_t mn = 0xffffffffu;
+#pragma unroll
+    for (int b = 0; b < W; b++) {
+        uint32_t diff = __builtin_amdgcn_bitop3_b32(sh[b], d.qh, d.qn, IFA_XOR_OR);
+        diff = __builtin_amdgcn_bitop3_b32(diff, sl[b], d.ql, IFA_OR_XOR);
+        m[b] = __popc(diff);
+        mn = min(mn, m[b]);
+    }
+    const IFA_CONST uint32_t *qw = as_const(a.qwords) + d.woff;
+    uint32_t hp = ln.h1, lp = ln.l1;
+    for (uint32_t t = 1; t < d.nw; t++) {
+        if (!__any(plain && mn <= d.k)) break;
+        const uint32_t x = ln.w + t + 1;
+        const uint32_t hn = a.hi[x], lnw = a.lo[x];
+        const uint32_t qh = qw[3 * t], ql = qw[3 * t + 1], qn = qw[3 * t + 2];
+        const uint32_t lmask = low_mask(d.len - 32u * t);
+        mn = 0xffffffffu;
+#pragma unroll
+        for (int b = 0; b < W; b++) {
+            const uint32_t s = ln.off + (uint32_t)b;
+            uint32_t diff = __builtin_amdgcn_bitop3_b32(funnel(hn, hp, s), qh, qn, IFA_XOR_OR);
+            diff = __builtin_amdgcn_bitop3_b32(diff, funnel(lnw, lp, s), ql, IFA_OR_XOR);
+            m[b] += __popc(diff & lmask);
+            mn = min(mn, m[b]);
+        }
+        hp = hn;
+        lp = lnw;
+    }
+    uint32_t cnt = 0;
+    uint64_t dig = 0;
+    if (plain && mn <= d.k) {
+        const uint64_t first = 32ull * ln.w + ln.off;
+        const Piece pc = a.pieces[find_piece(a, first)];
+        const uint32_t pos0 = (uint32_t)(pc.contig_off + (first - pc.start));
+#pragma unroll
+        for (int b = 0; b < W; b++) cnt += m[b] <= d.k ? 1u : 0u;
+        if (a.sink == kSinkRecords) {
+            unsigned long long slot = atomicAdd(a.hit_count, (unsigned long long)cnt);
+#pragma unroll
+            for (int b = 0; b < W; b++) {
+                if (m[b] <= d.k) {
+                    write_record(a, slot, d, pc.contig, pos0 + b, m[b], 0u);
+                    slot++;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < W; b++)
+                if (m[b] <= d.k) dig += hit_hash(pc.contig, pos0 + b, d.strand, m[b], 0u);
+        }
+    }
+    if (a.sink == kSinkCountDigest) wave_add_stats(a, d, cnt, dig, wave);
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
 {
     const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
     Lane ln = make_lane<W>(a, gl);
     const uint32_t wave = gl >> 6;
+    uint32_t sh[W], sl[W];
+#pragma unroll
+    for (int b = 0; b < W; b++) {
+        sh[b] = funnel(ln.h1, ln.h0, ln.off + (uint32_t)b);
+        sl[b] = funnel(ln.l1, ln.l0, ln.off + (uint32_t)b);
+    }
+    uint32_t cur_len = 32;
     for (uint32_t q = a.n_sparse; q < a.n_qs; q++) {
         const QS d = load_qs(a, q);
-        resolve<W>(a, d, ln, filter_cand_words<W>(a, d, ln), wave);
+        if (d.len < cur_len) {
+            mask_slices<W>(sh, sl, d.len);
+            cur_len = d.len;
+        }
+        dense_strand<W>(a, d, ln, sh, sl, wave);
+    }
+}
+
+// Dense query strands on the lanes scan_dense_kernel leaves out (an N, a
+// piece end, the carried prefix or the chunk tail among their bases): the
+// exact serial test. Waves without such a lane return at once.
+template <int W>
+__global__ __launch_bounds__(256) void scan_dense_cold_kernel(ScanArgs a)
+{
+    const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
+    Lane ln = make_lane<W>(a, gl);
+    const bool cold = ln.active && !lane_is_plain(a, ln);
+    if (!__any(cold)) return;
+    const uint32_t wave = gl >> 6;
+    for (uint32_t q = a.n_sparse; q < a.n_qs; q++) {
+        const QS d = load_qs(a, q);
+        uint32_t cnt = 0;
+        uint64_t dig = 0;
+        if (cold && filter_cand_words<W>(a, d, ln)) exact_serial<W>(a, d, ln, cnt, dig);
+        if (a.sink == kSinkCountDigest) wave_add_stats(a, d, cnt, dig, wave);
     }
 }
 
@@ -530,13 +639,17 @@ struct VariantDesc {
     void (*filter)(ScanArgs);
     void (*resolve)(ScanArgs);
     void (*dense)(ScanArgs);
+    void (*dense_cold)(ScanArgs);
     uint32_t windows;   // W
     uint32_t qunroll;   // QU
     uint32_t wg;        // filter workgroup size
 };
 
-#define IFA_V(W, QU, WG) \
-    { scan_filter_kernel<W, QU, WG>, scan_resolve_kernel<W>, scan_dense_kernel<W>, W, QU, WG }
+#define IFA_V(W, QU, WG)                                                                 \
+    {                                                                                    \
+        scan_filter_kernel<W, QU, WG>, scan_resolve_kernel<W>, scan_dense_kernel<W>,     \
+            scan_dense_cold_kernel<W>, W, QU, WG                                         \
+    }
 static const VariantDesc kVariantTable[] = {
     IFA_V(32, 1, 256),   // 0: default
     IFA_V(32, 1, 64),    IFA_V(32, 1, 128),  IFA_V(32, 1, 512),
@@ -588,13 +701,16 @@ hipError_t launch_resolve(const ScanArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// Dense part: every lane resolves query strands [n_sparse, n_qs).
+// Dense part: query strands [n_sparse, n_qs) on every lane (plain lanes in
+// the dense kernel, the others in the cold kernel).
 hipError_t launch_dense(const ScanArgs &a, hipStream_t s)
 {
     if (a.w_end <= a.w_begin || a.n_qs <= a.n_sparse) return hipSuccess;
     const VariantDesc &v = pick(a);
     const uint64_t lanes = filter_lanes(a, v);
-    hipLaunchKernelGGL(v.dense, dim3((uint32_t)((lanes + 255) / 256)), dim3(256), 0, s, a);
+    const dim3 grid((uint32_t)((lanes + 255) / 256));
+    hipLaunchKernelGGL(v.dense, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(v.dense_cold, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
