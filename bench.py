@@ -62,6 +62,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1,
                     help="scan kernel variant (default: autotuned on the workload's queries)")
+    ap.add_argument("--calib-valu", action="store_true",
+                    help="measure the issue rate of the scan's VALU instructions and exit")
+    ap.add_argument("--calib-mfma", action="store_true",
+                    help="measure the rate of the fp4 matrix-core instructions and exit")
+    ap.add_argument("--tune-cache", default="",
+                    help="autotuner cache file (a later run with the same queries reuses "
+                         "its choice)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a 1 GiB device copy kernel (calib_copy_kernel) 3 times, "
                          "to scale the HBM byte counters of a profiling run")
@@ -81,6 +88,49 @@ def calib_copy():
         f"({2 * (1 << 30) / ms.value / 1e6:.0f} GB/s)")
 
 
+def calib_valu():
+    """Issue rate of each instruction kind the filter uses (bitop3, alignbit,
+    bcnt, min3, xor): 16 independent chains per thread, 64 waves per CU."""
+    import ctypes
+    from paper_2607_27291_amd import build as b
+    L = ctypes.CDLL(b.CALIB_LIB)
+    L.ifa_calib_valu.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
+    L.ifa_calib_valu.restype = ctypes.c_double
+    out = {}
+    names = ["v_bitop3_b32", "v_alignbit_b32", "v_bcnt_u32_b32", "v_min3_u32", "v_xor_b32",
+             "v_bitop3_b32 (self chains)", "v_xor_b32 + v_bcnt_u32_b32 (self chains)"]
+    for op, name in enumerate(names):
+        for blocks in (256 * 8, 256 * 32):
+            g = L.ifa_calib_valu(op, blocks, 4096)
+            if g < 0:
+                raise RuntimeError(f"VALU probe {name} failed: HIP error {-g}")
+            key = f"{name} @{blocks // 256} blocks/CU"
+            out[key] = round(g / 1e3, 3)
+            log(f"{key}: {g / 1e3:.2f} T lane-ops/s")
+    return out
+
+
+def calib_mfma():
+    """Sustained rate of the fp4 (e2m1) MFMA instructions, four independent
+    accumulators per wave, at 8 and 32 workgroups of 256 threads per CU."""
+    import ctypes
+    from paper_2607_27291_amd import build as b
+    L = ctypes.CDLL(b.CALIB_LIB)
+    L.ifa_calib_mfma.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
+    L.ifa_calib_mfma.restype = ctypes.c_double
+    out = {}
+    for shape, name in enumerate(["v_mfma_scale_f32_32x32x64_f8f6f4 fp4",
+                                  "v_mfma_scale_f32_16x16x128_f8f6f4 fp4"]):
+        for blocks in (256 * 2, 256 * 8):
+            t = L.ifa_calib_mfma(shape, blocks, 2048)
+            if t < 0:
+                raise RuntimeError(f"MFMA probe {name} failed: HIP error {-t}")
+            key = f"{name} @{blocks // 256} blocks/CU"
+            out[key] = round(t, 1)
+            log(f"{key}: {t:.1f} TFLOP/s")
+    return out
+
+
 def choose_variant(ifa, s, args, queries, ks):
     """Autotune the kernel variant on a 64 Mi-base calibration chunk with the
     workload's queries, unless one is given."""
@@ -88,15 +138,21 @@ def choose_variant(ifa, s, args, queries, ks):
         ifa.ifa_set_variant(s.ctx, args.variant)
         return None
     s.load_queries(queries, ks)
-    chosen, ms = ifa.ifa_autotune(s.ctx, 64 << 20, 5)
+    chosen, ms = ifa.ifa_autotune(s.ctx, 64 << 20, 5, args.tune_cache or None)
     log(f"autotune: variant {chosen} {ifa.ifa_variant_info(chosen)}; "
         f"ms per variant {[round(float(x), 4) for x in ms]}")
     return {"chosen": chosen, "ms": [round(float(x), 4) for x in ms]}
 
 
-def roofline(ifa, st, ops_per_launch, variant):
+def roofline(ifa, st, sparse_strands, variant):
+    """Roofline of the filter kernel: its algorithmic VALU ops per launch are
+    OPS_PER_WINDOW_STRAND x the query strands it filters x the window starts
+    it evaluated (counted by the library: waves holding a reference N go
+    whole to the resolve kernel and are not counted), over its average
+    launch time from HIP events on the stream it runs on."""
     launches = max(1, st["filter_launches"])
     filter_ms_avg = st["filter_ms"] / launches
+    ops_per_launch = OPS_PER_WINDOW_STRAND * sparse_strands * st["filter_windows"] / launches
     achieved = ops_per_launch / (filter_ms_avg * 1e-3) / 1e12 if st["filter_launches"] else 0.0
     peak = PEAK_VALU_OPS / 1e12
     return {
@@ -111,6 +167,8 @@ def roofline(ifa, st, ops_per_launch, variant):
         "variant_shape": ifa.ifa_variant_info(variant),
         "kernel_ms_avg": round(filter_ms_avg, 4),
         "launches": st["filter_launches"],
+        "windows_per_launch": st["filter_windows"] // launches,
+        "work_items_per_launch": st["work_items"] // launches,
         "pass_ms_avg": round(st["kernel_ms"] / max(1, st["kernel_launches"]), 4),
     }
 
@@ -133,17 +191,33 @@ def base_record(args, value, ms_per_step, config):
     }
 
 
+_HIP = None
+
+
+def device_sync():
+    """hipDeviceSynchronize: every stream of the device is idle afterwards."""
+    global _HIP
+    if _HIP is None:
+        import ctypes
+        _HIP = ctypes.CDLL("libamdhip64.so")
+    rc = _HIP.hipDeviceSynchronize()
+    if rc != 0:
+        raise RuntimeError(f"hipDeviceSynchronize failed: {rc}")
+
+
 def timed_steps(ifa, s, args, step):
     for i in range(args.warmup):
         step()
         log(f"warmup step {i} done")
     ifa.ifa_get_stats(s.ctx)
     ifa.ifa_reset_stats(s.ctx)
+    device_sync()   # one GPU, so no barrier: the device is idle here
     t0 = time.perf_counter()
     res = []
     for i in range(args.steps):
         res.append(step())
         log(f"step {i} done")
+    device_sync()
     elapsed = time.perf_counter() - t0
     return elapsed, ifa.ifa_get_stats(s.ctx), res
 
@@ -195,7 +269,7 @@ def run_c2(args):
     out["kernel_only_gbpq_s"] = round(bpq_per_step * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
     out["autotune"] = tune
     # algorithmic VALU ops of one filter launch: every window of a chunk x 2 strands x queries
-    out["roofline"] = roofline(ifa, st, OPS_PER_WINDOW_STRAND * 2 * nq * (bases / chunks), variant)
+    out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant)
 
     if not args.no_cpu and args.cpu_sample > 0:
         import oracle
@@ -267,8 +341,7 @@ def run_c3(args):
     out["pass_ms_per_step"] = round(st["kernel_ms"] / args.steps, 3)
     out["autotune"] = tune
     # filter launches cover the sparse strands only; dense strands bypass it
-    out["roofline"] = roofline(ifa, st, OPS_PER_WINDOW_STRAND * n_sparse * (bases / chunks),
-                               variant)
+    out["roofline"] = roofline(ifa, st, n_sparse, variant)
     s.close()
     return out
 
@@ -360,8 +433,7 @@ def run_c4(args):
     out["h2d_gb_s"] = round(st["bases"] / 4 / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
     out["device_footprint_bytes"] = {"before": foot0, "after": foot1}
     out["autotune"] = tune
-    chunk_windows = 1 << 30
-    out["roofline"] = roofline(ifa, st, OPS_PER_WINDOW_STRAND * 2 * nq * chunk_windows, variant)
+    out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant)
     s.close()
     return out
 
@@ -427,6 +499,12 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is design-only)", file=sys.stderr)
         sys.exit(2)
+    if args.calib_valu:
+        print(json.dumps({"valu_peak_tops": calib_valu()}), flush=True)
+        return
+    if args.calib_mfma:
+        print(json.dumps({"mfma_fp4_tflops": calib_mfma()}), flush=True)
+        return
     if args.calib_copy:
         calib_copy()
     if args.workload == "c2":

@@ -79,9 +79,11 @@ typedef struct {
     uint32_t host_threads;  /* packing threads; 0 = hardware concurrency */
     uint32_t work_capacity; /* filter work items per list (one item per wave
                                and batch of 32 query strands with a candidate
-                               window); 0 = auto (2^22). A full list never
-                               loses work: it grows and the filtered part of
-                               the pass runs again */
+                               window); 0 = auto (2^22, or more when the
+                               loaded queries are expected to need it on
+                               random bases). A full list never loses work:
+                               it grows and the filtered part of the pass
+                               runs again */
     uint32_t reserved;      /* must be 0 */
 } ifa_config;
 
@@ -110,6 +112,10 @@ typedef struct {
     double filter_ms;        /* summed time of the filter kernel alone (the hot
                                 loop), HIP events on the compute stream */
     uint64_t filter_launches;/* filter kernel launches */
+    uint64_t filter_windows; /* window starts the filter kernel evaluated (those of
+                                waves holding a reference N are passed whole to the
+                                resolve kernel and not counted) */
+    uint64_t work_items;     /* work-list items the filter emitted */
 } ifa_stats;
 
 /* Fill *cfg with the defaults: device 0, 2^30-base chunks, automatic hit
@@ -201,11 +207,13 @@ ifa_status ifa_query_partition(const ifa_ctx *ctx, uint32_t *n_strands, uint32_t
 ifa_status ifa_device_footprint(const ifa_ctx *ctx, uint64_t *bytes);
 
 /* Kernel variants: tile shapes of the scan kernel (windows per lane, query
- * strands per loop iteration, workgroup size). Every variant computes the
- * same hits; they differ only in speed. */
+ * strands per loop iteration, workgroup size) and the arithmetic of the
+ * filter kernel (encoding 0: vector-ALU bit operations). Every variant
+ * computes the same hits; they differ only in speed. Any output pointer may
+ * be NULL. */
 uint32_t ifa_variant_count(void);
 ifa_status ifa_variant_info(uint32_t v, uint32_t *windows_per_lane, uint32_t *queries_per_iter,
-                            uint32_t *workgroup);
+                            uint32_t *workgroup, uint32_t *encoding);
 ifa_status ifa_set_variant(ifa_ctx *ctx, uint32_t v);
 ifa_status ifa_get_variant(const ifa_ctx *ctx, uint32_t *v);
 

@@ -51,7 +51,8 @@ class IfaStats(ctypes.Structure):
                 ("kernel_launches", ctypes.c_uint64), ("rescans", ctypes.c_uint64),
                 ("hits", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
                 ("h2d_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
-                ("filter_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64)]
+                ("filter_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64),
+                ("filter_windows", ctypes.c_uint64), ("work_items", ctypes.c_uint64)]
 
 
 class IfaServerConfig(ctypes.Structure):
@@ -117,7 +118,7 @@ def lib():
         L.ifa_variant_count.argtypes = []
         L.ifa_variant_count.restype = u32
         L.ifa_variant_info.argtypes = [u32, ctypes.POINTER(u32), ctypes.POINTER(u32),
-                                       ctypes.POINTER(u32)]
+                                       ctypes.POINTER(u32), ctypes.POINTER(u32)]
         L.ifa_variant_info.restype = st
         L.ifa_set_variant.argtypes = [vp, u32]
         L.ifa_set_variant.restype = st
@@ -290,11 +291,13 @@ def ifa_variant_count() -> int:
 
 
 def ifa_variant_info(v: int) -> dict:
-    a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
-    st = lib().ifa_variant_info(v, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    a, b, c, e = (ctypes.c_uint32() for _ in range(4))
+    st = lib().ifa_variant_info(v, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                ctypes.byref(e))
     if st != 0:
         raise IfaError(st, f"no variant {v}")
-    return {"windows_per_lane": a.value, "queries_per_iter": b.value, "workgroup": c.value}
+    return {"windows_per_lane": a.value, "queries_per_iter": b.value, "workgroup": c.value,
+            "encoding": e.value}
 
 
 def ifa_set_variant(ctx, v: int):

@@ -27,7 +27,8 @@ def build(force=True, verbose=False):
         obj = os.path.join(CSRC, src + ".o")
         cmd = [HIPCC, *COMMON, "-c", path, "-o", obj]
         if src.endswith(".hip"):
-            cmd[1:1] = DEVICE + ["-x", "hip"]
+            # matrix-core results stay in VGPRs: the filter reads every one
+            cmd[1:1] = DEVICE + ["-x", "hip", "-mllvm", "-amdgpu-mfma-vgpr-form"]
         else:
             cmd[1:1] = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
         if verbose:

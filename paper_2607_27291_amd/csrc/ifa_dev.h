@@ -89,7 +89,14 @@ struct ScanArgs {
     // sparse-path work list (filled by the filter kernel, read by resolve)
     WorkItem *work;
     unsigned int *work_count;
+    unsigned int *skip_count;   // waves the filter handed whole to the resolve kernel
     unsigned int work_cap;
+    // matrix-core filter operands for the sparse strands, two strands (x 16
+    // shifts) per 32-column tile: mq_b[(3 tile + K step) * 64 + lane] is the
+    // lane's fp4 B operand, mq_t[32 tile + column] the match count a window
+    // needs to stay a candidate (padding columns: unreachable)
+    const uint4 *mq_b;
+    const float *mq_t;
     // count+digest sink, kStripes slots per query (see kStripes)
     unsigned long long *q_count;
     unsigned long long *q_digest;

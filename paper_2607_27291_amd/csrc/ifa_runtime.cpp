@@ -34,7 +34,7 @@ hipError_t launch_dense(const ScanArgs &a, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
 hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s);
 uint32_t variant_count();
-void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg);
+void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg, uint32_t *enc);
 }  // namespace ifa
 
 using namespace ifa;
@@ -212,6 +212,8 @@ struct ifa_ctx {
     std::vector<uint32_t> h_qwords;
     DevBuf<QSDesc> d_qs;
     DevBuf<uint32_t> d_qwords;
+    DevBuf<uint4> d_mqb;              // matrix-core filter B operands
+    DevBuf<float> d_mqt;              // and required match counts
     DevBuf<unsigned long long> d_qcount, d_qdigest;
 
     // streaming
@@ -229,8 +231,9 @@ struct ifa_ctx {
     uint64_t buf_cap[2] = {0, 0};     // current records per hit buffer
     DevBuf<WorkItem> work[2];         // sparse-path work lists, one per hit buffer
     uint32_t work_cap[2] = {0, 0};
-    DevBuf<unsigned int> d_workcount; // [2]
+    DevBuf<unsigned int> d_workcount; // [4]: work items, skipped waves; per hit buffer
     HostBuf<unsigned int> h_workcount;
+    uint32_t work_want = 0;           // capacity both work lists grow to before a launch
     Job jobs[2];
     uint64_t job_seq = 0;
     std::vector<ifa_hit> hits;        // retired, not yet handed out
@@ -423,12 +426,15 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.n_sparse = c->n_sparse;
     a.policy = c->cfg.n_policy;
     a.qwords = c->d_qwords.p;
+    a.mq_b = c->d_mqb.p;
+    a.mq_t = c->d_mqt.p;
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
     a.variant = c->variant;
     a.work = c->work[hb].p;
-    a.work_count = c->d_workcount.p + hb;
+    a.work_count = c->d_workcount.p + 2 * hb;
+    a.skip_count = a.work_count + 1;
     a.work_cap = c->work_cap[hb];
     a.hits = c->d_hits[hb].p;
     a.hit_count = c->d_hitcount.p + hb;
@@ -496,7 +502,7 @@ void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, Pa
 {
     if (clear_hits && c->cfg.sink == IFA_SINK_RECORDS)
         hip_check(launch_clear_u64(a.hit_count, 1, c->comp_s), "clear hit counter");
-    hip_check(launch_clear_u32(a.work_count, 1, c->comp_s), "clear work counter");
+    hip_check(launch_clear_u32(a.work_count, 2, c->comp_s), "clear work counters");
     hip_check(hipEventRecord(ev.t0, c->comp_s), "event record");
     hip_check(launch_filter(a, c->comp_s), "filter launch");
     hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
@@ -511,19 +517,38 @@ void enqueue_count_copies(ifa_ctx *c, int hb)
         hip_check(hipMemcpyAsync(c->h_hitcount.p + hb, c->d_hitcount.p + hb,
                                  sizeof(unsigned long long), hipMemcpyDeviceToHost, c->comp_s),
                   "copy hit count");
-    hip_check(hipMemcpyAsync(c->h_workcount.p + hb, c->d_workcount.p + hb, sizeof(unsigned int),
-                             hipMemcpyDeviceToHost, c->comp_s),
-              "copy work count");
+    hip_check(hipMemcpyAsync(c->h_workcount.p + 2 * hb, c->d_workcount.p + 2 * hb,
+                             2 * sizeof(unsigned int), hipMemcpyDeviceToHost, c->comp_s),
+              "copy work counters");
 }
 
-void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse)
+// Book the times of a finished pass over words [w0, w1) whose counters are
+// on the host. The filter evaluated every window start of the range except
+// those of the waves it handed to the resolve kernel.
+void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse, int hb, uint32_t w0,
+                    uint32_t w1)
 {
     c->st.kernel_ms += elapsed(ev.t0, ev.t2);
     c->st.kernel_launches++;
     if (sparse) {
         c->st.filter_ms += elapsed(ev.t0, ev.t1);
         c->st.filter_launches++;
+        uint32_t wpl, qu, wg, enc;
+        variant_shape(c->variant, &wpl, &qu, &wg, &enc);
+        const uint64_t starts = 32ull * (w1 - w0);
+        const uint64_t skipped = 64ull * wpl * c->h_workcount.p[2 * hb + 1];
+        c->st.filter_windows += starts > skipped ? starts - skipped : 0;
+        c->st.work_items += c->h_workcount.p[2 * hb];
     }
+}
+
+// Make the work list of hit buffer hb at least work_want items long (the
+// list is not in use: its last pass has been retired).
+void ensure_work_list(ifa_ctx *c, int hb)
+{
+    if (c->work_cap[hb] >= c->work_want) return;
+    c->work[hb].alloc(c->work_want, "grow work list");
+    c->work_cap[hb] = c->work_want;
 }
 
 // After a pass whose resolve kernel found the work list too small (and so
@@ -531,11 +556,12 @@ void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse)
 // Its dense part is not repeated: it does not use the list.
 void settle_work_overflow(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t w1)
 {
-    while (c->h_workcount.p[hb] > c->work_cap[hb]) {
-        const uint64_t need = (uint64_t)c->h_workcount.p[hb];
+    while (c->h_workcount.p[2 * hb] > c->work_cap[hb]) {
+        const uint64_t need = (uint64_t)c->h_workcount.p[2 * hb];
         const uint64_t cap = std::min<uint64_t>(need + need / 4 + 1024, 0xffffffffull);
-        c->work[hb].alloc(cap, "grow work list");
-        c->work_cap[hb] = (uint32_t)cap;
+        // the other list grows before its next launch: both see the same load
+        c->work_want = std::max<uint32_t>(c->work_want, (uint32_t)cap);
+        ensure_work_list(c, hb);
         ScanArgs a = make_args(c, ch, hb);
         a.w_begin = w0;
         a.w_end = w1;
@@ -544,7 +570,7 @@ void settle_work_overflow(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, u
         enqueue_pass(c, a, false, false, ev);
         enqueue_count_copies(c, hb);
         hip_check(hipStreamSynchronize(c->comp_s), "sync");
-        add_pass_times(c, ev, true);
+        add_pass_times(c, ev, true, hb, w0, w1);
         ev.destroy();
         c->st.rescans++;
     }
@@ -563,7 +589,7 @@ void rescan_range(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t 
     enqueue_pass(c, a, true, true, ev);
     enqueue_count_copies(c, hb);
     hip_check(hipStreamSynchronize(c->comp_s), "sync");
-    add_pass_times(c, ev, c->n_sparse > 0);
+    add_pass_times(c, ev, c->n_sparse > 0, hb, w0, w1);
     ev.destroy();
     c->st.rescans++;
     settle_work_overflow(c, ch, hb, w0, w1);
@@ -593,8 +619,8 @@ void retire(ifa_ctx *c, Job &j)
     ev.t0 = j.k0;
     ev.t1 = j.kf;
     ev.t2 = j.k1;
-    add_pass_times(c, ev, c->n_sparse > 0);
     const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
+    add_pass_times(c, ev, c->n_sparse > 0, j.hitbuf, 0, words);
     settle_work_overflow(c, *j.chunk, j.hitbuf, 0, words);
     if (c->cfg.sink == IFA_SINK_RECORDS) {
         uint64_t n = c->h_hitcount.p[j.hitbuf];
@@ -624,6 +650,7 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     retire(c, j);   // frees the hit buffer and work list this job will use
     j.chunk = ch;
     j.hitbuf = (int)(c->job_seq % 2);
+    ensure_work_list(c, j.hitbuf);
     ScanArgs a = make_args(c, *ch, j.hitbuf);
     if (!j.k0) hip_check(hipEventCreate(&j.k0), "event");
     if (!j.kf) hip_check(hipEventCreate(&j.kf), "event");
@@ -854,6 +881,60 @@ void pack_query_strands(uint32_t strands, uint32_t n, const uint8_t *const *seq,
 // descending (the kernels mask their cached slices in place as L drops),
 // then by k. n_queries sizes the
 // count+digest accumulators, which this resets.
+// Expected work items the filter emits per chunk of chunk_bases uniform
+// random bases, for sparse strands qs[0, n_sparse): an item is one (wave,
+// batch of 32 strands) with a candidate among the wave's windows (64 lanes x
+// at most 16 windows); waves holding a reference N add items of their own,
+// for which the list grows when they are many.
+uint64_t expected_work_items(const std::vector<QSDesc> &qs, uint32_t n_sparse,
+                             uint64_t chunk_bases)
+{
+    const double waves = (double)chunk_bases / 1024.0 + 1.0;
+    double items = 0.0;
+    for (uint32_t b = 0; b < n_sparse; b += 32) {
+        double log_none = 0.0;
+        for (uint32_t s = b; s < std::min<uint32_t>(n_sparse, b + 32); s++) {
+            const double p = binom_cdf(std::min<uint32_t>(qs[s].len, 32u), 0.75, qs[s].thr);
+            log_none += 1024.0 * std::log1p(-std::min(p, 1.0 - 1e-12));
+        }
+        items += waves * -std::expm1(log_none);
+    }
+    return (uint64_t)(items * 1.5);
+}
+
+// Operands of the matrix-core filter for sparse strands qs[0, n_sparse): tile
+// nt holds strands 2nt and 2nt+1, column c = 16 (strand - 2nt) + shift r. The
+// B operand of K step t for lane l (column l % 32, half h = l / 32) has in
+// register b, nibble o the e2m1 value 1.0 (code 2) when the strand's base at
+// j = 16t + 8h + o - r exists (0 <= j < min(L, 32)), is not N and has code b
+// (= 2 hi + lo), else 0. need[c] = min(L, 32) - thr: the matches a window
+// must reach to remain a candidate (filter count <= thr).
+void build_mfma_operands(const std::vector<QSDesc> &qs, uint32_t n_sparse,
+                         std::vector<uint32_t> &b, std::vector<float> &need)
+{
+    const uint32_t n_tiles = (n_sparse + 1) / 2;
+    b.assign((size_t)n_tiles * 3 * 64 * 4, 0u);
+    need.assign((size_t)n_tiles * 32, 1e30f);
+    for (uint32_t nt = 0; nt < n_tiles; nt++) {
+        for (uint32_t c = 0; c < 32; c++) {
+            const uint32_t s = 2 * nt + c / 16, r = c % 16;
+            if (s >= n_sparse) continue;
+            const QSDesc &d = qs[s];
+            const uint32_t l32 = std::min<uint32_t>(d.len, 32u);
+            need[32 * nt + c] = (float)l32 - (float)d.thr;
+            for (uint32_t t = 0; t < 3; t++)
+                for (uint32_t h = 0; h < 2; h++)
+                    for (uint32_t o = 0; o < 8; o++) {
+                        const int32_t j = (int32_t)(16 * t + 8 * h + o) - (int32_t)r;
+                        if (j < 0 || j >= (int32_t)l32 || ((d.qn0 >> j) & 1u)) continue;
+                        const uint32_t cls = 2u * ((d.qh0 >> j) & 1u) + ((d.ql0 >> j) & 1u);
+                        const size_t lane = c + 32 * h;
+                        b[((3 * (size_t)nt + t) * 64 + lane) * 4 + cls] |= 2u << (4 * o);
+                    }
+        }
+    }
+}
+
 void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t> &&words,
                      uint32_t n_queries, uint32_t lmax)
 {
@@ -889,6 +970,22 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
         hip_check(hipMemcpy(c->d_qwords.p, words.data(), words.size() * sizeof(uint32_t),
                             hipMemcpyHostToDevice),
                   "upload query words");
+    {
+        std::vector<uint32_t> mb;
+        std::vector<float> mt;
+        build_mfma_operands(qs, n_sparse, mb, mt);
+        const size_t nb4 = std::max<size_t>(mb.size() / 4, 1), nt = std::max<size_t>(mt.size(), 1);
+        if (c->d_mqb.n < nb4 || !c->d_mqb.p) c->d_mqb.alloc(nb4, "matrix filter operands");
+        if (c->d_mqt.n < nt || !c->d_mqt.p) c->d_mqt.alloc(nt, "matrix filter counts");
+        if (!mb.empty())
+            hip_check(hipMemcpy(c->d_mqb.p, mb.data(), mb.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice),
+                      "upload matrix filter operands");
+        if (!mt.empty())
+            hip_check(hipMemcpy(c->d_mqt.p, mt.data(), mt.size() * sizeof(float),
+                                hipMemcpyHostToDevice),
+                      "upload matrix filter counts");
+    }
     if (c->cfg.sink == IFA_SINK_COUNT_DIGEST) {
         const size_t need = (size_t)std::max<uint32_t>(n_queries, 1) * kStripes;
         if (c->d_qcount.n < need) {
@@ -897,6 +994,13 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
         }
         hip_check(hipMemset(c->d_qcount.p, 0, need * sizeof(unsigned long long)), "memset");
         hip_check(hipMemset(c->d_qdigest.p, 0, need * sizeof(unsigned long long)), "memset");
+    }
+    // size the work lists for the expected load unless the caller fixed the
+    // initial capacity (they grow on overflow either way)
+    if (c->cfg.work_capacity == 0) {
+        const uint64_t est = expected_work_items(qs, n_sparse, c->cfg.chunk_bases);
+        c->work_want =
+            (uint32_t)std::min<uint64_t>(std::max<uint64_t>(est, c->work_want), 1ull << 28);
     }
     c->h_qs = std::move(qs);
     c->n_sparse = n_sparse;
@@ -1028,10 +1132,10 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
             c->work[i].alloc(wcap, "work list");
             c->work_cap[i] = wcap;
         }
-        c->d_workcount.alloc(2, "work counters");
-        c->h_workcount.alloc(2, "pinned work counters");
-        hip_check(hipMemset(c->d_workcount.p, 0, 2 * sizeof(unsigned int)), "memset");
-        c->h_workcount.p[0] = c->h_workcount.p[1] = 0;
+        c->d_workcount.alloc(4, "work counters");
+        c->h_workcount.alloc(4, "pinned work counters");
+        hip_check(hipMemset(c->d_workcount.p, 0, 4 * sizeof(unsigned int)), "memset");
+        for (int i = 0; i < 4; i++) c->h_workcount.p[i] = 0;
         c->d_hitcount.alloc(2, "hit counters");
         c->h_hitcount.alloc(2, "pinned hit counters");
         hip_check(hipMemset(c->d_hitcount.p, 0, 2 * sizeof(unsigned long long)), "memset");
@@ -1268,14 +1372,15 @@ ifa_status ifa_get_stats(ifa_ctx *c, ifa_stats *out)
 uint32_t ifa_variant_count(void) { return ifa::variant_count(); }
 
 ifa_status ifa_variant_info(uint32_t v, uint32_t *windows_per_lane, uint32_t *queries_per_iter,
-                            uint32_t *workgroup)
+                            uint32_t *workgroup, uint32_t *encoding)
 {
     if (v >= ifa::variant_count()) return IFA_E_INVALID;
-    uint32_t a, b, g;
-    ifa::variant_shape(v, &a, &b, &g);
+    uint32_t a, b, g, e;
+    ifa::variant_shape(v, &a, &b, &g, &e);
     if (windows_per_lane) *windows_per_lane = a;
     if (queries_per_iter) *queries_per_iter = b;
     if (workgroup) *workgroup = g;
+    if (encoding) *encoding = e;
     return IFA_OK;
 }
 
@@ -1361,7 +1466,7 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
         DevBuf<WorkItem> scratch_work;
         scratch_work.alloc(1u << 16, "tuning work list");
         DevBuf<unsigned int> scratch_wc;
-        scratch_wc.alloc(2, "tuning work counter");
+        scratch_wc.alloc(2, "tuning work counters");
         hipEvent_t e0, e1;
         hip_check(hipEventCreate(&e0), "event");
         hip_check(hipEventCreate(&e1), "event");
@@ -1376,9 +1481,10 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
             a.hit_cap = 1024;
             a.work = scratch_work.p;
             a.work_count = scratch_wc.p;
+            a.skip_count = scratch_wc.p + 1;
             a.work_cap = 1u << 16;
             auto pass = [&]() {
-                hip_check(launch_clear_u32(a.work_count, 1, c->comp_s), "clear");
+                hip_check(launch_clear_u32(a.work_count, 2, c->comp_s), "clear");
                 hip_check(launch_filter(a, c->comp_s), "tuning launch");
                 hip_check(launch_resolve(a, c->comp_s), "tuning launch");
                 hip_check(launch_dense(a, c->comp_s), "tuning launch");
@@ -1427,7 +1533,8 @@ ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
         b += c->d_hits[i].n * sizeof(uint4) + c->work[i].n * sizeof(WorkItem);
     }
     b += c->d_hitcount.n * sizeof(unsigned long long) + c->d_workcount.n * sizeof(unsigned int);
-    b += c->d_qs.n * sizeof(QSDesc) + c->d_qwords.n * sizeof(uint32_t);
+    b += c->d_qs.n * sizeof(QSDesc) + c->d_qwords.n * sizeof(uint32_t) +
+         c->d_mqb.n * sizeof(uint4) + c->d_mqt.n * sizeof(float);
     b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
     for (const auto &r : c->resident)
         b += r->planes.n * sizeof(uint32_t) + r->pieces.n * sizeof(Piece);

@@ -461,6 +461,7 @@ __global__ __launch_bounds__(WG) void scan_filter_kernel(ScanArgs a)
     const bool lane_n = ln.active && ((ln.n0 | ln.n1) != 0u);
     if (__any(lane_n)) {
         if ((threadIdx.x & 63u) == 0u) {
+            atomicAdd(a.skip_count, 1u);
             for (uint32_t qb = 0; qb < a.n_sparse; qb += 32) {
                 const uint32_t nb = min(32u, a.n_sparse - qb);
                 const unsigned int idx = atomicAdd(a.work_count, 1u);
@@ -477,6 +478,197 @@ __global__ __launch_bounds__(WG) void scan_filter_kernel(ScanArgs a)
         return;
     }
     filter_lane<W, QU>(a, ln, wave);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core filter (gfx950 fp4 MFMA).
+//
+// The filter count of window p and strand s is L32 minus the number of
+// matches over the first L32 = min(L, 32) bases, and the match count is a
+// dense contraction of one-hot codes:
+//   matches(p, s) = sum over j < L32, classes b of [S[p+j] = b] [Q_s[j] = b]
+// (a query N has no class, so it never matches). Windows are taken in groups
+// of 16 consecutive starts; group g covers the 48-base segment S[16g, 16g+48)
+// and the 16 shifts r of a strand become 16 columns of a banded operand:
+//   B[(i, b), (s, r)] = [Q_s[i - r] = b] for 0 <= i - r < L32, else 0,
+// so matches(16g + r, s) = sum over i < 48, b of A[g, (i, b)] B[(i, b), (s, r)]
+// with A[g, (i, b)] = [S[16g + i] = b]: a (groups x 192) by (192 x 16
+// strands) product in e2m1 (1.0 or 0), exact in the fp32 accumulator.
+//
+// One wave covers the 1024 window starts of a filter wave (64 lanes x 16):
+// two 32-group A tiles, each 3 K-steps of v_mfma_scale_f32_32x32x64_f8f6f4
+// (32 groups x 64 K per step). Operand layout of that instruction: lane l
+// holds row (A) or column (B) l % 32 and K elements 32 (l / 32) + e, e < 32,
+// element e in bits 4e..4e+3 of the lane's four registers; lane l of D holds
+// column l % 32, rows 8 (i / 4) + 4 (l / 32) + i % 4 in its 16 registers.
+// Here K step t, half h = l / 32 covers segment bases 16t + 8h + o, o < 8,
+// and element e = 8b + o: register b holds class b's one-hot nibbles of the
+// lane's 8 bases. The B operand (two strands x 16 shifts per 32-column tile,
+// built on the host in this order) and each column's required match count
+// come from mq_b / mq_t. A window may be a hit only if its matches reach the
+// column's count; per tile the wave takes the maximum over its rows.
+// ---------------------------------------------------------------------------
+
+typedef int ifa_v8i __attribute__((ext_vector_type(8)));
+typedef float ifa_v16f __attribute__((ext_vector_type(16)));
+
+// byte x -> bit 4o+1 (the e2m1 code of 1.0 in nibble o) for each set bit o
+struct SpreadTable {
+    uint32_t v[256];
+};
+constexpr SpreadTable make_spread_table()
+{
+    SpreadTable t{};
+    for (uint32_t x = 0; x < 256; x++) {
+        uint32_t s = 0;
+        for (uint32_t o = 0; o < 8; o++)
+            if ((x >> o) & 1u) s |= 2u << (4u * o);
+        t.v[x] = s;
+    }
+    return t;
+}
+__device__ const SpreadTable kSpread = make_spread_table();
+
+// The lane's A operand of one K step: one-hot nibbles of 8 bases whose hi and
+// lo bits are the low bytes of hb, lb. Register b = class b = 2 hi + lo.
+__device__ __forceinline__ ifa_v8i onehot_operand(uint32_t hb, uint32_t lb)
+{
+    const uint32_t sh = kSpread.v[hb & 0xffu], sl = kSpread.v[lb & 0xffu];
+    const uint32_t m = 0x22222222u;
+    ifa_v8i r = {};
+    r[0] = (int)(~sh & ~sl & m);
+    r[1] = (int)(~sh & sl & m);
+    r[2] = (int)(sh & ~sl & m);
+    r[3] = (int)(sh & sl & m);
+    return r;
+}
+
+__device__ __forceinline__ ifa_v16f mfma_fp4(const ifa_v8i &a, const ifa_v8i &b, const ifa_v16f &c)
+{
+    // cbsz = blgp = 4: both operands e2m1; E8M0 scales 127 = 1.0
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
+}
+
+// Work items for an N wave: every strand of the batch is listed.
+__device__ __forceinline__ void list_batch(const ScanArgs &a, uint32_t wave, uint32_t qb)
+{
+    const uint32_t nb = min(32u, a.n_sparse - qb);
+    const unsigned int idx = atomicAdd(a.work_count, 1u);
+    if (idx < a.work_cap) {
+        WorkItem it;
+        it.wave = wave;
+        it.qb = qb;
+        it.pending = nb == 32u ? 0xffffffffu : ((1u << nb) - 1u);
+        it.pad = 0;
+        a.work[idx] = it;
+    }
+}
+
+// Grid: x = workgroups sharing one batch of 32 sparse strands (16 column
+// tiles), y = batch. A workgroup copies its batch's B operands, required
+// counts and the spread table into LDS once, then its waves walk filter waves
+// blockIdx.x * (WG / 64) + wave, stepping by gridDim.x * (WG / 64). Dynamic
+// LDS: mq_lds_bytes(tiles of the batch).
+template <int WG>
+__global__ __launch_bounds__(WG) void scan_filter_mfma_kernel(ScanArgs a)
+{
+    extern __shared__ uint4 lds[];
+    const uint32_t qb = 32u * blockIdx.y;
+    const uint32_t n_tiles = (a.n_sparse + 1u) >> 1;
+    const uint32_t t0 = qb >> 1, tn = min(n_tiles, t0 + 16u) - t0;   // tiles of the batch
+    uint4 *sb = lds;                                                 // [tn][3][64]
+    float *st = reinterpret_cast<float *>(lds + 192u * tn);          // [tn][32]
+    uint32_t *sp = reinterpret_cast<uint32_t *>(st + 32u * tn);      // [256]
+    for (uint32_t i = threadIdx.x; i < 192u * tn; i += WG) sb[i] = a.mq_b[192u * t0 + i];
+    for (uint32_t i = threadIdx.x; i < 32u * tn; i += WG) st[i] = a.mq_t[32u * t0 + i];
+    for (uint32_t i = threadIdx.x; i < 256u; i += WG) sp[i] = kSpread.v[i];
+    __syncthreads();
+
+    const uint32_t l = threadIdx.x & 63u;
+    const uint32_t g = l & 31u, h = l >> 5;
+    const uint32_t last = (uint32_t)((a.chunk_len + 31) >> 5) + kPadWords - 1;
+    const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
+    const uint32_t stride = gridDim.x * (WG / 64u);
+    const ifa_v16f zero = {};
+    for (uint32_t wave = blockIdx.x * (WG / 64u) + (threadIdx.x >> 6); wave < n_waves;
+         wave += stride) {
+        // lane l of a filter wave stands for plane word w0 + l / 2 (16
+        // windows); the N test and the work items are those of the VALU filter
+        const uint32_t w0 = a.w_begin + 32u * wave;
+        const uint32_t lw = w0 + (l >> 1);
+        bool lane_n = false;
+        if (lw < a.w_end) lane_n = (a.nm[lw] | a.nm[min(lw + 1u, last)]) != 0u;
+        if (__any(lane_n)) {
+            if (l == 0u) {
+                if (blockIdx.y == 0) atomicAdd(a.skip_count, 1u);
+                list_batch(a, wave, qb);
+            }
+            continue;
+        }
+        // A operands: tile u holds groups 32u + g (window starts 512u + 16g)
+        ifa_v8i A[2][3];
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const uint32_t wa = min(w0 + 16u * u + (g >> 1), last);
+            const uint32_t wb = min(wa + 1u, last);
+            const uint64_t hh = ((uint64_t)a.hi[wb] << 32) | a.hi[wa];
+            const uint64_t ll = ((uint64_t)a.lo[wb] << 32) | a.lo[wa];
+#pragma unroll
+            for (int t = 0; t < 3; t++) {
+                const uint32_t x = 16u * (g & 1u) + 16u * t + 8u * h;   // < 64
+                const uint32_t s1 = sp[(uint32_t)(hh >> x) & 0xffu];
+                const uint32_t s0 = sp[(uint32_t)(ll >> x) & 0xffu];
+                const uint32_t m = 0x22222222u;
+                ifa_v8i r = {};
+                r[0] = (int)(~s1 & ~s0 & m);
+                r[1] = (int)(~s1 & s0 & m);
+                r[2] = (int)(s1 & ~s0 & m);
+                r[3] = (int)(s1 & s0 & m);
+                A[u][t] = r;
+            }
+        }
+        uint32_t pending = 0;   // wave-uniform
+        for (uint32_t nt = 0; nt < tn; nt++) {
+            ifa_v8i B[3];
+#pragma unroll
+            for (int t = 0; t < 3; t++) {
+                const uint4 v = sb[(3u * nt + (uint32_t)t) * 64u + l];
+                B[t] = ifa_v8i{(int)v.x, (int)v.y, (int)v.z, (int)v.w, 0, 0, 0, 0};
+            }
+            const float need = st[32u * nt + g];
+            ifa_v16f d0 = mfma_fp4(A[0][0], B[0], zero);
+            ifa_v16f d1 = mfma_fp4(A[1][0], B[0], zero);
+            d0 = mfma_fp4(A[0][1], B[1], d0);
+            d1 = mfma_fp4(A[1][1], B[1], d1);
+            d0 = mfma_fp4(A[0][2], B[2], d0);
+            d1 = mfma_fp4(A[1][2], B[2], d1);
+            // match counts are non-negative floats, which order as their bits
+            uint32_t mx = 0;
+#pragma unroll
+            for (int i = 0; i < 16; i++)
+                mx = max(max(__float_as_uint(d0[i]), __float_as_uint(d1[i])), mx);
+            const uint64_t m = __ballot(__uint_as_float(mx) >= need);
+            if (m & 0x0000ffff0000ffffull) pending |= 1u << (2u * nt);
+            if (m & 0xffff0000ffff0000ull) pending |= 2u << (2u * nt);
+        }
+        if (pending && l == 0u) {
+            const unsigned int idx = atomicAdd(a.work_count, 1u);
+            if (idx < a.work_cap) {
+                WorkItem it;
+                it.wave = wave;
+                it.qb = qb;
+                it.pending = pending;
+                it.pad = 0;
+                a.work[idx] = it;
+            }
+        }
+    }
+}
+
+// LDS bytes of the matrix-core filter for a batch of `tiles` column tiles.
+static uint32_t mq_lds_bytes(uint32_t tiles)
+{
+    return tiles * (192u * 16u + 32u * 4u) + 256u * 4u;
 }
 
 // One wave per work item (grid-stride). Does nothing when the filter kernel
@@ -643,12 +835,19 @@ struct VariantDesc {
     uint32_t windows;   // W
     uint32_t qunroll;   // QU
     uint32_t wg;        // filter workgroup size
+    uint32_t enc;       // filter arithmetic: 0 = VALU bit ops, 1 = fp4 matrix cores
 };
 
 #define IFA_V(W, QU, WG)                                                                 \
     {                                                                                    \
         scan_filter_kernel<W, QU, WG>, scan_resolve_kernel<W>, scan_dense_kernel<W>,     \
-            scan_dense_cold_kernel<W>, W, QU, WG                                         \
+            scan_dense_cold_kernel<W>, W, QU, WG, 0                                      \
+    }
+// matrix-core filter: waves of 16 windows per lane, resolved by the W = 16 kernels
+#define IFA_VM(WG)                                                                       \
+    {                                                                                    \
+        scan_filter_mfma_kernel<WG>, scan_resolve_kernel<16>, scan_dense_kernel<16>,     \
+            scan_dense_cold_kernel<16>, 16, 2, WG, 1                                     \
     }
 static const VariantDesc kVariantTable[] = {
     IFA_V(32, 1, 256),   // 0: default
@@ -657,23 +856,30 @@ static const VariantDesc kVariantTable[] = {
     IFA_V(16, 1, 256),   IFA_V(16, 1, 128),  IFA_V(16, 1, 512),
     IFA_V(16, 2, 256),   IFA_V(16, 2, 512),
     IFA_V(32, 2, 512),   IFA_V(16, 2, 1024),
+    IFA_VM(256),         IFA_VM(64),          IFA_VM(512),
 };
 #undef IFA_V
+#undef IFA_VM
 
 uint32_t variant_count() { return sizeof(kVariantTable) / sizeof(kVariantTable[0]); }
 
-void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg)
+void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg, uint32_t *enc)
 {
     const VariantDesc &d = kVariantTable[v < variant_count() ? v : 0];
     *windows = d.windows;
     *qunroll = d.qunroll;
     *wg = d.wg;
+    *enc = d.enc;
 }
 
 static const VariantDesc &pick(const ScanArgs &a)
 {
     return kVariantTable[a.variant < variant_count() ? a.variant : 0];
 }
+
+// Filter waves each wave of the matrix-core filter walks (amortizes the
+// workgroup's LDS fill).
+constexpr uint32_t kMqWavesPerWave = 8;
 
 // Filter lanes of the word range (a multiple of 64, whole waves).
 static uint64_t filter_lanes(const ScanArgs &a, const VariantDesc &v)
@@ -683,11 +889,22 @@ static uint64_t filter_lanes(const ScanArgs &a, const VariantDesc &v)
 }
 
 // Sparse part, step 1: the filter kernel fills the work list (the caller
-// clears *work_count first).
+// clears *work_count and *skip_count first).
 hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
 {
     if (a.w_end <= a.w_begin || a.n_sparse == 0) return hipSuccess;
     const VariantDesc &v = pick(a);
+    if (v.enc == 1) {
+        // each workgroup walks kMqWavesPerWave filter waves per wave of its
+        // own, for one batch of 32 strands (grid y)
+        const uint32_t waves = (a.w_end - a.w_begin + 31u) >> 5;
+        const uint32_t per_wg = (v.wg / 64u) * kMqWavesPerWave;
+        const uint32_t gx = (waves + per_wg - 1) / per_wg;
+        const uint32_t batches = (a.n_sparse + 31u) / 32u;
+        const uint32_t tiles = min(16u, (a.n_sparse + 1u) / 2u);
+        hipLaunchKernelGGL(v.filter, dim3(gx, batches), dim3(v.wg), mq_lds_bytes(tiles), s, a);
+        return hipGetLastError();
+    }
     const uint64_t lanes = filter_lanes(a, v);
     hipLaunchKernelGGL(v.filter, dim3((uint32_t)((lanes + v.wg - 1) / v.wg)), dim3(v.wg), 0, s, a);
     return hipGetLastError();

@@ -348,3 +348,73 @@ def test_dense_and_sparse_strands_with_work_list_overflow(ifa, orc, sink):
             if wcap == 4:
                 assert st["rescans"] > 0
     assert len(want) > 1000
+
+
+def matrix_variants(ifa):
+    return [v for v in range(ifa.ifa_variant_count()) if ifa.ifa_variant_info(v)["encoding"] == 1]
+
+
+@pytest.mark.parametrize("strands,policy", [(1, 0), (3, 1)])
+def test_matrix_core_filter_cases(ifa, orc, strands, policy):
+    """The fp4 matrix-core filter on the cases its tiling has to get right:
+    strand counts that are odd (a half-empty column tile) and span several
+    batches of 32, lengths below, at and above 32 with query Ns, thresholds
+    0-12, reference N runs and several chunks. Small hit buffers and work
+    lists force the re-scan and re-run paths through the same kernel."""
+    import synth
+    spec = synth.c2_spec(seed=91, total=900_000)
+    spec.n_param = 3e-3
+    spec.median = 60_000
+    ref = synth.gen_reference(spec)
+    rng = random.Random(91 + strands)
+    qs = [rand_dna(rng, rng.choice([5, 12, 18, 24, 31, 32, 33, 36, 47, 64, 100]),
+                   b"ACGT" if rng.random() < 0.85 else b"ACGTN") for _ in range(45)]
+    ks = [rng.randint(0, min(len(q), 12)) for q in qs]
+    want = orc.scan(qs, ref, ks, strands=strands, policy=policy)
+    _, cnt, dig = orc.scan(qs, ref, ks, strands=strands, policy=policy, stats=True, records=False)
+    vs = matrix_variants(ifa)
+    assert vs, "no matrix-core variant"
+    for v in vs:
+        for hcap, wcap in ((1 << 20, 0), (1 << 9, 8)):
+            say(f"matrix variant {v} strands {strands} policy {policy} hcap {hcap} wcap {wcap}")
+            with ifa.Scanner(chunk_bases=1 << 18, strands=strands, n_policy=policy,
+                             hit_capacity=hcap, work_capacity=wcap) as s:
+                ifa.ifa_set_variant(s.ctx, v)
+                s.load_queries(qs, ks)
+                s.scan_chunk(ref)
+                assert_same(s.collect(), want, f"variant {v} hcap {hcap} wcap {wcap}")
+        with ifa.Scanner(chunk_bases=1 << 18, strands=strands, n_policy=policy,
+                         sink=ifa.IFA_SINK_COUNT_DIGEST) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries(qs, ks)
+            s.scan_chunk(ref)
+            gc, gd = s.query_stats()
+            assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), f"variant {v} stats"
+    assert len(want) > 200
+
+
+def test_matrix_core_filter_emits_what_the_valu_filter_emits(ifa):
+    """Both filters compute the same count, so on the same chunk they list the
+    same work items (same waves, batches and pending strands) and skip the
+    same N waves: compared through the library's counters."""
+    import synth
+    spec = synth.c2_spec(seed=5, total=3_000_000)
+    spec.n_param = 1e-3
+    ref = synth.gen_reference(spec)
+    rng = random.Random(5)
+    qs = [rand_dna(rng, rng.choice([20, 28, 32, 40])) for _ in range(40)]
+    ks = [rng.randint(2, 7) for _ in qs]
+    seen = {}
+    for v in range(ifa.ifa_variant_count()):
+        info = ifa.ifa_variant_info(v)
+        if info["windows_per_lane"] != 16:
+            continue
+        say(f"work items of variant {v} {info}")
+        with ifa.Scanner(chunk_bases=1 << 20) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries(qs, ks)
+            s.scan_chunk(ref)
+            s.collect()
+            st = s.stats()
+            seen[v] = (st["work_items"], st["filter_windows"])
+    assert len(set(seen.values())) == 1, seen
