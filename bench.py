@@ -34,11 +34,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Gbp·query/s scanned (exact hits) + p50/p99 serving latency on 1 MI355X"
-PEAK_VALU_OPS = 256 * 64 * 2.4e9        # int32 VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
-# Algorithmic VALU ops per window x strand x query for the packed-word filter
-# on gfx950: two v_bitop3_b32 (the mismatch bits of 32 bases), one
-# v_bcnt_u32_b32 and half a v_min3_u32 (threshold fold over the windows).
+# 32-bit VALU lane-ops/s: 256 CUs x 4 SIMDs x 32 lanes per clock (two wave64
+# VALU issues per 4 clocks) x 2.4 GHz = 78.6 T, the published fp32 vector
+# rate (157.3 TFLOP/s) counted in fused operations.
+PEAK_VALU_OPS = 256 * 4 * 32 * 2.4e9
+# Algorithmic VALU ops per window x query strand for the packed-word filter:
+# two v_bitop3_b32 (the mismatch bits of 32 bases), one v_bcnt_u32_b32 and
+# half a v_min3_u32 (threshold fold over the windows).
 OPS_PER_WINDOW_STRAND = 3.5
+# Dense fp4 (e2m1) matrix-core peak of MI355X.
+PEAK_FP4_FLOPS = 10.1e15
+# Algorithmic flops per window x query strand for the matrix-core filter: the
+# one-hot match count over 32 positions x 4 base classes, 2 flops each.
+FLOPS_PER_WINDOW_STRAND = 2 * 32 * 4
 
 
 def log(*a):
@@ -145,26 +153,31 @@ def choose_variant(ifa, s, args, queries, ks):
 
 
 def roofline(ifa, st, sparse_strands, variant):
-    """Roofline of the filter kernel: its algorithmic VALU ops per launch are
-    OPS_PER_WINDOW_STRAND x the query strands it filters x the window starts
-    it evaluated (counted by the library: waves holding a reference N go
-    whole to the resolve kernel and are not counted), over its average
-    launch time from HIP events on the stream it runs on."""
+    """Roofline of the filter kernel (the dominant one): its algorithmic work
+    per launch is the per-unit figure (OPS_PER_WINDOW_STRAND VALU ops, or
+    FLOPS_PER_WINDOW_STRAND matrix-core flops for the fp4 variant) x the
+    query strands it filters x the window starts it evaluated (counted by the
+    library: waves holding a reference N go whole to the resolve kernel and
+    are not counted), over its average launch time from HIP events on the
+    stream it runs on."""
     launches = max(1, st["filter_launches"])
     filter_ms_avg = st["filter_ms"] / launches
-    ops_per_launch = OPS_PER_WINDOW_STRAND * sparse_strands * st["filter_windows"] / launches
-    achieved = ops_per_launch / (filter_ms_avg * 1e-3) / 1e12 if st["filter_launches"] else 0.0
-    peak = PEAK_VALU_OPS / 1e12
+    shape = ifa.ifa_variant_info(variant)
+    mfma = shape["encoding"] == 1
+    per_unit = FLOPS_PER_WINDOW_STRAND if mfma else OPS_PER_WINDOW_STRAND
+    work_per_launch = per_unit * sparse_strands * st["filter_windows"] / launches
+    achieved = work_per_launch / (filter_ms_avg * 1e-3) / 1e12 if st["filter_launches"] else 0.0
+    peak = (PEAK_FP4_FLOPS if mfma else PEAK_VALU_OPS) / 1e12
     return {
-        "bound": "alu",
+        "bound": "mfma" if mfma else "alu",
         "achieved": round(achieved, 3),
         "peak": round(peak, 3),
-        "unit": "TOP/s",
+        "unit": "TFLOP/s" if mfma else "TOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": None,
-        "kernel": "scan_filter_kernel",
+        "kernel": "scan_filter_mfma_kernel" if mfma else "scan_filter_kernel",
         "variant": variant,
-        "variant_shape": ifa.ifa_variant_info(variant),
+        "variant_shape": shape,
         "kernel_ms_avg": round(filter_ms_avg, 4),
         "launches": st["filter_launches"],
         "windows_per_launch": st["filter_windows"] // launches,

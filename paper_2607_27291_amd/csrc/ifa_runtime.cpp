@@ -1457,12 +1457,21 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
         hip_check(hipMemcpy(ch.pieces.p, &pc, sizeof pc, hipMemcpyHostToDevice), "upload piece");
         ch.len = calib_bases;
         ch.n_pieces = 1;
-        // hits go to a small scratch buffer and the work list to a scratch
-        // list; the tuner only times (a full scratch list skips the resolve)
+        // hits go to the context's kind of sink in scratch memory (a small
+        // record buffer, or scratch per-query counters: the sinks differ in
+        // cost when hits are dense) and the work list to a scratch list; the
+        // tuner only times (a full scratch list skips the resolve)
         DevBuf<uint4> scratch_hits;
         scratch_hits.alloc(1024, "tuning hit buffer");
         DevBuf<unsigned long long> scratch_cnt;
         scratch_cnt.alloc(2, "tuning counter");
+        DevBuf<unsigned long long> scratch_qc, scratch_qd;
+        const bool digest = c->cfg.sink == IFA_SINK_COUNT_DIGEST;
+        if (digest) {
+            const size_t need = (size_t)std::max<uint32_t>(c->n_queries, 1) * kStripes;
+            scratch_qc.alloc(need, "tuning query counters");
+            scratch_qd.alloc(need, "tuning query digests");
+        }
         DevBuf<WorkItem> scratch_work;
         scratch_work.alloc(1u << 16, "tuning work list");
         DevBuf<unsigned int> scratch_wc;
@@ -1475,10 +1484,12 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
         for (uint32_t v = 0; v < nv; v++) {
             c->variant = v;
             ScanArgs a = make_args(c, ch, 0);
-            a.sink = kSinkRecords;
+            a.sink = digest ? kSinkCountDigest : kSinkRecords;
             a.hits = scratch_hits.p;
             a.hit_count = scratch_cnt.p;
             a.hit_cap = 1024;
+            a.q_count = scratch_qc.p;
+            a.q_digest = scratch_qd.p;
             a.work = scratch_work.p;
             a.work_count = scratch_wc.p;
             a.skip_count = scratch_wc.p + 1;

@@ -836,18 +836,19 @@ struct VariantDesc {
     uint32_t qunroll;   // QU
     uint32_t wg;        // filter workgroup size
     uint32_t enc;       // filter arithmetic: 0 = VALU bit ops, 1 = fp4 matrix cores
+    uint32_t waves;     // matrix-core filter: waves launched over all batches
 };
 
 #define IFA_V(W, QU, WG)                                                                 \
     {                                                                                    \
         scan_filter_kernel<W, QU, WG>, scan_resolve_kernel<W>, scan_dense_kernel<W>,     \
-            scan_dense_cold_kernel<W>, W, QU, WG, 0                                      \
+            scan_dense_cold_kernel<W>, W, QU, WG, 0, 0                                   \
     }
 // matrix-core filter: waves of 16 windows per lane, resolved by the W = 16 kernels
-#define IFA_VM(WG)                                                                       \
+#define IFA_VM(WG, WAVES)                                                                \
     {                                                                                    \
         scan_filter_mfma_kernel<WG>, scan_resolve_kernel<16>, scan_dense_kernel<16>,     \
-            scan_dense_cold_kernel<16>, 16, 2, WG, 1                                     \
+            scan_dense_cold_kernel<16>, 16, 2, WG, 1, WAVES                              \
     }
 static const VariantDesc kVariantTable[] = {
     IFA_V(32, 1, 256),   // 0: default
@@ -856,7 +857,8 @@ static const VariantDesc kVariantTable[] = {
     IFA_V(16, 1, 256),   IFA_V(16, 1, 128),  IFA_V(16, 1, 512),
     IFA_V(16, 2, 256),   IFA_V(16, 2, 512),
     IFA_V(32, 2, 512),   IFA_V(16, 2, 1024),
-    IFA_VM(256),         IFA_VM(64),          IFA_VM(512),
+    IFA_VM(512, 32768),  IFA_VM(256, 32768),  IFA_VM(1024, 32768),
+    IFA_VM(512, 16384),  IFA_VM(512, 65536),  IFA_VM(1024, 65536),
 };
 #undef IFA_V
 #undef IFA_VM
@@ -877,10 +879,6 @@ static const VariantDesc &pick(const ScanArgs &a)
     return kVariantTable[a.variant < variant_count() ? a.variant : 0];
 }
 
-// Filter waves each wave of the matrix-core filter walks (amortizes the
-// workgroup's LDS fill).
-constexpr uint32_t kMqWavesPerWave = 8;
-
 // Filter lanes of the word range (a multiple of 64, whole waves).
 static uint64_t filter_lanes(const ScanArgs &a, const VariantDesc &v)
 {
@@ -895,12 +893,13 @@ hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
     if (a.w_end <= a.w_begin || a.n_sparse == 0) return hipSuccess;
     const VariantDesc &v = pick(a);
     if (v.enc == 1) {
-        // each workgroup walks kMqWavesPerWave filter waves per wave of its
-        // own, for one batch of 32 strands (grid y)
+        // about v.waves waves over all batches of 32 strands (grid y), at
+        // most one per filter wave; each walks its share of the filter waves
         const uint32_t waves = (a.w_end - a.w_begin + 31u) >> 5;
-        const uint32_t per_wg = (v.wg / 64u) * kMqWavesPerWave;
-        const uint32_t gx = (waves + per_wg - 1) / per_wg;
+        const uint32_t wpg = v.wg / 64u;
         const uint32_t batches = (a.n_sparse + 31u) / 32u;
+        const uint32_t want = (v.waves + wpg * batches - 1) / (wpg * batches);
+        const uint32_t gx = max(1u, min((waves + wpg - 1) / wpg, want));
         const uint32_t tiles = min(16u, (a.n_sparse + 1u) / 2u);
         hipLaunchKernelGGL(v.filter, dim3(gx, batches), dim3(v.wg), mq_lds_bytes(tiles), s, a);
         return hipGetLastError();
