@@ -44,9 +44,10 @@ PEAK_VALU_OPS = 256 * 4 * 32 * 2.4e9
 OPS_PER_WINDOW_STRAND = 3.5
 # Dense fp4 (e2m1) matrix-core peak of MI355X.
 PEAK_FP4_FLOPS = 10.1e15
-# Algorithmic flops per window x query strand for the matrix-core filter: the
-# one-hot match count over 32 positions x 4 base classes, 2 flops each.
-FLOPS_PER_WINDOW_STRAND = 2 * 32 * 4
+# Algorithmic flops per window x query strand for the matrix-core filters:
+# the match count over 32 positions as a contraction of base-class codes,
+# 2 flops per position and class: 4 classes (encoding 1) or 3 (encoding 2).
+FLOPS_PER_WINDOW_STRAND = {1: 2 * 32 * 4, 2: 2 * 32 * 3}
 
 
 def log(*a):
@@ -155,7 +156,7 @@ def choose_variant(ifa, s, args, queries, ks):
 def roofline(ifa, st, sparse_strands, variant):
     """Roofline of the filter kernel (the dominant one): its algorithmic work
     per launch is the per-unit figure (OPS_PER_WINDOW_STRAND VALU ops, or
-    FLOPS_PER_WINDOW_STRAND matrix-core flops for the fp4 variant) x the
+    FLOPS_PER_WINDOW_STRAND matrix-core flops for the fp4 variants) x the
     query strands it filters x the window starts it evaluated (counted by the
     library: waves holding a reference N go whole to the resolve kernel and
     are not counted), over its average launch time from HIP events on the
@@ -163,8 +164,8 @@ def roofline(ifa, st, sparse_strands, variant):
     launches = max(1, st["filter_launches"])
     filter_ms_avg = st["filter_ms"] / launches
     shape = ifa.ifa_variant_info(variant)
-    mfma = shape["encoding"] == 1
-    per_unit = FLOPS_PER_WINDOW_STRAND if mfma else OPS_PER_WINDOW_STRAND
+    mfma = shape["encoding"] in FLOPS_PER_WINDOW_STRAND
+    per_unit = FLOPS_PER_WINDOW_STRAND[shape["encoding"]] if mfma else OPS_PER_WINDOW_STRAND
     work_per_launch = per_unit * sparse_strands * st["filter_windows"] / launches
     achieved = work_per_launch / (filter_ms_avg * 1e-3) / 1e12 if st["filter_launches"] else 0.0
     peak = (PEAK_FP4_FLOPS if mfma else PEAK_VALU_OPS) / 1e12
@@ -175,7 +176,8 @@ def roofline(ifa, st, sparse_strands, variant):
         "unit": "TFLOP/s" if mfma else "TOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": None,
-        "kernel": "scan_filter_mfma_kernel" if mfma else "scan_filter_kernel",
+        "kernel": {0: "scan_filter_kernel", 1: "scan_filter_mfma_kernel",
+                   2: "scan_filter_mfma3_kernel"}[shape["encoding"]],
         "variant": variant,
         "variant_shape": shape,
         "kernel_ms_avg": round(filter_ms_avg, 4),

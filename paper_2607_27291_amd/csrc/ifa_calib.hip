@@ -224,3 +224,75 @@ extern "C" double ifa_calib_mfma(int shape, uint32_t blocks, uint32_t iters)
     const double flops = shape == 0 ? 2.0 * 32 * 32 * 64 : 2.0 * 16 * 16 * 128;
     return waves * iters * 4.0 * flops / (ms * 1e-3) / 1e12;
 }
+
+// Overlap probe: waves of one launch run either fp4 MFMA chains (four
+// independent accumulators) or v_max3_u32 chains (16 independent), chosen by
+// mode: 0 all MFMA, 1 all VALU, 2 even waves MFMA and odd waves VALU. Timing
+// the three shows whether the matrix core and the VALU run concurrently.
+__global__ __launch_bounds__(256) void calib_mix_kernel(float *out, uint32_t iters, uint32_t mode,
+                                                        uint32_t seed)
+{
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t wv = gid >> 6;
+    const bool do_mfma = mode == 0 || (mode == 2 && (wv & 1u) == 0u);
+    float s = 0.f;
+    if (do_mfma) {
+        calib_v8i va = {}, vb = {};
+        for (int j = 0; j < 4; j++) {
+            va[j] = (int)((gid * 2654435761u + seed * (uint32_t)(j + 1)) & 0x77777777u);
+            vb[j] = (int)((gid * 40503u + seed + (uint32_t)j * 977u) & 0x77777777u);
+        }
+        calib_v16f c0 = {}, c1 = {}, c2 = {}, c3 = {};
+        for (uint32_t i = 0; i < iters; i++) {
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, vb, c0, 4, 4, 0, 127, 0, 127);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(vb, va, c1, 4, 4, 0, 127, 0, 127);
+            c2 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, va, c2, 4, 4, 0, 127, 0, 127);
+            c3 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(vb, vb, c3, 4, 4, 0, 127, 0, 127);
+        }
+        for (int j = 0; j < 16; j++) s += c0[j] + c1[j] + c2[j] + c3[j];
+    } else {
+        uint32_t a[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) a[j] = gid * 2654435761u + (uint32_t)j * 40503u + seed;
+        // 8 x 16 max3 per iteration: as many VALU issue slots as 4 MFMAs
+        // leave at one VALU instruction per 4 clocks
+        for (uint32_t i = 0; i < iters; i++) {
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int j = 0; j < 16; j++)
+                    a[j] = max(max(a[j], a[(j + 1) & 15] ^ seed), a[(j + 5) & 15] + seed);
+        }
+        uint32_t x = 0;
+#pragma unroll
+        for (int j = 0; j < 16; j++) x ^= a[j];
+        s = (float)x;
+    }
+    out[gid] = s;
+}
+
+// Milliseconds of one calib_mix_kernel launch over blocks x 256 threads, or
+// a negative HIP error code.
+extern "C" double ifa_calib_mix(uint32_t mode, uint32_t blocks, uint32_t iters)
+{
+    if (mode > 2 || blocks == 0 || iters == 0) return -1.0;
+    const uint64_t threads = (uint64_t)blocks * 256u;
+    float *out = nullptr;
+    hipError_t e = hipMalloc((void **)&out, threads * sizeof(float));
+    if (e != hipSuccess) return -(double)e;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    hipLaunchKernelGGL(calib_mix_kernel, dim3(blocks), dim3(256), 0, 0, out, iters, mode, 12345u);
+    (void)hipEventRecord(a, 0);
+    hipLaunchKernelGGL(calib_mix_kernel, dim3(blocks), dim3(256), 0, 0, out, iters, mode, 54321u);
+    (void)hipEventRecord(b, 0);
+    e = hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(out);
+    if (e != hipSuccess) return -(double)e;
+    return ms;
+}

@@ -97,6 +97,10 @@ struct ScanArgs {
     // needs to stay a candidate (padding columns: unreachable)
     const uint4 *mq_b;
     const float *mq_t;
+    // three-class form: four strands (x 8 shifts) per tile, two K steps;
+    // mq3_b[(2 tile + K step) * 64 + lane], mq3_t[32 tile + column]
+    const uint4 *mq3_b;
+    const float *mq3_t;
     // count+digest sink, kStripes slots per query (see kStripes)
     unsigned long long *q_count;
     unsigned long long *q_digest;

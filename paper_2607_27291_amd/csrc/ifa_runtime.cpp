@@ -214,6 +214,8 @@ struct ifa_ctx {
     DevBuf<uint32_t> d_qwords;
     DevBuf<uint4> d_mqb;              // matrix-core filter B operands
     DevBuf<float> d_mqt;              // and required match counts
+    DevBuf<uint4> d_mq3b;             // three-class form of the same
+    DevBuf<float> d_mq3t;
     DevBuf<unsigned long long> d_qcount, d_qdigest;
 
     // streaming
@@ -428,6 +430,8 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.qwords = c->d_qwords.p;
     a.mq_b = c->d_mqb.p;
     a.mq_t = c->d_mqt.p;
+    a.mq3_b = c->d_mq3b.p;
+    a.mq3_t = c->d_mq3t.p;
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
@@ -935,6 +939,53 @@ void build_mfma_operands(const std::vector<QSDesc> &qs, uint32_t n_sparse,
     }
 }
 
+// Operands of the three-class matrix-core filter: tile nt holds strands
+// 4nt .. 4nt+3, column c = 8 (strand - 4nt) + shift r. For lane l (column
+// l % 32, half h = l / 32), K step t, register d the slot is z = 8h + 4t + d:
+// segment block k = z / 3 and class z % 3 (C, G, T; codes 1, 3, 2); nibble o
+// is segment base i = 8k + o and query base j = i - r. The value is +1.0
+// (e2m1 code 2) when 0 <= j < min(L, 32) and the query base there has the
+// slot's class, -1.0 (code 0xA) when it is A, else 0; slot 15 stays 0.
+// need[c] = min(L, 32) - thr - nA, nA = A bases among those positions.
+void build_mfma3_operands(const std::vector<QSDesc> &qs, uint32_t n_sparse,
+                          std::vector<uint32_t> &b, std::vector<float> &need)
+{
+    static const uint32_t kClass[3] = {1u, 3u, 2u};
+    const uint32_t n_tiles = (n_sparse + 3) / 4;
+    b.assign((size_t)n_tiles * 2 * 64 * 4, 0u);
+    need.assign((size_t)n_tiles * 32, 1e30f);
+    for (uint32_t nt = 0; nt < n_tiles; nt++) {
+        for (uint32_t c = 0; c < 32; c++) {
+            const uint32_t s = 4 * nt + c / 8, r = c % 8;
+            if (s >= n_sparse) continue;
+            const QSDesc &d = qs[s];
+            const uint32_t l32 = std::min<uint32_t>(d.len, 32u);
+            auto code = [&](uint32_t j) { return 2u * ((d.qh0 >> j) & 1u) + ((d.ql0 >> j) & 1u); };
+            uint32_t n_a = 0;
+            for (uint32_t j = 0; j < l32; j++)
+                if (!((d.qn0 >> j) & 1u) && code(j) == 0u) n_a++;
+            need[32 * nt + c] = (float)l32 - (float)d.thr - (float)n_a;
+            for (uint32_t h = 0; h < 2; h++)
+                for (uint32_t t = 0; t < 2; t++)
+                    for (uint32_t dd = 0; dd < 4; dd++) {
+                        const uint32_t z = 8 * h + 4 * t + dd;
+                        if (z >= 15) continue;
+                        const uint32_t k = z / 3, cls = kClass[z % 3];
+                        uint32_t word = 0;
+                        for (uint32_t o = 0; o < 8; o++) {
+                            const int32_t j = (int32_t)(8 * k + o) - (int32_t)r;
+                            if (j < 0 || j >= (int32_t)l32 || ((d.qn0 >> j) & 1u)) continue;
+                            const uint32_t q = code((uint32_t)j);
+                            if (q == cls) word |= 0x2u << (4 * o);
+                            else if (q == 0u) word |= 0xAu << (4 * o);
+                        }
+                        const size_t lane = c + 32 * h;
+                        b[((2 * (size_t)nt + t) * 64 + lane) * 4 + dd] = word;
+                    }
+        }
+    }
+}
+
 void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t> &&words,
                      uint32_t n_queries, uint32_t lmax)
 {
@@ -983,6 +1034,18 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
                       "upload matrix filter operands");
         if (!mt.empty())
             hip_check(hipMemcpy(c->d_mqt.p, mt.data(), mt.size() * sizeof(float),
+                                hipMemcpyHostToDevice),
+                      "upload matrix filter counts");
+        build_mfma3_operands(qs, n_sparse, mb, mt);
+        const size_t nb3 = std::max<size_t>(mb.size() / 4, 1), nt3 = std::max<size_t>(mt.size(), 1);
+        if (c->d_mq3b.n < nb3 || !c->d_mq3b.p) c->d_mq3b.alloc(nb3, "matrix filter operands");
+        if (c->d_mq3t.n < nt3 || !c->d_mq3t.p) c->d_mq3t.alloc(nt3, "matrix filter counts");
+        if (!mb.empty())
+            hip_check(hipMemcpy(c->d_mq3b.p, mb.data(), mb.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice),
+                      "upload matrix filter operands");
+        if (!mt.empty())
+            hip_check(hipMemcpy(c->d_mq3t.p, mt.data(), mt.size() * sizeof(float),
                                 hipMemcpyHostToDevice),
                       "upload matrix filter counts");
     }
@@ -1545,7 +1608,8 @@ ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
     }
     b += c->d_hitcount.n * sizeof(unsigned long long) + c->d_workcount.n * sizeof(unsigned int);
     b += c->d_qs.n * sizeof(QSDesc) + c->d_qwords.n * sizeof(uint32_t) +
-         c->d_mqb.n * sizeof(uint4) + c->d_mqt.n * sizeof(float);
+         c->d_mqb.n * sizeof(uint4) + c->d_mqt.n * sizeof(float) +
+         c->d_mq3b.n * sizeof(uint4) + c->d_mq3t.n * sizeof(float);
     b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
     for (const auto &r : c->resident)
         b += r->planes.n * sizeof(uint32_t) + r->pieces.n * sizeof(Piece);

@@ -671,6 +671,136 @@ static uint32_t mq_lds_bytes(uint32_t tiles)
     return tiles * (192u * 16u + 32u * 4u) + 256u * 4u;
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core filter, three-class form (fewer K steps).
+//
+// For a reference base that is not N, [S = A] = 1 - [S = C] - [S = G] -
+// [S = T], so with nA the number of A bases among the first L32 query bases
+//   matches(p, s) = nA + sum over j < L32, b in {C, G, T} of [S[p+j] = b] w
+// where w = +1 if Q_s[j] = b, -1 if Q_s[j] = A, 0 if Q_s[j] is another base
+// or N. Three indicator classes per base instead of four: groups of 8
+// windows read a 39-base segment, 117 K values, which fit two K steps of 64
+// (against three for the four-class form with 16 windows per group), so
+// every K element the instruction multiplies is used.
+//
+// Tile: 32 groups x 8 windows = 256 window starts; four tiles per filter wave.
+// Column tile: 4 strands x 8 shifts. K layout: the segment's 8-base blocks
+// k = 0..4 each give three indicator words (class C, G, T; nibble o = base
+// 8k + o, e2m1 1.0 or 0); slot z = 8h + 4t + d (K step t, lane half h,
+// register d) holds block z / 3, class z % 3; slot 15 meets only zero B
+// entries. A wave first writes the indicator words of its 1056-base stream
+// (blocks of 8 bases, three words each) to its own LDS area, where the slots
+// of lane (g, h) in tile u are the 8 consecutive words from 3 (32u + g) + 8h.
+// mq3_t holds the match count minus nA that a column needs.
+// ---------------------------------------------------------------------------
+
+constexpr uint32_t kM3Blocks = 136;            // 8-base blocks staged per wave
+constexpr uint32_t kM3Words = 3 * kM3Blocks;   // indicator words per wave
+
+template <int WG>
+__global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
+{
+    extern __shared__ uint4 lds[];
+    const uint32_t qb = 32u * blockIdx.y;
+    const uint32_t n_tiles = (a.n_sparse + 3u) >> 2;
+    const uint32_t t0 = qb >> 2, tn = min(n_tiles, t0 + 8u) - t0;   // tiles of the batch
+    uint4 *sb = lds;                                                // [tn][2][64]
+    float *st = reinterpret_cast<float *>(lds + 128u * tn);         // [tn][32]
+    uint32_t *sp = reinterpret_cast<uint32_t *>(st + 32u * tn);     // [256]
+    uint32_t *flat = sp + 256u + (threadIdx.x >> 6) * kM3Words;     // this wave's words
+    for (uint32_t i = threadIdx.x; i < 128u * tn; i += WG) sb[i] = a.mq3_b[128u * t0 + i];
+    for (uint32_t i = threadIdx.x; i < 32u * tn; i += WG) st[i] = a.mq3_t[32u * t0 + i];
+    for (uint32_t i = threadIdx.x; i < 256u; i += WG) sp[i] = kSpread.v[i];
+    __syncthreads();
+
+    const uint32_t l = threadIdx.x & 63u;
+    const uint32_t g = l & 31u, h = l >> 5;
+    const uint32_t last = (uint32_t)((a.chunk_len + 31) >> 5) + kPadWords - 1;
+    const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
+    const uint32_t stride = gridDim.x * (WG / 64u);
+    const ifa_v16f zero = {};
+    for (uint32_t wave = blockIdx.x * (WG / 64u) + (threadIdx.x >> 6); wave < n_waves;
+         wave += stride) {
+        const uint32_t w0 = a.w_begin + 32u * wave;
+        const uint32_t lw = w0 + (l >> 1);
+        bool lane_n = false;
+        if (lw < a.w_end) lane_n = (a.nm[lw] | a.nm[min(lw + 1u, last)]) != 0u;
+        if (__any(lane_n)) {
+            if (l == 0u) {
+                if (blockIdx.y == 0) atomicAdd(a.skip_count, 1u);
+                list_batch(a, wave, qb);
+            }
+            continue;
+        }
+        // stage the indicator words of blocks l, l + 64, l + 128
+#pragma unroll
+        for (uint32_t r = 0; r < 3; r++) {
+            const uint32_t b = l + 64u * r;
+            if (b < kM3Blocks) {
+                const uint32_t w = min(w0 + (b >> 2), last), sh = 8u * (b & 3u);
+                const uint32_t s1 = sp[(a.hi[w] >> sh) & 0xffu];
+                const uint32_t s0 = sp[(a.lo[w] >> sh) & 0xffu];
+                const uint32_t m = 0x22222222u;
+                flat[3u * b] = ~s1 & s0 & m;        // C (hi 0, lo 1)
+                flat[3u * b + 1u] = s1 & s0 & m;    // G (1, 1)
+                flat[3u * b + 2u] = s1 & ~s0 & m;   // T (1, 0)
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ifa_v8i A[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const uint32_t *f = flat + 3u * (32u * u + g) + 8u * h;
+#pragma unroll
+            for (int t = 0; t < 2; t++)
+                A[u][t] = ifa_v8i{(int)f[4 * t], (int)f[4 * t + 1], (int)f[4 * t + 2],
+                                  (int)f[4 * t + 3], 0, 0, 0, 0};
+        }
+        uint32_t pending = 0;   // wave-uniform
+        for (uint32_t nt = 0; nt < tn; nt++) {
+            const uint4 v0 = sb[(2u * nt) * 64u + l], v1 = sb[(2u * nt + 1u) * 64u + l];
+            const ifa_v8i B0 = {(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, 0, 0, 0, 0};
+            const ifa_v8i B1 = {(int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w, 0, 0, 0, 0};
+            const float need = st[32u * nt + g];
+            float mx = -1e30f;
+#pragma unroll
+            for (int p = 0; p < 2; p++) {
+                ifa_v16f d0 = mfma_fp4(A[2 * p][0], B0, zero);
+                ifa_v16f d1 = mfma_fp4(A[2 * p + 1][0], B0, zero);
+                d0 = mfma_fp4(A[2 * p][1], B1, d0);
+                d1 = mfma_fp4(A[2 * p + 1][1], B1, d1);
+#pragma unroll
+                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(d0[i], d1[i]), mx);
+            }
+            const uint64_t m = __ballot(mx >= need);
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++)
+                if (m & (0x000000ff000000ffull << (8u * q))) pending |= 1u << (4u * nt + q);
+        }
+        if (pending && l == 0u) {
+            const unsigned int idx = atomicAdd(a.work_count, 1u);
+            if (idx < a.work_cap) {
+                WorkItem it;
+                it.wave = wave;
+                it.qb = qb;
+                it.pending = pending;
+                it.pad = 0;
+                a.work[idx] = it;
+            }
+        }
+        // the next iteration rewrites this wave's words: all reads done first
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// LDS bytes of the three-class matrix filter for `tiles` column tiles.
+static uint32_t mq3_lds_bytes(uint32_t tiles, uint32_t wg)
+{
+    return tiles * (128u * 16u + 32u * 4u) + 256u * 4u + (wg / 64u) * kM3Words * 4u;
+}
+
 // One wave per work item (grid-stride). Does nothing when the filter kernel
 // overflowed the list: the host then grows it and runs the sparse part again.
 template <int W>
@@ -836,6 +966,7 @@ struct VariantDesc {
     uint32_t qunroll;   // QU
     uint32_t wg;        // filter workgroup size
     uint32_t enc;       // filter arithmetic: 0 = VALU bit ops, 1 = fp4 matrix cores
+                        // (four classes), 2 = fp4 matrix cores (three classes)
     uint32_t waves;     // matrix-core filter: waves launched over all batches
 };
 
@@ -844,7 +975,12 @@ struct VariantDesc {
         scan_filter_kernel<W, QU, WG>, scan_resolve_kernel<W>, scan_dense_kernel<W>,     \
             scan_dense_cold_kernel<W>, W, QU, WG, 0, 0                                   \
     }
-// matrix-core filter: waves of 16 windows per lane, resolved by the W = 16 kernels
+// matrix-core filters: waves of 16 windows per lane, resolved by the W = 16 kernels
+#define IFA_VM3(WG, WAVES)                                                               \
+    {                                                                                    \
+        scan_filter_mfma3_kernel<WG>, scan_resolve_kernel<16>, scan_dense_kernel<16>,    \
+            scan_dense_cold_kernel<16>, 16, 4, WG, 2, WAVES                              \
+    }
 #define IFA_VM(WG, WAVES)                                                                \
     {                                                                                    \
         scan_filter_mfma_kernel<WG>, scan_resolve_kernel<16>, scan_dense_kernel<16>,     \
@@ -859,9 +995,12 @@ static const VariantDesc kVariantTable[] = {
     IFA_V(32, 2, 512),   IFA_V(16, 2, 1024),
     IFA_VM(512, 32768),  IFA_VM(256, 32768),  IFA_VM(1024, 32768),
     IFA_VM(512, 16384),  IFA_VM(512, 65536),  IFA_VM(1024, 65536),
+    IFA_VM3(512, 32768), IFA_VM3(256, 32768), IFA_VM3(1024, 32768),
+    IFA_VM3(512, 65536), IFA_VM3(256, 16384),
 };
 #undef IFA_V
 #undef IFA_VM
+#undef IFA_VM3
 
 uint32_t variant_count() { return sizeof(kVariantTable) / sizeof(kVariantTable[0]); }
 
@@ -892,7 +1031,7 @@ hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
 {
     if (a.w_end <= a.w_begin || a.n_sparse == 0) return hipSuccess;
     const VariantDesc &v = pick(a);
-    if (v.enc == 1) {
+    if (v.enc == 1 || v.enc == 2) {
         // about v.waves waves over all batches of 32 strands (grid y), at
         // most one per filter wave; each walks its share of the filter waves
         const uint32_t waves = (a.w_end - a.w_begin + 31u) >> 5;
@@ -900,8 +1039,9 @@ hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
         const uint32_t batches = (a.n_sparse + 31u) / 32u;
         const uint32_t want = (v.waves + wpg * batches - 1) / (wpg * batches);
         const uint32_t gx = max(1u, min((waves + wpg - 1) / wpg, want));
-        const uint32_t tiles = min(16u, (a.n_sparse + 1u) / 2u);
-        hipLaunchKernelGGL(v.filter, dim3(gx, batches), dim3(v.wg), mq_lds_bytes(tiles), s, a);
+        const uint32_t lds = v.enc == 1 ? mq_lds_bytes(min(16u, (a.n_sparse + 1u) / 2u))
+                                        : mq3_lds_bytes(min(8u, (a.n_sparse + 3u) / 4u), v.wg);
+        hipLaunchKernelGGL(v.filter, dim3(gx, batches), dim3(v.wg), lds, s, a);
         return hipGetLastError();
     }
     const uint64_t lanes = filter_lanes(a, v);

@@ -351,7 +351,7 @@ def test_dense_and_sparse_strands_with_work_list_overflow(ifa, orc, sink):
 
 
 def matrix_variants(ifa):
-    return [v for v in range(ifa.ifa_variant_count()) if ifa.ifa_variant_info(v)["encoding"] == 1]
+    return [v for v in range(ifa.ifa_variant_count()) if ifa.ifa_variant_info(v)["encoding"] >= 1]
 
 
 @pytest.mark.parametrize("strands,policy", [(1, 0), (3, 1)])
