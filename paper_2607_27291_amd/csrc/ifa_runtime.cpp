@@ -210,12 +210,15 @@ struct ifa_ctx {
     std::vector<QSDesc> h_qs;         // sparse strands first, then dense
     uint32_t n_sparse = 0;
     std::vector<uint32_t> h_qwords;
-    DevBuf<QSDesc> d_qs;
-    DevBuf<uint32_t> d_qwords;
-    DevBuf<uint4> d_mqb;              // matrix-core filter B operands
-    DevBuf<float> d_mqt;              // and required match counts
-    DevBuf<uint4> d_mq3b;             // three-class form of the same
-    DevBuf<float> d_mq3t;
+    // device query tables, uploaded together through a pinned staging arena:
+    // strand descriptors, packed words, the matrix-core filters' B operands
+    // and required match counts (four- and three-class forms)
+    DevBuf<uint8_t> d_qarena;
+    HostBuf<uint8_t> h_qarena;
+    const QSDesc *dq_qs = nullptr;
+    const uint32_t *dq_words = nullptr;
+    const uint4 *dq_mqb = nullptr, *dq_mq3b = nullptr;
+    const float *dq_mqt = nullptr, *dq_mq3t = nullptr;
     DevBuf<unsigned long long> d_qcount, d_qdigest;
 
     // streaming
@@ -227,14 +230,14 @@ struct ifa_ctx {
 
     // hits
     DevBuf<uint4> d_hits[2];
-    DevBuf<unsigned long long> d_hitcount;   // [2]
-    HostBuf<unsigned long long> h_hitcount;  // [2]
+    // pass counters, 16 bytes per hit buffer hb: [2 hb] hit count, [2 hb + 1]
+    // work items (low word) and waves handed to the resolve kernel (high)
+    DevBuf<unsigned long long> d_ctr;   // [4]
+    HostBuf<unsigned long long> h_ctr;  // [4], pinned
     uint64_t hit_cap = 0;             // configured records per hit buffer
     uint64_t buf_cap[2] = {0, 0};     // current records per hit buffer
     DevBuf<WorkItem> work[2];         // sparse-path work lists, one per hit buffer
     uint32_t work_cap[2] = {0, 0};
-    DevBuf<unsigned int> d_workcount; // [4]: work items, skipped waves; per hit buffer
-    HostBuf<unsigned int> h_workcount;
     uint32_t work_want = 0;           // capacity both work lists grow to before a launch
     Job jobs[2];
     uint64_t job_seq = 0;
@@ -423,25 +426,25 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.w_begin = 0;
     a.w_end = (uint32_t)((ch.len + 31) >> 5);
     a.lmax = c->lmax;
-    a.qs = c->d_qs.p;
+    a.qs = c->dq_qs;
     a.n_qs = (uint32_t)c->h_qs.size();
     a.n_sparse = c->n_sparse;
     a.policy = c->cfg.n_policy;
-    a.qwords = c->d_qwords.p;
-    a.mq_b = c->d_mqb.p;
-    a.mq_t = c->d_mqt.p;
-    a.mq3_b = c->d_mq3b.p;
-    a.mq3_t = c->d_mq3t.p;
+    a.qwords = c->dq_words;
+    a.mq_b = c->dq_mqb;
+    a.mq_t = c->dq_mqt;
+    a.mq3_b = c->dq_mq3b;
+    a.mq3_t = c->dq_mq3t;
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
     a.variant = c->variant;
     a.work = c->work[hb].p;
-    a.work_count = c->d_workcount.p + 2 * hb;
+    a.work_count = reinterpret_cast<unsigned int *>(c->d_ctr.p + 2 * hb + 1);
     a.skip_count = a.work_count + 1;
     a.work_cap = c->work_cap[hb];
     a.hits = c->d_hits[hb].p;
-    a.hit_count = c->d_hitcount.p + hb;
+    a.hit_count = c->d_ctr.p + 2 * hb;
     a.hit_cap = c->buf_cap[hb];
     a.q_count = c->d_qcount.p;
     a.q_digest = c->d_qdigest.p;
@@ -504,9 +507,11 @@ struct PassEvents {
 // kernel. Counters are cleared by kernels on the stream first.
 void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, PassEvents &ev)
 {
-    if (clear_hits && c->cfg.sink == IFA_SINK_RECORDS)
-        hip_check(launch_clear_u64(a.hit_count, 1, c->comp_s), "clear hit counter");
-    hip_check(launch_clear_u32(a.work_count, 2, c->comp_s), "clear work counters");
+    // the pass counters of a hit buffer are adjacent (hit count, then the
+    // work and skip counts): one clear kernel
+    hip_check(clear_hits ? launch_clear_u64(a.hit_count, 2, c->comp_s)
+                         : launch_clear_u64(a.hit_count + 1, 1, c->comp_s),
+              "clear pass counters");
     hip_check(hipEventRecord(ev.t0, c->comp_s), "event record");
     hip_check(launch_filter(a, c->comp_s), "filter launch");
     hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
@@ -517,13 +522,20 @@ void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, Pa
 
 void enqueue_count_copies(ifa_ctx *c, int hb)
 {
-    if (c->cfg.sink == IFA_SINK_RECORDS)
-        hip_check(hipMemcpyAsync(c->h_hitcount.p + hb, c->d_hitcount.p + hb,
-                                 sizeof(unsigned long long), hipMemcpyDeviceToHost, c->comp_s),
-                  "copy hit count");
-    hip_check(hipMemcpyAsync(c->h_workcount.p + 2 * hb, c->d_workcount.p + 2 * hb,
-                             2 * sizeof(unsigned int), hipMemcpyDeviceToHost, c->comp_s),
-              "copy work counters");
+    hip_check(hipMemcpyAsync(c->h_ctr.p + 2 * hb, c->d_ctr.p + 2 * hb,
+                             2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->comp_s),
+              "copy pass counters");
+}
+
+// Pass counters of hit buffer hb on the host (valid after the pass's copy).
+uint64_t host_hits(const ifa_ctx *c, int hb) { return c->h_ctr.p[2 * hb]; }
+uint32_t host_work(const ifa_ctx *c, int hb)
+{
+    return reinterpret_cast<const unsigned int *>(c->h_ctr.p + 2 * hb + 1)[0];
+}
+uint32_t host_skip(const ifa_ctx *c, int hb)
+{
+    return reinterpret_cast<const unsigned int *>(c->h_ctr.p + 2 * hb + 1)[1];
 }
 
 // Book the times of a finished pass over words [w0, w1) whose counters are
@@ -540,9 +552,9 @@ void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse, int hb, uint3
         uint32_t wpl, qu, wg, enc;
         variant_shape(c->variant, &wpl, &qu, &wg, &enc);
         const uint64_t starts = 32ull * (w1 - w0);
-        const uint64_t skipped = 64ull * wpl * c->h_workcount.p[2 * hb + 1];
+        const uint64_t skipped = 64ull * wpl * host_skip(c, hb);
         c->st.filter_windows += starts > skipped ? starts - skipped : 0;
-        c->st.work_items += c->h_workcount.p[2 * hb];
+        c->st.work_items += host_work(c, hb);
     }
 }
 
@@ -560,8 +572,8 @@ void ensure_work_list(ifa_ctx *c, int hb)
 // Its dense part is not repeated: it does not use the list.
 void settle_work_overflow(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t w1)
 {
-    while (c->h_workcount.p[2 * hb] > c->work_cap[hb]) {
-        const uint64_t need = (uint64_t)c->h_workcount.p[2 * hb];
+    while (host_work(c, hb) > c->work_cap[hb]) {
+        const uint64_t need = (uint64_t)host_work(c, hb);
         const uint64_t cap = std::min<uint64_t>(need + need / 4 + 1024, 0xffffffffull);
         // the other list grows before its next launch: both see the same load
         c->work_want = std::max<uint32_t>(c->work_want, (uint32_t)cap);
@@ -597,7 +609,7 @@ void rescan_range(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t 
     ev.destroy();
     c->st.rescans++;
     settle_work_overflow(c, ch, hb, w0, w1);
-    uint64_t n = c->h_hitcount.p[hb];
+    uint64_t n = host_hits(c, hb);
     if (n <= c->buf_cap[hb]) {
         copy_records(c, hb, n);
         return;
@@ -627,7 +639,7 @@ void retire(ifa_ctx *c, Job &j)
     add_pass_times(c, ev, c->n_sparse > 0, j.hitbuf, 0, words);
     settle_work_overflow(c, *j.chunk, j.hitbuf, 0, words);
     if (c->cfg.sink == IFA_SINK_RECORDS) {
-        uint64_t n = c->h_hitcount.p[j.hitbuf];
+        uint64_t n = host_hits(c, j.hitbuf);
         if (n <= c->buf_cap[j.hitbuf]) {
             copy_records(c, j.hitbuf, n);
         } else {
@@ -1009,54 +1021,49 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
         if (!dense[i]) n_sparse++;
     }
     qs.swap(sorted);
-    if (c->d_qs.n < qs.size() || !c->d_qs.p)
-        c->d_qs.alloc(std::max<size_t>(qs.size(), 1), "query table");
-    if (c->d_qwords.n < words.size() || !c->d_qwords.p)
-        c->d_qwords.alloc(std::max<size_t>(words.size(), 1), "query words");
-    if (!qs.empty())
-        hip_check(hipMemcpy(c->d_qs.p, qs.data(), qs.size() * sizeof(QSDesc),
-                            hipMemcpyHostToDevice),
-                  "upload queries");
-    if (!words.empty())
-        hip_check(hipMemcpy(c->d_qwords.p, words.data(), words.size() * sizeof(uint32_t),
-                            hipMemcpyHostToDevice),
-                  "upload query words");
-    {
-        std::vector<uint32_t> mb;
-        std::vector<float> mt;
-        build_mfma_operands(qs, n_sparse, mb, mt);
-        const size_t nb4 = std::max<size_t>(mb.size() / 4, 1), nt = std::max<size_t>(mt.size(), 1);
-        if (c->d_mqb.n < nb4 || !c->d_mqb.p) c->d_mqb.alloc(nb4, "matrix filter operands");
-        if (c->d_mqt.n < nt || !c->d_mqt.p) c->d_mqt.alloc(nt, "matrix filter counts");
-        if (!mb.empty())
-            hip_check(hipMemcpy(c->d_mqb.p, mb.data(), mb.size() * sizeof(uint32_t),
-                                hipMemcpyHostToDevice),
-                      "upload matrix filter operands");
-        if (!mt.empty())
-            hip_check(hipMemcpy(c->d_mqt.p, mt.data(), mt.size() * sizeof(float),
-                                hipMemcpyHostToDevice),
-                      "upload matrix filter counts");
-        build_mfma3_operands(qs, n_sparse, mb, mt);
-        const size_t nb3 = std::max<size_t>(mb.size() / 4, 1), nt3 = std::max<size_t>(mt.size(), 1);
-        if (c->d_mq3b.n < nb3 || !c->d_mq3b.p) c->d_mq3b.alloc(nb3, "matrix filter operands");
-        if (c->d_mq3t.n < nt3 || !c->d_mq3t.p) c->d_mq3t.alloc(nt3, "matrix filter counts");
-        if (!mb.empty())
-            hip_check(hipMemcpy(c->d_mq3b.p, mb.data(), mb.size() * sizeof(uint32_t),
-                                hipMemcpyHostToDevice),
-                      "upload matrix filter operands");
-        if (!mt.empty())
-            hip_check(hipMemcpy(c->d_mq3t.p, mt.data(), mt.size() * sizeof(float),
-                                hipMemcpyHostToDevice),
-                      "upload matrix filter counts");
+    std::vector<uint32_t> mb, mb3;
+    std::vector<float> mt, mt3;
+    build_mfma_operands(qs, n_sparse, mb, mt);
+    build_mfma3_operands(qs, n_sparse, mb3, mt3);
+    // one upload of every table: parts at 256-byte offsets in one arena
+    struct Part {
+        const void *src;
+        size_t bytes, off;
+    } parts[6] = {{qs.data(), qs.size() * sizeof(QSDesc), 0},
+                  {words.data(), words.size() * sizeof(uint32_t), 0},
+                  {mb.data(), mb.size() * sizeof(uint32_t), 0},
+                  {mt.data(), mt.size() * sizeof(float), 0},
+                  {mb3.data(), mb3.size() * sizeof(uint32_t), 0},
+                  {mt3.data(), mt3.size() * sizeof(float), 0}};
+    size_t total = 0;
+    for (Part &pt : parts) {
+        pt.off = total;
+        total += (std::max<size_t>(pt.bytes, 16) + 255) & ~(size_t)255;
     }
+    // the arena's previous upload is complete before it is rewritten
+    hip_check(hipStreamSynchronize(c->comp_s), "sync");
+    if (c->h_qarena.n < total) c->h_qarena.alloc(total, "pinned query staging");
+    if (c->d_qarena.n < total) c->d_qarena.alloc(total, "query tables");
+    for (const Part &pt : parts)
+        if (pt.bytes) std::memcpy(c->h_qarena.p + pt.off, pt.src, pt.bytes);
+    hip_check(hipMemcpyAsync(c->d_qarena.p, c->h_qarena.p, total, hipMemcpyHostToDevice,
+                             c->comp_s),
+              "upload query tables");
+    uint8_t *base = c->d_qarena.p;
+    c->dq_qs = reinterpret_cast<const QSDesc *>(base + parts[0].off);
+    c->dq_words = reinterpret_cast<const uint32_t *>(base + parts[1].off);
+    c->dq_mqb = reinterpret_cast<const uint4 *>(base + parts[2].off);
+    c->dq_mqt = reinterpret_cast<const float *>(base + parts[3].off);
+    c->dq_mq3b = reinterpret_cast<const uint4 *>(base + parts[4].off);
+    c->dq_mq3t = reinterpret_cast<const float *>(base + parts[5].off);
     if (c->cfg.sink == IFA_SINK_COUNT_DIGEST) {
         const size_t need = (size_t)std::max<uint32_t>(n_queries, 1) * kStripes;
         if (c->d_qcount.n < need) {
             c->d_qcount.alloc(need, "query counters");
             c->d_qdigest.alloc(need, "query digests");
         }
-        hip_check(hipMemset(c->d_qcount.p, 0, need * sizeof(unsigned long long)), "memset");
-        hip_check(hipMemset(c->d_qdigest.p, 0, need * sizeof(unsigned long long)), "memset");
+        hip_check(launch_clear_u64(c->d_qcount.p, (uint32_t)need, c->comp_s), "clear counters");
+        hip_check(launch_clear_u64(c->d_qdigest.p, (uint32_t)need, c->comp_s), "clear digests");
     }
     // size the work lists for the expected load unless the caller fixed the
     // initial capacity (they grow on overflow either way)
@@ -1195,14 +1202,10 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
             c->work[i].alloc(wcap, "work list");
             c->work_cap[i] = wcap;
         }
-        c->d_workcount.alloc(4, "work counters");
-        c->h_workcount.alloc(4, "pinned work counters");
-        hip_check(hipMemset(c->d_workcount.p, 0, 4 * sizeof(unsigned int)), "memset");
-        for (int i = 0; i < 4; i++) c->h_workcount.p[i] = 0;
-        c->d_hitcount.alloc(2, "hit counters");
-        c->h_hitcount.alloc(2, "pinned hit counters");
-        hip_check(hipMemset(c->d_hitcount.p, 0, 2 * sizeof(unsigned long long)), "memset");
-        c->h_hitcount.p[0] = c->h_hitcount.p[1] = 0;
+        c->d_ctr.alloc(4, "pass counters");
+        c->h_ctr.alloc(4, "pinned pass counters");
+        hip_check(hipMemset(c->d_ctr.p, 0, 4 * sizeof(unsigned long long)), "memset");
+        for (int i = 0; i < 4; i++) c->h_ctr.p[i] = 0;
     });
     if (st != IFA_OK) {
         ifa_destroy(c);
@@ -1606,10 +1609,8 @@ ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
         b += c->slot[i].planes.n * sizeof(uint32_t) + c->slot[i].pieces.n * sizeof(Piece);
         b += c->d_hits[i].n * sizeof(uint4) + c->work[i].n * sizeof(WorkItem);
     }
-    b += c->d_hitcount.n * sizeof(unsigned long long) + c->d_workcount.n * sizeof(unsigned int);
-    b += c->d_qs.n * sizeof(QSDesc) + c->d_qwords.n * sizeof(uint32_t) +
-         c->d_mqb.n * sizeof(uint4) + c->d_mqt.n * sizeof(float) +
-         c->d_mq3b.n * sizeof(uint4) + c->d_mq3t.n * sizeof(float);
+    b += c->d_ctr.n * sizeof(unsigned long long);
+    b += c->d_qarena.n;
     b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
     for (const auto &r : c->resident)
         b += r->planes.n * sizeof(uint32_t) + r->pieces.n * sizeof(Piece);
