@@ -153,7 +153,28 @@ def choose_variant(ifa, s, args, queries, ks):
     return {"chosen": chosen, "ms": [round(float(x), 4) for x in ms]}
 
 
-def roofline(ifa, st, sparse_strands, variant):
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scan_filter_mfma3_c2_4gbp_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2607_27291_amd", "csrc", "ifa_scan.hip")
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` on the paper-scale workload from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that
+    summary is for another kernel or the kernel source changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            kv = dict(line.split(": ", 1) for line in f.read().splitlines() if ": " in line)
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if kv.get("kernel", "").strip() != kernel or kv.get("kernel_source_sha256", "").strip() != sha:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
+def roofline(ifa, st, sparse_strands, variant, traffic=False):
     """Roofline of the filter kernel (the dominant one): its algorithmic work
     per launch is the per-unit figure (OPS_PER_WINDOW_STRAND VALU ops, or
     FLOPS_PER_WINDOW_STRAND matrix-core flops for the fp4 variants) x the
@@ -169,15 +190,16 @@ def roofline(ifa, st, sparse_strands, variant):
     work_per_launch = per_unit * sparse_strands * st["filter_windows"] / launches
     achieved = work_per_launch / (filter_ms_avg * 1e-3) / 1e12 if st["filter_launches"] else 0.0
     peak = (PEAK_FP4_FLOPS if mfma else PEAK_VALU_OPS) / 1e12
-    return {
+    kernel = {0: "scan_filter_kernel", 1: "scan_filter_mfma_kernel",
+              2: "scan_filter_mfma3_kernel"}[shape["encoding"]]
+    out = {
         "bound": "mfma" if mfma else "alu",
         "achieved": round(achieved, 3),
         "peak": round(peak, 3),
         "unit": "TFLOP/s" if mfma else "TOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": None,
-        "kernel": {0: "scan_filter_kernel", 1: "scan_filter_mfma_kernel",
-                   2: "scan_filter_mfma3_kernel"}[shape["encoding"]],
+        "kernel": kernel,
         "variant": variant,
         "variant_shape": shape,
         "kernel_ms_avg": round(filter_ms_avg, 4),
@@ -186,6 +208,9 @@ def roofline(ifa, st, sparse_strands, variant):
         "work_items_per_launch": st["work_items"] // launches,
         "pass_ms_avg": round(st["kernel_ms"] / max(1, st["kernel_launches"]), 4),
     }
+    if traffic:
+        out["traffic"] = profiled_traffic(kernel)
+    return out
 
 
 def base_record(args, value, ms_per_step, config):
@@ -283,8 +308,9 @@ def run_c2(args):
                       })
     out["kernel_only_gbpq_s"] = round(bpq_per_step * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
     out["autotune"] = tune
-    # algorithmic VALU ops of one filter launch: every window of a chunk x 2 strands x queries
-    out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant)
+    # the committed traffic figure is for this workload at its default size
+    out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant,
+                               traffic=not args.total and not args.queries)
 
     if not args.no_cpu and args.cpu_sample > 0:
         import oracle

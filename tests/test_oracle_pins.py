@@ -11,6 +11,7 @@ Scalability"); reference Ns tracked apart from substitutions (Methods,
 threshold ("SIMD Optimization"); 0% false negatives for substitution counts
 0-16 ("Accuracy Validation", Table 6).
 """
+import os
 import random
 
 import numpy as np
@@ -38,9 +39,13 @@ def as_set(h):
 # ---------------------------------------------------------------------------
 
 # SplitMix64 reference outputs for seed 1234567 (the published sequence from
-# the reference implementation of Steele, Lea & Flood's generator).
-SPLITMIX64_1234567 = [6457827717110365317, 3203168211198807973, 9817491932198370423,
-                      4593380528125082431, 16408922859458223821]
+# the reference implementation of Steele, Lea & Flood's generator), kept as a
+# fixture with its citation.
+_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "splitmix64_seed1234567.txt")
+with open(_GOLDEN) as _f:
+    SPLITMIX64_1234567 = [int(x) for x in _f.read().split("\n") if x and not x.startswith("#")]
+assert len(SPLITMIX64_1234567) == 5
 
 
 def test_splitmix64_published_outputs(synth_mod):
