@@ -256,7 +256,7 @@ __device__ void exact_plain(const ScanArgs &a, const QS &d, const Lane &ln, uint
 
 // Sum cnt / dig over the wave and add them once, to stripe `stripe` of the
 // query's count+digest accumulators. Called by all 64 lanes.
-__device__ __forceinline__ void wave_add_stats(const ScanArgs &a, const QS &d, uint32_t cnt,
+__device__ __forceinline__ void wave_add_stats(const ScanArgs &a, uint32_t qid, uint32_t cnt,
                                                uint64_t dig, uint32_t stripe)
 {
     if (!__any(cnt != 0u)) return;
@@ -271,7 +271,7 @@ __device__ __forceinline__ void wave_add_stats(const ScanArgs &a, const QS &d, u
         dhi = (uint32_t)(sum >> 32);
     }
     if ((threadIdx.x & 63u) == 0u) {
-        const uint32_t slot = d.qid * kStripes + stripe % kStripes;
+        const uint32_t slot = qid * kStripes + stripe % kStripes;
         atomicAdd(&a.q_count[slot], (unsigned long long)cnt);
         atomicAdd(&a.q_digest[slot], ((unsigned long long)dhi << 32) | dlo);
     }
@@ -305,7 +305,7 @@ __device__ __forceinline__ void resolve(const ScanArgs &a, const QS &d, Lane &ln
             exact_serial<W>(a, d, ln, cnt, dig);
         }
     }
-    if (a.sink == kSinkCountDigest) wave_add_stats(a, d, cnt, dig, stripe);
+    if (a.sink == kSinkCountDigest) wave_add_stats(a, d.qid, cnt, dig, stripe);
 }
 
 // Minimum over the lane's W windows of the filter count for one query strand
@@ -835,12 +835,11 @@ __global__ __launch_bounds__(256) void scan_resolve_kernel(ScanArgs a)
 // registers. Dense strands come sorted by L descending so the cached word-0
 // slices can be masked in place.
 template <int W>
-__device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, Lane &ln,
+__device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, const Lane &ln,
+                                             bool plain, uint32_t contig, uint32_t pos0,
                                              const uint32_t (&sh)[W], const uint32_t (&sl)[W],
-                                             uint32_t wave)
+                                             uint32_t &cnt, uint64_t &dig)
 {
-    if (ln.plain < 0) ln.plain = (ln.active && lane_is_plain(a, ln)) ? 1 : 0;
-    const bool plain = ln.plain == 1;
     uint32_t m[W];
     uint32_t mn = 0xffffffffu;
 #pragma unroll
@@ -870,37 +869,35 @@ __device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, Lan
         hp = hn;
         lp = lnw;
     }
-    uint32_t cnt = 0;
-    uint64_t dig = 0;
+    if (!__any(plain && mn <= d.k)) return;
     if (plain && mn <= d.k) {
-        const uint64_t first = 32ull * ln.w + ln.off;
-        const Piece pc = a.pieces[find_piece(a, first)];
-        const uint32_t pos0 = (uint32_t)(pc.contig_off + (first - pc.start));
+        uint32_t c = 0;
 #pragma unroll
-        for (int b = 0; b < W; b++) cnt += m[b] <= d.k ? 1u : 0u;
+        for (int b = 0; b < W; b++) c += m[b] <= d.k ? 1u : 0u;
+        cnt += c;
         if (a.sink == kSinkRecords) {
-            unsigned long long slot = atomicAdd(a.hit_count, (unsigned long long)cnt);
+            unsigned long long slot = atomicAdd(a.hit_count, (unsigned long long)c);
 #pragma unroll
             for (int b = 0; b < W; b++) {
                 if (m[b] <= d.k) {
-                    write_record(a, slot, d, pc.contig, pos0 + b, m[b], 0u);
+                    write_record(a, slot, d, contig, pos0 + b, m[b], 0u);
                     slot++;
                 }
             }
-        } else {
-#pragma unroll
-            for (int b = 0; b < W; b++)
-                if (m[b] <= d.k) dig += hit_hash(pc.contig, pos0 + b, d.strand, m[b], 0u);
         }
     }
-    if (a.sink == kSinkCountDigest) wave_add_stats(a, d, cnt, dig, wave);
+    if (a.sink == kSinkCountDigest && plain && mn <= d.k) {
+#pragma unroll
+        for (int b = 0; b < W; b++)
+            if (m[b] <= d.k) dig += hit_hash(contig, pos0 + b, d.strand, m[b], 0u);
+    }
 }
 
 template <int W>
 __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
 {
     const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
-    Lane ln = make_lane<W>(a, gl);
+    const Lane ln = make_lane<W>(a, gl);
     const uint32_t wave = gl >> 6;
     uint32_t sh[W], sl[W];
 #pragma unroll
@@ -908,15 +905,39 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
         sh[b] = funnel(ln.h1, ln.h0, ln.off + (uint32_t)b);
         sl[b] = funnel(ln.l1, ln.l0, ln.off + (uint32_t)b);
     }
+    // plain lanes find their contig and position once for every strand
+    const bool plain = ln.active && lane_is_plain(a, ln);
+    uint32_t contig = 0, pos0 = 0;
+    if (plain) {
+        const uint64_t first = 32ull * ln.w + ln.off;
+        const Piece pc = a.pieces[find_piece(a, first)];
+        contig = pc.contig;
+        pos0 = (uint32_t)(pc.contig_off + (first - pc.start));
+    }
     uint32_t cur_len = 32;
+    // both strands of a query are adjacent: their counts are summed before
+    // the wave-wide reduction
+    uint32_t cnt = 0, qid = 0xffffffffu;
+    uint64_t dig = 0;
     for (uint32_t q = a.n_sparse; q < a.n_qs; q++) {
         const QS d = load_qs(a, q);
+        if (d.qid != qid) {
+            if (a.sink == kSinkCountDigest && qid != 0xffffffffu)
+                wave_add_stats(a, qid, cnt, dig, wave);
+            cnt = 0;
+            dig = 0;
+            qid = d.qid;
+        }
         if (d.len < cur_len) {
             mask_slices<W>(sh, sl, d.len);
             cur_len = d.len;
         }
-        dense_strand<W>(a, d, ln, sh, sl, wave);
+        // keep the hash keys of the W windows from being hoisted out of the
+        // strand loop (32 more live registers, half the occupancy)
+        asm volatile("" : "+v"(contig), "+v"(pos0));
+        dense_strand<W>(a, d, ln, plain, contig, pos0, sh, sl, cnt, dig);
     }
+    if (a.sink == kSinkCountDigest && qid != 0xffffffffu) wave_add_stats(a, qid, cnt, dig, wave);
 }
 
 // Dense query strands on the lanes scan_dense_kernel leaves out (an N, a
@@ -935,7 +956,7 @@ __global__ __launch_bounds__(256) void scan_dense_cold_kernel(ScanArgs a)
         uint32_t cnt = 0;
         uint64_t dig = 0;
         if (cold && filter_cand_words<W>(a, d, ln)) exact_serial<W>(a, d, ln, cnt, dig);
-        if (a.sink == kSinkCountDigest) wave_add_stats(a, d, cnt, dig, wave);
+        if (a.sink == kSinkCountDigest) wave_add_stats(a, d.qid, cnt, dig, wave);
     }
 }
 
