@@ -416,10 +416,20 @@ def run_c4(args):
     threads = synth.default_threads()
     log(f"c4: {total / 1e9:.0f} Gbp in {len(lens)} contigs, {len(batches)} batches, {nq} queries")
 
+    # the generator stands in for reading a reference and is the slowest
+    # stage: it gets every host thread, the packer half of them
+    gen_threads = threads
     s = ifa.Scanner(device=0, host_threads=max(1, threads // 2))
     tune = choose_variant(ifa, s, args, qs, ks)
     variant = ifa.ifa_get_variant(s.ctx)
+    s.load_queries(qs, ks)   # the footprint below includes the query tables
     foot0 = ifa.ifa_device_footprint(s.ctx)
+
+    # two batch buffers, written in turn: scan_chunk has packed batch b into
+    # the library's pinned staging before it returns, so the producer may
+    # refill b's buffer with batch b + 2 (reuse also skips first-touch faults)
+    max_batch = max(int(lens[idx].sum()) for idx in batches)
+    bufs = [np.empty(max_batch, dtype=np.uint8) for _ in range(2)]
 
     def gen_batch(b):
         idx = batches[b]
@@ -427,8 +437,8 @@ def run_c4(args):
         offs = np.zeros(len(idx), dtype=np.uint64)
         if len(idx) > 1:
             offs[1:] = np.cumsum(blen)[:-1]
-        buf = np.empty(int(blen.sum()), dtype=np.uint8)
-        synth.fill_contigs(spec, idx[0], blen, gcs[idx], buf, offs, max(1, threads // 2))
+        buf = bufs[b % 2][:int(blen.sum())]
+        synth.fill_contigs(spec, idx[0], blen, gcs[idx], buf, offs, gen_threads)
         return synth.Reference(buf, offs, blen)
 
     gen_s = [0.0]
@@ -471,7 +481,8 @@ def run_c4(args):
     out["gpu_busy_frac"] = round(st["kernel_ms"] / (elapsed * 1e3), 4)
     out["producer_gbp_s"] = round(total * (args.steps + args.warmup) / max(gen_s[0], 1e-9) / 1e9, 3)
     out["pack_gbp_s"] = round(st["bases"] / max(st["pack_ms"] * 1e-3, 1e-9) / 1e9, 3)
-    out["h2d_gb_s"] = round(st["bases"] / 4 / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
+    # four bit planes per base (hi, lo, N, piece end): half a byte per base
+    out["h2d_gb_s"] = round(st["bases"] / 2 / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
     out["device_footprint_bytes"] = {"before": foot0, "after": foot1}
     out["autotune"] = tune
     out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant)

@@ -40,8 +40,15 @@ def lib():
                                       ctypes.c_int]
         L.synth_fill_many.restype = ctypes.c_int
         L.synth_queries.argtypes = [u64, u64, u64, u32, u32, vp, u64, vp]
+        L.synth_set_simd.argtypes = [ctypes.c_int]
+        L.synth_set_simd.restype = None
         _lib = L
     return _lib
+
+
+def set_simd(on: bool):
+    """Use (default) or bypass the AVX2 base generator; output is identical."""
+    lib().synth_set_simd(1 if on else 0)
 
 
 def splitmix64(seed: int, n: int) -> np.ndarray:

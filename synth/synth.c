@@ -22,6 +22,9 @@
 #include <string.h>
 #include <math.h>
 #include <pthread.h>
+#if defined(__x86_64__)
+#include <immintrin.h>
+#endif
 
 #define SYN_GAMMA 0x9E3779B97F4A7C15ULL
 #define SYN_BLOCK 4096ULL
@@ -137,6 +140,54 @@ typedef struct {
 } syn_spec;
 
 /* fill out[0..n) with bases [x0, x0+n) of contig `c` (length clen, GC gc) */
+/* AVX2 path for whole draws (4 draws = 32 bases per step), the same draws and
+ * the same byte mapping as the scalar loop; synth_set_simd(0) turns it off
+ * (the tests compare both). */
+static int syn_simd = 1;
+
+void synth_set_simd(int on) { syn_simd = on; }
+
+#if defined(__x86_64__)
+__attribute__((target("avx2"))) static inline __m256i syn_mul64(__m256i z, uint64_t c)
+{
+    const __m256i clo = _mm256_set1_epi64x((long long)(c & 0xFFFFFFFFULL));
+    const __m256i chi = _mm256_set1_epi64x((long long)(c >> 32));
+    const __m256i lo = _mm256_mul_epu32(z, clo);
+    const __m256i t1 = _mm256_mul_epu32(_mm256_srli_epi64(z, 32), clo);
+    const __m256i t2 = _mm256_mul_epu32(z, chi);
+    return _mm256_add_epi64(lo, _mm256_slli_epi64(_mm256_add_epi64(t1, t2), 32));
+}
+
+/* whole draws from state *s (advanced), 8 bases each, into o; returns draws done */
+__attribute__((target("avx2"))) static uint64_t fill_draws_avx2(uint64_t *s, uint64_t draws,
+                                                               uint32_t thr, uint8_t *o)
+{
+    const __m256i g = _mm256_set_epi64x((long long)(4 * SYN_GAMMA), (long long)(3 * SYN_GAMMA),
+                                        (long long)(2 * SYN_GAMMA), (long long)SYN_GAMMA);
+    const __m256i step = _mm256_set1_epi64x((long long)(4 * SYN_GAMMA));
+    const __m256i m7 = _mm256_set1_epi8(0x7F), vthr = _mm256_set1_epi8((char)thr);
+    const __m256i cc = _mm256_set1_epi8('C'), cg = _mm256_set1_epi8('G');
+    const __m256i ca = _mm256_set1_epi8('A'), ct = _mm256_set1_epi8('T');
+    __m256i st = _mm256_add_epi64(_mm256_set1_epi64x((long long)*s), g);
+    uint64_t done = 0;
+    for (; done + 4 <= draws; done += 4) {
+        __m256i z = st;
+        z = syn_mul64(_mm256_xor_si256(z, _mm256_srli_epi64(z, 30)), 0xBF58476D1CE4E5B9ULL);
+        z = syn_mul64(_mm256_xor_si256(z, _mm256_srli_epi64(z, 27)), 0x94D049BB133111EBULL);
+        z = _mm256_xor_si256(z, _mm256_srli_epi64(z, 31));
+        const __m256i low7 = _mm256_and_si256(z, m7);
+        /* A/T where low7 >= thr (unsigned), G/C otherwise; the top bit picks G or T */
+        const __m256i at = _mm256_cmpeq_epi8(_mm256_max_epu8(low7, vthr), low7);
+        const __m256i gcb = _mm256_blendv_epi8(cc, cg, z);
+        const __m256i atb = _mm256_blendv_epi8(ca, ct, z);
+        _mm256_storeu_si256((__m256i *)(o + 8 * done), _mm256_blendv_epi8(gcb, atb, at));
+        st = _mm256_add_epi64(st, step);
+    }
+    *s += done * SYN_GAMMA;
+    return done;
+}
+#endif
+
 static void fill_range(const syn_spec *sp, uint64_t c, uint64_t clen, double gc,
                        uint64_t x0, uint64_t n, uint8_t *out)
 {
@@ -169,6 +220,13 @@ static void fill_range(const syn_spec *sp, uint64_t c, uint64_t clen, double gc,
         }
         /* whole draws */
         uint8_t *o = out + (pos - x0);
+#if defined(__x86_64__)
+        if (syn_simd && __builtin_cpu_supports("avx2")) {
+            const uint64_t done = fill_draws_avx2(&r.s, (bend - pos) / 8, thr, o);
+            o += 8 * done;
+            pos += 8 * done;
+        }
+#endif
         while (pos + 8 <= bend) {
             uint64_t v = syn_next(&r);
             o[0] = table[v & 0xFF];
