@@ -84,8 +84,13 @@ typedef struct {
                                random bases). A full list never loses work:
                                it grows and the filtered part of the pass
                                runs again */
-    uint32_t reserved;      /* must be 0 */
+    uint32_t flags;         /* IFA_FLAG_* bits; others must be 0 */
 } ifa_config;
+
+/* ifa_config.flags: replay each resident chunk's scan pass from a captured
+ * HIP graph while its launch arguments repeat (the first pass with new
+ * arguments runs eagerly; the second is captured). Results are identical. */
+#define IFA_FLAG_GRAPHS 1u
 
 /* One reported window (16 bytes). strand: 0 = +, 1 = - (reverse complement). */
 typedef struct {
@@ -116,6 +121,7 @@ typedef struct {
                                 waves holding a reference N are passed whole to the
                                 resolve kernel and not counted) */
     uint64_t work_items;     /* work-list items the filter emitted */
+    uint64_t graph_launches; /* scan passes replayed from a captured graph */
 } ifa_stats;
 
 /* Fill *cfg with the defaults: device 0, 2^30-base chunks, automatic hit

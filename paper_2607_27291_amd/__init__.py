@@ -30,6 +30,7 @@ IFA_MAX_QUERY_LEN = 256
 IFA_N_SEPARATE, IFA_N_AS_MISMATCH = 0, 1
 IFA_SINK_RECORDS, IFA_SINK_COUNT_DIGEST = 0, 1
 IFA_STRAND_FWD, IFA_STRAND_RC, IFA_STRAND_BOTH = 1, 2, 3
+IFA_FLAG_GRAPHS = 1
 
 STATUS = {0: "IFA_OK", 1: "IFA_E_INVALID", 2: "IFA_E_NOMEM", 3: "IFA_E_DEVICE",
           4: "IFA_E_STATE", 5: "IFA_E_TOO_LONG"}
@@ -43,7 +44,7 @@ class IfaConfig(ctypes.Structure):
                 ("chunk_bases", ctypes.c_uint64), ("hit_capacity", ctypes.c_uint64),
                 ("strands", ctypes.c_uint32), ("n_policy", ctypes.c_uint32),
                 ("sink", ctypes.c_uint32), ("host_threads", ctypes.c_uint32),
-                ("work_capacity", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("work_capacity", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class IfaStats(ctypes.Structure):
@@ -52,7 +53,8 @@ class IfaStats(ctypes.Structure):
                 ("hits", ctypes.c_uint64), ("kernel_ms", ctypes.c_double),
                 ("h2d_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
                 ("filter_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64),
-                ("filter_windows", ctypes.c_uint64), ("work_items", ctypes.c_uint64)]
+                ("filter_windows", ctypes.c_uint64), ("work_items", ctypes.c_uint64),
+                ("graph_launches", ctypes.c_uint64)]
 
 
 class IfaServerConfig(ctypes.Structure):
@@ -446,7 +448,7 @@ class Scanner:
 
     def __init__(self, *, device=0, chunk_bases=1 << 30, hit_capacity=0,
                  strands=IFA_STRAND_BOTH, n_policy=IFA_N_SEPARATE, sink=IFA_SINK_RECORDS,
-                 host_threads=0, work_capacity=0):
+                 host_threads=0, work_capacity=0, flags=0):
         cfg = ifa_config_default()
         cfg.device = device
         cfg.chunk_bases = chunk_bases
@@ -456,6 +458,7 @@ class Scanner:
         cfg.sink = sink
         cfg.host_threads = host_threads
         cfg.work_capacity = work_capacity
+        cfg.flags = flags
         self.ctx = ifa_create(cfg)
         self.n_queries = 0
 

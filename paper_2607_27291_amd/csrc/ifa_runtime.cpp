@@ -170,6 +170,21 @@ struct Staging {
 };
 
 // Device chunk: planes + piece table, either a stream slot or resident.
+// A captured scan pass of one resident chunk into one hit buffer: replayed
+// while the pass's launch arguments stay the same (the query tables' content
+// may change; their addresses and sizes may not).
+struct PassGraph {
+    ScanArgs args{};              // arguments of the last eager or captured pass
+    bool seen = false;            // args held a pass that ran
+    hipGraphExec_t exec = nullptr;
+    void reset()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        seen = false;
+    }
+};
+
 struct DevChunk {
     DevBuf<uint32_t> planes;      // 4 planes of `stride` words each
     DevBuf<Piece> pieces;
@@ -178,6 +193,13 @@ struct DevChunk {
     uint32_t own_from = 0;
     uint32_t n_pieces = 0;
     hipEvent_t free_ev = nullptr;   // last kernel reading it finished
+    bool resident = false;
+    PassGraph graph[2];             // per hit buffer (resident chunks)
+    ~DevChunk()
+    {
+        graph[0].reset();
+        graph[1].reset();
+    }
 };
 
 // A submitted scan of one device chunk whose hits are not yet retired.
@@ -676,10 +698,39 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     ev.t0 = j.k0;
     ev.t1 = j.kf;
     ev.t2 = j.k1;
-    enqueue_pass(c, a, true, true, ev);
-    hip_check(hipEventRecord(ch->free_ev, c->comp_s), "event record");
-    enqueue_count_copies(c, j.hitbuf);
-    hip_check(hipEventRecord(j.done, c->comp_s), "event record");
+    auto enqueue = [&]() {
+        enqueue_pass(c, a, true, true, ev);
+        hip_check(hipEventRecord(ch->free_ev, c->comp_s), "event record");
+        enqueue_count_copies(c, j.hitbuf);
+        hip_check(hipEventRecord(j.done, c->comp_s), "event record");
+    };
+    PassGraph *pg = nullptr;
+    if ((c->cfg.flags & IFA_FLAG_GRAPHS) && ch->resident) {
+        pg = &ch->graph[j.hitbuf];
+        // a pass whose arguments repeat is captured once, then replayed
+        if (!pg->seen || std::memcmp(&pg->args, &a, sizeof a) != 0) {
+            pg->reset();
+            pg->args = a;
+            pg->seen = true;
+            pg = nullptr;   // first time with these arguments: run eagerly
+        }
+    }
+    if (pg) {
+        if (!pg->exec) {
+            hipGraph_t g = nullptr;
+            hip_check(hipStreamBeginCapture(c->comp_s, hipStreamCaptureModeRelaxed),
+                      "begin capture");
+            enqueue();
+            hip_check(hipStreamEndCapture(c->comp_s, &g), "end capture");
+            const hipError_t e = hipGraphInstantiate(&pg->exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            hip_check(e, "instantiate pass graph");
+        }
+        hip_check(hipGraphLaunch(pg->exec, c->comp_s), "launch pass graph");
+        c->st.graph_launches++;
+    } else {
+        enqueue();
+    }
     j.active = true;
     c->job_seq++;
     c->st.chunks++;
@@ -1162,7 +1213,7 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
     if (cfg_in) cfg = *cfg_in; else ifa_config_default(&cfg);
     if (cfg.abi_version != IFA_ABI_VERSION || cfg.chunk_bases < 4096 ||
         cfg.chunk_bases > (1ull << 31) || (cfg.chunk_bases & 31) || cfg.strands < 1 ||
-        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || cfg.reserved != 0)
+        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || (cfg.flags & ~IFA_FLAG_GRAPHS) != 0)
         return IFA_E_INVALID;
     ifa_ctx *c = new (std::nothrow) ifa_ctx();
     if (!c) return IFA_E_NOMEM;
@@ -1371,6 +1422,7 @@ ifa_status ifa_ref_load(ifa_ctx *c, uint32_t n_contigs, const uint8_t *const *se
             pack_pending(c, s);
             seal(c, s);
             std::unique_ptr<DevChunk> d(new DevChunk());
+            d->resident = true;
             d->stride = words_with_pad(s.len);
             d->planes.alloc(4 * d->stride, "resident chunk");
             d->pieces.alloc(std::max<size_t>(s.pieces.size(), 1), "resident piece table");

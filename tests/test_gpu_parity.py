@@ -418,3 +418,45 @@ def test_matrix_core_filter_emits_what_the_valu_filter_emits(ifa):
             st = s.stats()
             seen[v] = (st["work_items"], st["filter_windows"])
     assert len(set(seen.values())) == 1, seen
+
+
+@pytest.mark.parametrize("sink", [0, 1])
+def test_resident_graph_replays_match_eager(ifa, orc, sink):
+    """Resident passes replayed from captured graphs give the eager results on
+    every replay, also after the query data changes under the same launch
+    arguments; eager scans by another context run between the replays."""
+    import synth
+    spec = synth.c2_spec(seed=66, total=3_000_000)
+    spec.n_param = 2e-3
+    spec.median = 100_000
+    ref = synth.gen_reference(spec)
+    rng = random.Random(66)
+    lens = [rng.choice([24, 31, 32, 36, 40]) for _ in range(12)]
+    qa = [rand_dna(rng, n) for n in lens]
+    qb = [rand_dna(rng, n) for n in lens]          # same shapes, other bases
+    ks = [rng.randint(0, 6) for _ in lens]
+    want = {}
+    for name, qs in (("a", qa), ("b", qb)):
+        if sink == 0:
+            want[name] = orc.scan(qs, ref, ks)
+        else:
+            _, cnt, dig = orc.scan(qs, ref, ks, stats=True, records=False)
+            want[name] = (cnt, dig)
+    cfg = dict(chunk_bases=1 << 20, sink=sink)
+    with ifa.Scanner(flags=ifa.IFA_FLAG_GRAPHS, **cfg) as g, ifa.Scanner(**cfg) as e:
+        g.ref_load(ref)
+        e.ref_load(ref)
+        for rep, name in enumerate(["a", "a", "a", "b", "a", "b"]):
+            qs = qa if name == "a" else qb
+            say(f"graph replay {rep} queries {name} sink {sink}")
+            for s in (g, e):
+                s.load_queries(qs, ks)
+                s.scan_resident()
+                if sink == 0:
+                    assert_same(s.collect(), want[name], f"rep {rep} {name}")
+                else:
+                    gc, gd = s.query_stats()
+                    assert np.array_equal(gc, want[name][0]) and np.array_equal(gd, want[name][1])
+        st = g.stats()
+        assert st["graph_launches"] > 0
+        assert e.stats()["graph_launches"] == 0
