@@ -217,7 +217,8 @@ ifa_status ifa_device_footprint(const ifa_ctx *ctx, uint64_t *bytes);
  * filter kernel (encoding 0: vector-ALU bit operations; 1: fp4 matrix cores
  * on four-class one-hot codes; 2: fp4 matrix cores on three-class codes).
  * Every variant computes the same hits; they differ only in speed. Any
- * output pointer may be NULL. */
+ * output pointer may be NULL. A new context starts with a three-class
+ * matrix-core variant; ifa_get_variant names it. */
 uint32_t ifa_variant_count(void);
 ifa_status ifa_variant_info(uint32_t v, uint32_t *windows_per_lane, uint32_t *queries_per_iter,
                             uint32_t *workgroup, uint32_t *encoding);

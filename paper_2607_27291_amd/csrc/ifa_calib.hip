@@ -227,8 +227,10 @@ extern "C" double ifa_calib_mfma(int shape, uint32_t blocks, uint32_t iters)
 
 // Overlap probe: waves of one launch run either fp4 MFMA chains (four
 // independent accumulators) or v_max3_u32 chains (16 independent), chosen by
-// mode: 0 all MFMA, 1 all VALU, 2 even waves MFMA and odd waves VALU. Timing
-// the three shows whether the matrix core and the VALU run concurrently.
+// mode: 0 all MFMA, 1 all VALU, 2 even waves MFMA and odd waves VALU, 3 every
+// wave both, interleaved one MFMA to four VALU instructions. Timing them
+// shows whether the matrix core and the VALU run concurrently, across waves
+// (2) and within one wave (3).
 __global__ __launch_bounds__(256) void calib_mix_kernel(float *out, uint32_t iters, uint32_t mode,
                                                         uint32_t seed)
 {
@@ -236,7 +238,39 @@ __global__ __launch_bounds__(256) void calib_mix_kernel(float *out, uint32_t ite
     const uint32_t wv = gid >> 6;
     const bool do_mfma = mode == 0 || (mode == 2 && (wv & 1u) == 0u);
     float s = 0.f;
-    if (do_mfma) {
+    if (mode == 3) {
+        calib_v8i va = {}, vb = {};
+        for (int j = 0; j < 4; j++) {
+            va[j] = (int)((gid * 2654435761u + seed * (uint32_t)(j + 1)) & 0x77777777u);
+            vb[j] = (int)((gid * 40503u + seed + (uint32_t)j * 977u) & 0x77777777u);
+        }
+        calib_v16f c0 = {}, c1 = {}, c2 = {}, c3 = {};
+        uint32_t a[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) a[j] = gid * 2654435761u + (uint32_t)j * 40503u + seed;
+        for (uint32_t i = 0; i < iters; i++) {
+            c0 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, vb, c0, 4, 4, 0, 127, 0, 127);
+            c1 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(vb, va, c1, 4, 4, 0, 127, 0, 127);
+            c2 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, va, c2, 4, 4, 0, 127, 0, 127);
+            c3 = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(vb, vb, c3, 4, 4, 0, 127, 0, 127);
+#pragma unroll
+            for (int r = 0; r < 2; r++)
+#pragma unroll
+                for (int j = 0; j < 16; j++)
+                    a[j] = max(max(a[j], a[(j + 1) & 15] ^ seed), a[(j + 5) & 15] + seed);
+            for (int q = 0; q < 4; q++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, 24, 0);
+            }
+        }
+        uint32_t x = 0;
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            s += c0[j] + c1[j] + c2[j] + c3[j];
+            x ^= a[j];
+        }
+        s += (float)x;
+    } else if (do_mfma) {
         calib_v8i va = {}, vb = {};
         for (int j = 0; j < 4; j++) {
             va[j] = (int)((gid * 2654435761u + seed * (uint32_t)(j + 1)) & 0x77777777u);
@@ -275,7 +309,7 @@ __global__ __launch_bounds__(256) void calib_mix_kernel(float *out, uint32_t ite
 // a negative HIP error code.
 extern "C" double ifa_calib_mix(uint32_t mode, uint32_t blocks, uint32_t iters)
 {
-    if (mode > 2 || blocks == 0 || iters == 0) return -1.0;
+    if (mode > 3 || blocks == 0 || iters == 0) return -1.0;
     const uint64_t threads = (uint64_t)blocks * 256u;
     float *out = nullptr;
     hipError_t e = hipMalloc((void **)&out, threads * sizeof(float));

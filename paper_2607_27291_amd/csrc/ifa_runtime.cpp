@@ -34,6 +34,7 @@ hipError_t launch_dense(const ScanArgs &a, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
 hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s);
 uint32_t variant_count();
+uint32_t variant_default();
 void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg, uint32_t *enc);
 }  // namespace ifa
 
@@ -222,7 +223,7 @@ struct ifa_ctx {
     hipStream_t copy_s = nullptr, comp_s = nullptr;
 
     // kernel variant (autotuner or caller's choice)
-    uint32_t variant = 0;
+    uint32_t variant = variant_default();
     std::vector<double> tune_ms;
 
     // queries

@@ -1008,7 +1008,7 @@ struct VariantDesc {
             scan_dense_cold_kernel<16>, 16, 2, WG, 1, WAVES                              \
     }
 static const VariantDesc kVariantTable[] = {
-    IFA_V(32, 1, 256),   // 0: default
+    IFA_V(32, 1, 256),   // 0
     IFA_V(32, 1, 64),    IFA_V(32, 1, 128),  IFA_V(32, 1, 512),
     IFA_V(32, 2, 256),   IFA_V(32, 2, 128),
     IFA_V(16, 1, 256),   IFA_V(16, 1, 128),  IFA_V(16, 1, 512),
@@ -1024,6 +1024,10 @@ static const VariantDesc kVariantTable[] = {
 #undef IFA_VM3
 
 uint32_t variant_count() { return sizeof(kVariantTable) / sizeof(kVariantTable[0]); }
+
+// Variant a context starts with: the three-class matrix-core filter with
+// 256-thread workgroups (index of IFA_VM3(256, 32768) above).
+uint32_t variant_default() { return 20; }
 
 void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg, uint32_t *enc)
 {

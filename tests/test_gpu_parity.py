@@ -269,6 +269,12 @@ def test_c2_scaled_full_parity(ifa, orc):
                 assert (p.query, p.contig, p.pos, p.strand) in found
 
 
+def test_default_variant_is_the_three_class_matrix_filter(ifa):
+    with ifa.Scanner() as s:
+        v = ifa.ifa_get_variant(s.ctx)
+        assert ifa.ifa_variant_info(v)["encoding"] == 2
+
+
 def test_every_kernel_variant_is_bit_exact(ifa, orc):
     """The autotuner may pick any variant, so each must give the oracle's hits."""
     import synth
