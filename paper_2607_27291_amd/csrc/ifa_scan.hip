@@ -254,26 +254,49 @@ __device__ void exact_plain(const ScanArgs &a, const QS &d, const Lane &ln, uint
     }
 }
 
+// Wave-wide sums with DPP moves (no LDS round trips): an inclusive scan
+// within each row of 16 lanes (row_shr 1, 2, 4, 8), then row 0's total is
+// broadcast into row 1 and row 2's into row 3 (row_bcast:15), then lane 31's
+// into rows 2 and 3 (row_bcast:31); lane 63 ends with the wave's total.
+// Lanes whose DPP source is out of range or masked read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_get(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, true);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void dpp_step(uint32_t &c, uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t tc = dpp_get<CTRL, ROWS>(c);
+    const uint32_t tl = dpp_get<CTRL, ROWS>(lo);
+    const uint32_t th = dpp_get<CTRL, ROWS>(hi);
+    const uint32_t nl = lo + tl;
+    hi += th + (nl < lo ? 1u : 0u);
+    lo = nl;
+    c += tc;
+}
+
 // Sum cnt / dig over the wave and add them once, to stripe `stripe` of the
 // query's count+digest accumulators. Called by all 64 lanes.
 __device__ __forceinline__ void wave_add_stats(const ScanArgs &a, uint32_t qid, uint32_t cnt,
                                                uint64_t dig, uint32_t stripe)
 {
     if (!__any(cnt != 0u)) return;
-    uint32_t dlo = (uint32_t)dig, dhi = (uint32_t)(dig >> 32);
-    for (int o = 32; o >= 1; o >>= 1) {
-        const uint32_t c_o = __shfl_xor(cnt, o);
-        const uint32_t lo_o = __shfl_xor(dlo, o);
-        const uint32_t hi_o = __shfl_xor(dhi, o);
-        const uint64_t sum = ((uint64_t)dhi << 32 | dlo) + ((uint64_t)hi_o << 32 | lo_o);
-        cnt += c_o;
-        dlo = (uint32_t)sum;
-        dhi = (uint32_t)(sum >> 32);
-    }
+    uint32_t lo = (uint32_t)dig, hi = (uint32_t)(dig >> 32);
+    dpp_step<0x111, 0xf>(cnt, lo, hi);   // row_shr:1
+    dpp_step<0x112, 0xf>(cnt, lo, hi);   // row_shr:2
+    dpp_step<0x114, 0xf>(cnt, lo, hi);   // row_shr:4
+    dpp_step<0x118, 0xf>(cnt, lo, hi);   // row_shr:8
+    dpp_step<0x142, 0xa>(cnt, lo, hi);   // row_bcast:15 into rows 1, 3
+    dpp_step<0x143, 0xc>(cnt, lo, hi);   // row_bcast:31 into rows 2, 3
+    const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)cnt, 63);
+    const uint32_t tl = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
+    const uint32_t th = (uint32_t)__builtin_amdgcn_readlane((int)hi, 63);
     if ((threadIdx.x & 63u) == 0u) {
         const uint32_t slot = qid * kStripes + stripe % kStripes;
-        atomicAdd(&a.q_count[slot], (unsigned long long)cnt);
-        atomicAdd(&a.q_digest[slot], ((unsigned long long)dhi << 32) | dlo);
+        atomicAdd(&a.q_count[slot], (unsigned long long)tc);
+        atomicAdd(&a.q_digest[slot], ((unsigned long long)th << 32) | tl);
     }
 }
 
@@ -919,8 +942,11 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
     // the wave-wide reduction
     uint32_t cnt = 0, qid = 0xffffffffu;
     uint64_t dig = 0;
+    // the next strand's descriptor is loaded while this one runs
+    QS nxt = load_qs(a, a.n_sparse);
     for (uint32_t q = a.n_sparse; q < a.n_qs; q++) {
-        const QS d = load_qs(a, q);
+        const QS d = nxt;
+        if (q + 1u < a.n_qs) nxt = load_qs(a, q + 1u);
         if (d.qid != qid) {
             if (a.sink == kSinkCountDigest && qid != 0xffffffffu)
                 wave_add_stats(a, qid, cnt, dig, wave);
