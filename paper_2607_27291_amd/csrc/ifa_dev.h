@@ -97,10 +97,14 @@ struct ScanArgs {
     // needs to stay a candidate (padding columns: unreachable)
     const uint4 *mq_b;
     const float *mq_t;
-    // three-class form: four strands (x 8 shifts) per tile, two K steps;
-    // mq3_b[(2 tile + K step) * 64 + lane], mq3_t[32 tile + column]
+    // three-class form: four strands (x 8 shifts) per tile, two K steps per
+    // 32-base prefix word, up to two words:
+    // mq3_b[((2 tile + word) * 2 + K step) * 64 + lane], mq3_t[32 tile + column],
+    // mq3_w[tile] = words the tile filters on; mq3_words = their maximum
     const uint4 *mq3_b;
     const float *mq3_t;
+    const uint32_t *mq3_w;
+    uint32_t mq3_words;
     // count+digest sink, kStripes slots per query (see kStripes)
     unsigned long long *q_count;
     unsigned long long *q_digest;

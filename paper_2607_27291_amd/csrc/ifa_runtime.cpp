@@ -242,6 +242,8 @@ struct ifa_ctx {
     const uint32_t *dq_words = nullptr;
     const uint4 *dq_mqb = nullptr, *dq_mq3b = nullptr;
     const float *dq_mqt = nullptr, *dq_mq3t = nullptr;
+    const uint32_t *dq_mq3w = nullptr;
+    uint32_t mq3_words = 1;           // most prefix words of any three-class column tile
     DevBuf<unsigned long long> d_qcount, d_qdigest;
 
     // streaming
@@ -458,6 +460,8 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.mq_t = c->dq_mqt;
     a.mq3_b = c->dq_mq3b;
     a.mq3_t = c->dq_mq3t;
+    a.mq3_w = c->dq_mq3w;
+    a.mq3_words = c->mq3_words;
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
@@ -954,15 +958,16 @@ void pack_query_strands(uint32_t strands, uint32_t n, const uint8_t *const *seq,
 // batch of 32 strands) with a candidate among the wave's windows (64 lanes x
 // at most 16 windows); waves holding a reference N add items of their own,
 // for which the list grows when they are many.
-uint64_t expected_work_items(const std::vector<QSDesc> &qs, uint32_t n_sparse,
-                             uint64_t chunk_bases)
+uint64_t expected_work_items(const std::vector<QSDesc> &qs, const std::vector<uint8_t> &fw,
+                             uint32_t n_sparse, uint64_t chunk_bases)
 {
     const double waves = (double)chunk_bases / 1024.0 + 1.0;
     double items = 0.0;
     for (uint32_t b = 0; b < n_sparse; b += 32) {
         double log_none = 0.0;
         for (uint32_t s = b; s < std::min<uint32_t>(n_sparse, b + 32); s++) {
-            const double p = binom_cdf(std::min<uint32_t>(qs[s].len, 32u), 0.75, qs[s].thr);
+            const uint32_t lf = std::min<uint32_t>(qs[s].len, 32u * std::max<uint32_t>(fw[s], 1u));
+            const double p = binom_cdf(lf, 0.75, qs[s].thr);
             log_none += 1024.0 * std::log1p(-std::min(p, 1.0 - 1e-12));
         }
         items += waves * -std::expm1(log_none);
@@ -1003,60 +1008,100 @@ void build_mfma_operands(const std::vector<QSDesc> &qs, uint32_t n_sparse,
     }
 }
 
+// Longest filter prefix, in 32-base words (the three-class matrix filter
+// reads up to this many; the other filters read one).
+constexpr uint32_t kFilterWords = 2;
+
 // Operands of the three-class matrix-core filter: tile nt holds strands
-// 4nt .. 4nt+3, column c = 8 (strand - 4nt) + shift r. For lane l (column
+// 4nt .. 4nt+3, column c = 8 (strand - 4nt) + shift r, and filters on the
+// first Lf = min(L, 32 W) bases of each, W = words[nt] = the most prefix words
+// (filter_words) any of its strands needs. For word w < W, lane l (column
 // l % 32, half h = l / 32), K step t, register d the slot is z = 8h + 4t + d:
 // segment block k = z / 3 and class z % 3 (C, G, T; codes 1, 3, 2); nibble o
-// is segment base i = 8k + o and query base j = i - r. The value is +1.0
-// (e2m1 code 2) when 0 <= j < min(L, 32) and the query base there has the
-// slot's class, -1.0 (code 0xA) when it is A, else 0; slot 15 stays 0.
-// need[c] = min(L, 32) - thr - nA, nA = A bases among those positions.
-void build_mfma3_operands(const std::vector<QSDesc> &qs, uint32_t n_sparse,
-                          std::vector<uint32_t> &b, std::vector<float> &need)
+// is segment base i = 8k + o and query base j = 32w + i - r. The value is
+// +1.0 (e2m1 code 2) when 32w <= j < min(32(w + 1), Lf) and the query base
+// there has the slot's class, -1.0 (code 0xA) when it is A, else 0; slot 15
+// stays 0. Layout: b[(((2 nt + w) * 2 + t) * 64 + lane) * 4 + d] (word 1 is
+// zero when W = 1). need[c] = Lf - thr - nA, nA = A bases among the first Lf.
+void build_mfma3_operands(const std::vector<QSDesc> &qs, const std::vector<uint32_t> &qw,
+                          const std::vector<uint8_t> &fw, uint32_t n_sparse,
+                          std::vector<uint32_t> &b, std::vector<float> &need,
+                          std::vector<uint32_t> &words)
 {
     static const uint32_t kClass[3] = {1u, 3u, 2u};
     const uint32_t n_tiles = (n_sparse + 3) / 4;
-    b.assign((size_t)n_tiles * 2 * 64 * 4, 0u);
+    b.assign((size_t)n_tiles * kFilterWords * 2 * 64 * 4, 0u);
     need.assign((size_t)n_tiles * 32, 1e30f);
+    words.assign(n_tiles, 1u);
+    for (uint32_t nt = 0; nt < n_tiles; nt++)
+        for (uint32_t s = 4 * nt; s < std::min(n_sparse, 4 * nt + 4); s++)
+            words[nt] = std::max<uint32_t>(words[nt], fw[s]);
     for (uint32_t nt = 0; nt < n_tiles; nt++) {
         for (uint32_t c = 0; c < 32; c++) {
             const uint32_t s = 4 * nt + c / 8, r = c % 8;
             if (s >= n_sparse) continue;
             const QSDesc &d = qs[s];
-            const uint32_t l32 = std::min<uint32_t>(d.len, 32u);
-            auto code = [&](uint32_t j) { return 2u * ((d.qh0 >> j) & 1u) + ((d.ql0 >> j) & 1u); };
+            const uint32_t lf = std::min<uint32_t>(d.len, 32u * words[nt]);
+            // the strand's bases 0 .. lf-1 (lf <= 64) from its packed words
+            uint8_t code[64], isn[64];
+            for (uint32_t j = 0; j < lf; j++) {
+                const uint32_t wd = j >> 5, bit = j & 31;
+                const uint32_t qh = wd == 0 ? d.qh0 : qw[d.woff + 3 * wd];
+                const uint32_t ql = wd == 0 ? d.ql0 : qw[d.woff + 3 * wd + 1];
+                const uint32_t qn = wd == 0 ? d.qn0 : qw[d.woff + 3 * wd + 2];
+                code[j] = (uint8_t)(2u * ((qh >> bit) & 1u) + ((ql >> bit) & 1u));
+                isn[j] = (uint8_t)((qn >> bit) & 1u);
+            }
             uint32_t n_a = 0;
-            for (uint32_t j = 0; j < l32; j++)
-                if (!((d.qn0 >> j) & 1u) && code(j) == 0u) n_a++;
-            need[32 * nt + c] = (float)l32 - (float)d.thr - (float)n_a;
-            for (uint32_t h = 0; h < 2; h++)
-                for (uint32_t t = 0; t < 2; t++)
-                    for (uint32_t dd = 0; dd < 4; dd++) {
-                        const uint32_t z = 8 * h + 4 * t + dd;
-                        if (z >= 15) continue;
-                        const uint32_t k = z / 3, cls = kClass[z % 3];
-                        uint32_t word = 0;
-                        for (uint32_t o = 0; o < 8; o++) {
-                            const int32_t j = (int32_t)(8 * k + o) - (int32_t)r;
-                            if (j < 0 || j >= (int32_t)l32 || ((d.qn0 >> j) & 1u)) continue;
-                            const uint32_t q = code((uint32_t)j);
-                            if (q == cls) word |= 0x2u << (4 * o);
-                            else if (q == 0u) word |= 0xAu << (4 * o);
+            for (uint32_t j = 0; j < lf; j++)
+                if (!isn[j] && code[j] == 0u) n_a++;
+            need[32 * nt + c] = (float)lf - (float)d.thr - (float)n_a;
+            for (uint32_t w = 0; w < words[nt]; w++)
+                for (uint32_t h = 0; h < 2; h++)
+                    for (uint32_t t = 0; t < 2; t++)
+                        for (uint32_t dd = 0; dd < 4; dd++) {
+                            const uint32_t z = 8 * h + 4 * t + dd;
+                            if (z >= 15) continue;
+                            const uint32_t k = z / 3, cls = kClass[z % 3];
+                            uint32_t word = 0;
+                            for (uint32_t o = 0; o < 8; o++) {
+                                const int32_t j = (int32_t)(32 * w + 8 * k + o) - (int32_t)r;
+                                if (j < (int32_t)(32 * w) || j >= (int32_t)std::min(32 * w + 32, lf))
+                                    continue;
+                                if (isn[j]) continue;
+                                if (code[j] == cls) word |= 0x2u << (4 * o);
+                                else if (code[j] == 0u) word |= 0xAu << (4 * o);
+                            }
+                            const size_t lane = c + 32 * h;
+                            b[((((size_t)nt * kFilterWords + w) * 2 + t) * 64 + lane) * 4 + dd] = word;
                         }
-                        const size_t lane = c + 32 * h;
-                        b[((2 * (size_t)nt + t) * 64 + lane) * 4 + dd] = word;
-                    }
         }
     }
+}
+
+// 32-base words of the strand's prefix a filter needs so that it passes a
+// window in under half of the 1024-window waves on iid bases (P(Bin(Lf, 3/4)
+// <= thr) * 1024 < 1/2 with Lf = min(L, 32 w)), for w up to kFilterWords;
+// 0 when no such prefix exists (the strand is dense).
+
+uint32_t filter_words(const QSDesc &d)
+{
+    for (uint32_t w = 1; w <= kFilterWords; w++) {
+        const uint32_t lf = std::min<uint32_t>(d.len, 32u * w);
+        if (d.thr < lf && binom_cdf(lf, 0.75, d.thr) * 1024.0 < 0.5) return w;
+        if (lf == d.len) break;
+    }
+    return 0;
 }
 
 void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t> &&words,
                      uint32_t n_queries, uint32_t lmax)
 {
-    std::vector<uint8_t> dense(qs.size());
-    for (size_t i = 0; i < qs.size(); i++)
-        dense[i] = qs[i].thr >= 32u ||
-                   binom_cdf(std::min<uint32_t>(qs[i].len, 32u), 0.75, qs[i].k) * 1024.0 >= 0.5;
+    std::vector<uint8_t> fw(qs.size()), dense(qs.size());
+    for (size_t i = 0; i < qs.size(); i++) {
+        fw[i] = (uint8_t)filter_words(qs[i]);
+        dense[i] = fw[i] == 0;
+    }
     std::vector<size_t> order(qs.size());
     for (size_t i = 0; i < order.size(); i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
@@ -1066,27 +1111,31 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
         return a.k < b.k;
     });
     std::vector<QSDesc> sorted;
+    std::vector<uint8_t> sorted_fw;
     sorted.reserve(qs.size());
     uint32_t n_sparse = 0;
     for (size_t i : order) {
         sorted.push_back(qs[i]);
+        sorted_fw.push_back(fw[i]);
         if (!dense[i]) n_sparse++;
     }
     qs.swap(sorted);
-    std::vector<uint32_t> mb, mb3;
+    std::vector<uint32_t> mb, mb3, mw3;
     std::vector<float> mt, mt3;
     build_mfma_operands(qs, n_sparse, mb, mt);
-    build_mfma3_operands(qs, n_sparse, mb3, mt3);
+    build_mfma3_operands(qs, words, sorted_fw, n_sparse, mb3, mt3, mw3);
+    c->mq3_words = mw3.empty() ? 1u : *std::max_element(mw3.begin(), mw3.end());
     // one upload of every table: parts at 256-byte offsets in one arena
     struct Part {
         const void *src;
         size_t bytes, off;
-    } parts[6] = {{qs.data(), qs.size() * sizeof(QSDesc), 0},
+    } parts[7] = {{qs.data(), qs.size() * sizeof(QSDesc), 0},
                   {words.data(), words.size() * sizeof(uint32_t), 0},
                   {mb.data(), mb.size() * sizeof(uint32_t), 0},
                   {mt.data(), mt.size() * sizeof(float), 0},
                   {mb3.data(), mb3.size() * sizeof(uint32_t), 0},
-                  {mt3.data(), mt3.size() * sizeof(float), 0}};
+                  {mt3.data(), mt3.size() * sizeof(float), 0},
+                  {mw3.data(), mw3.size() * sizeof(uint32_t), 0}};
     size_t total = 0;
     for (Part &pt : parts) {
         pt.off = total;
@@ -1108,6 +1157,7 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     c->dq_mqt = reinterpret_cast<const float *>(base + parts[3].off);
     c->dq_mq3b = reinterpret_cast<const uint4 *>(base + parts[4].off);
     c->dq_mq3t = reinterpret_cast<const float *>(base + parts[5].off);
+    c->dq_mq3w = reinterpret_cast<const uint32_t *>(base + parts[6].off);
     if (c->cfg.sink == IFA_SINK_COUNT_DIGEST) {
         const size_t need = (size_t)std::max<uint32_t>(n_queries, 1) * kStripes;
         if (c->d_qcount.n < need) {
@@ -1120,7 +1170,7 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     // size the work lists for the expected load unless the caller fixed the
     // initial capacity (they grow on overflow either way)
     if (c->cfg.work_capacity == 0) {
-        const uint64_t est = expected_work_items(qs, n_sparse, c->cfg.chunk_bases);
+        const uint64_t est = expected_work_items(qs, sorted_fw, n_sparse, c->cfg.chunk_bases);
         c->work_want =
             (uint32_t)std::min<uint64_t>(std::max<uint64_t>(est, c->work_want), 1ull << 28);
     }

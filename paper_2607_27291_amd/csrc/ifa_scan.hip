@@ -717,22 +717,28 @@ static uint32_t mq_lds_bytes(uint32_t tiles)
 // mq3_t holds the match count minus nA that a column needs.
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t kM3Blocks = 136;            // 8-base blocks staged per wave
-constexpr uint32_t kM3Words = 3 * kM3Blocks;   // indicator words per wave
+// 8-base blocks a wave stages: its 1024 windows read up to base
+// 1024 + 32 NW + 7 of its stream (block 132 + 4 (NW - 1) at most)
+__host__ __device__ constexpr uint32_t m3_blocks(int nw) { return 136u + 4u * (uint32_t)(nw - 1); }
 
-template <int WG>
+// NW: most prefix words (32 bases each) of the launch's column tiles; tile nt
+// filters on mq3_w[nt] <= NW of them, each adding two K steps to its sums.
+template <int WG, int NW>
 __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
 {
+    constexpr uint32_t kBlocks = m3_blocks(NW), kWords = 3 * kBlocks;
     extern __shared__ uint4 lds[];
     const uint32_t qb = 32u * blockIdx.y;
     const uint32_t n_tiles = (a.n_sparse + 3u) >> 2;
     const uint32_t t0 = qb >> 2, tn = min(n_tiles, t0 + 8u) - t0;   // tiles of the batch
-    uint4 *sb = lds;                                                // [tn][2][64]
-    float *st = reinterpret_cast<float *>(lds + 128u * tn);         // [tn][32]
-    uint32_t *sp = reinterpret_cast<uint32_t *>(st + 32u * tn);     // [256]
-    uint32_t *flat = sp + 256u + (threadIdx.x >> 6) * kM3Words;     // this wave's words
-    for (uint32_t i = threadIdx.x; i < 128u * tn; i += WG) sb[i] = a.mq3_b[128u * t0 + i];
+    uint4 *sb = lds;                                                // [tn][2 words][2][64]
+    float *st = reinterpret_cast<float *>(lds + 256u * tn);         // [tn][32]
+    uint32_t *sw = reinterpret_cast<uint32_t *>(st + 32u * tn);     // [8]
+    uint32_t *sp = sw + 8;                                          // [256]
+    uint32_t *flat = sp + 256u + (threadIdx.x >> 6) * kWords;       // this wave's words
+    for (uint32_t i = threadIdx.x; i < 256u * tn; i += WG) sb[i] = a.mq3_b[256u * t0 + i];
     for (uint32_t i = threadIdx.x; i < 32u * tn; i += WG) st[i] = a.mq3_t[32u * t0 + i];
+    for (uint32_t i = threadIdx.x; i < tn; i += WG) sw[i] = a.mq3_w[t0 + i];
     for (uint32_t i = threadIdx.x; i < 256u; i += WG) sp[i] = kSpread.v[i];
     __syncthreads();
 
@@ -759,7 +765,7 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
 #pragma unroll
         for (uint32_t r = 0; r < 3; r++) {
             const uint32_t b = l + 64u * r;
-            if (b < kM3Blocks) {
+            if (b < kBlocks) {
                 const uint32_t w = min(w0 + (b >> 2), last), sh = 8u * (b & 3u);
                 const uint32_t s1 = sp[(a.hi[w] >> sh) & 0xffu];
                 const uint32_t s0 = sp[(a.lo[w] >> sh) & 0xffu];
@@ -772,28 +778,44 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        ifa_v8i A[4][2];
+        // word w of group g reads the segment from block g + 4w
+        ifa_v8i A[NW][4][2];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const uint32_t *f = flat + 3u * (32u * u + g) + 8u * h;
+        for (int w = 0; w < NW; w++)
 #pragma unroll
-            for (int t = 0; t < 2; t++)
-                A[u][t] = ifa_v8i{(int)f[4 * t], (int)f[4 * t + 1], (int)f[4 * t + 2],
-                                  (int)f[4 * t + 3], 0, 0, 0, 0};
-        }
+            for (int u = 0; u < 4; u++) {
+                const uint32_t *f = flat + 3u * (32u * u + g + 4u * w) + 8u * h;
+#pragma unroll
+                for (int t = 0; t < 2; t++)
+                    A[w][u][t] = ifa_v8i{(int)f[4 * t], (int)f[4 * t + 1], (int)f[4 * t + 2],
+                                         (int)f[4 * t + 3], 0, 0, 0, 0};
+            }
         uint32_t pending = 0;   // wave-uniform
         for (uint32_t nt = 0; nt < tn; nt++) {
-            const uint4 v0 = sb[(2u * nt) * 64u + l], v1 = sb[(2u * nt + 1u) * 64u + l];
+            const uint4 v0 = sb[(4u * nt) * 64u + l], v1 = sb[(4u * nt + 1u) * 64u + l];
             const ifa_v8i B0 = {(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, 0, 0, 0, 0};
             const ifa_v8i B1 = {(int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w, 0, 0, 0, 0};
+            ifa_v8i B2 = {}, B3 = {};
+            const bool two = NW == 2 && __builtin_amdgcn_readfirstlane(sw[nt]) == 2u;
+            if (two) {
+                const uint4 v2 = sb[(4u * nt + 2u) * 64u + l], v3 = sb[(4u * nt + 3u) * 64u + l];
+                B2 = ifa_v8i{(int)v2.x, (int)v2.y, (int)v2.z, (int)v2.w, 0, 0, 0, 0};
+                B3 = ifa_v8i{(int)v3.x, (int)v3.y, (int)v3.z, (int)v3.w, 0, 0, 0, 0};
+            }
             const float need = st[32u * nt + g];
             float mx = -1e30f;
 #pragma unroll
             for (int p = 0; p < 2; p++) {
-                ifa_v16f d0 = mfma_fp4(A[2 * p][0], B0, zero);
-                ifa_v16f d1 = mfma_fp4(A[2 * p + 1][0], B0, zero);
-                d0 = mfma_fp4(A[2 * p][1], B1, d0);
-                d1 = mfma_fp4(A[2 * p + 1][1], B1, d1);
+                ifa_v16f d0 = mfma_fp4(A[0][2 * p][0], B0, zero);
+                ifa_v16f d1 = mfma_fp4(A[0][2 * p + 1][0], B0, zero);
+                d0 = mfma_fp4(A[0][2 * p][1], B1, d0);
+                d1 = mfma_fp4(A[0][2 * p + 1][1], B1, d1);
+                if (two) {
+                    d0 = mfma_fp4(A[NW - 1][2 * p][0], B2, d0);
+                    d1 = mfma_fp4(A[NW - 1][2 * p + 1][0], B2, d1);
+                    d0 = mfma_fp4(A[NW - 1][2 * p][1], B3, d0);
+                    d1 = mfma_fp4(A[NW - 1][2 * p + 1][1], B3, d1);
+                }
 #pragma unroll
                 for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(d0[i], d1[i]), mx);
             }
@@ -819,9 +841,10 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
 }
 
 // LDS bytes of the three-class matrix filter for `tiles` column tiles.
-static uint32_t mq3_lds_bytes(uint32_t tiles, uint32_t wg)
+static uint32_t mq3_lds_bytes(uint32_t tiles, uint32_t wg, int nw)
 {
-    return tiles * (128u * 16u + 32u * 4u) + 256u * 4u + (wg / 64u) * kM3Words * 4u;
+    return tiles * (256u * 16u + 32u * 4u) + 8u * 4u + 256u * 4u +
+           (wg / 64u) * 3u * m3_blocks(nw) * 4u;
 }
 
 // One wave per work item (grid-stride). Does nothing when the filter kernel
@@ -1006,6 +1029,7 @@ __global__ void clear_u32_kernel(unsigned int *p, uint32_t n)
 
 struct VariantDesc {
     void (*filter)(ScanArgs);
+    void (*filter2)(ScanArgs);   // for query sets whose filter prefix spans two words
     void (*resolve)(ScanArgs);
     void (*dense)(ScanArgs);
     void (*dense_cold)(ScanArgs);
@@ -1019,19 +1043,21 @@ struct VariantDesc {
 
 #define IFA_V(W, QU, WG)                                                                 \
     {                                                                                    \
-        scan_filter_kernel<W, QU, WG>, scan_resolve_kernel<W>, scan_dense_kernel<W>,     \
-            scan_dense_cold_kernel<W>, W, QU, WG, 0, 0                                   \
+        scan_filter_kernel<W, QU, WG>, scan_filter_kernel<W, QU, WG>,                    \
+            scan_resolve_kernel<W>, scan_dense_kernel<W>, scan_dense_cold_kernel<W>, W, QU,  \
+            WG, 0, 0                                                                     \
     }
 // matrix-core filters: waves of 16 windows per lane, resolved by the W = 16 kernels
 #define IFA_VM3(WG, WAVES)                                                               \
     {                                                                                    \
-        scan_filter_mfma3_kernel<WG>, scan_resolve_kernel<16>, scan_dense_kernel<16>,    \
-            scan_dense_cold_kernel<16>, 16, 4, WG, 2, WAVES                              \
+        scan_filter_mfma3_kernel<WG, 1>, scan_filter_mfma3_kernel<WG, 2>,                \
+            scan_resolve_kernel<16>, scan_dense_kernel<16>, scan_dense_cold_kernel<16>, 16,  \
+            4, WG, 2, WAVES                                                              \
     }
 #define IFA_VM(WG, WAVES)                                                                \
     {                                                                                    \
-        scan_filter_mfma_kernel<WG>, scan_resolve_kernel<16>, scan_dense_kernel<16>,     \
-            scan_dense_cold_kernel<16>, 16, 2, WG, 1, WAVES                              \
+        scan_filter_mfma_kernel<WG>, scan_filter_mfma_kernel<WG>, scan_resolve_kernel<16>, \
+            scan_dense_kernel<16>, scan_dense_cold_kernel<16>, 16, 2, WG, 1, WAVES       \
     }
 static const VariantDesc kVariantTable[] = {
     IFA_V(32, 1, 256),   // 0
@@ -1090,9 +1116,11 @@ hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
         const uint32_t batches = (a.n_sparse + 31u) / 32u;
         const uint32_t want = (v.waves + wpg * batches - 1) / (wpg * batches);
         const uint32_t gx = max(1u, min((waves + wpg - 1) / wpg, want));
-        const uint32_t lds = v.enc == 1 ? mq_lds_bytes(min(16u, (a.n_sparse + 1u) / 2u))
-                                        : mq3_lds_bytes(min(8u, (a.n_sparse + 3u) / 4u), v.wg);
-        hipLaunchKernelGGL(v.filter, dim3(gx, batches), dim3(v.wg), lds, s, a);
+        const bool two = v.enc == 2 && a.mq3_words >= 2;
+        const uint32_t lds =
+            v.enc == 1 ? mq_lds_bytes(min(16u, (a.n_sparse + 1u) / 2u))
+                       : mq3_lds_bytes(min(8u, (a.n_sparse + 3u) / 4u), v.wg, two ? 2 : 1);
+        hipLaunchKernelGGL(two ? v.filter2 : v.filter, dim3(gx, batches), dim3(v.wg), lds, s, a);
         return hipGetLastError();
     }
     const uint64_t lanes = filter_lanes(a, v);

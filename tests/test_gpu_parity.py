@@ -466,3 +466,74 @@ def test_resident_graph_replays_match_eager(ifa, orc, sink):
         st = g.stats()
         assert st["graph_launches"] > 0
         assert e.stats()["graph_launches"] == 0
+
+
+@pytest.mark.parametrize("sink", [0, 1])
+def test_two_word_filter_prefix(ifa, orc, sink):
+    """Long queries with thresholds the 32-base prefix cannot filter (the
+    three-class matrix filter then reads 64 bases; column tiles mixing one-
+    and two-word strands share a launch) match the oracle under every
+    variant, and those strands leave the dense path."""
+    import synth
+    spec = synth.c2_spec(seed=123, total=1_200_000)
+    spec.n_param = 3e-3
+    spec.median = 80_000
+    ref = synth.gen_reference(spec)
+    rng = random.Random(123)
+    qs, ks = [], []
+    for _ in range(30):
+        L = rng.choice([33, 40, 47, 56, 64, 90, 150])
+        qs.append(rand_dna(rng, L, b"ACGT" if rng.random() < 0.85 else b"ACGTN"))
+        ks.append(rng.randint(min(L // 4, 20), min(L // 3 + 2, 24)))
+    for _ in range(10):   # strands a 32-base prefix filters on its own
+        qs.append(rand_dna(rng, rng.choice([28, 32, 36])))
+        ks.append(rng.randint(0, 6))
+    # the partition rule: the shortest prefix of one or two 32-base words
+    # whose filter passes a window in under half of the 1024-window waves
+    from scipy.stats import binom
+
+    def words(L, k):
+        for w in (1, 2):
+            lf = min(L, 32 * w)
+            if min(k, L) < lf and binom.cdf(min(k, L), lf, 0.75) * 1024 < 0.5:
+                return w
+            if lf == L:
+                break
+        return 0
+    fws = [words(len(q), k) for q, k in zip(qs, ks)]
+    assert fws.count(2) >= 10
+    # plant near copies so that hits exist for the long queries too
+    buf = bytearray(ref.buf.tobytes())
+    for qi, q in enumerate(qs[:30]):
+        for _ in range(2):
+            c = rng.randrange(ref.n_contigs)
+            n = int(ref.lens[c])
+            if n < len(q) + 10:
+                continue
+            p = int(ref.offs[c]) + rng.randint(0, n - len(q))
+            src = bytearray(q if rng.random() < 0.5 else q.translate(COMP)[::-1])
+            for j in rng.sample(range(len(q)), min(len(q), ks[qi])):
+                src[j] = rng.choice(b"ACGT")
+            buf[p:p + len(q)] = src
+    ref = synth.Reference(np.frombuffer(bytes(buf), dtype=np.uint8).copy(), ref.offs, ref.lens)
+    if sink == 0:
+        want = orc.scan(qs, ref, ks)
+        assert len(want) > 30
+    else:
+        _, cnt, dig = orc.scan(qs, ref, ks, stats=True, records=False)
+    for v in range(ifa.ifa_variant_count()):
+        info = ifa.ifa_variant_info(v)
+        if info["encoding"] == 0 and info["workgroup"] != 256:
+            continue   # VALU shapes: one is enough here (they filter on 32 bases)
+        say(f"two-word prefix, variant {v} {info} sink {sink}")
+        with ifa.Scanner(chunk_bases=1 << 19, sink=sink) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries(qs, ks)
+            strands, filtered = ifa.ifa_query_partition(s.ctx)
+            assert (strands, filtered) == (2 * len(qs), 2 * sum(1 for w in fws if w))
+            s.scan_chunk(ref)
+            if sink == 0:
+                assert_same(s.collect(), want, f"variant {v}")
+            else:
+                gc, gd = s.query_stats()
+                assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), f"variant {v}"
