@@ -349,14 +349,27 @@ __device__ __forceinline__ uint32_t filter_min(const uint32_t (&sh)[W], const ui
 }
 
 // The filter decision formed from the lane's plane words (cold paths), over
-// the first min(L, 32) bases. N positions: under N_SEPARATE they are left out
-// of the count, and a window whose N count there already exceeds maxN is
-// pushed past any threshold; under N_AS_MISMATCH they are mismatches.
+// the first min(L, 32 nw) bases, nw = 1 or 2 (the prefix words the strand's
+// three-class matrix tile filters on). N positions: under N_SEPARATE they are
+// left out of the count, and a window whose N count there already exceeds
+// maxN is pushed past any threshold; under N_AS_MISMATCH they are mismatches.
 template <int W>
-__device__ __forceinline__ bool filter_cand_words(const ScanArgs &a, const QS &d, const Lane &ln)
+__device__ __forceinline__ bool filter_cand_words(const ScanArgs &a, const QS &d, const Lane &ln,
+                                                  uint32_t nw)
 {
-    if (d.thr >= 32u) return true;
-    const uint32_t lmask = low_mask(d.len);
+    const bool two = nw >= 2u && d.len > 32u;
+    if (!two && d.thr >= 32u) return true;
+    const uint32_t lmask = low_mask(d.len), lmask1 = two ? low_mask(d.len - 32u) : 0u;
+    uint32_t h2 = 0, l2 = 0, n2 = 0, qh1 = 0, ql1 = 0, qn1 = 0;
+    if (two) {
+        const IFA_CONST uint32_t *qw = as_const(a.qwords) + d.woff;
+        h2 = a.hi[ln.w + 2];
+        l2 = a.lo[ln.w + 2];
+        n2 = a.nm[ln.w + 2];
+        qh1 = qw[3];
+        ql1 = qw[4];
+        qn1 = qw[5];
+    }
     uint32_t mn = 0xffffffffu;
 #pragma unroll 4
     for (int b = 0; b < W; b++) {
@@ -365,14 +378,27 @@ __device__ __forceinline__ bool filter_cand_words(const ScanArgs &a, const QS &d
         diff = __builtin_amdgcn_bitop3_b32(diff, funnel(ln.l1, ln.l0, s), d.ql, IFA_OR_XOR);
         const uint32_t rn = funnel(ln.n1, ln.n0, s) & lmask;
         diff &= lmask;
+        uint32_t d1 = 0, rn1 = 0;
+        if (two) {
+            d1 = __builtin_amdgcn_bitop3_b32(funnel(h2, ln.h1, s), qh1, qn1, IFA_XOR_OR);
+            d1 = __builtin_amdgcn_bitop3_b32(d1, funnel(l2, ln.l1, s), ql1, IFA_OR_XOR) & lmask1;
+            rn1 = funnel(n2, ln.n1, s) & lmask1;
+        }
         if (a.policy == kNSeparate) {
-            const uint32_t over = __popc(rn) > d.maxn ? 64u : 0u;
-            mn = min(mn, (uint32_t)__popc(diff & ~rn) + over);
+            const uint32_t over = __popc(rn) + __popc(rn1) > d.maxn ? 512u : 0u;
+            mn = min(mn, (uint32_t)(__popc(diff & ~rn) + __popc(d1 & ~rn1)) + over);
         } else {
-            mn = min(mn, (uint32_t)__popc(diff | rn));
+            mn = min(mn, (uint32_t)(__popc(diff | rn) + __popc(d1 | rn1)));
         }
     }
     return mn <= d.thr;
+}
+
+// Prefix words (1 or 2) the strand at sparse index q filters on: those of its
+// three-class matrix column tile; 1 for dense strands.
+__device__ __forceinline__ uint32_t strand_filter_words(const ScanArgs &a, uint32_t q)
+{
+    return q < a.n_sparse ? a.mq3_w[q >> 2] : 1u;
 }
 
 // Lane state of filter-grid lane `gl` (relative to w_begin).
@@ -865,7 +891,8 @@ __global__ __launch_bounds__(256) void scan_resolve_kernel(ScanArgs a)
             const uint32_t j = __builtin_ctz(pending);
             pending &= pending - 1u;
             const QS d = load_qs(a, qb + j);
-            resolve<W>(a, d, ln, filter_cand_words<W>(a, d, ln), wave);
+            resolve<W>(a, d, ln, filter_cand_words<W>(a, d, ln, strand_filter_words(a, qb + j)),
+                       wave);
         }
     }
 }
@@ -1004,7 +1031,7 @@ __global__ __launch_bounds__(256) void scan_dense_cold_kernel(ScanArgs a)
         const QS d = load_qs(a, q);
         uint32_t cnt = 0;
         uint64_t dig = 0;
-        if (cold && filter_cand_words<W>(a, d, ln)) exact_serial<W>(a, d, ln, cnt, dig);
+        if (cold && filter_cand_words<W>(a, d, ln, 1u)) exact_serial<W>(a, d, ln, cnt, dig);
         if (a.sink == kSinkCountDigest) wave_add_stats(a, d.qid, cnt, dig, wave);
     }
 }
