@@ -105,6 +105,9 @@ struct ScanArgs {
     const float *mq3_t;
     const uint32_t *mq3_w;
     uint32_t mq3_words;
+    // matrix-core filters: batch of 32 strands of grid row 0 (the grid's y
+    // dimension holds at most 65535 batches per launch)
+    uint32_t batch0;
     // count+digest sink, kStripes slots per query (see kStripes)
     unsigned long long *q_count;
     unsigned long long *q_digest;

@@ -622,7 +622,7 @@ template <int WG>
 __global__ __launch_bounds__(WG) void scan_filter_mfma_kernel(ScanArgs a)
 {
     extern __shared__ uint4 lds[];
-    const uint32_t qb = 32u * blockIdx.y;
+    const uint32_t qb = 32u * (a.batch0 + blockIdx.y);
     const uint32_t n_tiles = (a.n_sparse + 1u) >> 1;
     const uint32_t t0 = qb >> 1, tn = min(n_tiles, t0 + 16u) - t0;   // tiles of the batch
     uint4 *sb = lds;                                                 // [tn][3][64]
@@ -649,7 +649,7 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma_kernel(ScanArgs a)
         if (lw < a.w_end) lane_n = (a.nm[lw] | a.nm[min(lw + 1u, last)]) != 0u;
         if (__any(lane_n)) {
             if (l == 0u) {
-                if (blockIdx.y == 0) atomicAdd(a.skip_count, 1u);
+                if (a.batch0 + blockIdx.y == 0) atomicAdd(a.skip_count, 1u);
                 list_batch(a, wave, qb);
             }
             continue;
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
 {
     constexpr uint32_t kBlocks = m3_blocks(NW), kWords = 3 * kBlocks;
     extern __shared__ uint4 lds[];
-    const uint32_t qb = 32u * blockIdx.y;
+    const uint32_t qb = 32u * (a.batch0 + blockIdx.y);
     const uint32_t n_tiles = (a.n_sparse + 3u) >> 2;
     const uint32_t t0 = qb >> 2, tn = min(n_tiles, t0 + 8u) - t0;   // tiles of the batch
     uint4 *sb = lds;                                                // [tn][2 words][2][64]
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
         if (lw < a.w_end) lane_n = (a.nm[lw] | a.nm[min(lw + 1u, last)]) != 0u;
         if (__any(lane_n)) {
             if (l == 0u) {
-                if (blockIdx.y == 0) atomicAdd(a.skip_count, 1u);
+                if (a.batch0 + blockIdx.y == 0) atomicAdd(a.skip_count, 1u);
                 list_batch(a, wave, qb);
             }
             continue;
@@ -1147,8 +1147,15 @@ hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
         const uint32_t lds =
             v.enc == 1 ? mq_lds_bytes(min(16u, (a.n_sparse + 1u) / 2u))
                        : mq3_lds_bytes(min(8u, (a.n_sparse + 3u) / 4u), v.wg, two ? 2 : 1);
-        hipLaunchKernelGGL(two ? v.filter2 : v.filter, dim3(gx, batches), dim3(v.wg), lds, s, a);
-        return hipGetLastError();
+        for (uint32_t b0 = 0; b0 < batches; b0 += 65535u) {
+            ScanArgs part = a;
+            part.batch0 = b0;
+            hipLaunchKernelGGL(two ? v.filter2 : v.filter, dim3(gx, min(65535u, batches - b0)),
+                               dim3(v.wg), lds, s, part);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
     }
     const uint64_t lanes = filter_lanes(a, v);
     hipLaunchKernelGGL(v.filter, dim3((uint32_t)((lanes + v.wg - 1) / v.wg)), dim3(v.wg), 0, s, a);
