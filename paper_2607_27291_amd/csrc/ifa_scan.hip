@@ -496,6 +496,26 @@ __device__ __forceinline__ void filter_lane(const ScanArgs &a, const Lane &ln, u
     }
 }
 
+// Work items for a wave that holds an N: every strand of the batch at qb is
+// listed, as items of up to 8 strands so that different resolve waves share
+// the batch (these items carry all their strands, unlike filtered ones).
+__device__ __forceinline__ void list_batch(const ScanArgs &a, uint32_t wave, uint32_t qb)
+{
+    const uint32_t nb = min(32u, a.n_sparse - qb);
+    const uint32_t all = nb == 32u ? 0xffffffffu : ((1u << nb) - 1u);
+    const unsigned int idx = atomicAdd(a.work_count, (nb + 7u) / 8u);
+    for (uint32_t p = 0; 8u * p < nb; p++) {
+        if (idx + p < a.work_cap) {
+            WorkItem it;
+            it.wave = wave;
+            it.qb = qb;
+            it.pending = all & (0xffu << (8u * p));
+            it.pad = 0;
+            a.work[idx + p] = it;
+        }
+    }
+}
+
 template <int W, int QU, int WG>
 __global__ __launch_bounds__(WG) void scan_filter_kernel(ScanArgs a)
 {
@@ -511,18 +531,7 @@ __global__ __launch_bounds__(WG) void scan_filter_kernel(ScanArgs a)
     if (__any(lane_n)) {
         if ((threadIdx.x & 63u) == 0u) {
             atomicAdd(a.skip_count, 1u);
-            for (uint32_t qb = 0; qb < a.n_sparse; qb += 32) {
-                const uint32_t nb = min(32u, a.n_sparse - qb);
-                const unsigned int idx = atomicAdd(a.work_count, 1u);
-                if (idx < a.work_cap) {
-                    WorkItem it;
-                    it.wave = wave;
-                    it.qb = qb;
-                    it.pending = nb == 32u ? 0xffffffffu : ((1u << nb) - 1u);
-                    it.pad = 0;
-                    a.work[idx] = it;
-                }
-            }
+            for (uint32_t qb = 0; qb < a.n_sparse; qb += 32) list_batch(a, wave, qb);
         }
         return;
     }
@@ -596,21 +605,6 @@ __device__ __forceinline__ ifa_v16f mfma_fp4(const ifa_v8i &a, const ifa_v8i &b,
 {
     // cbsz = blgp = 4: both operands e2m1; E8M0 scales 127 = 1.0
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
-}
-
-// Work items for an N wave: every strand of the batch is listed.
-__device__ __forceinline__ void list_batch(const ScanArgs &a, uint32_t wave, uint32_t qb)
-{
-    const uint32_t nb = min(32u, a.n_sparse - qb);
-    const unsigned int idx = atomicAdd(a.work_count, 1u);
-    if (idx < a.work_cap) {
-        WorkItem it;
-        it.wave = wave;
-        it.qb = qb;
-        it.pending = nb == 32u ? 0xffffffffu : ((1u << nb) - 1u);
-        it.pad = 0;
-        a.work[idx] = it;
-    }
 }
 
 // Grid: x = workgroups sharing one batch of 32 sparse strands (16 column
