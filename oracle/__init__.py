@@ -19,7 +19,7 @@ import numpy as np
 
 from . import build as _build
 
-HIT_DTYPE = np.dtype([("query", "<u4"), ("contig", "<u4"), ("pos", "<u4"), ("strand", "u1"),
+HIT_DTYPE = np.dtype([("query", "<u4"), ("contig", "<u4"), ("pos", "<i4"), ("strand", "u1"),
                       ("n_ref", "u1"), ("mismatches", "<u2")])
 assert HIT_DTYPE.itemsize == 16
 
@@ -35,15 +35,17 @@ def lib():
             _build.build()
         L = ctypes.CDLL(_build.LIB)
         vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+        i64 = ctypes.c_int64
         L.orc_scan.argtypes = [u32, vp, vp, vp, vp, u32, vp, vp, u32, u32, u32, ctypes.c_int,
-                               ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(u64), vp, vp]
+                               ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp),
+                               ctypes.POINTER(u64), vp, vp]
         L.orc_scan.restype = ctypes.c_int
         L.orc_free.argtypes = [vp]
         L.orc_mix64.argtypes = [u64]
         L.orc_mix64.restype = u64
-        L.orc_hit_hash.argtypes = [u32, u32, u32, u32, u32]
+        L.orc_hit_hash.argtypes = [u32, i32, u32, u32, u32]
         L.orc_hit_hash.restype = u64
-        L.orc_eval_window.argtypes = [vp, u32, i32, i32, vp, u64, u64, u32, u32,
+        L.orc_eval_window.argtypes = [vp, u32, i32, i32, vp, u64, i64, u32, u32, ctypes.c_int,
                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.orc_eval_window.restype = ctypes.c_int
         _lib = L
@@ -88,13 +90,14 @@ class _Contigs:
 
 
 def scan(queries, contigs, max_subs, max_n=None, *, first_ordinal=0, strands=3,
-         policy=N_SEPARATE, threads=None, records=True, stats=False):
+         policy=N_SEPARATE, overhang=False, threads=None, records=True, stats=False):
     """Run the C oracle.
 
     queries: list of byte strings; contigs: list of byte strings / uint8 arrays
     (or a synth.Reference); max_subs: per-query ints; max_n: per-query ints or
-    None (floor(L/4)). Returns a HIT_DTYPE array in (contig, pos, strand,
-    query) order; with stats=True returns (hits, counts, digests).
+    None (floor(L/4)); overhang: also the windows hanging off a contig end by
+    at most min(maxN, L - 1) bases. Returns a HIT_DTYPE array in (contig, pos,
+    strand, query) order; with stats=True returns (hits, counts, digests).
     """
     if hasattr(contigs, "pointer_array"):
         ptrs, lens = contigs.pointer_array()
@@ -116,7 +119,8 @@ def scan(queries, contigs, max_subs, max_n=None, *, first_ordinal=0, strands=3,
     n_out = ctypes.c_uint64()
     rc = lib().orc_scan(nq, qptrs, qlen.ctypes.data, ks.ctypes.data,
                         None if mn is None else mn.ctypes.data, nc, ptrs, lens.ctypes.data,
-                        first_ordinal, strands, policy, threads or _default_threads(),
+                        first_ordinal, strands, policy, 1 if overhang else 0,
+                        threads or _default_threads(),
                         1 if records else 0, ctypes.byref(out), ctypes.byref(n_out),
                         counts.ctypes.data, digests.ctypes.data)
     del keep
@@ -134,15 +138,18 @@ def scan(queries, contigs, max_subs, max_n=None, *, first_ordinal=0, strands=3,
     return hits
 
 
-def eval_window(query, max_subs, contig, pos, strand, max_n=-1, policy=N_SEPARATE):
-    """Exact (hit, mismatches, n_ref) of one window; None if it does not fit."""
+def eval_window(query, max_subs, contig, pos, strand, max_n=-1, policy=N_SEPARATE,
+                overhang=False):
+    """Exact (hit, mismatches, n_ref) of one window; None if it is not a
+    window of the scan."""
     q = np.frombuffer(_as_bytes(query), dtype=np.uint8)
     c = contig if isinstance(contig, np.ndarray) else np.frombuffer(_as_bytes(contig), np.uint8)
     c = np.ascontiguousarray(c, dtype=np.uint8)
     m = ctypes.c_int32()
     nr = ctypes.c_int32()
     rc = lib().orc_eval_window(q.ctypes.data, len(q), max_subs, max_n, c.ctypes.data, c.size,
-                               pos, strand, policy, ctypes.byref(m), ctypes.byref(nr))
+                               pos, strand, policy, 1 if overhang else 0, ctypes.byref(m),
+                               ctypes.byref(nr))
     if rc < 0:
         return None
     return bool(rc), m.value, nr.value
@@ -167,21 +174,30 @@ for _i, _ch in enumerate(b"ACGT"):
 
 
 def brute_scan(queries, contigs, max_subs, max_n=None, *, first_ordinal=0, strands=3,
-               policy=N_SEPARATE):
+               policy=N_SEPARATE, overhang=False):
     """Every window of every contig, every query and strand, by whole-array
-    comparison. Same output format and order as `scan`."""
+    comparison. Same output format and order as `scan`. With overhang the
+    contig is first padded with L - 1 N codes on each side and a window may
+    hold at most min(maxN, L - 1) of them."""
     rows = []
     for ci, c in enumerate(contigs):
-        r = _CODE[np.frombuffer(_as_bytes(c), dtype=np.uint8)]
-        n = r.size
+        r0 = _CODE[np.frombuffer(_as_bytes(c), dtype=np.uint8)]
+        n = r0.size
         for j, qq in enumerate(queries):
             q = _CODE[np.frombuffer(_as_bytes(qq), dtype=np.uint8)]
             L = q.size
-            if L > n:
-                continue
+            mn = L // 4 if max_n is None else max_n[j]
             K = min(max_subs[j], L)
-            M = min(L // 4 if max_n is None else max_n[j], L)
-            W = np.lib.stride_tricks.sliding_window_view(r, L)        # (n-L+1, L)
+            M = min(mn, L)
+            pad = L - 1 if overhang else 0
+            r = np.concatenate([np.full(pad, 4, np.int8), r0, np.full(pad, 4, np.int8)])
+            off_contig = np.concatenate([np.ones(pad, bool), np.zeros(n, bool),
+                                         np.ones(pad, bool)])
+            if L > r.size:
+                continue
+            W = np.lib.stride_tricks.sliding_window_view(r, L)        # (n+2pad-L+1, L)
+            off = np.lib.stride_tricks.sliding_window_view(off_contig, L).sum(axis=1)
+            inside = off <= min(mn, L - 1)
             rN = W == 4
             nref = rN.sum(axis=1)
             qrc = np.where(q[::-1] == 4, 4, 3 - q[::-1])
@@ -194,8 +210,10 @@ def brute_scan(queries, contigs, max_subs, max_n=None, *, first_ordinal=0, stran
                 else:
                     m = ((W != qs[None, :]) | rN | (qs[None, :] == 4)).sum(axis=1)
                     ok = m <= K
+                ok &= inside if overhang else off == 0
                 for p in np.nonzero(ok)[0]:
-                    rows.append((j, first_ordinal + ci, int(p), s, int(nref[p]), int(m[p])))
+                    rows.append((j, first_ordinal + ci, int(p) - pad, s, int(nref[p]),
+                                 int(m[p])))
     out = np.array(rows, dtype=HIT_DTYPE) if rows else np.zeros(0, dtype=HIT_DTYPE)
     return sort_hits(out)
 

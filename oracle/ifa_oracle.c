@@ -23,9 +23,23 @@
  *   - a window is a hit iff m <= K and n_ref <= M ("exceed" ends a lane in
  *     the SIMD kernel description, so equality is still a hit), with
  *     K = min(maxSubs, L) and M = min(maxN, L);
- *   - only windows wholly inside one contig are tested;
+ *   - without overhang only windows wholly inside one contig are tested;
  *   - policy AS_MISMATCH (alternative reading): every reference or query N
  *     position counts in m and there is no maxN test.
+ * Overhang (Methods, "Algorithm Design": soft-clipped alignments at contig
+ * boundaries, up to 25% of the query length by default; short contigs are
+ * fused with N padding and the kernel counts reference Ns apart from
+ * substitutions). Readings:
+ *   - a window may start at p in [-C, n - L + C]; its bases off the contig
+ *     read as N, so they count in n_ref (and, under AS_MISMATCH, in m);
+ *   - the clip limit is C = min(maxN, L - 1) with the same maxN (default
+ *     floor(L/4)): the paper's clip count is its reference-N count, and a
+ *     window keeps at least one base on the contig;
+ *   - the off-contig bases of a window, left and right together, must not
+ *     exceed C (under N_SEPARATE n_ref <= M implies it);
+ *   - pos is the window's first base, negative for a left overhang;
+ *   - a contig is never fused with its neighbour: off-contig bases are N
+ *     whatever lies beyond the contig in the input.
  * Output order is reference order (Results, "Accuracy Validation": the
  * primary is the first valid alignment in reference order), tie-broken by
  * strand (+ first) then query index.
@@ -43,7 +57,7 @@
 typedef struct {
     uint32_t query;
     uint32_t contig;
-    uint32_t pos;
+    int32_t pos;
     uint8_t strand;
     uint8_t n_ref;
     uint16_t mismatches;
@@ -75,10 +89,11 @@ uint64_t orc_mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
-uint64_t orc_hit_hash(uint32_t contig, uint32_t pos, uint32_t strand, uint32_t mism,
+/* pos enters the key as its 32-bit two's complement pattern */
+uint64_t orc_hit_hash(uint32_t contig, int32_t pos, uint32_t strand, uint32_t mism,
                       uint32_t nref)
 {
-    uint64_t key = ((uint64_t)contig << 32) | (uint64_t)pos;
+    uint64_t key = ((uint64_t)contig << 32) | (uint64_t)(uint32_t)pos;
     uint64_t aux = (uint64_t)strand | ((uint64_t)mism << 1) | ((uint64_t)nref << 10);
     return orc_mix64(key ^ (aux << 45));
 }
@@ -89,12 +104,14 @@ typedef struct {
     int L;
     int K;              /* min(maxSubs, L) */
     int M;              /* min(maxN, L) */
+    int C;              /* clip limit min(maxN, L - 1); used with overhang */
     uint8_t *code[2];   /* [0] query codes, [1] reverse complement */
 } orc_query;
 
 typedef struct {
     uint32_t contig;    /* index into the contig arrays */
-    uint64_t p0, p1;    /* window starts [p0, p1) */
+    uint64_t p0, p1;    /* window starts [p0, p1) inside the contig */
+    int edge;           /* 1: instead, the overhanging windows of the contig */
 } orc_item;
 
 typedef struct {
@@ -106,6 +123,7 @@ typedef struct {
     uint32_t first_ordinal;
     uint32_t strands;
     uint32_t policy;
+    int overhang;
     int want_records;
     int maxL;
     orc_item *items;
@@ -170,9 +188,70 @@ static int orc_test_window(const uint8_t *qc, int L, const uint8_t *r, int K, in
     return 1;
 }
 
+static void emit_hit(orc_worker *W, uint32_t j, uint32_t contig, int64_t p, int s, int m,
+                     int nref)
+{
+    orc_job *J = W->J;
+    orc_hit h;
+    h.query = j;
+    h.contig = J->first_ordinal + contig;
+    h.pos = (int32_t)p;
+    h.strand = (uint8_t)s;
+    h.n_ref = (uint8_t)nref;
+    h.mismatches = (uint16_t)m;
+    if (W->counts) W->counts[j] += 1;
+    if (W->digests)
+        W->digests[j] += orc_hit_hash(h.contig, h.pos, h.strand, h.mismatches, h.n_ref);
+    if (J->want_records && push_hit(W, &h) != 0) W->failed = 1;
+}
+
+/* The overhanging windows of one contig: starts p in [-C, n - L + C] that
+ * are not wholly inside it, with at most C bases off the contig, which read
+ * as N. */
+static void run_edge(orc_worker *W, uint32_t contig, uint8_t *win)
+{
+    orc_job *J = W->J;
+    const uint8_t *src = J->ctg[contig];
+    const int64_t n = (int64_t)J->clen[contig];
+    for (uint32_t j = 0; j < J->nq; j++) {
+        const orc_query *Q = &J->qs[j];
+        const int64_t L = Q->L, C = Q->C;
+        for (int64_t p = -C; p <= n - L + C; p++) {
+            if (p >= 0 && p <= n - L) {                    /* wholly inside: skip them */
+                p = n - L;
+                continue;
+            }
+            int64_t off = 0;
+            for (int64_t i = 0; i < L; i++) {
+                const int64_t x = p + i;
+                if (x < 0 || x >= n) {
+                    win[i] = 4;
+                    off++;
+                } else {
+                    win[i] = (uint8_t)orc_norm(src[x]);
+                }
+            }
+            if (off > C) continue;
+            for (int s = 0; s < 2; s++) {
+                if (!(J->strands & (1u << s))) continue;
+                int m, nref;
+                if (!orc_test_window(Q->code[s], (int)L, win, Q->K, Q->M, J->policy, &m,
+                                     &nref))
+                    continue;
+                emit_hit(W, j, contig, p, s, m, nref);
+                if (W->failed) return;
+            }
+        }
+    }
+}
+
 static void run_item(orc_worker *W, const orc_item *it, uint8_t *codes)
 {
     orc_job *J = W->J;
+    if (it->edge) {
+        run_edge(W, it->contig, codes);
+        return;
+    }
     const uint8_t *src = J->ctg[it->contig];
     uint64_t n = J->clen[it->contig];
     /* normalise the bases this item's windows can touch */
@@ -194,21 +273,8 @@ static void run_item(orc_worker *W, const orc_item *it, uint8_t *codes)
                 int m, nref;
                 if (!orc_test_window(Q->code[s], L, r, Q->K, Q->M, J->policy, &m, &nref))
                     continue;
-                orc_hit h;
-                h.query = j;
-                h.contig = J->first_ordinal + it->contig;
-                h.pos = (uint32_t)p;
-                h.strand = (uint8_t)s;
-                h.n_ref = (uint8_t)nref;
-                h.mismatches = (uint16_t)m;
-                if (W->counts) W->counts[j] += 1;
-                if (W->digests)
-                    W->digests[j] += orc_hit_hash(h.contig, h.pos, h.strand, h.mismatches,
-                                                  h.n_ref);
-                if (J->want_records && push_hit(W, &h) != 0) {
-                    W->failed = 1;
-                    return;
-                }
+                emit_hit(W, j, it->contig, (int64_t)p, s, m, nref);
+                if (W->failed) return;
             }
         }
     }
@@ -220,6 +286,7 @@ static void *orc_worker_main(void *arg)
 {
     orc_worker *W = (orc_worker *)arg;
     orc_job *J = W->J;
+    /* also the window buffer of edge items (maxL codes) */
     uint8_t *codes = (uint8_t *)malloc(ORC_ITEM_WINDOWS + (size_t)J->maxL + 1);
     if (!codes) {
         W->failed = 1;
@@ -240,7 +307,7 @@ static void *orc_worker_main(void *arg)
 static int hit_cmp(const void *x, const void *y)
 {
     const orc_hit *a = (const orc_hit *)x, *b = (const orc_hit *)y;
-    if (a->contig != b->contig) return a->contig < b->contig ? -1 : 1;
+    if (a->contig != b->contig) return a->contig < b->contig ? -1 : 1;   /* pos is signed */
     if (a->pos != b->pos) return a->pos < b->pos ? -1 : 1;
     if (a->strand != b->strand) return a->strand < b->strand ? -1 : 1;
     if (a->query != b->query) return a->query < b->query ? -1 : 1;
@@ -257,18 +324,21 @@ void orc_free(void *p)
  * arguments or allocation failure. When want_records is set, *out receives a
  * malloc'd array of *n_out hits in (contig, pos, strand, query) order (free
  * with orc_free). counts/digests, when not NULL, are nq-long arrays that this
- * call overwrites.
+ * call overwrites. overhang = 1 adds the windows that hang off a contig end.
+ * Contigs must be shorter than 2^31 bases (pos is an int32).
  */
 int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
              const int32_t *max_subs, const int32_t *max_n,
              uint32_t nc, const uint8_t *const *ctg, const uint64_t *clen,
-             uint32_t first_ordinal, uint32_t strands, uint32_t policy, int threads,
-             int want_records, orc_hit **out, uint64_t *n_out, uint64_t *counts,
-             uint64_t *digests)
+             uint32_t first_ordinal, uint32_t strands, uint32_t policy, int overhang,
+             int threads, int want_records, orc_hit **out, uint64_t *n_out,
+             uint64_t *counts, uint64_t *digests)
 {
     if (out) *out = NULL;
     if (n_out) *n_out = 0;
-    if (strands < 1 || strands > 3 || policy > 1) return -1;
+    if (strands < 1 || strands > 3 || policy > 1 || overhang < 0 || overhang > 1) return -1;
+    for (uint32_t c = 0; c < nc; c++)
+        if (clen[c] >= (1ull << 31)) return -1;
     orc_job J;
     memset(&J, 0, sizeof J);
     J.nq = nq;
@@ -277,6 +347,7 @@ int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
     J.first_ordinal = first_ordinal;
     J.strands = strands;
     J.policy = policy;
+    J.overhang = overhang;
     J.want_records = want_records;
     J.qs = (orc_query *)calloc(nq ? nq : 1, sizeof(orc_query));
     if (!J.qs) return -1;
@@ -290,6 +361,7 @@ int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
         Q->K = max_subs[j] < L ? max_subs[j] : L;
         int mn = max_n ? max_n[j] : L / 4;
         Q->M = mn < L ? mn : L;
+        Q->C = mn < L - 1 ? mn : L - 1;
         Q->code[0] = (uint8_t *)malloc((size_t)L);
         Q->code[1] = (uint8_t *)malloc((size_t)L);
         if (!Q->code[0] || !Q->code[1]) goto done;
@@ -306,7 +378,7 @@ int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
     uint64_t item = total_bases / ((uint64_t)threads * 8u);
     if (item < 4096) item = 4096;
     if (item > ORC_ITEM_WINDOWS) item = ORC_ITEM_WINDOWS;
-    uint64_t n_items = 0;
+    uint64_t n_items = overhang ? nc : 0;
     for (uint32_t c = 0; c < nc; c++)
         n_items += (clen[c] + item - 1) / item;
     J.items = (orc_item *)malloc((n_items ? n_items : 1) * sizeof(orc_item));
@@ -318,6 +390,13 @@ int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
             it->contig = c;
             it->p0 = p;
             it->p1 = p + item < clen[c] ? p + item : clen[c];
+            it->edge = 0;
+        }
+        if (overhang) {
+            orc_item *it = &J.items[J.n_items++];
+            it->contig = c;
+            it->p0 = it->p1 = 0;
+            it->edge = 1;
         }
     }
     pthread_mutex_init(&J.mu, NULL);
@@ -398,22 +477,29 @@ done:
 /*
  * Evaluate one (query, window, strand) exactly, without the early stop:
  * writes the full mismatch count and n_ref. Returns 1 if the window is a hit,
- * 0 if not, -1 if the window does not fit in the contig or arguments are bad.
+ * 0 if not, -1 if it is not a window of the scan (it leaves the contig, or,
+ * with overhang, leaves it by more than the clip limit) or arguments are bad.
  */
 int orc_eval_window(const uint8_t *q, uint32_t L, int32_t max_subs, int32_t max_n,
-                    const uint8_t *ctg, uint64_t clen, uint64_t pos, uint32_t strand,
-                    uint32_t policy, int32_t *m_out, int32_t *nref_out)
+                    const uint8_t *ctg, uint64_t clen, int64_t pos, uint32_t strand,
+                    uint32_t policy, int overhang, int32_t *m_out, int32_t *nref_out)
 {
-    if (L < 1 || (uint64_t)L > clen || pos > clen - L || strand > 1 || max_subs < 0 ||
-        policy > 1)
+    if (L < 1 || strand > 1 || max_subs < 0 || policy > 1 || clen >= (1ull << 31))
         return -1;
     int K = max_subs < (int32_t)L ? max_subs : (int32_t)L;
     int mn = max_n < 0 ? (int)L / 4 : max_n;
     int M = mn < (int)L ? mn : (int)L;
+    int C = mn < (int)L - 1 ? mn : (int)L - 1;
+    const int64_t n = (int64_t)clen;
+    int off = 0;
+    for (uint32_t i = 0; i < L; i++)
+        if (pos + (int64_t)i < 0 || pos + (int64_t)i >= n) off++;
+    if (overhang ? off > C : off > 0) return -1;
     int m = 0, nref = 0;
     for (uint32_t i = 0; i < L; i++) {
         int qc = strand == 0 ? orc_norm(q[i]) : orc_comp(orc_norm(q[L - 1 - i]));
-        int r = orc_norm(ctg[pos + i]);
+        const int64_t x = pos + (int64_t)i;
+        int r = (x < 0 || x >= n) ? 4 : orc_norm(ctg[x]);
         if (r == 4) nref++;
         if (policy == ORC_N_SEPARATE) {
             if (r != 4 && qc != r) m++;
