@@ -26,6 +26,16 @@
  * coordinate of the window in its contig. Bytes are case-insensitive; every
  * byte other than A/C/G/T/a/c/g/t is N.
  *
+ * With IFA_FLAG_OVERHANG (soft-clipped alignments at contig boundaries,
+ * Methods, "Algorithm Design": up to 25 % of the query length by default;
+ * short contigs are fused with N padding) the windows also include those that
+ * hang off either end of a contig, or both: starts p in [-C, n - L + C] for a
+ * contig of n bases, C = min(maxN, L - 1), with at most C of the window's
+ * bases off the contig. Off-contig bases read as N in the definition above
+ * (they count in n_ref, and in m under IFA_N_AS_MISMATCH). pos is then
+ * negative for a window that hangs off the left end. A contig is never
+ * fused with its neighbour.
+ *
  * General conventions
  *   - Every entry point returns an ifa_status; a failed call changes nothing
  *     (all or nothing) and leaves a message for ifa_last_error.
@@ -45,7 +55,7 @@
 extern "C" {
 #endif
 
-#define IFA_ABI_VERSION 1u
+#define IFA_ABI_VERSION 2u
 #define IFA_MAX_QUERY_LEN 256u
 
 typedef struct ifa_ctx ifa_ctx;
@@ -91,12 +101,16 @@ typedef struct {
  * HIP graph while its launch arguments repeat (the first pass with new
  * arguments runs eagerly; the second is captured). Results are identical. */
 #define IFA_FLAG_GRAPHS 1u
+/* ifa_config.flags: also report the windows that overhang a contig end (see
+ * the definition at the top). Off by default. */
+#define IFA_FLAG_OVERHANG 2u
 
 /* One reported window (16 bytes). strand: 0 = +, 1 = - (reverse complement). */
 typedef struct {
     uint32_t query;         /* index of the query in the last ifa_load_queries */
     uint32_t contig;        /* global contig ordinal, in stream order from 0 */
-    uint32_t pos;           /* 0-based leftmost forward coordinate in the contig */
+    int32_t pos;            /* 0-based leftmost forward coordinate in the contig
+                               (negative: the window starts before the contig) */
     uint8_t strand;
     uint8_t n_ref;          /* reference non-ACGT bases in the window */
     uint16_t mismatches;    /* m as defined above */
@@ -145,7 +159,7 @@ ifa_status ifa_load_queries(ifa_ctx *ctx, uint32_t n, const uint8_t *const *seq,
                             const uint32_t *len, const int32_t *max_subs,
                             const int32_t *max_n);
 
-/* Stream n_contigs contigs (seq[i] -> len[i] bytes, len[i] < 2^32) into the
+/* Stream n_contigs contigs (seq[i] -> len[i] bytes, len[i] < 2^31) into the
  * scan. Contigs take global ordinals in call order; *first_ordinal (may be
  * NULL) receives the first one. Empty or short contigs take an ordinal and
  * yield no windows. Contigs are packed to 2-bit planes on host threads and
@@ -157,7 +171,7 @@ ifa_status ifa_scan_chunk(ifa_ctx *ctx, uint32_t n_contigs, const uint8_t *const
                           const uint64_t *len, uint32_t *first_ordinal);
 
 /* Wait for every submitted scan and hand out the hits found so far in
- * reference order: (contig, pos, strand, query) ascending (Results, "Accuracy
+ * reference order: (contig, pos, strand, query) ascending, pos signed (Results, "Accuracy
  * Validation": output follows the reference stream). Writes at most cap
  * records to out; *n_written gets the count written and *n_remaining (may be
  * NULL) the count still held; call again to drain the rest. With the
@@ -174,7 +188,7 @@ const char *ifa_last_error(const ifa_ctx *ctx);
 
 /* Count+digest sink: waits for every submitted scan, then writes for each
  * loaded query the number of hits and the wrapping 64-bit sum over its hits of
- *   mix64(((contig << 32) | pos) ^ (aux << 45)),
+ *   mix64(((contig << 32) | (uint32_t)pos) ^ (aux << 45)),
  *   aux = strand | (mismatches << 1) | (n_ref << 10),
  * mix64 being the SplitMix64 output finaliser (shifts 30, 27, 31; multipliers
  * 0xBF58476D1CE4E5B9, 0x94D049BB133111EB). count and digest are arrays of the

@@ -25,17 +25,18 @@ __all__ = [
     "ifa_server_take", "ifa_server_info", "Scanner", "Server", "collect_all",
 ]
 
-IFA_ABI_VERSION = 1
+IFA_ABI_VERSION = 2
 IFA_MAX_QUERY_LEN = 256
 IFA_N_SEPARATE, IFA_N_AS_MISMATCH = 0, 1
 IFA_SINK_RECORDS, IFA_SINK_COUNT_DIGEST = 0, 1
 IFA_STRAND_FWD, IFA_STRAND_RC, IFA_STRAND_BOTH = 1, 2, 3
 IFA_FLAG_GRAPHS = 1
+IFA_FLAG_OVERHANG = 2
 
 STATUS = {0: "IFA_OK", 1: "IFA_E_INVALID", 2: "IFA_E_NOMEM", 3: "IFA_E_DEVICE",
           4: "IFA_E_STATE", 5: "IFA_E_TOO_LONG"}
 
-HIT_DTYPE = np.dtype([("query", "<u4"), ("contig", "<u4"), ("pos", "<u4"), ("strand", "u1"),
+HIT_DTYPE = np.dtype([("query", "<u4"), ("contig", "<u4"), ("pos", "<i4"), ("strand", "u1"),
                       ("n_ref", "u1"), ("mismatches", "<u2")])
 
 

@@ -34,8 +34,12 @@ struct Piece {
     uint64_t len;         // bases
     uint64_t contig_off;  // contig coordinate of the first base
     uint32_t contig;      // global contig ordinal
-    uint32_t pad;
+    uint32_t flags;       // kPieceContigStart | kPieceContigEnd
 };
+// Piece.flags: the piece holds the contig's first base (contig_off == 0) /
+// its last base.
+constexpr uint32_t kPieceContigStart = 1u;
+constexpr uint32_t kPieceContigEnd = 2u;
 static_assert(sizeof(Piece) == 32, "Piece layout");
 
 // One (query, strand) entry, 32 bytes so a wave reads it with a single scalar

@@ -31,6 +31,7 @@ namespace ifa {
 hipError_t launch_filter(const ScanArgs &a, hipStream_t s);
 hipError_t launch_resolve(const ScanArgs &a, hipStream_t s);
 hipError_t launch_dense(const ScanArgs &a, hipStream_t s);
+hipError_t launch_edge(const ScanArgs &a, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
 hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s);
 uint32_t variant_count();
@@ -531,7 +532,8 @@ struct PassEvents {
 
 // Enqueue one pass of the scan over a's word range: the sparse part (filter
 // kernel, then resolve kernel over the work list) and, if `dense`, the dense
-// kernel. Counters are cleared by kernels on the stream first.
+// kernels and (with IFA_FLAG_OVERHANG) the overhanging windows. Counters are
+// cleared by kernels on the stream first.
 void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, PassEvents &ev)
 {
     // the pass counters of a hit buffer are adjacent (hit count, then the
@@ -544,6 +546,8 @@ void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, Pa
     hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
     hip_check(launch_resolve(a, c->comp_s), "resolve launch");
     if (dense) hip_check(launch_dense(a, c->comp_s), "dense launch");
+    if (dense && (c->cfg.flags & IFA_FLAG_OVERHANG))
+        hip_check(launch_edge(a, c->comp_s), "overhang launch");
     hip_check(hipEventRecord(ev.t2, c->comp_s), "event record");
 }
 
@@ -841,6 +845,8 @@ void append_contigs(ifa_ctx *c, uint32_t n_contigs, const uint8_t *const *seq,
             p.len = carry + take;
             p.contig_off = x - carry;
             p.contig = ordinal;
+            p.flags = (p.contig_off == 0 ? kPieceContigStart : 0u) |
+                      (x + take == n ? kPieceContigEnd : 0u);
             s->pieces.push_back(p);
             s->tasks.push_back(PackTask{src + (x - carry), s->len, carry + take});
             s->len += carry + take;
@@ -1264,7 +1270,7 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
     if (cfg_in) cfg = *cfg_in; else ifa_config_default(&cfg);
     if (cfg.abi_version != IFA_ABI_VERSION || cfg.chunk_bases < 4096 ||
         cfg.chunk_bases > (1ull << 31) || (cfg.chunk_bases & 31) || cfg.strands < 1 ||
-        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || (cfg.flags & ~IFA_FLAG_GRAPHS) != 0)
+        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || (cfg.flags & ~(IFA_FLAG_GRAPHS | IFA_FLAG_OVERHANG)) != 0)
         return IFA_E_INVALID;
     ifa_ctx *c = new (std::nothrow) ifa_ctx();
     if (!c) return IFA_E_NOMEM;
@@ -1371,7 +1377,7 @@ ifa_status ifa_scan_chunk(ifa_ctx *c, uint32_t n_contigs, const uint8_t *const *
         if (!c->have_queries) fail(IFA_E_STATE, "no queries loaded");
         if (n_contigs > 0 && (!seq || !len)) fail(IFA_E_INVALID, "NULL argument");
         for (uint32_t i = 0; i < n_contigs; i++) {
-            if (len[i] >= (1ull << 32)) fail(IFA_E_INVALID, "contig longer than 2^32 - 1");
+            if (len[i] >= (1ull << 31)) fail(IFA_E_INVALID, "contig longer than 2^31 - 1");
             if (len[i] > 0 && !seq[i]) fail(IFA_E_INVALID, "NULL contig pointer");
         }
         use_device(c);
@@ -1458,7 +1464,7 @@ ifa_status ifa_ref_load(ifa_ctx *c, uint32_t n_contigs, const uint8_t *const *se
     return guarded(c, [&]() {
         if (n_contigs > 0 && (!seq || !len)) fail(IFA_E_INVALID, "NULL argument");
         for (uint32_t i = 0; i < n_contigs; i++) {
-            if (len[i] >= (1ull << 32)) fail(IFA_E_INVALID, "contig longer than 2^32 - 1");
+            if (len[i] >= (1ull << 31)) fail(IFA_E_INVALID, "contig longer than 2^31 - 1");
             if (len[i] > 0 && !seq[i]) fail(IFA_E_INVALID, "NULL contig pointer");
         }
         if (c->stage[c->cur].len != 0)

@@ -34,6 +34,8 @@
 // Variants (template parameters, chosen by the autotuner): windows per lane
 // W, query strands per filter iteration QU, and workgroup size.
 #include <hip/hip_runtime.h>
+#include <algorithm>
+#include <climits>
 
 #include "ifa_dev.h"
 
@@ -1030,6 +1032,95 @@ __global__ __launch_bounds__(256) void scan_dense_cold_kernel(ScanArgs a)
     }
 }
 
+// Windows that hang off a contig end (soft clip at contig boundaries). Each
+// (piece, query strand) task is one wave: a piece holding the contig's first
+// base tests the starts p in [-C, -1], one holding its last base the starts
+// [max(0, n - L + 1), n - L + C], C = min(maxN, L - 1); bases off the contig
+// read as N and at most C of them may be in a window. A window belongs to the
+// piece (and chunk) owning its last on-contig base and to the word range
+// holding that base, so each is tested once, and all of its on-contig bases
+// lie in that piece: a contig's first piece starts at its first base, and a
+// chunk repeats the kCarry bases before a split.
+__global__ __launch_bounds__(256) void scan_edge_kernel(ScanArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t waves = gridDim.x * 4u;
+    const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
+    const uint64_t tasks = (uint64_t)a.n_pieces * a.n_qs;
+    for (uint64_t t = wave; t < tasks; t += waves) {
+        const uint32_t pi = (uint32_t)(t / a.n_qs);
+        const uint32_t q = (uint32_t)(t - (uint64_t)pi * a.n_qs);
+        const Piece pc = a.pieces[pi];
+        if ((pc.flags & (kPieceContigStart | kPieceContigEnd)) == 0u) continue;
+        const QS d = load_qs(a, q);
+        const int64_t L = d.len;
+        const int64_t C = (int64_t)d.maxn < L - 1 ? (int64_t)d.maxn : L - 1;
+        if (C <= 0) continue;
+        const int64_t c0 = (int64_t)pc.contig_off;
+        const int64_t own_lo =
+            c0 + (a.own_from > pc.start ? (int64_t)(a.own_from - pc.start) : (int64_t)0);
+        const int64_t own_hi = c0 + (int64_t)pc.len - 1;
+        const bool has_end = (pc.flags & kPieceContigEnd) != 0u;
+        const int64_t n = has_end ? c0 + (int64_t)pc.len : INT64_MAX;
+        const int64_t nl = (pc.flags & kPieceContigStart) ? C : 0;
+        const int64_t r0 = has_end ? (n - L + 1 > 0 ? n - L + 1 : 0) : 0;
+        const int64_t nr = has_end ? (n - L + C - r0 + 1 > 0 ? n - L + C - r0 + 1 : 0) : 0;
+        const int64_t base = (int64_t)pc.start - c0;   // chunk position of contig base 0
+        const IFA_CONST uint32_t *qw = as_const(a.qwords) + d.woff;
+        uint32_t cnt = 0;
+        uint64_t dig = 0;
+        for (int64_t i0 = 0; i0 < nl + nr; i0 += 64) {
+            const int64_t idx = i0 + lane;
+            const int64_t p = idx < nl ? idx - C : r0 + (idx - nl);
+            const int64_t e = p + L - 1 < n - 1 ? p + L - 1 : n - 1;   // last on-contig base
+            const int64_t first = p > 0 ? p : 0;                        // first on-contig base
+            const int64_t off = L - (e - first + 1);
+            bool ok = idx < nl + nr && off >= 1 && off <= C && first >= c0 && e >= own_lo &&
+                      e <= own_hi;
+            if (ok) {
+                const int64_t ew = (base + e) >> 5;
+                ok = ew >= (int64_t)a.w_begin && ew < (int64_t)a.w_end;
+            }
+            uint32_t m = 0, nref = 0;
+            if (ok) {
+                for (uint32_t t2 = 0; t2 < d.nw; t2++) {
+                    const int64_t cw = p + 32 * (int64_t)t2;   // contig coordinate of bit 0
+                    const uint32_t lmask = low_mask((uint32_t)(L - 32 * (int64_t)t2));
+                    const int64_t lo_b = first - cw < 0 ? 0 : (first - cw > 32 ? 32 : first - cw);
+                    const int64_t hi_b = e + 1 - cw < 0 ? 0 : (e + 1 - cw > 32 ? 32 : e + 1 - cw);
+                    uint32_t rh = 0u, rl = 0u, rn = 0u, vm = 0u;
+                    if (lo_b < hi_b) {
+                        const uint64_t u = (uint64_t)(base + cw + lo_b);   // an on-contig base
+                        const uint32_t x = (uint32_t)(u >> 5), sh = (uint32_t)(u & 31u);
+                        rh = funnel(a.hi[x + 1], a.hi[x], sh) << lo_b;
+                        rl = funnel(a.lo[x + 1], a.lo[x], sh) << lo_b;
+                        rn = funnel(a.nm[x + 1], a.nm[x], sh) << lo_b;
+                        vm = low_mask((uint32_t)hi_b) & ~low_mask((uint32_t)lo_b);
+                    }
+                    const uint32_t rne = ((rn & vm) | ~vm) & lmask;   // N or off the contig
+                    const uint32_t diff = (qw[3 * t2] ^ rh) | (qw[3 * t2 + 1] ^ rl) | qw[3 * t2 + 2];
+                    if (a.policy == kNSeparate)
+                        m += __popc(diff & ~rne & lmask);
+                    else
+                        m += __popc((diff | rne) & lmask);
+                    nref += __popc(rne);
+                }
+                ok = m <= d.k && (a.policy != kNSeparate || nref <= d.maxn);
+            }
+            if (ok) {
+                const uint32_t pos = (uint32_t)(int32_t)p;
+                if (a.sink == kSinkRecords) {
+                    write_record(a, atomicAdd(a.hit_count, 1ull), d, pc.contig, pos, m, nref);
+                } else {
+                    cnt += 1;
+                    dig += hit_hash(pc.contig, pos, d.strand, m, nref);
+                }
+            }
+        }
+        if (a.sink == kSinkCountDigest) wave_add_stats(a, d.qid, cnt, dig, wave);
+    }
+}
+
 // Clears counters on the stream (a kernel, so the launch sequence can be
 // captured in a graph).
 __global__ void clear_u64_kernel(unsigned long long *p, uint32_t n)
@@ -1174,6 +1265,17 @@ hipError_t launch_dense(const ScanArgs &a, hipStream_t s)
     const dim3 grid((uint32_t)((lanes + 255) / 256));
     hipLaunchKernelGGL(v.dense, grid, dim3(256), 0, s, a);
     hipLaunchKernelGGL(v.dense_cold, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Overhanging windows of the word range: one wave per (piece, query strand)
+// task, grid-stride.
+hipError_t launch_edge(const ScanArgs &a, hipStream_t s)
+{
+    const uint64_t tasks = (uint64_t)a.n_pieces * a.n_qs;
+    if (a.w_end <= a.w_begin || tasks == 0) return hipSuccess;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((tasks + 3) / 4, 2048);
+    hipLaunchKernelGGL(scan_edge_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@ import os
 import re
 import subprocess
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ifa.h")
 
@@ -36,6 +38,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     import paper_2607_27291_amd as ifa
     assert ifa.HIT_DTYPE.itemsize == 16
+    assert ifa.HIT_DTYPE["pos"] == np.dtype("<i4")             # signed: overhang starts < 0
     assert ctypes.sizeof(ifa.IfaConfig) == 48
     cfg = ifa.ifa_config_default()
     assert cfg.abi_version == ifa.IFA_ABI_VERSION
@@ -54,6 +57,10 @@ def test_null_and_bad_arguments_are_rejected_without_a_device():
     cfg = ifa.ifa_config_default()
     cfg.abi_version = 99
     assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
+    cfg = ifa.ifa_config_default()
+    cfg.flags = 4                                             # no such flag
+    assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
+    assert ifa.IFA_FLAG_GRAPHS == 1 and ifa.IFA_FLAG_OVERHANG == 2
     L.ifa_destroy(None)                                       # NULL-safe
     assert L.ifa_load_queries(None, 0, None, None, None, None) == 1
     assert L.ifa_scan_chunk(None, 0, None, None, None) == 1

@@ -1,0 +1,221 @@
+"""Parity of the HIP scan with the oracle when windows may overhang a contig
+end (IFA_FLAG_OVERHANG: soft clip up to min(maxN, L - 1) bases, off-contig
+bases read as N). Bit-exact on all six record fields, in reference order, and
+on the count+digest sink. Inputs are seeded; each test prints its case before
+touching the GPU.
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+COMP = bytes.maketrans(b"ACGTacgt", b"TGCAtgca")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rand_dna(rng, n, alphabet=b"ACGT"):
+    return bytes(rng.choice(alphabet) for _ in range(n))
+
+
+def revcomp(s: bytes) -> bytes:
+    return s.translate(COMP)[::-1]
+
+
+@pytest.fixture(scope="module")
+def ifa():
+    import paper_2607_27291_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+def gpu_scan(ifa, queries, contigs, ks, mn=None, *, calls=1, **cfg):
+    cfg["flags"] = cfg.get("flags", 0) | ifa.IFA_FLAG_OVERHANG
+    with ifa.Scanner(**cfg) as s:
+        s.load_queries(queries, ks, mn)
+        parts = np.array_split(np.arange(len(contigs)), max(calls, 1)) if contigs else []
+        for idx in parts:
+            s.scan_chunk([contigs[i] for i in idx])
+        return s.collect()
+
+
+def assert_same(a, b, ctx=""):
+    if not np.array_equal(a, b):
+        sa = {tuple(r) for r in a.tolist()}
+        sb = {tuple(r) for r in b.tolist()}
+        raise AssertionError(f"{ctx}: gpu {len(a)} oracle {len(b)}; only gpu "
+                             f"{sorted(sa - sb)[:5]} only oracle {sorted(sb - sa)[:5]}")
+
+
+def _end_planted(rng, qs, n_contigs, lo, hi, alpha=b"ACGT"):
+    """Contigs with copies of the queries hanging off either end (and whole
+    short contigs cut from a query), so that overhanging hits exist."""
+    out = []
+    for _ in range(n_contigs):
+        n = rng.randint(lo, hi)
+        c = bytearray(rand_dna(rng, n, alpha))
+        q = rng.choice(qs)
+        L = len(q)
+        o = rng.randint(1, max(1, L // 4 + 1))
+        src = q if rng.random() < 0.5 else revcomp(q)
+        if n >= L:
+            if rng.random() < 0.5:
+                c[:L - o] = src[o:]
+            else:
+                c[n - (L - o):] = src[:L - o]
+        out.append(bytes(c))
+    for _ in range(3):
+        q = rng.choice(qs)
+        L = len(q)
+        a = rng.randint(0, L // 8 + 1)
+        b = rng.randint(0, L // 8 + 1)
+        if a + b < L:
+            out.append(q[a:L - b])
+    rng.shuffle(out)
+    return out
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_overhang_random_small_cases(ifa, orc, policy):
+    rng = random.Random(2100 + policy)
+    for trial in range(40):
+        nq = rng.randint(1, 6)
+        qs = [rand_dna(rng, rng.choice([1, 2, 4, 7, 16, 31, 32, 33, 40, 64, 65, 100, 256]),
+                       b"ACGT" if rng.random() < 0.85 else b"ACGTN") for _ in range(nq)]
+        contigs = _end_planted(rng, qs, rng.randint(0, 8), 0, 400,
+                               rng.choice([b"ACGT", b"ACGT", b"ACGTN", b"acgtNNRY"]))
+        ks = [rng.randint(0, len(q) + 1) if rng.random() < 0.4 else rng.randint(0, 4) for q in qs]
+        mn = None if rng.random() < 0.5 else [rng.randint(0, len(q)) for q in qs]
+        strands = rng.choice([1, 2, 3])
+        chunk = rng.choice([4096, 4096 + 32 * 7, 1 << 16])
+        say(f"overhang trial {trial} policy {policy} nq {nq} nc {len(contigs)} chunk {chunk}")
+        want = orc.scan(qs, contigs, ks, mn, strands=strands, policy=policy, overhang=True)
+        got = gpu_scan(ifa, qs, contigs, ks, mn, strands=strands, n_policy=policy,
+                       chunk_bases=chunk, calls=rng.choice([1, 2, 3]))
+        assert_same(got, want, f"trial {trial}")
+
+
+def test_overhang_contigs_split_across_chunks(ifa, orc):
+    """Contigs that start or end next to a chunk boundary, short contigs split
+    by a boundary, and contigs longer than a chunk: each overhanging window is
+    owned by the chunk holding its last on-contig base."""
+    rng = random.Random(2200)
+    qs = [rand_dna(rng, L) for L in (12, 20, 33, 48, 64, 100)]
+    for chunk in (4096, 4096 + 32, 8192):
+        contigs = []
+        used = 0
+        for i in range(40):
+            # lengths that put a contig end within a query length of a boundary
+            to_edge = chunk - (used % chunk)
+            n = rng.choice([to_edge - rng.randint(0, 60), to_edge + rng.randint(0, 60),
+                            rng.randint(1, 120), rng.randint(5000, 12000)])
+            n = max(1, n)
+            c = bytearray(rand_dna(rng, n))
+            q = rng.choice(qs)
+            L, o = len(q), rng.randint(1, len(q) // 4)
+            if n >= L:
+                c[:L - o] = q[o:]
+                c[n - (L - o):] = revcomp(q)[:L - o]
+            contigs.append(bytes(c))
+            used += n
+        ks = [2, 3, 4, 6, 8, 12]
+        say(f"split contigs: chunk {chunk}, {used} bases")
+        want = orc.scan(qs, contigs, ks, overhang=True)
+        assert (want["pos"] < 0).any()
+        for calls in (1, 4):
+            got = gpu_scan(ifa, qs, contigs, ks, chunk_bases=chunk, calls=calls)
+            assert_same(got, want, f"chunk {chunk} calls {calls}")
+
+
+def test_overhang_with_overflow_rescan(ifa, orc):
+    rng = random.Random(2300)
+    qs = [rand_dna(rng, 10), rand_dna(rng, 12)]
+    contigs = [rand_dna(rng, rng.randint(3, 40)) for _ in range(300)]
+    contigs += [rand_dna(rng, 6000) for _ in range(2)]
+    ks = [4, 5]
+    say("overhang overflow: hit capacities 5, 100, 2^20")
+    want = orc.scan(qs, contigs, ks, overhang=True)
+    assert len(want) > 1000
+    for cap in (5, 100, 1 << 20):
+        got = gpu_scan(ifa, qs, contigs, ks, hit_capacity=cap, chunk_bases=4096)
+        assert_same(got, want, f"cap {cap}")
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_overhang_count_digest(ifa, orc, policy):
+    rng = random.Random(2400 + policy)
+    qs = [rand_dna(rng, rng.randint(8, 70)) for _ in range(30)]
+    ks = [rng.randint(0, 10) for _ in qs]
+    contigs = _end_planted(rng, qs, 400, 20, 3000, b"ACGTACGTACGTN")
+    say(f"overhang count+digest policy {policy}: {len(contigs)} contigs")
+    h, cnt, dig = orc.scan(qs, contigs, ks, policy=policy, overhang=True, stats=True)
+    assert (h["pos"] < 0).any() and int(cnt.sum()) > 100
+    with ifa.Scanner(sink=ifa.IFA_SINK_COUNT_DIGEST, n_policy=policy, chunk_bases=1 << 16,
+                     flags=ifa.IFA_FLAG_OVERHANG) as s:
+        s.load_queries(qs, ks)
+        s.scan_chunk(contigs)
+        gc, gd = s.query_stats()
+    assert np.array_equal(gc, cnt)
+    assert np.array_equal(gd, dig)
+
+
+def test_overhang_dense_and_sparse_strands(ifa, orc):
+    """Short queries with high thresholds take the dense kernels and long ones
+    the filter; the overhanging windows of both come from the same kernel."""
+    rng = random.Random(2500)
+    qs = [rand_dna(rng, L) for L in (8, 10, 12, 24, 36, 70, 130)]
+    ks = [3, 4, 6, 2, 4, 12, 20]
+    contigs = _end_planted(rng, qs, 200, 10, 2000)
+    say("overhang dense + sparse strands")
+    want = orc.scan(qs, contigs, ks, overhang=True)
+    for variant in (0, 13, 20):
+        with ifa.Scanner(chunk_bases=1 << 16, flags=ifa.IFA_FLAG_OVERHANG) as s:
+            s.load_queries(qs, ks)
+            ifa.ifa_set_variant(s.ctx, variant)
+            s.scan_chunk(contigs)
+            got = s.collect()
+        assert_same(got, want, f"variant {variant}")
+
+
+def test_overhang_resident_and_graph_replays(ifa, orc):
+    rng = random.Random(2600)
+    qs = [rand_dna(rng, rng.randint(18, 60)) for _ in range(6)]
+    contigs = _end_planted(rng, qs, 300, 50, 20000)
+    ks = [rng.randint(2, 8) for _ in qs]
+    say("overhang resident reference, eager and graph replays")
+    want = orc.scan(qs, contigs, ks, overhang=True)
+    for flags in (ifa.IFA_FLAG_OVERHANG, ifa.IFA_FLAG_OVERHANG | ifa.IFA_FLAG_GRAPHS):
+        with ifa.Scanner(chunk_bases=1 << 20, flags=flags) as s:
+            s.ref_load(contigs)
+            for rep in range(3):
+                s.load_queries(qs, ks)
+                s.scan_resident()
+                got = s.collect()
+                assert_same(got, want, f"flags {flags} replay {rep}")
+
+
+def test_overhang_off_is_unchanged(ifa, orc):
+    rng = random.Random(2700)
+    qs = [rand_dna(rng, 20), rand_dna(rng, 33)]
+    contigs = _end_planted(rng, qs, 50, 5, 500)
+    say("overhang flag off")
+    want = orc.scan(qs, contigs, [3, 4])
+    with ifa.Scanner(chunk_bases=4096) as s:
+        s.load_queries(qs, [3, 4])
+        s.scan_chunk(contigs)
+        got = s.collect()
+    assert_same(got, want, "flag off")
+    assert (want["pos"] >= 0).all()
