@@ -66,6 +66,10 @@ def parse():
     ap.add_argument("--total", type=int, default=0, help="reference bases (0 = workload default)")
     ap.add_argument("--queries", type=int, default=0, help="query count (0 = workload default)")
     ap.add_argument("--ks", default="0,4,8", help="c2: maxSubs values, one pass each")
+    ap.add_argument("--overhang", action="store_true",
+                    help="c2/c3: also report windows overhanging contig ends (soft clip)")
+    ap.add_argument("--median", type=float, default=0.0,
+                    help="c2: median contig length in bases (0 = the workload's 3 Mbp)")
     ap.add_argument("--cpu-sample", type=int, default=250_000_000,
                     help="c2: reference bases the oracle baseline scans per maxSubs (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -249,6 +253,22 @@ def device_sync():
         raise RuntimeError(f"hipDeviceSynchronize failed: {rc}")
 
 
+def scanner_flags(ifa, args):
+    return ((ifa.IFA_FLAG_GRAPHS if args.graphs else 0) |
+            (ifa.IFA_FLAG_OVERHANG if args.overhang else 0))
+
+
+def add_overhang(out, args, st):
+    """With --overhang: the overhanging-window kernel's share of the passes."""
+    if not args.overhang:
+        return
+    out["config"]["workload"] += ", windows overhanging contig ends included"
+    out["overhang"] = {
+        "edge_ms_per_step": round(st["edge_ms"] / args.steps, 4),
+        "share_of_kernel_time": round(st["edge_ms"] / max(st["kernel_ms"], 1e-9), 4),
+    }
+
+
 def timed_steps(ifa, s, args, step):
     for i in range(args.warmup):
         step()
@@ -277,12 +297,12 @@ def run_c2(args):
     ks = [int(x) for x in args.ks.split(",")]
     total = args.total or 4_000_000_000
     t0 = time.time()
-    w = synth.c2_paper_scale(total=total)
+    w = synth.c2_paper_scale(total=total, median=args.median or 3e6)
     log(f"generated {w.ref.total / 1e9:.2f} Gbp in {w.ref.n_contigs} contigs, "
         f"{len(w.plants)} planted copies ({time.time() - t0:.1f} s)")
     nq = len(w.queries)
 
-    s = ifa.Scanner(device=0, flags=ifa.IFA_FLAG_GRAPHS if args.graphs else 0)
+    s = ifa.Scanner(device=0, flags=scanner_flags(ifa, args))
     t0 = time.time()
     s.ref_load(w.ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
@@ -310,6 +330,10 @@ def run_c2(args):
                           "device_chunks": chunks,
                           "hits_per_step": sum(res) // max(1, args.steps),
                       })
+    if args.median:
+        out["config"]["workload"] += f", median contig {args.median:.0f} bp"
+        out["config"]["contigs"] = int(w.ref.n_contigs)
+    add_overhang(out, args, st)
     out["kernel_only_gbpq_s"] = round(bpq_per_step * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
     out["autotune"] = tune
     out["graph_launches"] = st["graph_launches"]
@@ -357,8 +381,7 @@ def run_c3(args):
     t0 = time.time()
     w = synth.c3_batched(total=total, n_queries=nq)
     log(f"generated {w.ref.total / 1e9:.2f} Gbp, {nq} queries ({time.time() - t0:.1f} s)")
-    s = ifa.Scanner(device=0, sink=ifa.IFA_SINK_COUNT_DIGEST,
-                    flags=ifa.IFA_FLAG_GRAPHS if args.graphs else 0)
+    s = ifa.Scanner(device=0, sink=ifa.IFA_SINK_COUNT_DIGEST, flags=scanner_flags(ifa, args))
     s.ref_load(w.ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
     tune = choose_variant(ifa, s, args, w.queries, w.max_subs)
@@ -387,6 +410,7 @@ def run_c3(args):
     out["filter_ms_per_step"] = round(st["filter_ms"] / args.steps, 3)
     out["pass_ms_per_step"] = round(st["kernel_ms"] / args.steps, 3)
     out["autotune"] = tune
+    add_overhang(out, args, st)
     # filter launches cover the sparse strands only; dense strands bypass it
     out["roofline"] = roofline(ifa, st, n_sparse, variant)
     s.close()

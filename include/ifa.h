@@ -136,6 +136,8 @@ typedef struct {
                                 resolve kernel and not counted) */
     uint64_t work_items;     /* work-list items the filter emitted */
     uint64_t graph_launches; /* scan passes replayed from a captured graph */
+    double edge_ms;          /* summed time of the overhanging-window kernel
+                                (IFA_FLAG_OVERHANG), HIP events on the compute stream */
 } ifa_stats;
 
 /* Fill *cfg with the defaults: device 0, 2^30-base chunks, automatic hit

@@ -55,7 +55,7 @@ class IfaStats(ctypes.Structure):
                 ("h2d_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
                 ("filter_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64),
                 ("filter_windows", ctypes.c_uint64), ("work_items", ctypes.c_uint64),
-                ("graph_launches", ctypes.c_uint64)]
+                ("graph_launches", ctypes.c_uint64), ("edge_ms", ctypes.c_double)]
 
 
 class IfaServerConfig(ctypes.Structure):

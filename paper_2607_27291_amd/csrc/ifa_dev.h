@@ -112,6 +112,9 @@ struct ScanArgs {
     // matrix-core filters: batch of 32 strands of grid row 0 (the grid's y
     // dimension holds at most 65535 batches per launch)
     uint32_t batch0;
+    // overhang kernel: pieces per wave for the strand with the widest clip
+    // (64 / (2 C) lanes each, at least 1); 0 = no strand can overhang
+    uint32_t edge_pmin;
     // count+digest sink, kStripes slots per query (see kStripes)
     unsigned long long *q_count;
     unsigned long long *q_digest;

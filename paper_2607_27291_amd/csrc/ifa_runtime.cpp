@@ -209,6 +209,7 @@ struct Job {
     DevChunk *chunk = nullptr;
     int hitbuf = 0;
     hipEvent_t k0 = nullptr, kf = nullptr, k1 = nullptr;  // start / filter end / stop
+    hipEvent_t ke = nullptr;                              // overhang kernel start
     hipEvent_t done = nullptr;              // hit count copied to the host
     bool active = false;
 };
@@ -245,6 +246,7 @@ struct ifa_ctx {
     const float *dq_mqt = nullptr, *dq_mq3t = nullptr;
     const uint32_t *dq_mq3w = nullptr;
     uint32_t mq3_words = 1;           // most prefix words of any three-class column tile
+    uint32_t edge_pmin = 0;           // overhang kernel: pieces per wave (ScanArgs.edge_pmin)
     DevBuf<unsigned long long> d_qcount, d_qdigest;
 
     // streaming
@@ -463,6 +465,7 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.mq3_t = c->dq_mq3t;
     a.mq3_w = c->dq_mq3w;
     a.mq3_words = c->mq3_words;
+    a.edge_pmin = c->edge_pmin;
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
@@ -511,22 +514,24 @@ void copy_records(ifa_ctx *c, int hb, uint64_t n)
     c->st.hits += n;
 }
 
-// Timing events of one pass: t0 before the filter, t1 after it, t2 after the
-// last scan kernel.
+// Timing events of one pass: t0 before the filter, t1 after it, te before
+// the overhanging-window kernel, t2 after the last scan kernel.
 struct PassEvents {
-    hipEvent_t t0 = nullptr, t1 = nullptr, t2 = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr, te = nullptr, t2 = nullptr;
     void create()
     {
         if (!t0) hip_check(hipEventCreate(&t0), "event");
         if (!t1) hip_check(hipEventCreate(&t1), "event");
+        if (!te) hip_check(hipEventCreate(&te), "event");
         if (!t2) hip_check(hipEventCreate(&t2), "event");
     }
     void destroy()
     {
         if (t0) (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
+        if (te) (void)hipEventDestroy(te);
         if (t2) (void)hipEventDestroy(t2);
-        t0 = t1 = t2 = nullptr;
+        t0 = t1 = te = t2 = nullptr;
     }
 };
 
@@ -546,6 +551,7 @@ void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, Pa
     hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
     hip_check(launch_resolve(a, c->comp_s), "resolve launch");
     if (dense) hip_check(launch_dense(a, c->comp_s), "dense launch");
+    hip_check(hipEventRecord(ev.te, c->comp_s), "event record");
     if (dense && (c->cfg.flags & IFA_FLAG_OVERHANG))
         hip_check(launch_edge(a, c->comp_s), "overhang launch");
     hip_check(hipEventRecord(ev.t2, c->comp_s), "event record");
@@ -577,6 +583,7 @@ void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse, int hb, uint3
 {
     c->st.kernel_ms += elapsed(ev.t0, ev.t2);
     c->st.kernel_launches++;
+    if (c->cfg.flags & IFA_FLAG_OVERHANG) c->st.edge_ms += elapsed(ev.te, ev.t2);
     if (sparse) {
         c->st.filter_ms += elapsed(ev.t0, ev.t1);
         c->st.filter_launches++;
@@ -665,6 +672,7 @@ void retire(ifa_ctx *c, Job &j)
     PassEvents ev;
     ev.t0 = j.k0;
     ev.t1 = j.kf;
+    ev.te = j.ke;
     ev.t2 = j.k1;
     const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
     add_pass_times(c, ev, c->n_sparse > 0, j.hitbuf, 0, words);
@@ -702,10 +710,12 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     if (!j.k0) hip_check(hipEventCreate(&j.k0), "event");
     if (!j.kf) hip_check(hipEventCreate(&j.kf), "event");
     if (!j.k1) hip_check(hipEventCreate(&j.k1), "event");
+    if (!j.ke) hip_check(hipEventCreate(&j.ke), "event");
     if (!j.done) hip_check(hipEventCreateWithFlags(&j.done, hipEventDisableTiming), "event");
     PassEvents ev;
     ev.t0 = j.k0;
     ev.t1 = j.kf;
+    ev.te = j.ke;
     ev.t2 = j.k1;
     auto enqueue = [&]() {
         enqueue_pass(c, a, true, true, ev);
@@ -1131,6 +1141,11 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     build_mfma_operands(qs, n_sparse, mb, mt);
     build_mfma3_operands(qs, words, sorted_fw, n_sparse, mb3, mt3, mw3);
     c->mq3_words = mw3.empty() ? 1u : *std::max_element(mw3.begin(), mw3.end());
+    // overhang kernel packing: 2 C window slots per piece and strand, C =
+    // min(maxN, L - 1); the widest clip sets the pieces per wave of the grid
+    uint32_t cmax = 0;
+    for (const QSDesc &d : qs) cmax = std::max<uint32_t>(cmax, std::min<uint32_t>(d.maxn, d.len - 1u));
+    c->edge_pmin = cmax == 0 ? 0u : (2u * cmax <= 64u ? 64u / (2u * cmax) : 1u);
     // one upload of every table: parts at 256-byte offsets in one arena
     struct Part {
         const void *src;
@@ -1337,6 +1352,7 @@ void ifa_destroy(ifa_ctx *c)
         if (j.k0) (void)hipEventDestroy(j.k0);
         if (j.k1) (void)hipEventDestroy(j.k1);
         if (j.kf) (void)hipEventDestroy(j.kf);
+        if (j.ke) (void)hipEventDestroy(j.ke);
         if (j.done) (void)hipEventDestroy(j.done);
     }
     for (int i = 0; i < 2; i++) {

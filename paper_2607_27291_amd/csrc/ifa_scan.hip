@@ -1032,73 +1032,100 @@ __global__ __launch_bounds__(256) void scan_dense_cold_kernel(ScanArgs a)
     }
 }
 
-// Windows that hang off a contig end (soft clip at contig boundaries). Each
-// (piece, query strand) task is one wave: a piece holding the contig's first
-// base tests the starts p in [-C, -1], one holding its last base the starts
-// [max(0, n - L + 1), n - L + C], C = min(maxN, L - 1); bases off the contig
-// read as N and at most C of them may be in a window. A window belongs to the
-// piece (and chunk) owning its last on-contig base and to the word range
-// holding that base, so each is tested once, and all of its on-contig bases
-// lie in that piece: a contig's first piece starts at its first base, and a
-// chunk repeats the kCarry bases before a split.
+// Windows that hang off a contig end (soft clip at contig boundaries). For a
+// query strand with clip limit C = min(maxN, L - 1) a piece has 2C window
+// slots: slot i < C is the start i - C (a piece holding the contig's first
+// base), slot C + o - 1 the start n - L + o, o in [1, C] (a piece holding its
+// last base; starts below 0 are left slots). Bases off the contig read as N
+// and at most C of them may be in a window. A window belongs to the piece
+// (and chunk) owning its last on-contig base and to the word range holding
+// that base, so each is tested once; all of its on-contig bases lie in that
+// piece, because a contig's first piece starts at its first base and a chunk
+// repeats the kCarry bases before a split.
+//
+// Task (b, q): one wave tests strand q against pieces [b P, b P + P), P =
+// 64 / 2C pieces side by side (one piece over several rounds when 2C > 64).
+// Tasks are walked grid-stride with (b, q) stepped incrementally, 32-bit.
+// Coordinates are piece-local (contigs and chunks are below 2^31 bases).
 __global__ __launch_bounds__(256) void scan_edge_kernel(ScanArgs a)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t waves = gridDim.x * 4u;
     const uint32_t wave = blockIdx.x * 4u + (threadIdx.x >> 6);
-    const uint64_t tasks = (uint64_t)a.n_pieces * a.n_qs;
-    for (uint64_t t = wave; t < tasks; t += waves) {
-        const uint32_t pi = (uint32_t)(t / a.n_qs);
-        const uint32_t q = (uint32_t)(t - (uint64_t)pi * a.n_qs);
-        const Piece pc = a.pieces[pi];
-        if ((pc.flags & (kPieceContigStart | kPieceContigEnd)) == 0u) continue;
+    const uint32_t nb = (a.n_pieces + a.edge_pmin - 1u) / a.edge_pmin;
+    const uint32_t dq = waves % a.n_qs, db = waves / a.n_qs;
+    uint32_t q = wave % a.n_qs, b = wave / a.n_qs;
+    const uint32_t own_from = (uint32_t)a.own_from;
+    const IFA_CONST uint32_t *pw = as_const(reinterpret_cast<const uint32_t *>(a.pieces));
+    // task t = b n_qs + q advances by `waves`: (b, q) += (db, dq) with a carry
+    for (; b < nb; q += dq, b += db + (q >= a.n_qs ? 1u : 0u), q -= (q >= a.n_qs ? a.n_qs : 0u)) {
         const QS d = load_qs(a, q);
-        const int64_t L = d.len;
-        const int64_t C = (int64_t)d.maxn < L - 1 ? (int64_t)d.maxn : L - 1;
+        const int32_t L = (int32_t)d.len;
+        const int32_t C = (int32_t)d.maxn < L - 1 ? (int32_t)d.maxn : L - 1;
         if (C <= 0) continue;
-        const int64_t c0 = (int64_t)pc.contig_off;
-        const int64_t own_lo =
-            c0 + (a.own_from > pc.start ? (int64_t)(a.own_from - pc.start) : (int64_t)0);
-        const int64_t own_hi = c0 + (int64_t)pc.len - 1;
-        const bool has_end = (pc.flags & kPieceContigEnd) != 0u;
-        const int64_t n = has_end ? c0 + (int64_t)pc.len : INT64_MAX;
-        const int64_t nl = (pc.flags & kPieceContigStart) ? C : 0;
-        const int64_t r0 = has_end ? (n - L + 1 > 0 ? n - L + 1 : 0) : 0;
-        const int64_t nr = has_end ? (n - L + C - r0 + 1 > 0 ? n - L + C - r0 + 1 : 0) : 0;
-        const int64_t base = (int64_t)pc.start - c0;   // chunk position of contig base 0
+        const uint32_t S = 2u * (uint32_t)C;               // slots per piece
+        const uint32_t P = S <= 64u ? 64u / S : 1u;         // pieces per wave
+        if (b * P >= a.n_pieces) continue;
         const IFA_CONST uint32_t *qw = as_const(a.qwords) + d.woff;
         uint32_t cnt = 0;
         uint64_t dig = 0;
-        for (int64_t i0 = 0; i0 < nl + nr; i0 += 64) {
-            const int64_t idx = i0 + lane;
-            const int64_t p = idx < nl ? idx - C : r0 + (idx - nl);
-            const int64_t e = p + L - 1 < n - 1 ? p + L - 1 : n - 1;   // last on-contig base
-            const int64_t first = p > 0 ? p : 0;                        // first on-contig base
-            const int64_t off = L - (e - first + 1);
-            bool ok = idx < nl + nr && off >= 1 && off <= C && first >= c0 && e >= own_lo &&
-                      e <= own_hi;
+        for (uint32_t s0 = 0; s0 < P * S; s0 += 64u) {
+            const uint32_t slot = s0 + lane;
+            const uint32_t pi = b * P + slot / S;
+            const int32_t i = (int32_t)(slot % S);
+            bool ok = slot < P * S && pi < a.n_pieces;
+            uint32_t start = 0, len = 0, flags = 0, contig = 0;
+            int32_t c0 = 0;
             if (ok) {
-                const int64_t ew = (base + e) >> 5;
-                ok = ew >= (int64_t)a.w_begin && ew < (int64_t)a.w_end;
+                const IFA_CONST uint32_t *r = pw + 8u * pi;   // Piece, 8 words
+                start = r[0];
+                len = r[2];
+                c0 = (int32_t)r[4];
+                contig = r[6];
+                flags = r[7];
+            }
+            const bool has_end = (flags & kPieceContigEnd) != 0u;
+            // window start pl and its on-contig bases [f, e], piece-local
+            int32_t pl, f, e, off;
+            if (i < C) {
+                ok = ok && (flags & kPieceContigStart) != 0u;   // then c0 == 0
+                pl = i - C;
+                f = 0;
+                e = (has_end && pl > (int32_t)len - L) ? (int32_t)len - 1 : pl + L - 1;
+                off = L - (e + 1);
+            } else {
+                const int32_t o = i - C + 1;
+                pl = (int32_t)len - L + o;
+                ok = ok && has_end && c0 + pl >= 0 && pl >= 0;
+                f = pl;
+                e = (int32_t)len - 1;
+                off = o;
+            }
+            const int32_t own_lo = own_from > start ? (int32_t)(own_from - start) : 0;
+            ok = ok && off <= C && e >= own_lo && e <= (int32_t)len - 1 && f <= e;
+            if (ok) {
+                const uint32_t ew = (start + (uint32_t)e) >> 5;
+                ok = ew >= a.w_begin && ew < a.w_end;
             }
             uint32_t m = 0, nref = 0;
             if (ok) {
-                for (uint32_t t2 = 0; t2 < d.nw; t2++) {
-                    const int64_t cw = p + 32 * (int64_t)t2;   // contig coordinate of bit 0
-                    const uint32_t lmask = low_mask((uint32_t)(L - 32 * (int64_t)t2));
-                    const int64_t lo_b = first - cw < 0 ? 0 : (first - cw > 32 ? 32 : first - cw);
-                    const int64_t hi_b = e + 1 - cw < 0 ? 0 : (e + 1 - cw > 32 ? 32 : e + 1 - cw);
+                for (uint32_t t = 0; t < d.nw; t++) {
+                    const int32_t cw = pl + 32 * (int32_t)t;   // piece-local base of bit 0
+                    const uint32_t lmask = low_mask((uint32_t)(L - 32 * (int32_t)t));
+                    const int32_t lo_b = min(max(f - cw, 0), 32);
+                    const int32_t hi_b = min(max(e + 1 - cw, 0), 32);
                     uint32_t rh = 0u, rl = 0u, rn = 0u, vm = 0u;
                     if (lo_b < hi_b) {
-                        const uint64_t u = (uint64_t)(base + cw + lo_b);   // an on-contig base
-                        const uint32_t x = (uint32_t)(u >> 5), sh = (uint32_t)(u & 31u);
+                        const uint32_t u = start + (uint32_t)(cw + lo_b);   // on-contig base
+                        const uint32_t x = u >> 5, sh = u & 31u;
                         rh = funnel(a.hi[x + 1], a.hi[x], sh) << lo_b;
                         rl = funnel(a.lo[x + 1], a.lo[x], sh) << lo_b;
                         rn = funnel(a.nm[x + 1], a.nm[x], sh) << lo_b;
                         vm = low_mask((uint32_t)hi_b) & ~low_mask((uint32_t)lo_b);
                     }
                     const uint32_t rne = ((rn & vm) | ~vm) & lmask;   // N or off the contig
-                    const uint32_t diff = (qw[3 * t2] ^ rh) | (qw[3 * t2 + 1] ^ rl) | qw[3 * t2 + 2];
+                    const uint32_t diff =
+                        (qw[3 * t] ^ rh) | (qw[3 * t + 1] ^ rl) | qw[3 * t + 2];
                     if (a.policy == kNSeparate)
                         m += __popc(diff & ~rne & lmask);
                     else
@@ -1108,12 +1135,12 @@ __global__ __launch_bounds__(256) void scan_edge_kernel(ScanArgs a)
                 ok = m <= d.k && (a.policy != kNSeparate || nref <= d.maxn);
             }
             if (ok) {
-                const uint32_t pos = (uint32_t)(int32_t)p;
+                const uint32_t pos = (uint32_t)(c0 + pl);
                 if (a.sink == kSinkRecords) {
-                    write_record(a, atomicAdd(a.hit_count, 1ull), d, pc.contig, pos, m, nref);
+                    write_record(a, atomicAdd(a.hit_count, 1ull), d, contig, pos, m, nref);
                 } else {
                     cnt += 1;
-                    dig += hit_hash(pc.contig, pos, d.strand, m, nref);
+                    dig += hit_hash(contig, pos, d.strand, m, nref);
                 }
             }
         }
@@ -1268,13 +1295,14 @@ hipError_t launch_dense(const ScanArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-// Overhanging windows of the word range: one wave per (piece, query strand)
-// task, grid-stride.
+// Overhanging windows of the word range: one wave per (block of pieces,
+// query strand) task, grid-stride.
 hipError_t launch_edge(const ScanArgs &a, hipStream_t s)
 {
-    const uint64_t tasks = (uint64_t)a.n_pieces * a.n_qs;
-    if (a.w_end <= a.w_begin || tasks == 0) return hipSuccess;
-    const uint32_t blocks = (uint32_t)std::min<uint64_t>((tasks + 3) / 4, 2048);
+    if (a.w_end <= a.w_begin || a.n_pieces == 0 || a.n_qs == 0 || a.edge_pmin == 0)
+        return hipSuccess;
+    const uint64_t tasks = (uint64_t)((a.n_pieces + a.edge_pmin - 1) / a.edge_pmin) * a.n_qs;
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((tasks + 3) / 4, 4096);
     hipLaunchKernelGGL(scan_edge_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -309,10 +309,13 @@ def c2_spec(seed: int = 2, total: int = 4_000_000_000) -> RefSpec:
 
 
 def c2_paper_scale(seed: int = 2, total: int = 4_000_000_000, k: int = 4,
-                   plants_per_query: int | None = None, n_queries: int = 10) -> Workload:
+                   plants_per_query: int | None = None, n_queries: int = 10,
+                   median: float = 3e6) -> Workload:
     """10 queries of length 30-36; 1 planted copy per query per 100 Mbp with
-    0-8 substitutions, strand a fair coin; maxSubs k for every query."""
+    0-8 substitutions, strand a fair coin; maxSubs k for every query. `median`
+    sets the median contig length (a fragmented assembly when small)."""
     spec = c2_spec(seed, total)
+    spec.median = median
     ref = gen_reference(spec)
     qs = gen_queries(seed, n_queries, 30, 36)
     if plants_per_query is None:
