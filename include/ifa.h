@@ -316,6 +316,58 @@ ifa_status ifa_server_take(ifa_server *srv, uint64_t request_id, ifa_hit *out, u
 
 ifa_status ifa_server_info(const ifa_server *srv, ifa_server_stats *out);
 
+/* ------------------------------------------------------------------------
+ * SAM text. The aligner streams the reference, so its SAM output is
+ * headerless and a separate header is concatenated in front of it (Methods,
+ * "Output Format"). A query's primary alignment is its first valid alignment
+ * in reference order, every other one is secondary (Results, "Accuracy
+ * Validation"); queries without a hit get no line. Host code only.
+ *
+ * One line per hit: QNAME, FLAG (16 = reverse-complement strand, 256 =
+ * secondary), RNAME, POS (1-based first aligned base), MAPQ 255, CIGAR
+ * [aS]mM[bS] (a, b = bases off the contig's left / right end, IFA_FLAG_OVERHANG),
+ * RNEXT *, PNEXT 0, TLEN 0, SEQ (the strand sequence as compared: the query or
+ * its reverse complement, upper case, N for non-ACGT), QUAL *, NM:i
+ * (mismatches over the aligned bases) and XN:i (reference Ns over the aligned
+ * bases). The header holds @HD VN:1.6 SO:coordinate, one @SQ per contig in
+ * ordinal order and @PG ID:ifa.
+ * ------------------------------------------------------------------------ */
+typedef struct ifa_sam ifa_sam;
+
+/* A writer for the hits of one query set: seq/len as given to
+ * ifa_load_queries, names[j] the query names (non-empty, no tab or newline),
+ * n_policy the context's IFA_N_* policy. Copies what it needs.
+ * Errors: IFA_E_INVALID, IFA_E_NOMEM. */
+ifa_status ifa_sam_create(uint32_t n_queries, const uint8_t *const *seq, const uint32_t *len,
+                          const char *const *names, uint32_t n_policy, ifa_sam **out);
+
+/* NULL-safe. */
+void ifa_sam_destroy(ifa_sam *w);
+
+/* Message of the writer's last failed call ("" if none); lives until its next call. */
+const char *ifa_sam_last_error(const ifa_sam *w);
+
+/* Name and length of contigs first_ordinal .. first_ordinal + n - 1, the
+ * ordinals ifa_scan_chunk / ifa_ref_load gave them; added in ordinal order
+ * without gaps. Errors: IFA_E_INVALID (order, name, len >= 2^31). */
+ifa_status ifa_sam_add_contigs(ifa_sam *w, uint32_t first_ordinal, uint32_t n,
+                               const char *const *names, const uint64_t *len);
+
+/* The header for the contigs added so far. *n_bytes receives its size; with
+ * buf == NULL nothing else happens, else it is copied to buf (no NUL) and
+ * IFA_E_INVALID is returned when cap is smaller. */
+ifa_status ifa_sam_header(const ifa_sam *w, char *buf, uint64_t cap, uint64_t *n_bytes);
+
+/* Format hits (in reference order, as ifa_collect_hits hands them out; the
+ * order continues across calls) into buf as whole lines, no NUL. Stops at the
+ * first line that does not fit or at the first invalid hit; *n_consumed and
+ * *n_bytes tell how far it got. The primary/secondary state advances only
+ * over consumed hits. Errors (nothing consumed): IFA_E_INVALID when the first
+ * hit is invalid (query or contig unknown, out of reference order, window not
+ * on its contig) or its line alone exceeds cap. */
+ifa_status ifa_sam_format(ifa_sam *w, const ifa_hit *hits, uint64_t n, char *buf, uint64_t cap,
+                          uint64_t *n_consumed, uint64_t *n_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,9 @@ __all__ = [
     "ifa_set_variant", "ifa_get_variant", "ifa_autotune", "ifa_query_partition",
     "ifa_device_footprint", "ifa_server_config_default", "ifa_server_create",
     "ifa_server_destroy", "ifa_server_submit", "ifa_server_step", "ifa_server_poll",
-    "ifa_server_take", "ifa_server_info", "Scanner", "Server", "collect_all",
+    "ifa_server_take", "ifa_server_info", "ifa_sam_create", "ifa_sam_destroy",
+    "ifa_sam_last_error", "ifa_sam_add_contigs", "ifa_sam_header", "ifa_sam_format",
+    "SamWriter", "Scanner", "Server", "collect_all",
 ]
 
 IFA_ABI_VERSION = 2
@@ -149,6 +151,19 @@ def lib():
         L.ifa_server_take.restype = st
         L.ifa_server_info.argtypes = [vp, ctypes.POINTER(IfaServerStats)]
         L.ifa_server_info.restype = st
+        L.ifa_sam_create.argtypes = [u32, vp, vp, vp, u32, ctypes.POINTER(vp)]
+        L.ifa_sam_create.restype = st
+        L.ifa_sam_destroy.argtypes = [vp]
+        L.ifa_sam_destroy.restype = None
+        L.ifa_sam_last_error.argtypes = [vp]
+        L.ifa_sam_last_error.restype = ctypes.c_char_p
+        L.ifa_sam_add_contigs.argtypes = [vp, u32, u32, vp, vp]
+        L.ifa_sam_add_contigs.restype = st
+        L.ifa_sam_header.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
+        L.ifa_sam_header.restype = st
+        L.ifa_sam_format.argtypes = [vp, vp, u64, vp, u64, ctypes.POINTER(u64),
+                                     ctypes.POINTER(u64)]
+        L.ifa_sam_format.restype = st
         _lib = L
     return _lib
 
@@ -391,6 +406,103 @@ def ifa_server_info(srv) -> dict:
     st = IfaServerStats()
     lib().ifa_server_info(srv, ctypes.byref(st))
     return {k: getattr(st, k) for k, _ in IfaServerStats._fields_}
+
+
+def _sam_check(w, status):
+    if status != 0:
+        msg = lib().ifa_sam_last_error(w) if w else b""
+        raise IfaError(status, (msg or b"").decode(errors="replace"))
+
+
+def _names(names):
+    keep = [n.encode() if isinstance(n, str) else bytes(n) for n in names]
+    return keep, (ctypes.c_char_p * max(len(keep), 1))(*keep)
+
+
+def ifa_sam_create(queries, names, n_policy=IFA_N_SEPARATE):
+    sa = _SeqArray(queries, np.uint32)
+    keep, arr = _names(names)
+    if len(keep) != sa.n:
+        raise ValueError("one name per query is required")
+    w = ctypes.c_void_p()
+    _sam_check(None, lib().ifa_sam_create(sa.n, sa.ptrs, sa.lens.ctypes.data, arr, n_policy,
+                                          ctypes.byref(w)))
+    return w
+
+
+def ifa_sam_destroy(w):
+    lib().ifa_sam_destroy(w)
+
+
+def ifa_sam_last_error(w) -> str:
+    return (lib().ifa_sam_last_error(w) or b"").decode(errors="replace")
+
+
+def ifa_sam_add_contigs(w, first_ordinal: int, names, lens):
+    keep, arr = _names(names)
+    ln = np.ascontiguousarray(list(lens) or [0], dtype=np.uint64)
+    if len(ln) < len(keep):
+        raise ValueError("one length per contig is required")
+    _sam_check(w, lib().ifa_sam_add_contigs(w, first_ordinal, len(keep), arr, ln.ctypes.data))
+
+
+def ifa_sam_header(w) -> str:
+    n = ctypes.c_uint64()
+    _sam_check(w, lib().ifa_sam_header(w, None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(max(n.value, 1))
+    _sam_check(w, lib().ifa_sam_header(w, buf, n.value, ctypes.byref(n)))
+    return buf.raw[:n.value].decode()
+
+
+def ifa_sam_format(w, hits, cap: int = 1 << 20, buf=None):
+    """One call: returns (text, hits consumed). `buf` (a ctypes char buffer of
+    at least cap bytes) may be passed in to be reused."""
+    h = np.ascontiguousarray(hits, dtype=HIT_DTYPE)
+    if buf is None:
+        buf = ctypes.create_string_buffer(max(cap, 1))
+    used, nb = ctypes.c_uint64(), ctypes.c_uint64()
+    _sam_check(w, lib().ifa_sam_format(w, h.ctypes.data if h.size else None, h.size, buf, cap,
+                                       ctypes.byref(used), ctypes.byref(nb)))
+    return ctypes.string_at(buf, nb.value).decode(), used.value
+
+
+class SamWriter:
+    """SAM text for the hits of one query set (convenience over ifa_sam_*)."""
+
+    def __init__(self, queries, names, n_policy=IFA_N_SEPARATE):
+        self.w = ifa_sam_create(queries, names, n_policy)
+        self.n_contigs = 0
+        self.buf = None
+
+    def add_contigs(self, names, lens, first_ordinal=None):
+        first = self.n_contigs if first_ordinal is None else first_ordinal
+        ifa_sam_add_contigs(self.w, first, names, lens)
+        self.n_contigs = first + len(names)
+
+    def header(self) -> str:
+        return ifa_sam_header(self.w)
+
+    def format(self, hits) -> str:
+        cap = 1 << 22
+        if self.buf is None:
+            self.buf = ctypes.create_string_buffer(cap)
+        parts, i = [], 0
+        while i < len(hits):
+            text, used = ifa_sam_format(self.w, hits[i:], cap, self.buf)
+            parts.append(text)
+            i += used
+        return "".join(parts)
+
+    def close(self):
+        if self.w:
+            ifa_sam_destroy(self.w)
+            self.w = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Server:
