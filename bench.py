@@ -68,6 +68,8 @@ def parse():
     ap.add_argument("--ks", default="0,4,8", help="c2: maxSubs values, one pass each")
     ap.add_argument("--overhang", action="store_true",
                     help="c2/c3: also report windows overhanging contig ends (soft clip)")
+    ap.add_argument("--sam", action="store_true",
+                    help="c2: also time the SAM text of one step's hits (host writer)")
     ap.add_argument("--median", type=float, default=0.0,
                     help="c2: median contig length in bases (0 = the workload's 3 Mbp)")
     ap.add_argument("--cpu-sample", type=int, default=250_000_000,
@@ -269,6 +271,25 @@ def add_overhang(out, args, st):
     }
 
 
+def time_sam(ifa, w, hit_sets):
+    """SAM text of one step's hits (each maxSubs pass of the step is a
+    separate query set, so a separate writer): host time and line rate."""
+    names = [f"q{j}" for j in range(len(w.queries))]
+    cnames = [f"chr{i}" for i in range(w.ref.n_contigs)]
+    lens = [int(x) for x in w.ref.lens]
+    t0 = time.perf_counter()
+    lines = nbytes = 0
+    for h in hit_sets:
+        with ifa.SamWriter(w.queries, names) as sw:
+            sw.add_contigs(cnames, lens)
+            text = sw.header() + sw.format(h)
+        lines += len(h)
+        nbytes += len(text)
+    dt = time.perf_counter() - t0
+    return {"lines": lines, "bytes": nbytes, "ms": round(dt * 1e3, 3),
+            "lines_per_s": round(lines / dt, 1) if dt > 0 else None}
+
+
 def timed_steps(ifa, s, args, step):
     for i in range(args.warmup):
         step()
@@ -310,12 +331,17 @@ def run_c2(args):
     tune = choose_variant(ifa, s, args, w.queries, [4] * nq)
     variant = ifa.ifa_get_variant(s.ctx)
 
+    last_hits = []
+
     def step():
         found = 0
+        last_hits.clear()
         for k in ks:
             s.load_queries(w.queries, [k] * nq)
             s.scan_resident()
-            found += len(s.collect())
+            h = s.collect()
+            last_hits.append(h)
+            found += len(h)
         return found
 
     elapsed, st, res = timed_steps(ifa, s, args, step)
@@ -334,6 +360,8 @@ def run_c2(args):
         out["config"]["workload"] += f", median contig {args.median:.0f} bp"
         out["config"]["contigs"] = int(w.ref.n_contigs)
     add_overhang(out, args, st)
+    if args.sam:
+        out["sam"] = time_sam(ifa, w, last_hits)
     out["kernel_only_gbpq_s"] = round(bpq_per_step * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
     out["autotune"] = tune
     out["graph_launches"] = st["graph_launches"]
