@@ -37,7 +37,7 @@ def lib():
         vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
         i64 = ctypes.c_int64
         L.orc_scan.argtypes = [u32, vp, vp, vp, vp, u32, vp, vp, u32, u32, u32, ctypes.c_int,
-                               ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp),
+                               vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp),
                                ctypes.POINTER(u64), vp, vp]
         L.orc_scan.restype = ctypes.c_int
         L.orc_free.argtypes = [vp]
@@ -48,6 +48,12 @@ def lib():
         L.orc_eval_window.argtypes = [vp, u32, i32, i32, vp, u64, i64, u32, u32, ctypes.c_int,
                                       ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.orc_eval_window.restype = ctypes.c_int
+        L.orc_splitmix64.argtypes = [u64, u64]
+        L.orc_splitmix64.restype = u64
+        L.orc_keff.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_keff.restype = ctypes.c_int
+        L.orc_minhits.argtypes = [i32, i32, i32, i32, i32, u64, u64, u32]
+        L.orc_minhits.restype = i64
         _lib = L
     return _lib
 
@@ -89,15 +95,23 @@ class _Contigs:
         self.n = n
 
 
+class _SeedSpec(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_void_p), ("thr", ctypes.c_void_p), ("mask", ctypes.c_int32),
+                ("step", ctypes.c_int32)]
+
+
 def scan(queries, contigs, max_subs, max_n=None, *, first_ordinal=0, strands=3,
-         policy=N_SEPARATE, overhang=False, threads=None, records=True, stats=False):
+         policy=N_SEPARATE, overhang=False, seeds=None, threads=None, records=True,
+         stats=False):
     """Run the C oracle.
 
     queries: list of byte strings; contigs: list of byte strings / uint8 arrays
     (or a synth.Reference); max_subs: per-query ints; max_n: per-query ints or
     None (floor(L/4)); overhang: also the windows hanging off a contig end by
-    at most min(maxN, L - 1) bases. Returns a HIT_DTYPE array in (contig, pos,
-    strand, query) order; with stats=True returns (hits, counts, digests).
+    at most min(maxN, L - 1) bases; seeds: indexed mode, a dict with per-query
+    "k", per-query-and-strand "thr" ([[t_fwd, t_rc], ...]), "mask" and "step"
+    (see indexed_params). Returns a HIT_DTYPE array in (contig, pos, strand,
+    query) order; with stats=True returns (hits, counts, digests).
     """
     if hasattr(contigs, "pointer_array"):
         ptrs, lens = contigs.pointer_array()
@@ -115,11 +129,19 @@ def scan(queries, contigs, max_subs, max_n=None, *, first_ordinal=0, strands=3,
     mn = None if max_n is None else np.array(list(max_n) or [0], dtype=np.int32)
     counts = np.zeros(max(nq, 1), dtype=np.uint64)
     digests = np.zeros(max(nq, 1), dtype=np.uint64)
+    spec = None
+    if seeds is not None:
+        sk = np.ascontiguousarray(list(seeds["k"]) or [1], dtype=np.int32)
+        st = np.ascontiguousarray(np.asarray(seeds["thr"], dtype=np.int32).reshape(-1) if nq
+                                  else [0, 0], dtype=np.int32)
+        spec = _SeedSpec(sk.ctypes.data, st.ctypes.data, int(seeds.get("mask", 0)),
+                         int(seeds.get("step", 1)))
     out = ctypes.c_void_p()
     n_out = ctypes.c_uint64()
     rc = lib().orc_scan(nq, qptrs, qlen.ctypes.data, ks.ctypes.data,
                         None if mn is None else mn.ctypes.data, nc, ptrs, lens.ctypes.data,
                         first_ordinal, strands, policy, 1 if overhang else 0,
+                        None if spec is None else ctypes.byref(spec),
                         threads or _default_threads(),
                         1 if records else 0, ctypes.byref(out), ctypes.byref(n_out),
                         counts.ctypes.data, digests.ctypes.data)
@@ -157,6 +179,71 @@ def eval_window(query, max_subs, contig, pos, strand, max_n=-1, policy=N_SEPARAT
 
 def mix64(z: int) -> int:
     return int(lib().orc_mix64(z))
+
+
+def splitmix64(seed: int, n: int) -> int:
+    """Draw n (0-based) of the SplitMix64 stream with this seed."""
+    return int(lib().orc_splitmix64(seed, n))
+
+
+def keff(k: int, mask: int = 0, step: int = 1) -> int:
+    return int(lib().orc_keff(k, mask, step))
+
+
+def minhits(valid, subs, k, mask=0, step=1, iters=200_000, seed=1, ppm=999_000) -> int:
+    """MinHits for a query with `valid` seeds (see ifa_oracle.c); may be <= 0."""
+    r = int(lib().orc_minhits(valid, subs, k, mask, step, iters, seed, ppm))
+    if r == -(1 << 63):
+        raise ValueError("bad MinHits arguments")
+    return r
+
+
+# Indexed-mode defaults (Methods, "Algorithm Design"): candidate seed lengths,
+# 200,000 Monte Carlo trials, 99.9 % probability.
+SEED_KS = (8, 9, 10, 12, 14)
+
+
+def _valid_seeds(codes, k, mask, step):
+    lo = (k - mask) // 2
+    n = 0
+    for i in range(0, len(codes) - k + 1, step):
+        if all(codes[i + t] != 4 for t in range(k) if t < lo or t >= lo + mask):
+            n += 1
+    return n
+
+
+def indexed_params(queries, max_subs, *, ks=SEED_KS, mask=0, step=1, iters=200_000, seed=1,
+                   ppm=999_000):
+    """Per query: the seed length k and the per-strand seed thresholds.
+
+    Readings of the multi-K rule (Methods, "Algorithm Design"): the longest k
+    in `ks` (k <= L, k > mask) whose MinHits on the query's forward strand is
+    at least 1; if none, the shortest such k; a query shorter than every k
+    uses k = L. The threshold of a strand is max(1, MinHits) for its own
+    valid-seed count: a window needs one error-free seed to be found at all.
+    """
+    out_k, out_thr = [], []
+    cache = {}
+
+    def mh(v, s, k):
+        key = (v, s, k)
+        if key not in cache:
+            cache[key] = minhits(v, s, k, mask, step, iters, seed, ppm) if v > 0 else 0
+        return cache[key]
+
+    for q, s in zip(queries, max_subs):
+        c = _CODE[np.frombuffer(_as_bytes(q), dtype=np.uint8)].tolist()
+        rc = [4 if x == 4 else 3 - x for x in reversed(c)]
+        L = len(c)
+        s = min(int(s), L)
+        cand = sorted((k for k in ks if k <= L and k > mask), reverse=True)
+        if not cand:
+            k = L if L > mask else L
+            cand = [k]
+        k = next((k for k in cand if mh(_valid_seeds(c, k, mask, step), s, k) >= 1), cand[-1])
+        out_k.append(k)
+        out_thr.append([max(1, mh(_valid_seeds(x, k, mask, step), s, k)) for x in (c, rc)])
+    return {"k": out_k, "thr": out_thr, "mask": mask, "step": step}
 
 
 def hit_hash(contig, pos, strand, mism, nref) -> int:

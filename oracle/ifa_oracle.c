@@ -44,6 +44,15 @@
  * primary is the first valid alignment in reference order), tie-broken by
  * strand (+ first) then query index.
  *
+ * Indexed mode (Methods, "Algorithm Design"): query k-mer seeds, a central
+ * portion of each k-mer optionally masked, sampled every `step` offsets; a
+ * window is reported only if it is a hit as above AND at least T of the
+ * query's valid seeds (no N at an unmasked position) occur error-free at the
+ * same offset of the window (reference bases equal at every unmasked
+ * position). T comes from the MinHits computation below (orc_minhits) and the
+ * k from the longest-k rule; those choices are made by the caller and passed
+ * in (orc_seed_spec). Overhanging windows are not combined with seeds.
+ *
  * Count+digest: per query, the number of hits and the wrapping 64-bit sum of
  *   H = mix64(((contig << 32) | pos) ^ (aux << 45)),
  *   aux = strand | (mismatches << 1) | (n_ref << 10),
@@ -64,6 +73,15 @@ typedef struct {
 } orc_hit;
 
 enum { ORC_N_SEPARATE = 0, ORC_N_AS_MISMATCH = 1 };
+
+/* Indexed-mode seeds: k[j] per query, thr[2j + s] per query strand, the
+ * length of the masked centre of every k-mer, and the sampling step. */
+typedef struct {
+    const int32_t *k;
+    const int32_t *thr;
+    int32_t mask;
+    int32_t step;
+} orc_seed_spec;
 
 /* base code: A 0, C 1, G 2, T 3, anything else 4 (N) */
 static int orc_norm(uint8_t b)
@@ -124,6 +142,7 @@ typedef struct {
     uint32_t strands;
     uint32_t policy;
     int overhang;
+    const orc_seed_spec *seeds;   /* NULL: brute force, no seed condition */
     int want_records;
     int maxL;
     orc_item *items;
@@ -186,6 +205,38 @@ static int orc_test_window(const uint8_t *qc, int L, const uint8_t *r, int K, in
     *m_out = m;
     *nref_out = nref;
     return 1;
+}
+
+/* Error-free seeds of query strand codes qc (length L) in the window r: the
+ * sampled offsets i = 0, step, 2 step, ... (i + k <= L) whose k-mer holds no
+ * query N at an unmasked position and equals the window's bases at every
+ * unmasked position. The masked centre is [(k - mask) / 2, that + mask). */
+static int orc_seed_hits(const uint8_t *qc, int L, const uint8_t *r, int k, int mask, int step)
+{
+    const int lo = (k - mask) / 2, hi = lo + mask;
+    int hits = 0;
+    for (int i = 0; i + k <= L; i += step) {
+        int valid = 1, match = 1;
+        for (int t = 0; t < k; t++) {
+            if (t >= lo && t < hi) continue;
+            if (qc[i + t] == 4) {
+                valid = 0;
+                break;
+            }
+            if (r[i + t] != qc[i + t]) match = 0;   /* a reference N equals nothing */
+        }
+        hits += valid && match;
+    }
+    return hits;
+}
+
+/* The seed condition of indexed mode (always true without seeds). */
+static int orc_seeds_ok(const orc_job *J, uint32_t j, int s, const uint8_t *qc, int L,
+                        const uint8_t *r)
+{
+    if (!J->seeds) return 1;
+    const orc_seed_spec *S = J->seeds;
+    return orc_seed_hits(qc, L, r, S->k[j], S->mask, S->step) >= S->thr[2 * j + s];
 }
 
 static void emit_hit(orc_worker *W, uint32_t j, uint32_t contig, int64_t p, int s, int m,
@@ -273,6 +324,7 @@ static void run_item(orc_worker *W, const orc_item *it, uint8_t *codes)
                 int m, nref;
                 if (!orc_test_window(Q->code[s], L, r, Q->K, Q->M, J->policy, &m, &nref))
                     continue;
+                if (!orc_seeds_ok(J, j, s, Q->code[s], L, r)) continue;
                 emit_hit(W, j, it->contig, (int64_t)p, s, m, nref);
                 if (W->failed) return;
             }
@@ -324,19 +376,22 @@ void orc_free(void *p)
  * arguments or allocation failure. When want_records is set, *out receives a
  * malloc'd array of *n_out hits in (contig, pos, strand, query) order (free
  * with orc_free). counts/digests, when not NULL, are nq-long arrays that this
- * call overwrites. overhang = 1 adds the windows that hang off a contig end.
+ * call overwrites. overhang = 1 adds the windows that hang off a contig end;
+ * seeds (may be NULL) adds the indexed-mode seed condition.
  * Contigs must be shorter than 2^31 bases (pos is an int32).
  */
 int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
              const int32_t *max_subs, const int32_t *max_n,
              uint32_t nc, const uint8_t *const *ctg, const uint64_t *clen,
              uint32_t first_ordinal, uint32_t strands, uint32_t policy, int overhang,
-             int threads, int want_records, orc_hit **out, uint64_t *n_out,
-             uint64_t *counts, uint64_t *digests)
+             const orc_seed_spec *seeds, int threads, int want_records, orc_hit **out,
+             uint64_t *n_out, uint64_t *counts, uint64_t *digests)
 {
     if (out) *out = NULL;
     if (n_out) *n_out = 0;
     if (strands < 1 || strands > 3 || policy > 1 || overhang < 0 || overhang > 1) return -1;
+    if (seeds && (overhang || !seeds->k || !seeds->thr || seeds->step < 1 || seeds->mask < 0))
+        return -1;
     for (uint32_t c = 0; c < nc; c++)
         if (clen[c] >= (1ull << 31)) return -1;
     orc_job J;
@@ -348,6 +403,7 @@ int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
     J.strands = strands;
     J.policy = policy;
     J.overhang = overhang;
+    J.seeds = seeds;
     J.want_records = want_records;
     J.qs = (orc_query *)calloc(nq ? nq : 1, sizeof(orc_query));
     if (!J.qs) return -1;
@@ -356,6 +412,8 @@ int orc_scan(uint32_t nq, const uint8_t *const *q, const uint32_t *qlen,
     for (uint32_t j = 0; j < nq; j++) {
         int L = (int)qlen[j];
         if (L < 1 || max_subs[j] < 0 || (max_n && max_n[j] < 0)) goto done;
+        if (seeds && (seeds->k[j] < 1 || seeds->k[j] > L || seeds->mask >= seeds->k[j]))
+            goto done;
         orc_query *Q = &J.qs[j];
         Q->L = L;
         Q->K = max_subs[j] < L ? max_subs[j] : L;
@@ -512,4 +570,109 @@ int orc_eval_window(const uint8_t *q, uint32_t L, int32_t max_subs, int32_t max_
     if (m > K) return 0;
     if (policy == ORC_N_SEPARATE && nref > M) return 0;
     return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* MinHits (Methods, "Algorithm Design"): the minimum number of error-free
+ * seeds that a valid alignment keeps with a given probability, by Monte
+ * Carlo with a fixed seed; at probability 1 the deterministic lower bound
+ * validKmers - kEffective * maxSubs - maxClips.
+ *
+ * Model (readings): a query with V valid seeds is taken as V k-mers at
+ * offsets 0, step, ..., (V - 1) step over a span of (V - 1) step + k bases
+ * (for an N-free query sampled every base, exactly its L bases); each trial
+ * places min(maxSubs, span) substitutions at distinct positions drawn
+ * uniformly over the span, and counts the seeds with no substitution at an
+ * unmasked position. The answer is the largest t with at least ppm / 10^6 of
+ * the trials keeping t or more seeds. kEffective is the most seeds one
+ * substitution can touch; maxClips is 0 (seeds are not combined with
+ * overhanging windows).
+ *
+ * Random draws: SplitMix64 (Steele, Lea & Flood 2014), draw n of stream
+ * `seed` = mix64(seed + (n + 1) * 0x9E3779B97F4A7C15); a uniform position in
+ * [0, m) is the high 64 bits of draw * m (Lemire's multiply-shift). A trial
+ * picks its positions by a partial Fisher-Yates shuffle (slot c swapped with
+ * a uniform slot in [c, span)) of the position array the previous trial left
+ * (initially 0, 1, ..., span - 1); the draw counter runs on across trials.
+ */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t n)
+{
+    return orc_mix64(seed + (n + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+static int orc_kmer_unmasked(int t, int k, int mask)
+{
+    const int lo = (k - mask) / 2;
+    return t < lo || t >= lo + mask;
+}
+
+int orc_keff(int k, int mask, int step)
+{
+    int best = 0;
+    for (int x = 0; x < k + step * k; x++) {
+        int c = 0;
+        for (int v = 0; v * step <= x; v++) {
+            const int t = x - v * step;
+            if (t < k && orc_kmer_unmasked(t, k, mask)) c++;
+        }
+        if (c > best) best = c;
+    }
+    return best;
+}
+
+/* MinHits; may be <= 0 (the caller takes max(1, .)). INT64_MIN on bad
+ * arguments or no memory. */
+int64_t orc_minhits(int32_t V, int32_t subs, int32_t k, int32_t mask, int32_t step,
+                    uint64_t iters, uint64_t seed, uint32_t ppm)
+{
+    if (V <= 0 || k < 1 || mask < 0 || mask >= k || step < 1 || subs < 0 || ppm > 1000000)
+        return INT64_MIN;
+    const int span = (V - 1) * step + k;
+    const int s = subs < span ? subs : span;
+    if (ppm == 1000000) return (int64_t)V - (int64_t)orc_keff(k, mask, step) * s;
+    if (iters == 0) return INT64_MIN;
+    int *pos = (int *)malloc((size_t)span * sizeof(int));
+    uint8_t *dead = (uint8_t *)malloc((size_t)V);
+    uint64_t *hist = (uint64_t *)calloc((size_t)V + 1, sizeof(uint64_t));
+    if (!pos || !dead || !hist) {
+        free(pos);
+        free(dead);
+        free(hist);
+        return INT64_MIN;
+    }
+    for (int i = 0; i < span; i++) pos[i] = i;
+    uint64_t n = 0;
+    for (uint64_t it = 0; it < iters; it++) {
+        for (int c = 0; c < s; c++) {
+            const uint64_t r = orc_splitmix64(seed, n++);
+            const int j = c + (int)(((unsigned __int128)r * (uint64_t)(span - c)) >> 64);
+            const int tmp = pos[c];
+            pos[c] = pos[j];
+            pos[j] = tmp;
+        }
+        memset(dead, 0, (size_t)V);
+        for (int c = 0; c < s; c++) {
+            const int x = pos[c];
+            for (int v = 0; v < V; v++) {
+                const int t = x - v * step;
+                if (t >= 0 && t < k && orc_kmer_unmasked(t, k, mask)) dead[v] = 1;
+            }
+        }
+        int alive = 0;
+        for (int v = 0; v < V; v++) alive += !dead[v];
+        hist[alive]++;
+    }
+    int64_t ans = 0;
+    uint64_t acc = 0;
+    for (int t = V; t >= 0; t--) {
+        acc += hist[t];
+        if ((unsigned __int128)acc * 1000000u >= (unsigned __int128)ppm * iters) {
+            ans = t;
+            break;
+        }
+    }
+    free(pos);
+    free(dead);
+    free(hist);
+    return ans;
 }
