@@ -104,6 +104,26 @@ typedef struct {
 /* ifa_config.flags: also report the windows that overhang a contig end (see
  * the definition at the top). Off by default. */
 #define IFA_FLAG_OVERHANG 2u
+/* ifa_config.flags: indexed mode (Methods, "Algorithm Design"): a window is
+ * reported only if it is a hit as defined at the top AND at least T of the
+ * query strand's seeds occur error-free at the same offset of the window.
+ * Seeds are the strand's k-mers at offsets 0, step, 2 step, ... with no N at
+ * an unmasked position (a centre of `mask` bases of every k-mer is ignored);
+ * a seed occurs error-free when the window's bases equal it at every
+ * unmasked position. k is the longest candidate length whose MinHits is at
+ * least 1 (else the shortest; a query shorter than every candidate uses
+ * k = L); T = max(1, MinHits) for the strand's own seed count. MinHits is
+ * the largest t such that, over `iters` Monte Carlo trials placing
+ * min(maxSubs, span) substitutions uniformly at distinct positions of a
+ * query modelled as V seeds spanning (V - 1) step + k bases, at least
+ * prob_ppm / 10^6 of the trials leave t or more seeds error-free; at
+ * prob_ppm = 10^6 it is the deterministic bound V - kEffective x maxSubs,
+ * kEffective the most seeds one substitution can touch. Trials draw from
+ * SplitMix64 (stream `seed`, draw n = mix64(seed + (n + 1) x golden gamma),
+ * uniform positions by multiply-shift) through a partial Fisher-Yates
+ * shuffle of a position array kept across trials. Not combined with
+ * IFA_FLAG_OVERHANG. */
+#define IFA_FLAG_INDEXED 4u
 
 /* One reported window (16 bytes). strand: 0 = +, 1 = - (reverse complement). */
 typedef struct {
@@ -227,6 +247,32 @@ ifa_status ifa_query_partition(const ifa_ctx *ctx, uint32_t *n_strands, uint32_t
 /* Device memory held by the context, in bytes: stream chunk buffers, hit
  * buffers, work lists, query tables, counters and any resident reference. */
 ifa_status ifa_device_footprint(const ifa_ctx *ctx, uint64_t *bytes);
+
+/* Indexed-mode parameters (IFA_FLAG_INDEXED), with the paper's defaults
+ * (Methods, "Algorithm Design"): candidate seed lengths 8, 9, 10, 12, 14;
+ * no mask; step 1; probability 99.9 %; 200,000 trials; a fixed seed. */
+#define IFA_MAX_SEED_KS 8
+typedef struct {
+    uint32_t n_k;                   /* candidate lengths in k[], 1..IFA_MAX_SEED_KS */
+    uint32_t k[IFA_MAX_SEED_KS];    /* each in [mask + 1, 16] */
+    uint32_t mask;                  /* masked centre of every k-mer, bases */
+    uint32_t step;                  /* seed sampling step, >= 1 */
+    uint32_t prob_ppm;              /* MinHits probability x 10^6, <= 10^6 */
+    uint32_t reserved;              /* must be 0 */
+    uint64_t iters;                 /* Monte Carlo trials, >= 1 */
+    uint64_t seed;                  /* SplitMix64 stream of the trials */
+} ifa_index_params;
+
+void ifa_index_params_default(ifa_index_params *p);
+
+/* Set the parameters used by the next ifa_load_queries of an indexed-mode
+ * context. Errors: IFA_E_INVALID (bad values, or not an indexed context). */
+ifa_status ifa_set_index_params(ifa_ctx *ctx, const ifa_index_params *p);
+
+/* Seeds chosen for the loaded queries: k[j] per query and thr[2 j + s] per
+ * query and strand (0 for a strand not scanned). Arrays of the loaded query
+ * count (and twice that). Errors: IFA_E_STATE (no queries, or not indexed). */
+ifa_status ifa_query_seeds(const ifa_ctx *ctx, uint32_t *k, uint32_t *thr);
 
 /* Kernel variants: tile shapes of the scan kernel (windows per lane, query
  * strands per loop iteration, workgroup size) and the arithmetic of the

@@ -22,7 +22,8 @@ __all__ = [
     "ifa_set_variant", "ifa_get_variant", "ifa_autotune", "ifa_query_partition",
     "ifa_device_footprint", "ifa_server_config_default", "ifa_server_create",
     "ifa_server_destroy", "ifa_server_submit", "ifa_server_step", "ifa_server_poll",
-    "ifa_server_take", "ifa_server_info", "ifa_sam_create", "ifa_sam_destroy",
+    "ifa_server_take", "ifa_server_info", "ifa_index_params_default", "ifa_set_index_params",
+    "ifa_query_seeds", "ifa_sam_create", "ifa_sam_destroy",
     "ifa_sam_last_error", "ifa_sam_add_contigs", "ifa_sam_header", "ifa_sam_format",
     "SamWriter", "Scanner", "Server", "collect_all",
 ]
@@ -34,6 +35,8 @@ IFA_SINK_RECORDS, IFA_SINK_COUNT_DIGEST = 0, 1
 IFA_STRAND_FWD, IFA_STRAND_RC, IFA_STRAND_BOTH = 1, 2, 3
 IFA_FLAG_GRAPHS = 1
 IFA_FLAG_OVERHANG = 2
+IFA_FLAG_INDEXED = 4
+IFA_MAX_SEED_KS = 8
 
 STATUS = {0: "IFA_OK", 1: "IFA_E_INVALID", 2: "IFA_E_NOMEM", 3: "IFA_E_DEVICE",
           4: "IFA_E_STATE", 5: "IFA_E_TOO_LONG"}
@@ -58,6 +61,13 @@ class IfaStats(ctypes.Structure):
                 ("filter_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64),
                 ("filter_windows", ctypes.c_uint64), ("work_items", ctypes.c_uint64),
                 ("graph_launches", ctypes.c_uint64), ("edge_ms", ctypes.c_double)]
+
+
+class IfaIndexParams(ctypes.Structure):
+    _fields_ = [("n_k", ctypes.c_uint32), ("k", ctypes.c_uint32 * 8), ("mask", ctypes.c_uint32),
+                ("step", ctypes.c_uint32), ("prob_ppm", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("iters", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64)]
 
 
 class IfaServerConfig(ctypes.Structure):
@@ -151,6 +161,12 @@ def lib():
         L.ifa_server_take.restype = st
         L.ifa_server_info.argtypes = [vp, ctypes.POINTER(IfaServerStats)]
         L.ifa_server_info.restype = st
+        L.ifa_index_params_default.argtypes = [ctypes.POINTER(IfaIndexParams)]
+        L.ifa_index_params_default.restype = None
+        L.ifa_set_index_params.argtypes = [vp, ctypes.POINTER(IfaIndexParams)]
+        L.ifa_set_index_params.restype = st
+        L.ifa_query_seeds.argtypes = [vp, vp, vp]
+        L.ifa_query_seeds.restype = st
         L.ifa_sam_create.argtypes = [u32, vp, vp, vp, u32, ctypes.POINTER(vp)]
         L.ifa_sam_create.restype = st
         L.ifa_sam_destroy.argtypes = [vp]
@@ -406,6 +422,35 @@ def ifa_server_info(srv) -> dict:
     st = IfaServerStats()
     lib().ifa_server_info(srv, ctypes.byref(st))
     return {k: getattr(st, k) for k, _ in IfaServerStats._fields_}
+
+
+def ifa_index_params_default() -> IfaIndexParams:
+    p = IfaIndexParams()
+    lib().ifa_index_params_default(ctypes.byref(p))
+    return p
+
+
+def ifa_set_index_params(ctx, p=None, **kw):
+    """Set indexed-mode parameters: an IfaIndexParams, or keyword overrides of
+    the defaults (ks=[...], mask, step, prob_ppm, iters, seed)."""
+    if p is None:
+        p = ifa_index_params_default()
+    if "ks" in kw:
+        ks = list(kw.pop("ks"))
+        p.n_k = len(ks)
+        for i in range(8):
+            p.k[i] = ks[i] if i < len(ks) else 0
+    for name, v in kw.items():
+        setattr(p, name, v)
+    _check(ctx, lib().ifa_set_index_params(ctx, ctypes.byref(p)))
+
+
+def ifa_query_seeds(ctx, n_queries: int):
+    """(k per query, thresholds [n, 2] per query and strand)."""
+    k = np.zeros(max(n_queries, 1), dtype=np.uint32)
+    thr = np.zeros(max(2 * n_queries, 2), dtype=np.uint32)
+    _check(ctx, lib().ifa_query_seeds(ctx, k.ctypes.data, thr.ctypes.data))
+    return k[:n_queries], thr[:2 * n_queries].reshape(n_queries, 2)
 
 
 def _sam_check(w, status):

@@ -15,7 +15,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
 # Packed FP32 instructions stay off in every device compile.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["ifa_scan.hip", "ifa_runtime.cpp", "ifa_sam.cpp"]
+SOURCES = ["ifa_scan.hip", "ifa_runtime.cpp", "ifa_sam.cpp", "ifa_seed.cpp"]
 
 
 def build(force=True, verbose=False):

@@ -61,6 +61,18 @@ struct QSDesc {
 };
 static_assert(sizeof(QSDesc) == 32, "QSDesc layout");
 
+// Indexed mode: per query strand, its seed length, the error-free seeds a
+// hit needs, and the offsets where a seed starts (sampled every `step` bases,
+// no N at an unmasked position): bit i of valid[i / 32].
+constexpr uint32_t kMaxSeedCfg = 8;   // distinct seed lengths of one query set
+struct SeedInfo {
+    uint32_t k;
+    uint32_t thr;
+    uint32_t pad[2];
+    uint32_t valid[kMaxQWords];
+};
+static_assert(sizeof(SeedInfo) == 48, "SeedInfo layout");
+
 // Work item of the sparse path: wave `wave` of the filter grid has at least
 // one candidate window for the query strands qb + j, j a set bit of `pending`.
 struct WorkItem {
@@ -115,6 +127,18 @@ struct ScanArgs {
     // overhang kernel: pieces per wave for the strand with the widest clip
     // (64 / (2 C) lanes each, at least 1); 0 = no strand can overhang
     uint32_t edge_pmin;
+    // indexed mode: one seed table per distinct seed length k (seed_k[c]):
+    // 2^seed_bits[c] buckets, bucket b = (key * 0x9E3779B1) >> (32 - bits)
+    // holding entries seed_ent[c][seed_dir[c][b] .. seed_dir[c][b + 1]),
+    // entry = (key, strand << 8 | offset). key = the seed's hi bits then lo
+    // bits, its masked centre (seed_mask bases) squeezed out.
+    const SeedInfo *seed_info;
+    uint32_t seed_ncfg;
+    uint32_t seed_mask;
+    uint32_t seed_k[kMaxSeedCfg];
+    uint32_t seed_bits[kMaxSeedCfg];
+    const uint32_t *seed_dir[kMaxSeedCfg];
+    const uint2 *seed_ent[kMaxSeedCfg];
     // count+digest sink, kStripes slots per query (see kStripes)
     unsigned long long *q_count;
     unsigned long long *q_digest;

@@ -26,12 +26,14 @@
 
 #include "../../include/ifa.h"
 #include "ifa_dev.h"
+#include "ifa_seed.h"
 
 namespace ifa {
 hipError_t launch_filter(const ScanArgs &a, hipStream_t s);
 hipError_t launch_resolve(const ScanArgs &a, hipStream_t s);
 hipError_t launch_dense(const ScanArgs &a, hipStream_t s);
 hipError_t launch_edge(const ScanArgs &a, hipStream_t s);
+hipError_t launch_seed(const ScanArgs &a, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
 hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s);
 uint32_t variant_count();
@@ -248,6 +250,13 @@ struct ifa_ctx {
     uint32_t mq3_words = 1;           // most prefix words of any three-class column tile
     uint32_t edge_pmin = 0;           // overhang kernel: pieces per wave (ScanArgs.edge_pmin)
     DevBuf<unsigned long long> d_qcount, d_qdigest;
+    // indexed mode: parameters, MinHits cache, the query set's seeds and
+    // their device tables
+    SeedParams seedp;
+    MinHitsCache mh_cache;
+    SeedBuild seeds;
+    DevBuf<SeedInfo> d_seed_info;
+    DevBuf<uint32_t> d_seed_dir[kMaxSeedCfg], d_seed_ent[kMaxSeedCfg];
 
     // streaming
     Staging stage[2];
@@ -466,6 +475,17 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.mq3_w = c->dq_mq3w;
     a.mq3_words = c->mq3_words;
     a.edge_pmin = c->edge_pmin;
+    if (c->cfg.flags & IFA_FLAG_INDEXED) {
+        a.seed_info = c->d_seed_info.p;
+        a.seed_ncfg = (uint32_t)c->seeds.cfg.size();
+        a.seed_mask = c->seedp.mask;
+        for (uint32_t i = 0; i < a.seed_ncfg; i++) {
+            a.seed_k[i] = c->seeds.cfg[i].k;
+            a.seed_bits[i] = c->seeds.cfg[i].bits;
+            a.seed_dir[i] = c->d_seed_dir[i].p;
+            a.seed_ent[i] = reinterpret_cast<const uint2 *>(c->d_seed_ent[i].p);
+        }
+    }
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
@@ -547,6 +567,14 @@ void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, Pa
                          : launch_clear_u64(a.hit_count + 1, 1, c->comp_s),
               "clear pass counters");
     hip_check(hipEventRecord(ev.t0, c->comp_s), "event record");
+    if (c->cfg.flags & IFA_FLAG_INDEXED) {
+        // indexed mode: seed lookups and their verification, one kernel
+        hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
+        if (dense) hip_check(launch_seed(a, c->comp_s), "seed launch");
+        hip_check(hipEventRecord(ev.te, c->comp_s), "event record");
+        hip_check(hipEventRecord(ev.t2, c->comp_s), "event record");
+        return;
+    }
     hip_check(launch_filter(a, c->comp_s), "filter launch");
     hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
     hip_check(launch_resolve(a, c->comp_s), "resolve launch");
@@ -1206,6 +1234,50 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     c->hits_sorted = true;
 }
 
+// Indexed mode: seeds of the query set just installed (c->h_qs, device
+// order) and their device tables.
+void install_seeds(ifa_ctx *c, uint32_t n, const uint32_t *len, const int32_t *max_subs,
+                   const uint8_t *const *seq, const int32_t *max_n)
+{
+    // the query set is unusable until its seed tables match it
+    c->have_queries = false;
+    // every query's forward strand, packed like the strands
+    std::vector<QSDesc> fq;
+    std::vector<uint32_t> fw, foff(n);
+    uint32_t lmax = 0;
+    pack_query_strands(1u, n, seq, len, max_subs, max_n, 0, fq, fw, lmax);
+    for (uint32_t j = 0; j < n; j++) foff[j] = fq[j].woff;
+    SeedBuild b;
+    build_seeds(c->seedp, n, len, max_subs, c->h_qs, c->h_qwords, fw, foff, c->threads,
+                c->mh_cache, b);
+    if (b.cfg.size() > kMaxSeedCfg) fail(IFA_E_INVALID, "more than 8 distinct seed lengths");
+    hip_check(hipStreamSynchronize(c->comp_s), "sync");
+    c->d_seed_info.alloc(std::max<size_t>(b.info.size(), 1), "seed info");
+    if (!b.info.empty())
+        hip_check(hipMemcpy(c->d_seed_info.p, b.info.data(), b.info.size() * sizeof(SeedInfo),
+                            hipMemcpyHostToDevice),
+                  "upload seed info");
+    for (size_t i = 0; i < kMaxSeedCfg; i++) {
+        if (i >= b.cfg.size()) {
+            c->d_seed_dir[i].release();
+            c->d_seed_ent[i].release();
+            continue;
+        }
+        const SeedBuild::Cfg &g = b.cfg[i];
+        c->d_seed_dir[i].alloc(g.dir.size(), "seed directory");
+        c->d_seed_ent[i].alloc(std::max<size_t>(g.ent.size(), 2), "seed entries");
+        hip_check(hipMemcpy(c->d_seed_dir[i].p, g.dir.data(), g.dir.size() * sizeof(uint32_t),
+                            hipMemcpyHostToDevice),
+                  "upload seed directory");
+        if (!g.ent.empty())
+            hip_check(hipMemcpy(c->d_seed_ent[i].p, g.ent.data(), g.ent.size() * sizeof(uint32_t),
+                                hipMemcpyHostToDevice),
+                      "upload seed entries");
+    }
+    c->seeds = std::move(b);
+    c->have_queries = true;
+}
+
 // Autotune cache key: device architecture, query-strand count band (log2),
 // longest query in words, threshold band. Tile choice depends on these.
 std::string tune_key(ifa_ctx *c)
@@ -1285,7 +1357,8 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
     if (cfg_in) cfg = *cfg_in; else ifa_config_default(&cfg);
     if (cfg.abi_version != IFA_ABI_VERSION || cfg.chunk_bases < 4096 ||
         cfg.chunk_bases > (1ull << 31) || (cfg.chunk_bases & 31) || cfg.strands < 1 ||
-        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || (cfg.flags & ~(IFA_FLAG_GRAPHS | IFA_FLAG_OVERHANG)) != 0)
+        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || (cfg.flags & ~(IFA_FLAG_GRAPHS | IFA_FLAG_OVERHANG | IFA_FLAG_INDEXED)) != 0 ||
+        ((cfg.flags & IFA_FLAG_INDEXED) && (cfg.flags & IFA_FLAG_OVERHANG)))
         return IFA_E_INVALID;
     ifa_ctx *c = new (std::nothrow) ifa_ctx();
     if (!c) return IFA_E_NOMEM;
@@ -1377,11 +1450,20 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
         if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
         validate_queries(n, seq, len, max_subs, max_n);
         use_device(c);
+        const bool indexed = (c->cfg.flags & IFA_FLAG_INDEXED) != 0;
+        if (indexed) {
+            if (2ull * n >= (1ull << 24)) fail(IFA_E_INVALID, "indexed mode takes < 2^23 queries");
+            for (uint32_t j = 0; j < n; j++)
+                if (len[j] <= c->seedp.mask)
+                    fail(IFA_E_INVALID, "query " + std::to_string(j) +
+                                            " is not longer than the seed mask");
+        }
         std::vector<QSDesc> qs;
         std::vector<uint32_t> words;
         uint32_t lmax = 0;
         pack_query_strands(c->cfg.strands, n, seq, len, max_subs, max_n, 0, qs, words, lmax);
         install_queries(c, std::move(qs), std::move(words), n, lmax);
+        if (indexed) install_seeds(c, n, len, max_subs, seq, max_n);
     });
 }
 
@@ -1737,9 +1819,63 @@ ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
     b += c->d_ctr.n * sizeof(unsigned long long);
     b += c->d_qarena.n;
     b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
+    b += c->d_seed_info.n * sizeof(SeedInfo);
+    for (size_t i = 0; i < kMaxSeedCfg; i++)
+        b += (c->d_seed_dir[i].n + c->d_seed_ent[i].n) * sizeof(uint32_t);
     for (const auto &r : c->resident)
         b += r->planes.n * sizeof(uint32_t) + r->pieces.n * sizeof(Piece);
     *bytes = b;
+    return IFA_OK;
+}
+
+void ifa_index_params_default(ifa_index_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    const uint32_t ks[] = {8, 9, 10, 12, 14};
+    p->n_k = 5;
+    for (uint32_t i = 0; i < 5; i++) p->k[i] = ks[i];
+    p->mask = 0;
+    p->step = 1;
+    p->prob_ppm = 999000;
+    p->iters = 200000;
+    p->seed = 1;
+}
+
+ifa_status ifa_set_index_params(ifa_ctx *c, const ifa_index_params *p)
+{
+    if (!c || !p) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (!(c->cfg.flags & IFA_FLAG_INDEXED)) fail(IFA_E_INVALID, "not an indexed context");
+        if (p->n_k < 1 || p->n_k > IFA_MAX_SEED_KS || p->step < 1 || p->prob_ppm > 1000000u ||
+            p->iters < 1 || p->iters > (1ull << 31) || p->reserved != 0)
+            fail(IFA_E_INVALID, "bad index parameters");
+        for (uint32_t i = 0; i < p->n_k; i++)
+            if (p->k[i] <= p->mask || p->k[i] > 16) fail(IFA_E_INVALID, "seed length out of range");
+        SeedParams q;
+        q.n_k = p->n_k;
+        for (uint32_t i = 0; i < p->n_k; i++) q.k[i] = p->k[i];
+        q.mask = p->mask;
+        q.step = p->step;
+        q.ppm = p->prob_ppm;
+        q.iters = p->iters;
+        q.seed = p->seed;
+        const bool same = q.mask == c->seedp.mask && q.step == c->seedp.step &&
+                          q.ppm == c->seedp.ppm && q.iters == c->seedp.iters &&
+                          q.seed == c->seedp.seed;
+        if (!same) c->mh_cache.clear();
+        c->seedp = q;
+    });
+}
+
+ifa_status ifa_query_seeds(const ifa_ctx *c, uint32_t *k, uint32_t *thr)
+{
+    if (!c) return IFA_E_INVALID;
+    if (!(c->cfg.flags & IFA_FLAG_INDEXED) || !c->have_queries) return IFA_E_STATE;
+    if (k)
+        for (uint32_t j = 0; j < c->n_queries; j++) k[j] = c->seeds.qk[j];
+    if (thr)
+        for (size_t j = 0; j < 2 * (size_t)c->n_queries; j++) thr[j] = c->seeds.qthr[j];
     return IFA_OK;
 }
 
@@ -1908,6 +2044,7 @@ ifa_status ifa_server_create(ifa_ctx *c, const ifa_server_config *cfg_in, ifa_se
     return guarded(c, [&]() {
         if (c->resident.empty()) fail(IFA_E_STATE, "no resident reference: call ifa_ref_load");
         if (c->cfg.sink != IFA_SINK_RECORDS) fail(IFA_E_STATE, "serving needs the records sink");
+        if (c->cfg.flags & IFA_FLAG_INDEXED) fail(IFA_E_STATE, "serving runs brute-force mode");
         if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
         ifa_server_config cfg;
         if (cfg_in) cfg = *cfg_in; else ifa_server_config_default(&cfg);

@@ -1148,6 +1148,132 @@ __global__ __launch_bounds__(256) void scan_edge_kernel(ScanArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// indexed mode
+// ---------------------------------------------------------------------------
+
+// Bits [lo, lo + mask) squeezed out of x (the masked centre of a seed).
+__device__ __forceinline__ uint32_t squeeze_mask(uint32_t x, uint32_t lo, uint32_t mask)
+{
+    return (x & low_mask(lo)) | ((x >> (lo + mask)) << lo);
+}
+
+// Equality bits of query word t of strand d against the window at chunk
+// position 32 w + b: 1 where both bases are A/C/G/T and equal (0 past L).
+__device__ __forceinline__ uint32_t eq_word(const ScanArgs &a, const QS &d,
+                                            const IFA_CONST uint32_t *qw, uint32_t w, uint32_t b,
+                                            uint32_t t)
+{
+    if (t >= d.nw) return 0u;
+    const uint32_t x = w + t;
+    const uint32_t rh = funnel(a.hi[x + 1], a.hi[x], b);
+    const uint32_t rl = funnel(a.lo[x + 1], a.lo[x], b);
+    const uint32_t rn = funnel(a.nm[x + 1], a.nm[x], b);
+    const uint32_t diff = (qw[3 * t] ^ rh) | (qw[3 * t + 1] ^ rl) | qw[3 * t + 2] | rn;
+    return ~diff & low_mask(d.len - 32u * t);
+}
+
+// A seed of strand q at offset i matched the reference at chunk position r:
+// test window p = r - i. It is reported when it is a hit (every query word,
+// the N rule, piece ends, chunk ownership), holds at least the strand's
+// threshold of error-free seeds, and i is its first error-free seed, so that
+// each window is reported by exactly one of its seeds.
+__device__ void seed_verify(const ScanArgs &a, uint32_t q, uint32_t i, uint64_t r, uint32_t stripe)
+{
+    if (r < i) return;
+    const uint64_t p = r - i;
+    const QS d = load_qs(a, q);
+    const uint32_t L = d.len;
+    if (p + L > a.chunk_len || p + L - 1 < (uint64_t)a.own_from) return;
+    const IFA_CONST uint32_t *qw = as_const(a.qwords) + d.woff;
+    const uint32_t w = (uint32_t)(p >> 5), b = (uint32_t)(p & 31u);
+    uint32_t m = 0, nref = 0, ends = 0;
+    for (uint32_t t = 0; t < d.nw; t++) {
+        const uint32_t i0 = 32u * t;
+        const uint32_t lmask = low_mask(L - i0);
+        const uint32_t emask = (L - 1 > i0) ? low_mask(L - 1 - i0) : 0u;
+        const uint32_t x = w + t;
+        const uint32_t rh = funnel(a.hi[x + 1], a.hi[x], b);
+        const uint32_t rl = funnel(a.lo[x + 1], a.lo[x], b);
+        const uint32_t rn = funnel(a.nm[x + 1], a.nm[x], b);
+        const uint32_t re = funnel(a.em[x + 1], a.em[x], b);
+        const uint32_t diff = (qw[3 * t] ^ rh) | (qw[3 * t + 1] ^ rl) | qw[3 * t + 2];
+        ends |= re & emask;
+        if (a.policy == kNSeparate)
+            m += __popc(diff & ~rn & lmask);
+        else
+            m += __popc((diff | rn) & lmask);
+        nref += __popc(rn & lmask);
+    }
+    if (ends || m > d.k || (a.policy == kNSeparate && nref > d.maxn)) return;
+    // error-free seeds, in offset order; a seed spans at most two words
+    const SeedInfo *si = a.seed_info + q;
+    const uint32_t k = si->k, thr = si->thr;
+    const uint32_t lo = (k - a.seed_mask) / 2;
+    const uint32_t unm = low_mask(lo) | (low_mask(k) & ~low_mask(lo + a.seed_mask));
+    uint32_t cnt = 0;
+    uint32_t cur = eq_word(a, d, qw, w, b, 0);
+    for (uint32_t t = 0; t < d.nw && cnt < thr; t++) {
+        const uint32_t nxt = eq_word(a, d, qw, w, b, t + 1);
+        uint32_t v = si->valid[t];
+        while (v && cnt < thr) {
+            const uint32_t o = __builtin_ctz(v);
+            v &= v - 1u;
+            if ((funnel(nxt, cur, o) & unm) != unm) continue;
+            if (32u * t + o < i) return;   // an earlier seed reports this window
+            cnt++;
+        }
+        cur = nxt;
+    }
+    if (cnt < thr) return;
+    const Piece pc = a.pieces[find_piece(a, p)];
+    const uint32_t pos = (uint32_t)(pc.contig_off + (p - pc.start));
+    if (a.sink == kSinkRecords) {
+        write_record(a, atomicAdd(a.hit_count, 1ull), d, pc.contig, pos, m, nref);
+    } else {
+        const uint32_t slot = d.qid * kStripes + stripe % kStripes;
+        atomicAdd(&a.q_count[slot], 1ull);
+        atomicAdd(&a.q_digest[slot], (unsigned long long)hit_hash(pc.contig, pos, d.strand, m, nref));
+    }
+}
+
+// Indexed mode (Methods, "Algorithm Design"): every lane takes the 32 seed
+// starts of a plane word of the range, forms the seed key of each start for
+// every seed length of the query set (no key where an unmasked base is N),
+// and looks it up in that length's bucketed table of query seeds; each
+// matching (strand, offset) entry names one window to verify.
+__global__ __launch_bounds__(256) void scan_seed_kernel(ScanArgs a)
+{
+    const uint32_t lanes = gridDim.x * blockDim.x;
+    for (uint32_t w = a.w_begin + blockIdx.x * blockDim.x + threadIdx.x; w < a.w_end; w += lanes) {
+        const uint32_t h0 = a.hi[w], h1 = a.hi[w + 1], l0 = a.lo[w], l1 = a.lo[w + 1];
+        const uint32_t n0 = a.nm[w], n1 = a.nm[w + 1];
+#pragma unroll 1
+        for (uint32_t c = 0; c < a.seed_ncfg; c++) {
+            const uint32_t k = a.seed_k[c], bits = a.seed_bits[c];
+            const uint32_t lo = (k - a.seed_mask) / 2, u = k - a.seed_mask;
+            const uint32_t km = low_mask(k);
+            const uint32_t unm = low_mask(lo) | (km & ~low_mask(lo + a.seed_mask));
+            const uint32_t *dir = a.seed_dir[c];
+            const uint2 *ent = a.seed_ent[c];
+#pragma unroll 1
+            for (uint32_t b = 0; b < 32u; b++) {
+                const uint64_t r = 32ull * w + b;
+                if (r + k > a.chunk_len) break;
+                if (funnel(n1, n0, b) & unm) continue;
+                const uint32_t key = (squeeze_mask(funnel(h1, h0, b) & km, lo, a.seed_mask) << u) |
+                                     squeeze_mask(funnel(l1, l0, b) & km, lo, a.seed_mask);
+                const uint32_t bk = (key * 0x9E3779B1u) >> (32u - bits);
+                const uint32_t e1 = dir[bk + 1];
+                for (uint32_t e = dir[bk]; e < e1; e++) {
+                    const uint2 en = ent[e];
+                    if (en.x == key) seed_verify(a, en.y >> 8, en.y & 255u, r, w);
+                }
+            }
+        }
+    }
+}
+
 // Clears counters on the stream (a kernel, so the launch sequence can be
 // captured in a graph).
 __global__ void clear_u64_kernel(unsigned long long *p, uint32_t n)
@@ -1304,6 +1430,16 @@ hipError_t launch_edge(const ScanArgs &a, hipStream_t s)
     const uint64_t tasks = (uint64_t)((a.n_pieces + a.edge_pmin - 1) / a.edge_pmin) * a.n_qs;
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((tasks + 3) / 4, 4096);
     hipLaunchKernelGGL(scan_edge_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Indexed mode: seed starts of the word range, grid-stride.
+hipError_t launch_seed(const ScanArgs &a, hipStream_t s)
+{
+    if (a.w_end <= a.w_begin || a.seed_ncfg == 0) return hipSuccess;
+    const uint32_t words = a.w_end - a.w_begin;
+    const uint32_t blocks = std::min<uint32_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(scan_seed_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,50 @@
+// ifa_seed.h -- indexed mode, host side (see ifa_seed.cpp).
+#pragma once
+#include <cstdint>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "ifa_dev.h"
+
+namespace ifa {
+
+struct SeedParams {
+    uint32_t n_k = 5;                                     // the paper's default lengths
+    uint32_t k[kMaxSeedCfg] = {8, 9, 10, 12, 14, 0, 0, 0};
+    uint32_t mask = 0;
+    uint32_t step = 1;
+    uint32_t ppm = 999000;
+    uint64_t iters = 200000;
+    uint64_t seed = 1;
+};
+
+// MinHits results by (valid seeds, maxSubs, k) for the current parameters.
+using MinHitsCache = std::map<std::tuple<uint32_t, uint32_t, uint32_t>, int64_t>;
+
+struct SeedBuild {
+    std::vector<SeedInfo> info;      // per query strand, in device order
+    std::vector<uint32_t> qk;        // per query: seed length
+    std::vector<uint32_t> qthr;      // per query and strand: threshold (0: not scanned)
+    struct Cfg {
+        uint32_t k = 0, bits = 0;
+        std::vector<uint32_t> dir;   // 2^bits + 1 bucket starts
+        std::vector<uint32_t> ent;   // (key, strand << 8 | offset) pairs
+    };
+    std::vector<Cfg> cfg;
+};
+
+uint32_t seed_keff(uint32_t k, uint32_t mask, uint32_t step);
+int64_t seed_minhits(uint32_t V, uint32_t subs, uint32_t k, uint32_t mask, uint32_t step,
+                     uint64_t iters, uint64_t seed, uint32_t ppm);
+
+// qs/words: the context's query strands (device order) and their packed
+// words; fwd_words/fwd_off: every query's forward strand packed the same way
+// (words of query j start at fwd_off[j]).
+void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
+                 const int32_t *max_subs, const std::vector<QSDesc> &qs,
+                 const std::vector<uint32_t> &words, const std::vector<uint32_t> &fwd_words,
+                 const std::vector<uint32_t> &fwd_off, unsigned threads, MinHitsCache &cache,
+                 SeedBuild &out);
+
+}  // namespace ifa

@@ -58,9 +58,12 @@ def test_null_and_bad_arguments_are_rejected_without_a_device():
     cfg.abi_version = 99
     assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
     cfg = ifa.ifa_config_default()
-    cfg.flags = 4                                             # no such flag
+    cfg.flags = 8                                             # no such flag
     assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
-    assert ifa.IFA_FLAG_GRAPHS == 1 and ifa.IFA_FLAG_OVERHANG == 2
+    cfg.flags = ifa.IFA_FLAG_INDEXED | ifa.IFA_FLAG_OVERHANG  # not combined
+    assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
+    assert (ifa.IFA_FLAG_GRAPHS, ifa.IFA_FLAG_OVERHANG, ifa.IFA_FLAG_INDEXED) == (1, 2, 4)
+    assert L.ifa_set_index_params(None, None) == 1
     L.ifa_destroy(None)                                       # NULL-safe
     assert L.ifa_load_queries(None, 0, None, None, None, None) == 1
     assert L.ifa_scan_chunk(None, 0, None, None, None) == 1
@@ -71,3 +74,13 @@ def test_binding_names_mirror_the_c_entry_points():
     import paper_2607_27291_amd as ifa
     for name in declared_functions():
         assert hasattr(ifa, name), name
+
+
+def test_index_params_defaults_are_the_papers():
+    """Candidate seed lengths 8, 9, 10, 12, 14; 200,000 Monte Carlo trials;
+    99.9 % probability (Methods, "Algorithm Design")."""
+    import paper_2607_27291_amd as ifa
+    p = ifa.ifa_index_params_default()
+    assert list(p.k)[:p.n_k] == [8, 9, 10, 12, 14]
+    assert (p.iters, p.prob_ppm, p.mask, p.step) == (200_000, 999_000, 0, 1)
+    assert ctypes.sizeof(ifa.IfaIndexParams) == 72
