@@ -236,10 +236,9 @@ def indexed_params(queries, max_subs, *, ks=SEED_KS, mask=0, step=1, iters=200_0
         rc = [4 if x == 4 else 3 - x for x in reversed(c)]
         L = len(c)
         s = min(int(s), L)
-        cand = sorted((k for k in ks if k <= L and k > mask), reverse=True)
-        if not cand:
-            k = L if L > mask else L
-            cand = [k]
+        if L <= mask:
+            raise ValueError("a query must be longer than the seed mask")
+        cand = sorted((k for k in ks if k <= L and k > mask), reverse=True) or [L]
         k = next((k for k in cand if mh(_valid_seeds(c, k, mask, step), s, k) >= 1), cand[-1])
         out_k.append(k)
         out_thr.append([max(1, mh(_valid_seeds(x, k, mask, step), s, k)) for x in (c, rc)])
