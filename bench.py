@@ -19,6 +19,11 @@ Other workloads (--workload):
       queries (log-uniform), L 18-150, maxSubs 0-L/4, against 16 Gbp
       resident; continuous batching versus serial first-in-first-out scans
       over the same trace, plus a run at 70% of the measured capacity.
+  idx indexed mode: 100,000 reads of 150 bp cut from a 4 Gbp resident
+      reference with exactly s substitutions, maxSubs s, for s in 0, 4, 8,
+      16 (one query set each; seed tables built on the host, seed lookup
+      and verification on the GPU); reports per-level time and the recall
+      of the reads' origins.
 
 Prints one JSON line. `value` is Gbp*query/s (reference bases x queries,
 both strands inside one unit) over the timed steps, wall clock.
@@ -29,6 +34,8 @@ import os
 import sys
 import threading
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -59,7 +66,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "idx"])
+    ap.add_argument("--subs", default="0,4,8,16",
+                    help="idx: substitutions per read = maxSubs, one query set each")
+    ap.add_argument("--read-len", type=int, default=150, help="idx: read length")
     ap.add_argument("--requests", type=int, default=50, help="c5: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="c5: Poisson arrivals per second")
     ap.add_argument("--chunk-bases", type=int, default=1 << 28, help="c5: resident chunk size")
@@ -603,6 +613,69 @@ def run_c5(args):
     return out
 
 
+# --------------------------------------------------------------------------
+# idx: indexed mode, reads cut from the reference (the paper's substitution
+# sweep of indexed mode: 100,000 reads of 150 bp, maxSubs 0..16, 4 Gbp)
+# --------------------------------------------------------------------------
+
+def run_idx(args):
+    import synth
+    import paper_2607_27291_amd as ifa
+
+    total = args.total or 4_000_000_000
+    n = args.queries or 100_000
+    L = args.read_len
+    levels = [int(x) for x in args.subs.split(",")]
+    t0 = time.time()
+    ref = synth.gen_reference(synth.c2_spec(seed=6, total=total))
+    log(f"generated {ref.total / 1e9:.2f} Gbp in {ref.n_contigs} contigs ({time.time() - t0:.1f} s)")
+    s = ifa.Scanner(device=0, flags=ifa.IFA_FLAG_INDEXED)
+    s.ref_load(ref)
+    bases, chunks = ifa.ifa_ref_info(s.ctx)
+    per_level = []
+    load_s = scan_s = 0.0
+    for subs in levels:
+        reads, origin = synth.sample_reads(ref, n, L, subs, seed=6)
+        device_sync()
+        t0 = time.perf_counter()
+        s.load_queries(reads, [subs] * n)
+        t1 = time.perf_counter()
+        ifa.ifa_reset_stats(s.ctx)
+        s.scan_resident()
+        hits = s.collect()
+        device_sync()
+        t2 = time.perf_counter()
+        st = ifa.ifa_get_stats(s.ctx)
+        k, thr = ifa.ifa_query_seeds(s.ctx, n)
+        found = set(zip(hits["query"].tolist(), hits["contig"].tolist(), hits["pos"].tolist(),
+                        hits["strand"].tolist()))
+        recall = sum((j, int(c), int(p), int(st_)) in found
+                     for j, (c, p, st_) in enumerate(origin.tolist())) / n
+        load_s += t1 - t0
+        scan_s += t2 - t1
+        per_level.append({"max_subs": subs, "load_s": round(t1 - t0, 3),
+                          "scan_s": round(t2 - t1, 3), "kernel_ms": round(st["kernel_ms"], 2),
+                          "hits": int(len(hits)), "recall": round(recall, 5),
+                          "seed_k": sorted(set(int(x) for x in k)),
+                          "thr_median": int(np.median(thr[:, 0]))})
+        log(f"maxSubs {subs}: load {t1 - t0:.2f} s, scan {t2 - t1:.3f} s, "
+            f"kernel {st['kernel_ms']:.1f} ms, {len(hits)} hits, recall {recall:.4f}")
+    s.close()
+    bpq = bases * n * len(levels)
+    out = base_record(args, bpq / (load_s + scan_s) / 1e9, (load_s + scan_s) * 1e3 / len(levels), {
+        "workload": f"indexed mode: {n} reads of {L} bp cut from {bases / 1e9:.2f} Gbp resident, "
+                    f"exactly s substitutions with maxSubs s, s in {levels} (one query set each)",
+        "reference_bases": bases,
+        "queries": n,
+        "device_chunks": chunks,
+    })
+    out["steps"] = len(levels)
+    out["warmup"] = 0
+    out["scan_only_gbpq_s"] = round(bpq / scan_s / 1e9, 3)
+    out["levels"] = per_level
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -623,6 +696,8 @@ def main():
         out = run_c3(args)
     elif args.workload == "c4":
         out = run_c4(args)
+    elif args.workload == "idx":
+        out = run_idx(args)
     else:
         out = run_c5(args)
     print(json.dumps(out), flush=True)

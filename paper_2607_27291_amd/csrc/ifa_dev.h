@@ -73,6 +73,18 @@ struct SeedInfo {
 };
 static_assert(sizeof(SeedInfo) == 48, "SeedInfo layout");
 
+// Indexed mode: one seed table per distinct seed length k of the query set:
+// 2^bits buckets, bucket b = (key * 0x9E3779B1) >> (32 - bits) holding the
+// entries ent[dir[b] .. dir[b + 1]), entry = (key, strand << 8 | offset).
+// key = the seed's hi bits then lo bits, its masked centre squeezed out.
+struct SeedTable {
+    uint32_t k;
+    uint32_t bits;
+    const uint32_t *dir;
+    const uint2 *ent;
+};
+static_assert(sizeof(SeedTable) == 24, "SeedTable layout");
+
 // Work item of the sparse path: wave `wave` of the filter grid has at least
 // one candidate window for the query strands qb + j, j a set bit of `pending`.
 struct WorkItem {
@@ -127,18 +139,12 @@ struct ScanArgs {
     // overhang kernel: pieces per wave for the strand with the widest clip
     // (64 / (2 C) lanes each, at least 1); 0 = no strand can overhang
     uint32_t edge_pmin;
-    // indexed mode: one seed table per distinct seed length k (seed_k[c]):
-    // 2^seed_bits[c] buckets, bucket b = (key * 0x9E3779B1) >> (32 - bits)
-    // holding entries seed_ent[c][seed_dir[c][b] .. seed_dir[c][b + 1]),
-    // entry = (key, strand << 8 | offset). key = the seed's hi bits then lo
-    // bits, its masked centre (seed_mask bases) squeezed out.
+    // indexed mode: per-strand seed data, seed_ncfg tables (in device
+    // memory), the masked centre length of every seed
     const SeedInfo *seed_info;
+    const SeedTable *seed_tab;
     uint32_t seed_ncfg;
     uint32_t seed_mask;
-    uint32_t seed_k[kMaxSeedCfg];
-    uint32_t seed_bits[kMaxSeedCfg];
-    const uint32_t *seed_dir[kMaxSeedCfg];
-    const uint2 *seed_ent[kMaxSeedCfg];
     // count+digest sink, kStripes slots per query (see kStripes)
     unsigned long long *q_count;
     unsigned long long *q_digest;

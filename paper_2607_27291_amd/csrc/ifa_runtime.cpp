@@ -257,6 +257,7 @@ struct ifa_ctx {
     SeedBuild seeds;
     DevBuf<SeedInfo> d_seed_info;
     DevBuf<uint32_t> d_seed_dir[kMaxSeedCfg], d_seed_ent[kMaxSeedCfg];
+    DevBuf<SeedTable> d_seed_tab;     // [kMaxSeedCfg]
 
     // streaming
     Staging stage[2];
@@ -477,14 +478,9 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.edge_pmin = c->edge_pmin;
     if (c->cfg.flags & IFA_FLAG_INDEXED) {
         a.seed_info = c->d_seed_info.p;
+        a.seed_tab = c->d_seed_tab.p;
         a.seed_ncfg = (uint32_t)c->seeds.cfg.size();
         a.seed_mask = c->seedp.mask;
-        for (uint32_t i = 0; i < a.seed_ncfg; i++) {
-            a.seed_k[i] = c->seeds.cfg[i].k;
-            a.seed_bits[i] = c->seeds.cfg[i].bits;
-            a.seed_dir[i] = c->d_seed_dir[i].p;
-            a.seed_ent[i] = reinterpret_cast<const uint2 *>(c->d_seed_ent[i].p);
-        }
     }
     a.pieces = ch.pieces.p;
     a.n_pieces = ch.n_pieces;
@@ -527,9 +523,12 @@ void copy_records(ifa_ctx *c, int hb, uint64_t n)
     if (n == 0) return;
     size_t old = c->hits.size();
     c->hits.resize(old + n);
-    hip_check(hipMemcpy(c->hits.data() + old, c->d_hits[hb].p, n * sizeof(ifa_hit),
-                        hipMemcpyDeviceToHost),
+    // ordered after the pass on its own stream: a copy on another stream may
+    // read records a graph-launched kernel has not yet written back
+    hip_check(hipMemcpyAsync(c->hits.data() + old, c->d_hits[hb].p, n * sizeof(ifa_hit),
+                             hipMemcpyDeviceToHost, c->comp_s),
               "copy hit records");
+    hip_check(hipStreamSynchronize(c->comp_s), "sync record copy");
     c->hits_sorted = false;
     c->st.hits += n;
 }
@@ -745,11 +744,13 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     ev.t1 = j.kf;
     ev.te = j.ke;
     ev.t2 = j.k1;
+    // the pass and its counter copy (what a graph holds); the events the host
+    // waits on are recorded on the stream after it, never inside a graph: a
+    // host wait on an event recorded by a graph node has returned before a
+    // replay finished
     auto enqueue = [&]() {
         enqueue_pass(c, a, true, true, ev);
-        hip_check(hipEventRecord(ch->free_ev, c->comp_s), "event record");
         enqueue_count_copies(c, j.hitbuf);
-        hip_check(hipEventRecord(j.done, c->comp_s), "event record");
     };
     PassGraph *pg = nullptr;
     if ((c->cfg.flags & IFA_FLAG_GRAPHS) && ch->resident) {
@@ -778,6 +779,8 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     } else {
         enqueue();
     }
+    hip_check(hipEventRecord(ch->free_ev, c->comp_s), "event record");
+    hip_check(hipEventRecord(j.done, c->comp_s), "event record");
     j.active = true;
     c->job_seq++;
     c->st.chunks++;
@@ -1251,29 +1254,45 @@ void install_seeds(ifa_ctx *c, uint32_t n, const uint32_t *len, const int32_t *m
     build_seeds(c->seedp, n, len, max_subs, c->h_qs, c->h_qwords, fw, foff, c->threads,
                 c->mh_cache, b);
     if (b.cfg.size() > kMaxSeedCfg) fail(IFA_E_INVALID, "more than 8 distinct seed lengths");
+    // uploads are ordered on the compute stream (the stream does not wait for
+    // the null stream) and complete before the host tables are released
     hip_check(hipStreamSynchronize(c->comp_s), "sync");
-    c->d_seed_info.alloc(std::max<size_t>(b.info.size(), 1), "seed info");
+    // buffers grow only, so repeated query sets of the same shape keep their
+    // device addresses (and their captured pass graphs)
+    if (c->d_seed_info.n < std::max<size_t>(b.info.size(), 1))
+        c->d_seed_info.alloc(std::max<size_t>(b.info.size(), 1), "seed info");
     if (!b.info.empty())
-        hip_check(hipMemcpy(c->d_seed_info.p, b.info.data(), b.info.size() * sizeof(SeedInfo),
-                            hipMemcpyHostToDevice),
+        hip_check(hipMemcpyAsync(c->d_seed_info.p, b.info.data(),
+                                 b.info.size() * sizeof(SeedInfo), hipMemcpyHostToDevice,
+                                 c->comp_s),
                   "upload seed info");
     for (size_t i = 0; i < kMaxSeedCfg; i++) {
-        if (i >= b.cfg.size()) {
-            c->d_seed_dir[i].release();
-            c->d_seed_ent[i].release();
-            continue;
-        }
+        if (i >= b.cfg.size()) continue;
         const SeedBuild::Cfg &g = b.cfg[i];
-        c->d_seed_dir[i].alloc(g.dir.size(), "seed directory");
-        c->d_seed_ent[i].alloc(std::max<size_t>(g.ent.size(), 2), "seed entries");
-        hip_check(hipMemcpy(c->d_seed_dir[i].p, g.dir.data(), g.dir.size() * sizeof(uint32_t),
-                            hipMemcpyHostToDevice),
+        if (c->d_seed_dir[i].n < g.dir.size()) c->d_seed_dir[i].alloc(g.dir.size(), "seed directory");
+        if (c->d_seed_ent[i].n < std::max<size_t>(g.ent.size(), 2))
+            c->d_seed_ent[i].alloc(std::max<size_t>(g.ent.size(), 2), "seed entries");
+        hip_check(hipMemcpyAsync(c->d_seed_dir[i].p, g.dir.data(),
+                                 g.dir.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                 c->comp_s),
                   "upload seed directory");
         if (!g.ent.empty())
-            hip_check(hipMemcpy(c->d_seed_ent[i].p, g.ent.data(), g.ent.size() * sizeof(uint32_t),
-                                hipMemcpyHostToDevice),
+            hip_check(hipMemcpyAsync(c->d_seed_ent[i].p, g.ent.data(),
+                                     g.ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                     c->comp_s),
                       "upload seed entries");
     }
+    SeedTable tab[kMaxSeedCfg] = {};
+    for (size_t i = 0; i < b.cfg.size(); i++) {
+        tab[i].k = b.cfg[i].k;
+        tab[i].bits = b.cfg[i].bits;
+        tab[i].dir = c->d_seed_dir[i].p;
+        tab[i].ent = reinterpret_cast<const uint2 *>(c->d_seed_ent[i].p);
+    }
+    if (!c->d_seed_tab.p) c->d_seed_tab.alloc(kMaxSeedCfg, "seed table descriptors");
+    hip_check(hipMemcpyAsync(c->d_seed_tab.p, tab, sizeof tab, hipMemcpyHostToDevice, c->comp_s),
+              "upload seed table descriptors");
+    hip_check(hipStreamSynchronize(c->comp_s), "sync seed uploads");
     c->seeds = std::move(b);
     c->have_queries = true;
 }
@@ -1533,9 +1552,10 @@ ifa_status ifa_query_stats(ifa_ctx *c, uint64_t *count, uint64_t *digest)
         const size_t n = (size_t)c->n_queries * kStripes;
         std::vector<uint64_t> buf(n ? n : 1);
         if (count) {
-            hip_check(hipMemcpy(buf.data(), c->d_qcount.p, n * sizeof(uint64_t),
-                                hipMemcpyDeviceToHost),
+            hip_check(hipMemcpyAsync(buf.data(), c->d_qcount.p, n * sizeof(uint64_t),
+                                     hipMemcpyDeviceToHost, c->comp_s),
                       "copy counts");
+            hip_check(hipStreamSynchronize(c->comp_s), "sync count copy");
             for (uint32_t q = 0; q < c->n_queries; q++) {
                 uint64_t acc = 0;
                 for (uint32_t k = 0; k < kStripes; k++) acc += buf[(size_t)q * kStripes + k];
@@ -1543,9 +1563,10 @@ ifa_status ifa_query_stats(ifa_ctx *c, uint64_t *count, uint64_t *digest)
             }
         }
         if (digest) {
-            hip_check(hipMemcpy(buf.data(), c->d_qdigest.p, n * sizeof(uint64_t),
-                                hipMemcpyDeviceToHost),
+            hip_check(hipMemcpyAsync(buf.data(), c->d_qdigest.p, n * sizeof(uint64_t),
+                                     hipMemcpyDeviceToHost, c->comp_s),
                       "copy digests");
+            hip_check(hipStreamSynchronize(c->comp_s), "sync digest copy");
             for (uint32_t q = 0; q < c->n_queries; q++) {
                 uint64_t acc = 0;
                 for (uint32_t k = 0; k < kStripes; k++) acc += buf[(size_t)q * kStripes + k];
@@ -1722,12 +1743,14 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
             N[w] = 0xffffffffu;
             E[w] = 0xffffffffu;
         }
-        hip_check(hipMemcpy(ch.planes.p, host.data(), host.size() * sizeof(uint32_t),
-                            hipMemcpyHostToDevice),
+        hip_check(hipMemcpyAsync(ch.planes.p, host.data(), host.size() * sizeof(uint32_t),
+                                 hipMemcpyHostToDevice, c->comp_s),
                   "upload calibration chunk");
         Piece pc{};
         pc.len = calib_bases;
-        hip_check(hipMemcpy(ch.pieces.p, &pc, sizeof pc, hipMemcpyHostToDevice), "upload piece");
+        hip_check(hipMemcpyAsync(ch.pieces.p, &pc, sizeof pc, hipMemcpyHostToDevice, c->comp_s),
+                  "upload piece");
+        hip_check(hipStreamSynchronize(c->comp_s), "sync calibration upload");
         ch.len = calib_bases;
         ch.n_pieces = 1;
         // hits go to the context's kind of sink in scratch memory (a small
@@ -1819,7 +1842,7 @@ ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
     b += c->d_ctr.n * sizeof(unsigned long long);
     b += c->d_qarena.n;
     b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
-    b += c->d_seed_info.n * sizeof(SeedInfo);
+    b += c->d_seed_info.n * sizeof(SeedInfo) + c->d_seed_tab.n * sizeof(SeedTable);
     for (size_t i = 0; i < kMaxSeedCfg; i++)
         b += (c->d_seed_dir[i].n + c->d_seed_ent[i].n) * sizeof(uint32_t);
     for (const auto &r : c->resident)

@@ -1250,12 +1250,13 @@ __global__ __launch_bounds__(256) void scan_seed_kernel(ScanArgs a)
         const uint32_t n0 = a.nm[w], n1 = a.nm[w + 1];
 #pragma unroll 1
         for (uint32_t c = 0; c < a.seed_ncfg; c++) {
-            const uint32_t k = a.seed_k[c], bits = a.seed_bits[c];
+            const SeedTable tab = a.seed_tab[c];
+            const uint32_t k = tab.k, bits = tab.bits;
             const uint32_t lo = (k - a.seed_mask) / 2, u = k - a.seed_mask;
             const uint32_t km = low_mask(k);
             const uint32_t unm = low_mask(lo) | (km & ~low_mask(lo + a.seed_mask));
-            const uint32_t *dir = a.seed_dir[c];
-            const uint2 *ent = a.seed_ent[c];
+            const uint32_t *dir = tab.dir;
+            const uint2 *ent = tab.ent;
 #pragma unroll 1
             for (uint32_t b = 0; b < 32u; b++) {
                 const uint64_t r = 32ull * w + b;

@@ -12,7 +12,6 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
-#include <mutex>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -104,12 +103,13 @@ int64_t seed_minhits(uint32_t V, uint32_t subs, uint32_t k, uint32_t mask, uint3
 
 namespace {
 
-// bits [i, i + n) of a little-endian bit string held in 32-bit words
-inline uint32_t bits_at(const uint32_t *w, uint32_t nwords, uint32_t i, uint32_t n)
+// bits [i, i + n) (n <= 32) of plane `pl` of a strand packed as 32-bit
+// words (hi, lo, qn) x nw
+inline uint32_t bits_at(const uint32_t *w3, uint32_t nw, uint32_t pl, uint32_t i, uint32_t n)
 {
     const uint32_t a = i >> 5, sh = i & 31u;
-    uint64_t v = w[a];
-    if (a + 1 < nwords) v |= (uint64_t)w[a + 1] << 32;
+    uint64_t v = w3[3 * a + pl];
+    if (a + 1 < nw) v |= (uint64_t)w3[3 * (a + 1) + pl] << 32;
     v >>= sh;
     return n >= 32 ? (uint32_t)v : (uint32_t)v & ((1u << n) - 1u);
 }
@@ -125,15 +125,10 @@ inline uint32_t squeeze(uint32_t x, uint32_t k, uint32_t mask)
 bool strand_seed(const uint32_t *w3, uint32_t nw, uint32_t i, uint32_t k, uint32_t mask,
                  uint32_t *key)
 {
-    uint32_t h[kMaxQWords], l[kMaxQWords], q[kMaxQWords];
-    for (uint32_t t = 0; t < nw; t++) {
-        h[t] = w3[3 * t];
-        l[t] = w3[3 * t + 1];
-        q[t] = w3[3 * t + 2];
-    }
-    if (squeeze(bits_at(q, nw, i, k), k, mask) != 0u) return false;
+    if (squeeze(bits_at(w3, nw, 2, i, k), k, mask) != 0u) return false;
     const uint32_t u = k - mask;
-    *key = (squeeze(bits_at(h, nw, i, k), k, mask) << u) | squeeze(bits_at(l, nw, i, k), k, mask);
+    *key = (squeeze(bits_at(w3, nw, 0, i, k), k, mask) << u) |
+           squeeze(bits_at(w3, nw, 1, i, k), k, mask);
     return true;
 }
 
@@ -205,16 +200,20 @@ void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
         const uint32_t nw = (qlen[j] + 31) / 32;
         return count_seeds(fwd_words.data() + fwd_off[j], nw, qlen[j], k, P.mask, P.step);
     };
+    std::vector<uint32_t> vcur(n_queries);   // forward seeds at the current try
     for (;;) {
         std::vector<Tuple> want;
         for (uint32_t j = 0; j < n_queries; j++)
-            if (!out.qk[j]) want.emplace_back(fwd_valid(j, cand[j][at[j]]), subs[j], cand[j][at[j]]);
+            if (!out.qk[j]) {
+                vcur[j] = fwd_valid(j, cand[j][at[j]]);
+                want.emplace_back(vcur[j], subs[j], cand[j][at[j]]);
+            }
         if (want.empty()) break;
         resolve(want);
         for (uint32_t j = 0; j < n_queries; j++) {
             if (out.qk[j]) continue;
             const uint32_t k = cand[j][at[j]];
-            if (minhits(fwd_valid(j, k), subs[j], k) >= 1 || at[j] + 1 == cand[j].size())
+            if (minhits(vcur[j], subs[j], k) >= 1 || at[j] + 1 == cand[j].size())
                 out.qk[j] = k;
             else
                 at[j]++;
@@ -257,31 +256,40 @@ void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
         }
     }
     for (auto &c : out.cfg) {
-        std::vector<std::pair<uint32_t, uint32_t>> ent;   // (key, strand << 8 | offset)
+        // entries grouped by bucket (a counting sort), strand then offset
+        // order inside a bucket
+        size_t n_ent = 0;
+        for (size_t q = 0; q < qs.size(); q++)
+            if (out.info[q].k == c.k)
+                for (uint32_t t = 0; t < kMaxQWords; t++)
+                    n_ent += (size_t)__builtin_popcount(out.info[q].valid[t]);
+        uint32_t bits = 4;
+        while (bits < 24 && (1ull << bits) < 2 * n_ent) bits++;
+        c.bits = bits;
+        const uint32_t sh = 32 - bits;
+        c.dir.assign((1u << bits) + 1, 0);
+        std::vector<uint32_t> keys;
+        std::vector<uint32_t> tags;
+        keys.reserve(n_ent);
+        tags.reserve(n_ent);
         for (size_t q = 0; q < qs.size(); q++) {
             if (out.info[q].k != c.k) continue;
             const QSDesc &d = qs[q];
             uint32_t key;
             for (uint32_t i = 0; i + c.k <= d.len; i += P.step)
-                if (strand_seed(words.data() + d.woff, d.nw, i, c.k, P.mask, &key))
-                    ent.emplace_back(key, ((uint32_t)q << 8) | i);
+                if (strand_seed(words.data() + d.woff, d.nw, i, c.k, P.mask, &key)) {
+                    keys.push_back(key);
+                    tags.push_back(((uint32_t)q << 8) | i);
+                    c.dir[((key * 0x9E3779B1u) >> sh) + 1]++;
+                }
         }
-        uint32_t bits = 4;
-        while (bits < 24 && (1ull << bits) < 2 * ent.size()) bits++;
-        c.bits = bits;
-        auto bucket = [&](uint32_t key) { return (key * 0x9E3779B1u) >> (32 - bits); };
-        std::sort(ent.begin(), ent.end(), [&](const auto &x, const auto &y) {
-            const uint32_t bx = bucket(x.first), by = bucket(y.first);
-            if (bx != by) return bx < by;
-            return x < y;
-        });
-        c.dir.assign((1u << bits) + 1, 0);
-        for (const auto &e : ent) c.dir[bucket(e.first) + 1]++;
         for (uint32_t b = 0; b < (1u << bits); b++) c.dir[b + 1] += c.dir[b];
-        c.ent.resize(2 * ent.size());
-        for (size_t i = 0; i < ent.size(); i++) {
-            c.ent[2 * i] = ent[i].first;
-            c.ent[2 * i + 1] = ent[i].second;
+        std::vector<uint32_t> fill(c.dir.begin(), c.dir.end() - 1);
+        c.ent.assign(2 * keys.size(), 0);
+        for (size_t e = 0; e < keys.size(); e++) {
+            const uint32_t at_ = fill[(keys[e] * 0x9E3779B1u) >> sh]++;
+            c.ent[2 * (size_t)at_] = keys[e];
+            c.ent[2 * (size_t)at_ + 1] = tags[e];
         }
     }
 }

@@ -219,6 +219,46 @@ class Plant:
     subs: int        # number of substituted positions
 
 
+def sample_reads(ref: Reference, n: int, L: int, subs: int, seed: int):
+    """n reads of L bases cut from uniformly random in-contig positions that
+    hold only A/C/G/T, each with exactly `subs` substitutions at distinct
+    positions (new base uniform among the other three), reverse-complemented
+    with probability 1/2. Returns (reads, origins) with origins an (n, 3)
+    int64 array of (contig, pos, strand)."""
+    rng = np.random.Generator(np.random.PCG64([seed, 104729, L, subs]))
+    offs = ref.offs.astype(np.int64)
+    ends = offs + ref.lens.astype(np.int64)
+    total = int(ends[-1])
+    acgt = np.zeros(256, dtype=bool)
+    acgt[list(b"ACGT")] = True
+    got_g = np.zeros(0, dtype=np.int64)
+    while got_g.size < n:
+        g = rng.integers(0, total - L + 1, size=2 * (n - got_g.size) + 16)
+        c = np.searchsorted(offs, g, side="right") - 1
+        ok = g + L <= ends[c]
+        g = g[ok]
+        win = ref.buf[g[:, None] + np.arange(L)[None, :]]
+        g = g[acgt[win].all(axis=1)]
+        got_g = np.concatenate([got_g, g])[:n]
+    c = np.searchsorted(offs, got_g, side="right") - 1
+    reads = ref.buf[got_g[:, None] + np.arange(L)[None, :]].copy()
+    if subs > 0:
+        where = np.argsort(rng.random((n, L)), axis=1)[:, :subs]
+        code = np.full(256, 0, dtype=np.uint8)
+        code[list(b"ACGT")] = np.arange(4, dtype=np.uint8)
+        rows = np.arange(n)[:, None]
+        old = code[reads[rows, where]]
+        new = (old + rng.integers(1, 4, size=(n, subs))) % 4
+        reads[rows, where] = np.frombuffer(b"ACGT", dtype=np.uint8)[new]
+    strand = (rng.random(n) < 0.5).astype(np.int64)
+    comp = np.arange(256, dtype=np.uint8)
+    comp[list(b"ACGT")] = list(b"TGCA")
+    rc = comp[reads[:, ::-1]]
+    reads = np.where(strand[:, None] == 1, rc, reads)
+    origins = np.stack([c, got_g - offs[c], strand], axis=1)
+    return [r.tobytes() for r in reads], origins
+
+
 def plant_copies(ref: Reference, queries: list[bytes], per_query: int, max_subs: int,
                  seed: int, rc_exact_half: bool = False) -> list[Plant]:
     """Overwrite reference windows with copies of each query carrying exactly
