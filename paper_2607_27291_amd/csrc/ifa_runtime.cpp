@@ -1169,8 +1169,12 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     qs.swap(sorted);
     std::vector<uint32_t> mb, mb3, mw3;
     std::vector<float> mt, mt3;
-    build_mfma_operands(qs, n_sparse, mb, mt);
-    build_mfma3_operands(qs, words, sorted_fw, n_sparse, mb3, mt3, mw3);
+    // the matrix-core filters' operands serve brute-force passes only
+    const bool indexed = (c->cfg.flags & IFA_FLAG_INDEXED) != 0;
+    if (!indexed) {
+        build_mfma_operands(qs, n_sparse, mb, mt);
+        build_mfma3_operands(qs, words, sorted_fw, n_sparse, mb3, mt3, mw3);
+    }
     c->mq3_words = mw3.empty() ? 1u : *std::max_element(mw3.begin(), mw3.end());
     // overhang kernel packing: 2 C window slots per piece and strand, C =
     // min(maxN, L - 1); the widest clip sets the pieces per wave of the grid
@@ -1221,7 +1225,7 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     }
     // size the work lists for the expected load unless the caller fixed the
     // initial capacity (they grow on overflow either way)
-    if (c->cfg.work_capacity == 0) {
+    if (c->cfg.work_capacity == 0 && !indexed) {
         const uint64_t est = expected_work_items(qs, sorted_fw, n_sparse, c->cfg.chunk_bases);
         c->work_want =
             (uint32_t)std::min<uint64_t>(std::max<uint64_t>(est, c->work_want), 1ull << 28);

@@ -142,6 +142,21 @@ uint32_t count_seeds(const uint32_t *w3, uint32_t nw, uint32_t L, uint32_t k, ui
 
 using Tuple = std::tuple<uint32_t, uint32_t, uint32_t>;   // (V, subs, k)
 
+// f(i) for i in [0, n) on up to `threads` threads, in contiguous blocks
+template <class F>
+void parallel_for(size_t n, unsigned threads, F &&f)
+{
+    const unsigned nt = (unsigned)std::max<size_t>(1, std::min<size_t>(threads, n / 256 + 1));
+    std::vector<std::thread> pool;
+    auto run = [&](unsigned t) {
+        const size_t a = n * t / nt, b = n * (t + 1) / nt;
+        for (size_t i = a; i < b; i++) f(i);
+    };
+    for (unsigned t = 1; t < nt; t++) pool.emplace_back(run, t);
+    run(0);
+    for (auto &th : pool) th.join();
+}
+
 }  // namespace
 
 void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
@@ -202,12 +217,12 @@ void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
     };
     std::vector<uint32_t> vcur(n_queries);   // forward seeds at the current try
     for (;;) {
+        parallel_for(n_queries, threads, [&](size_t j) {
+            if (!out.qk[j]) vcur[j] = fwd_valid((uint32_t)j, cand[j][at[j]]);
+        });
         std::vector<Tuple> want;
         for (uint32_t j = 0; j < n_queries; j++)
-            if (!out.qk[j]) {
-                vcur[j] = fwd_valid(j, cand[j][at[j]]);
-                want.emplace_back(vcur[j], subs[j], cand[j][at[j]]);
-            }
+            if (!out.qk[j]) want.emplace_back(vcur[j], subs[j], cand[j][at[j]]);
         if (want.empty()) break;
         resolve(want);
         for (uint32_t j = 0; j < n_queries; j++) {
@@ -224,8 +239,7 @@ void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
     out.info.assign(qs.size(), SeedInfo{});
     out.qthr.assign(2 * (size_t)n_queries, 0);
     std::vector<uint32_t> nvalid(qs.size());
-    std::vector<Tuple> want;
-    for (size_t q = 0; q < qs.size(); q++) {
+    parallel_for(qs.size(), threads, [&](size_t q) {
         const QSDesc &d = qs[q];
         SeedInfo &si = out.info[q];
         si.k = out.qk[d.qid];
@@ -236,8 +250,9 @@ void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
                 n++;
             }
         nvalid[q] = n;
-        want.emplace_back(n, subs[d.qid], si.k);
-    }
+    });
+    std::vector<Tuple> want;
+    for (size_t q = 0; q < qs.size(); q++) want.emplace_back(nvalid[q], subs[qs[q].qid], out.info[q].k);
     resolve(want);
     for (size_t q = 0; q < qs.size(); q++) {
         const QSDesc &d = qs[q];
@@ -268,21 +283,24 @@ void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
         c.bits = bits;
         const uint32_t sh = 32 - bits;
         c.dir.assign((1u << bits) + 1, 0);
-        std::vector<uint32_t> keys;
-        std::vector<uint32_t> tags;
-        keys.reserve(n_ent);
-        tags.reserve(n_ent);
-        for (size_t q = 0; q < qs.size(); q++) {
-            if (out.info[q].k != c.k) continue;
+        // keys of every seed of this length, strands in order (each strand's
+        // slice located by a prefix sum of its seed count), in parallel
+        std::vector<size_t> first(qs.size() + 1, 0);
+        for (size_t q = 0; q < qs.size(); q++)
+            first[q + 1] = first[q] + (out.info[q].k == c.k ? nvalid[q] : 0);
+        std::vector<uint32_t> keys(n_ent), tags(n_ent);
+        parallel_for(qs.size(), threads, [&](size_t q) {
+            if (out.info[q].k != c.k) return;
             const QSDesc &d = qs[q];
+            size_t at_ = first[q];
             uint32_t key;
             for (uint32_t i = 0; i + c.k <= d.len; i += P.step)
                 if (strand_seed(words.data() + d.woff, d.nw, i, c.k, P.mask, &key)) {
-                    keys.push_back(key);
-                    tags.push_back(((uint32_t)q << 8) | i);
-                    c.dir[((key * 0x9E3779B1u) >> sh) + 1]++;
+                    keys[at_] = key;
+                    tags[at_++] = ((uint32_t)q << 8) | i;
                 }
-        }
+        });
+        for (size_t e = 0; e < n_ent; e++) c.dir[((keys[e] * 0x9E3779B1u) >> sh) + 1]++;
         for (uint32_t b = 0; b < (1u << bits); b++) c.dir[b + 1] += c.dir[b];
         std::vector<uint32_t> fill(c.dir.begin(), c.dir.end() - 1);
         c.ent.assign(2 * keys.size(), 0);
