@@ -24,6 +24,9 @@ Other workloads (--workload):
       16 (one query set each; seed tables built on the host, seed lookup
       and verification on the GPU); reports per-level time and the recall
       of the reads' origins.
+  cross brute force against indexed mode on the same resident 4 Gbp for query
+      sets of 1 to 2,000 queries (L 30-36, maxSubs 4), load + scan each; the
+      first count at which indexed mode is faster is the mode crossover.
 
 Prints one JSON line. `value` is Gbp*query/s (reference bases x queries,
 both strands inside one unit) over the timed steps, wall clock.
@@ -66,7 +69,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "idx"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "idx", "cross"])
+    ap.add_argument("--counts", default="1,10,30,100,200,300,500,1000,2000",
+                    help="cross: query counts at which both modes are timed")
     ap.add_argument("--subs", default="0,4,8,16",
                     help="idx: substitutions per read = maxSubs, one query set each")
     ap.add_argument("--read-len", type=int, default=150, help="idx: read length")
@@ -676,6 +681,56 @@ def run_idx(args):
     return out
 
 
+# --------------------------------------------------------------------------
+# cross: brute force versus indexed mode by query count (the mode crossover)
+# --------------------------------------------------------------------------
+
+def run_cross(args):
+    import synth
+    import paper_2607_27291_amd as ifa
+
+    total = args.total or 4_000_000_000
+    counts = [int(x) for x in args.counts.split(",")]
+    ref = synth.gen_reference(synth.c2_spec(seed=7, total=total))
+    qs_all = synth.gen_queries(7, max(counts), 30, 36)
+    ctx = {m: ifa.Scanner(device=0, flags=f) for m, f in
+           (("brute", 0), ("indexed", ifa.IFA_FLAG_INDEXED))}
+    for s in ctx.values():
+        s.ref_load(ref)
+    bases, _ = ifa.ifa_ref_info(ctx["brute"].ctx)
+    rows = []
+    for n in counts:
+        row = {"queries": n}
+        for mode, s in ctx.items():
+            qs = qs_all[:n]
+            for rep in range(2):          # the second run is timed (warm caches)
+                device_sync()
+                t0 = time.perf_counter()
+                s.load_queries(qs, [4] * n)
+                s.scan_resident()
+                h = s.collect()
+                device_sync()
+                dt = time.perf_counter() - t0
+            row[mode + "_s"] = round(dt, 4)
+            row[mode + "_hits"] = int(len(h))
+        rows.append(row)
+        log(f"{n} queries: brute {row['brute_s']:.3f} s, indexed {row['indexed_s']:.3f} s")
+    for s in ctx.values():
+        s.close()
+    cross = next((r["queries"] for r in rows if r["indexed_s"] < r["brute_s"]), None)
+    tot_b = sum(r["brute_s"] for r in rows)
+    out = base_record(args, bases * sum(counts) / tot_b / 1e9, tot_b * 1e3 / len(rows), {
+        "workload": f"mode crossover: query sets of {counts} queries L30-36, maxSubs 4, vs "
+                    f"{bases / 1e9:.2f} Gbp resident; brute force and indexed mode, load + scan",
+        "reference_bases": bases,
+    })
+    out["steps"] = len(rows)
+    out["warmup"] = len(rows)
+    out["crossover_queries"] = cross
+    out["rows"] = rows
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -698,6 +753,8 @@ def main():
         out = run_c4(args)
     elif args.workload == "idx":
         out = run_idx(args)
+    elif args.workload == "cross":
+        out = run_cross(args)
     else:
         out = run_c5(args)
     print(json.dumps(out), flush=True)

@@ -124,6 +124,12 @@ typedef struct {
  * shuffle of a position array kept across trials. Not combined with
  * IFA_FLAG_OVERHANG. */
 #define IFA_FLAG_INDEXED 4u
+/* ifa_config.flags: choose the mode per query set (Discussion: the mode is
+ * selected explicitly or automatically from the query count): a set of at
+ * least ifa_index_params.auto_queries queries runs in indexed mode, a smaller
+ * one by brute force. Not combined with IFA_FLAG_OVERHANG; IFA_FLAG_INDEXED
+ * takes precedence. */
+#define IFA_FLAG_AUTO_MODE 8u
 
 /* One reported window (16 bytes). strand: 0 = +, 1 = - (reverse complement). */
 typedef struct {
@@ -248,7 +254,7 @@ ifa_status ifa_query_partition(const ifa_ctx *ctx, uint32_t *n_strands, uint32_t
  * buffers, work lists, query tables, counters and any resident reference. */
 ifa_status ifa_device_footprint(const ifa_ctx *ctx, uint64_t *bytes);
 
-/* Indexed-mode parameters (IFA_FLAG_INDEXED), with the paper's defaults
+/* Indexed-mode parameters (IFA_FLAG_INDEXED, IFA_FLAG_AUTO_MODE), with the paper's defaults
  * (Methods, "Algorithm Design"): candidate seed lengths 8, 9, 10, 12, 14;
  * no mask; step 1; probability 99.9 %; 200,000 trials; a fixed seed. */
 #define IFA_MAX_SEED_KS 8
@@ -258,21 +264,27 @@ typedef struct {
     uint32_t mask;                  /* masked centre of every k-mer, bases */
     uint32_t step;                  /* seed sampling step, >= 1 */
     uint32_t prob_ppm;              /* MinHits probability x 10^6, <= 10^6 */
-    uint32_t reserved;              /* must be 0 */
+    uint32_t auto_queries;          /* IFA_FLAG_AUTO_MODE: indexed from this many
+                                       queries on (default: the measured crossover) */
     uint64_t iters;                 /* Monte Carlo trials, >= 1 */
     uint64_t seed;                  /* SplitMix64 stream of the trials */
 } ifa_index_params;
 
 void ifa_index_params_default(ifa_index_params *p);
 
-/* Set the parameters used by the next ifa_load_queries of an indexed-mode
- * context. Errors: IFA_E_INVALID (bad values, or not an indexed context). */
+/* Set the parameters used by the next ifa_load_queries of an indexed-mode or
+ * auto-mode context. Errors: IFA_E_INVALID (bad values, or a context with
+ * neither flag). */
 ifa_status ifa_set_index_params(ifa_ctx *ctx, const ifa_index_params *p);
 
 /* Seeds chosen for the loaded queries: k[j] per query and thr[2 j + s] per
  * query and strand (0 for a strand not scanned). Arrays of the loaded query
  * count (and twice that). Errors: IFA_E_STATE (no queries, or not indexed). */
 ifa_status ifa_query_seeds(const ifa_ctx *ctx, uint32_t *k, uint32_t *thr);
+
+/* Mode of the loaded query set: *indexed = 1 for indexed mode, 0 for brute
+ * force. Errors: IFA_E_STATE (no queries loaded). */
+ifa_status ifa_query_mode(const ifa_ctx *ctx, uint32_t *indexed);
 
 /* Kernel variants: tile shapes of the scan kernel (windows per lane, query
  * strands per loop iteration, workgroup size) and the arithmetic of the

@@ -23,7 +23,7 @@ __all__ = [
     "ifa_device_footprint", "ifa_server_config_default", "ifa_server_create",
     "ifa_server_destroy", "ifa_server_submit", "ifa_server_step", "ifa_server_poll",
     "ifa_server_take", "ifa_server_info", "ifa_index_params_default", "ifa_set_index_params",
-    "ifa_query_seeds", "ifa_sam_create", "ifa_sam_destroy",
+    "ifa_query_seeds", "ifa_query_mode", "ifa_sam_create", "ifa_sam_destroy",
     "ifa_sam_last_error", "ifa_sam_add_contigs", "ifa_sam_header", "ifa_sam_format",
     "SamWriter", "Scanner", "Server", "collect_all",
 ]
@@ -36,6 +36,7 @@ IFA_STRAND_FWD, IFA_STRAND_RC, IFA_STRAND_BOTH = 1, 2, 3
 IFA_FLAG_GRAPHS = 1
 IFA_FLAG_OVERHANG = 2
 IFA_FLAG_INDEXED = 4
+IFA_FLAG_AUTO_MODE = 8
 IFA_MAX_SEED_KS = 8
 
 STATUS = {0: "IFA_OK", 1: "IFA_E_INVALID", 2: "IFA_E_NOMEM", 3: "IFA_E_DEVICE",
@@ -66,7 +67,7 @@ class IfaStats(ctypes.Structure):
 class IfaIndexParams(ctypes.Structure):
     _fields_ = [("n_k", ctypes.c_uint32), ("k", ctypes.c_uint32 * 8), ("mask", ctypes.c_uint32),
                 ("step", ctypes.c_uint32), ("prob_ppm", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("iters", ctypes.c_uint64),
+                ("auto_queries", ctypes.c_uint32), ("iters", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64)]
 
 
@@ -167,6 +168,8 @@ def lib():
         L.ifa_set_index_params.restype = st
         L.ifa_query_seeds.argtypes = [vp, vp, vp]
         L.ifa_query_seeds.restype = st
+        L.ifa_query_mode.argtypes = [vp, ctypes.POINTER(u32)]
+        L.ifa_query_mode.restype = st
         L.ifa_sam_create.argtypes = [u32, vp, vp, vp, u32, ctypes.POINTER(vp)]
         L.ifa_sam_create.restype = st
         L.ifa_sam_destroy.argtypes = [vp]
@@ -451,6 +454,13 @@ def ifa_query_seeds(ctx, n_queries: int):
     thr = np.zeros(max(2 * n_queries, 2), dtype=np.uint32)
     _check(ctx, lib().ifa_query_seeds(ctx, k.ctypes.data, thr.ctypes.data))
     return k[:n_queries], thr[:2 * n_queries].reshape(n_queries, 2)
+
+
+def ifa_query_mode(ctx) -> int:
+    """1 if the loaded query set runs in indexed mode, 0 for brute force."""
+    v = ctypes.c_uint32()
+    _check(ctx, lib().ifa_query_mode(ctx, ctypes.byref(v)))
+    return v.value
 
 
 def _sam_check(w, status):

@@ -253,6 +253,7 @@ struct ifa_ctx {
     // indexed mode: parameters, MinHits cache, the query set's seeds and
     // their device tables
     SeedParams seedp;
+    bool indexed = false;             // mode of the loaded query set
     MinHitsCache mh_cache;
     SeedBuild seeds;
     DevBuf<SeedInfo> d_seed_info;
@@ -476,7 +477,7 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.mq3_w = c->dq_mq3w;
     a.mq3_words = c->mq3_words;
     a.edge_pmin = c->edge_pmin;
-    if (c->cfg.flags & IFA_FLAG_INDEXED) {
+    if (c->indexed) {
         a.seed_info = c->d_seed_info.p;
         a.seed_tab = c->d_seed_tab.p;
         a.seed_ncfg = (uint32_t)c->seeds.cfg.size();
@@ -566,7 +567,7 @@ void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, Pa
                          : launch_clear_u64(a.hit_count + 1, 1, c->comp_s),
               "clear pass counters");
     hip_check(hipEventRecord(ev.t0, c->comp_s), "event record");
-    if (c->cfg.flags & IFA_FLAG_INDEXED) {
+    if (c->indexed) {
         // indexed mode: seed lookups and their verification, one kernel
         hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
         if (dense) hip_check(launch_seed(a, c->comp_s), "seed launch");
@@ -1170,7 +1171,7 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     std::vector<uint32_t> mb, mb3, mw3;
     std::vector<float> mt, mt3;
     // the matrix-core filters' operands serve brute-force passes only
-    const bool indexed = (c->cfg.flags & IFA_FLAG_INDEXED) != 0;
+    const bool indexed = c->indexed;
     if (!indexed) {
         build_mfma_operands(qs, n_sparse, mb, mt);
         build_mfma3_operands(qs, words, sorted_fw, n_sparse, mb3, mt3, mw3);
@@ -1380,8 +1381,9 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
     if (cfg_in) cfg = *cfg_in; else ifa_config_default(&cfg);
     if (cfg.abi_version != IFA_ABI_VERSION || cfg.chunk_bases < 4096 ||
         cfg.chunk_bases > (1ull << 31) || (cfg.chunk_bases & 31) || cfg.strands < 1 ||
-        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || (cfg.flags & ~(IFA_FLAG_GRAPHS | IFA_FLAG_OVERHANG | IFA_FLAG_INDEXED)) != 0 ||
-        ((cfg.flags & IFA_FLAG_INDEXED) && (cfg.flags & IFA_FLAG_OVERHANG)))
+        cfg.strands > 3 || cfg.n_policy > 1 || cfg.sink > 1 || (cfg.flags & ~(IFA_FLAG_GRAPHS | IFA_FLAG_OVERHANG | IFA_FLAG_INDEXED |
+                       IFA_FLAG_AUTO_MODE)) != 0 ||
+        ((cfg.flags & (IFA_FLAG_INDEXED | IFA_FLAG_AUTO_MODE)) && (cfg.flags & IFA_FLAG_OVERHANG)))
         return IFA_E_INVALID;
     ifa_ctx *c = new (std::nothrow) ifa_ctx();
     if (!c) return IFA_E_NOMEM;
@@ -1473,7 +1475,8 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
         if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
         validate_queries(n, seq, len, max_subs, max_n);
         use_device(c);
-        const bool indexed = (c->cfg.flags & IFA_FLAG_INDEXED) != 0;
+        const bool indexed = (c->cfg.flags & IFA_FLAG_INDEXED) ||
+                             ((c->cfg.flags & IFA_FLAG_AUTO_MODE) && n >= c->seedp.auto_queries);
         if (indexed) {
             if (2ull * n >= (1ull << 24)) fail(IFA_E_INVALID, "indexed mode takes < 2^23 queries");
             for (uint32_t j = 0; j < n; j++)
@@ -1485,6 +1488,7 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
         std::vector<uint32_t> words;
         uint32_t lmax = 0;
         pack_query_strands(c->cfg.strands, n, seq, len, max_subs, max_n, 0, qs, words, lmax);
+        c->indexed = indexed;
         install_queries(c, std::move(qs), std::move(words), n, lmax);
         if (indexed) install_seeds(c, n, len, max_subs, seq, max_n);
     });
@@ -1867,15 +1871,25 @@ void ifa_index_params_default(ifa_index_params *p)
     p->prob_ppm = 999000;
     p->iters = 200000;
     p->seed = 1;
+    p->auto_queries = kAutoQueries;
+}
+
+ifa_status ifa_query_mode(const ifa_ctx *c, uint32_t *indexed)
+{
+    if (!c || !indexed) return IFA_E_INVALID;
+    if (!c->have_queries) return IFA_E_STATE;
+    *indexed = c->indexed ? 1u : 0u;
+    return IFA_OK;
 }
 
 ifa_status ifa_set_index_params(ifa_ctx *c, const ifa_index_params *p)
 {
     if (!c || !p) return IFA_E_INVALID;
     return guarded(c, [&]() {
-        if (!(c->cfg.flags & IFA_FLAG_INDEXED)) fail(IFA_E_INVALID, "not an indexed context");
+        if (!(c->cfg.flags & (IFA_FLAG_INDEXED | IFA_FLAG_AUTO_MODE)))
+            fail(IFA_E_INVALID, "not an indexed or auto-mode context");
         if (p->n_k < 1 || p->n_k > IFA_MAX_SEED_KS || p->step < 1 || p->prob_ppm > 1000000u ||
-            p->iters < 1 || p->iters > (1ull << 31) || p->reserved != 0)
+            p->iters < 1 || p->iters > (1ull << 31))
             fail(IFA_E_INVALID, "bad index parameters");
         for (uint32_t i = 0; i < p->n_k; i++)
             if (p->k[i] <= p->mask || p->k[i] > 16) fail(IFA_E_INVALID, "seed length out of range");
@@ -1887,6 +1901,7 @@ ifa_status ifa_set_index_params(ifa_ctx *c, const ifa_index_params *p)
         q.ppm = p->prob_ppm;
         q.iters = p->iters;
         q.seed = p->seed;
+        q.auto_queries = p->auto_queries;
         const bool same = q.mask == c->seedp.mask && q.step == c->seedp.step &&
                           q.ppm == c->seedp.ppm && q.iters == c->seedp.iters &&
                           q.seed == c->seedp.seed;
@@ -1898,7 +1913,7 @@ ifa_status ifa_set_index_params(ifa_ctx *c, const ifa_index_params *p)
 ifa_status ifa_query_seeds(const ifa_ctx *c, uint32_t *k, uint32_t *thr)
 {
     if (!c) return IFA_E_INVALID;
-    if (!(c->cfg.flags & IFA_FLAG_INDEXED) || !c->have_queries) return IFA_E_STATE;
+    if (!c->indexed || !c->have_queries) return IFA_E_STATE;
     if (k)
         for (uint32_t j = 0; j < c->n_queries; j++) k[j] = c->seeds.qk[j];
     if (thr)
@@ -2013,6 +2028,7 @@ void server_step(ifa_server *S)
         owner.insert(owner.end(), r.n_queries, (uint32_t)i);
         lmax = std::max(lmax, r.lmax);
     }
+    c->indexed = false;   // serving runs brute-force passes
     install_queries(c, std::move(qs), std::move(words), (uint32_t)owner.size(), lmax);
     DevChunk *ch = c->resident[S->cursor].get();
     c->st.bases += ch->len - ch->own_from;

@@ -9,6 +9,11 @@
 
 namespace ifa {
 
+// Query count from which automatic mode selection picks indexed mode: the
+// first count at which indexed mode's load + scan beat brute force's on the
+// paper-scale 4 Gbp resident reference (queries of 30-36 bases, maxSubs 4).
+constexpr uint32_t kAutoQueries = 100;
+
 struct SeedParams {
     uint32_t n_k = 5;                                     // the paper's default lengths
     uint32_t k[kMaxSeedCfg] = {8, 9, 10, 12, 14, 0, 0, 0};
@@ -17,6 +22,7 @@ struct SeedParams {
     uint32_t ppm = 999000;
     uint64_t iters = 200000;
     uint64_t seed = 1;
+    uint32_t auto_queries = kAutoQueries;
 };
 
 // MinHits results by (valid seeds, maxSubs, k) for the current parameters.

@@ -58,11 +58,14 @@ def test_null_and_bad_arguments_are_rejected_without_a_device():
     cfg.abi_version = 99
     assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
     cfg = ifa.ifa_config_default()
-    cfg.flags = 8                                             # no such flag
+    cfg.flags = 16                                            # no such flag
     assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
     cfg.flags = ifa.IFA_FLAG_INDEXED | ifa.IFA_FLAG_OVERHANG  # not combined
     assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
-    assert (ifa.IFA_FLAG_GRAPHS, ifa.IFA_FLAG_OVERHANG, ifa.IFA_FLAG_INDEXED) == (1, 2, 4)
+    cfg.flags = ifa.IFA_FLAG_AUTO_MODE | ifa.IFA_FLAG_OVERHANG
+    assert L.ifa_create(ctypes.byref(cfg), ctypes.byref(ctx)) == 1
+    assert (ifa.IFA_FLAG_GRAPHS, ifa.IFA_FLAG_OVERHANG, ifa.IFA_FLAG_INDEXED,
+            ifa.IFA_FLAG_AUTO_MODE) == (1, 2, 4, 8)
     assert L.ifa_set_index_params(None, None) == 1
     L.ifa_destroy(None)                                       # NULL-safe
     assert L.ifa_load_queries(None, 0, None, None, None, None) == 1
@@ -83,4 +86,5 @@ def test_index_params_defaults_are_the_papers():
     p = ifa.ifa_index_params_default()
     assert list(p.k)[:p.n_k] == [8, 9, 10, 12, 14]
     assert (p.iters, p.prob_ppm, p.mask, p.step) == (200_000, 999_000, 0, 1)
+    assert p.auto_queries >= 1
     assert ctypes.sizeof(ifa.IfaIndexParams) == 72

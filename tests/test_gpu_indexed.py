@@ -213,3 +213,32 @@ def test_indexed_errors(ifa):
         ifa.ifa_set_index_params(s.ctx, mask=4, ks=(9,), iters=100)
         with pytest.raises(ifa.IfaError):           # query not longer than the mask
             s.load_queries([b"ACGT"], [0])
+
+
+def test_auto_mode_follows_the_query_count(ifa, orc):
+    """IFA_FLAG_AUTO_MODE: a query set below auto_queries runs by brute force
+    (the brute-force oracle's hits), one at or above it in indexed mode (the
+    indexed oracle's hits); the same context switches between them."""
+    rng = random.Random(3500)
+    qs = [rand_dna(rng, rng.randint(20, 60)) for _ in range(12)]
+    ks = [rng.randint(0, 5) for _ in qs]
+    contigs = _planted(rng, qs, ks, 20, 500, 20000)
+    params = dict(iters=2000, auto_queries=8)
+    with ifa.Scanner(chunk_bases=1 << 18, flags=ifa.IFA_FLAG_AUTO_MODE) as s:
+        ifa.ifa_set_index_params(s.ctx, **params)
+        s.ref_load(contigs)
+        for n in (3, 12, 7, 8):
+            say(f"auto mode: {n} queries")
+            s.load_queries(qs[:n], ks[:n])
+            s.scan_resident()
+            got = s.collect()
+            p = dict(params)
+            p.pop("auto_queries")
+            if n >= 8:
+                assert ifa.ifa_query_mode(s.ctx) == 1
+                seeds, _ = oracle_seeds(orc, qs[:n], ks[:n], p)
+                want = orc.scan(qs[:n], contigs, ks[:n], seeds=seeds)
+            else:
+                assert ifa.ifa_query_mode(s.ctx) == 0
+                want = orc.scan(qs[:n], contigs, ks[:n])
+            assert_same(got, want, f"auto {n}")
