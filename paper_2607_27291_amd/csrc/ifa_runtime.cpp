@@ -524,12 +524,12 @@ void copy_records(ifa_ctx *c, int hb, uint64_t n)
     if (n == 0) return;
     size_t old = c->hits.size();
     c->hits.resize(old + n);
-    // ordered after the pass on its own stream: a copy on another stream may
-    // read records a graph-launched kernel has not yet written back
-    hip_check(hipMemcpyAsync(c->hits.data() + old, c->d_hits[hb].p, n * sizeof(ifa_hit),
-                             hipMemcpyDeviceToHost, c->comp_s),
+    // the pass's done event has been waited on (it is recorded after the
+    // pass, outside any graph); a copy on the compute stream would also wait
+    // for the passes queued behind this one
+    hip_check(hipMemcpy(c->hits.data() + old, c->d_hits[hb].p, n * sizeof(ifa_hit),
+                        hipMemcpyDeviceToHost),
               "copy hit records");
-    hip_check(hipStreamSynchronize(c->comp_s), "sync record copy");
     c->hits_sorted = false;
     c->st.hits += n;
 }
