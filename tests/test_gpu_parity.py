@@ -489,13 +489,13 @@ def test_two_word_filter_prefix(ifa, orc, sink):
         qs.append(rand_dna(rng, rng.choice([28, 32, 36])))
         ks.append(rng.randint(0, 6))
     # the partition rule: the shortest prefix of one or two 32-base words
-    # whose filter passes a window in under half of the 1024-window waves
+    # whose filter passes a window in under 1/32 of the 1024-window waves
     from scipy.stats import binom
 
     def words(L, k):
         for w in (1, 2):
             lf = min(L, 32 * w)
-            if min(k, L) < lf and binom.cdf(min(k, L), lf, 0.75) * 1024 < 0.5:
+            if min(k, L) < lf and binom.cdf(min(k, L), lf, 0.75) * 1024 < 1 / 32:
                 return w
             if lf == L:
                 break
