@@ -903,11 +903,17 @@ __global__ __launch_bounds__(256) void scan_resolve_kernel(ScanArgs a)
 // scan_dense_cold_kernel, so that their code does not weigh on this loop's
 // registers. Dense strands come sorted by L descending so the cached word-0
 // slices can be masked in place.
+// Count+digest in the dense kernel: list the hits in LDS and hash them with
+// every lane busy (W = 16); at W = 32 the list would halve the occupancy.
+template <int W>
+constexpr bool kCompactHits = W <= 16;
+
 template <int W>
 __device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, const Lane &ln,
                                              bool plain, uint32_t contig, uint32_t pos0,
                                              const uint32_t (&sh)[W], const uint32_t (&sl)[W],
-                                             uint32_t &cnt, uint64_t &dig)
+                                             uint32_t &cnt, uint64_t &dig, uint2 *hits,
+                                             const uint32_t *contigs)
 {
     uint32_t m[W];
     uint32_t mn = 0xffffffffu;
@@ -955,19 +961,61 @@ __device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, con
             }
         }
     }
-    if (a.sink == kSinkCountDigest && plain && mn <= d.k) {
+    if (a.sink == kSinkCountDigest && !kCompactHits<W>) {
+        if (plain && mn <= d.k) {
+#pragma unroll
+            for (int b = 0; b < W; b++)
+                if (m[b] <= d.k) dig += hit_hash(contig, pos0 + b, d.strand, m[b], 0u);
+        }
+    } else if (a.sink == kSinkCountDigest) {
+        // Hash the hits with every lane busy: the lanes' hits are listed in
+        // this wave's LDS area (slot = hits of lower lanes, from ballots of
+        // the count's bits), then lane i hashes entries i, i + 64, ...
+        // Hashing in place would run the hash for all 64 lanes at every
+        // window any lane hits.
+        uint32_t hm = 0;
+        if (plain && mn <= d.k) {
+#pragma unroll
+            for (int b = 0; b < W; b++) hm |= (m[b] <= d.k ? 1u : 0u) << b;
+        }
+        const uint32_t c = __popc(hm);
+        uint32_t off = 0, total = 0;
+#pragma unroll
+        for (int j = 0; j < 6; j++) {   // c <= 32 < 2^6
+            const uint64_t bj = __ballot((c >> j) & 1u);
+            off += __builtin_amdgcn_mbcnt_hi((uint32_t)(bj >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bj, 0u))
+                   << j;
+            total += (uint32_t)__popcll(bj) << j;
+        }
+        const uint32_t lane = threadIdx.x & 63u;
 #pragma unroll
         for (int b = 0; b < W; b++)
-            if (m[b] <= d.k) dig += hit_hash(contig, pos0 + b, d.strand, m[b], 0u);
+            if ((hm >> b) & 1u) hits[off++] = make_uint2(pos0 + (uint32_t)b, m[b] | (lane << 16));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t i = lane; i < total; i += 64u) {
+            const uint2 e = hits[i];
+            dig += hit_hash(contigs[e.y >> 16], e.x, d.strand, e.y & 0xffffu, 0u);
+        }
+        // the next strand rewrites the list: every read is done first
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
 template <int W>
 __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
 {
+    // per wave: the hit list of the strand being hashed (at most 64 W hits)
+    // and the contig of every lane
+    __shared__ uint2 hit_lds[4][kCompactHits<W> ? 64 * W : 1];
+    __shared__ uint32_t contig_lds[4][kCompactHits<W> ? 64 : 1];
     const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
     const Lane ln = make_lane<W>(a, gl);
     const uint32_t wave = gl >> 6;
+    uint2 *hits = hit_lds[threadIdx.x >> 6];
+    uint32_t *contigs = contig_lds[threadIdx.x >> 6];
     uint32_t sh[W], sl[W];
 #pragma unroll
     for (int b = 0; b < W; b++) {
@@ -982,6 +1030,12 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
         const Piece pc = a.pieces[find_piece(a, first)];
         contig = pc.contig;
         pos0 = (uint32_t)(pc.contig_off + (first - pc.start));
+    }
+    if (kCompactHits<W>) {
+        contigs[threadIdx.x & 63u] = contig;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     uint32_t cur_len = 32;
     // both strands of a query are adjacent: their counts are summed before
@@ -1007,7 +1061,7 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
         // keep the hash keys of the W windows from being hoisted out of the
         // strand loop (32 more live registers, half the occupancy)
         asm volatile("" : "+v"(contig), "+v"(pos0));
-        dense_strand<W>(a, d, ln, plain, contig, pos0, sh, sl, cnt, dig);
+        dense_strand<W>(a, d, ln, plain, contig, pos0, sh, sl, cnt, dig, hits, contigs);
     }
     if (a.sink == kSinkCountDigest && qid != 0xffffffffu) wave_add_stats(a, qid, cnt, dig, wave);
 }
