@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--sam", action="store_true",
                     help="c2: also time the SAM text of one step's hits (host writer)")
     ap.add_argument("--median", type=float, default=0.0,
-                    help="c2: median contig length in bases (0 = the workload's 3 Mbp)")
+                    help="c2/c3: median contig length in bases (0 = the workload's 3 Mbp)")
     ap.add_argument("--cpu-sample", type=int, default=250_000_000,
                     help="c2: reference bases the oracle baseline scans per maxSubs (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -422,7 +422,7 @@ def run_c3(args):
     total = args.total or 1_000_000_000
     nq = args.queries or 10_000
     t0 = time.time()
-    w = synth.c3_batched(total=total, n_queries=nq)
+    w = synth.c3_batched(total=total, n_queries=nq, median=args.median or 3e6)
     log(f"generated {w.ref.total / 1e9:.2f} Gbp, {nq} queries ({time.time() - t0:.1f} s)")
     s = ifa.Scanner(device=0, sink=ifa.IFA_SINK_COUNT_DIGEST, flags=scanner_flags(ifa, args))
     s.ref_load(w.ref)
@@ -441,7 +441,9 @@ def run_c3(args):
     n_sparse = ifa.ifa_sparse_count(s.ctx)
     out = base_record(args, bpq * args.steps / elapsed / 1e9, elapsed * 1e3 / args.steps, {
         "workload": f"batched scan: {nq} queries L18-50, maxSubs 0-16, vs "
-                    f"{bases / 1e9:.2f} Gbp resident, count+digest",
+                    f"{bases / 1e9:.2f} Gbp resident, count+digest"
+                    + (f", median contig {args.median:.0f} bp ({w.ref.n_contigs} contigs)"
+                       if args.median else ""),
         "reference_bases": bases,
         "queries": nq,
         "device_chunks": chunks,
@@ -707,11 +709,15 @@ def run_cross(args):
                 device_sync()
                 t0 = time.perf_counter()
                 s.load_queries(qs, [4] * n)
+                t1 = time.perf_counter()
+                ifa.ifa_reset_stats(s.ctx)
                 s.scan_resident()
                 h = s.collect()
                 device_sync()
                 dt = time.perf_counter() - t0
             row[mode + "_s"] = round(dt, 4)
+            row[mode + "_load_s"] = round(t1 - t0, 4)
+            row[mode + "_kernel_ms"] = round(ifa.ifa_get_stats(s.ctx)["kernel_ms"], 3)
             row[mode + "_hits"] = int(len(h))
         rows.append(row)
         log(f"{n} queries: brute {row['brute_s']:.3f} s, indexed {row['indexed_s']:.3f} s")

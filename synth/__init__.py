@@ -364,10 +364,13 @@ def c2_paper_scale(seed: int = 2, total: int = 4_000_000_000, k: int = 4,
     return Workload(f"c2_k{k}", ref, qs, [k] * n_queries, plants, spec)
 
 
-def c3_batched(seed: int = 3, total: int = 1_000_000_000, n_queries: int = 10_000) -> Workload:
+def c3_batched(seed: int = 3, total: int = 1_000_000_000, n_queries: int = 10_000,
+               median: float = 3e6) -> Workload:
     """10,000 queries, lengths U{18..50}, maxSubs U{0..16} per query; reference
-    from the paper-scale generator; no planted copies."""
+    from the paper-scale generator (median contig length `median`); no planted
+    copies."""
     spec = c2_spec(seed, total)
+    spec.median = median
     ref = gen_reference(spec) if total > 0 else None
     qs = gen_queries(seed, n_queries, 18, 50)
     rng = np.random.Generator(np.random.PCG64([seed, 31]))
