@@ -182,19 +182,31 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scan_filter_mfma3_c2_4gbp_hbm_
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2607_27291_amd", "csrc", "ifa_scan.hip")
 
 
+def kernel_code_sha256(path):
+    """SHA-256 of a kernel source file's code: comments, trailing blanks and
+    empty lines removed, so that a comment edit does not count as a change
+    (any code change in the file, in any kernel, does)."""
+    import hashlib
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = [ln.rstrip() for ln in text.splitlines()]
+    return hashlib.sha256("\n".join(ln for ln in lines if ln).encode()).hexdigest()
+
+
 def profiled_traffic(kernel):
     """HBM bytes per launch of `kernel` on the paper-scale workload from the
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when that
-    summary is for another kernel or the kernel source changed since."""
-    import hashlib
+    summary is for another kernel or the kernel code changed since."""
     try:
         with open(TRAFFIC_PROFILE) as f:
             kv = dict(line.split(": ", 1) for line in f.read().splitlines() if ": " in line)
-        with open(KERNEL_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = kernel_code_sha256(KERNEL_SOURCE)
     except OSError:
         return None
-    if kv.get("kernel", "").strip() != kernel or kv.get("kernel_source_sha256", "").strip() != sha:
+    if kv.get("kernel", "").strip() != kernel or kv.get("kernel_code_sha256", "").strip() != sha:
         return None
     return int(kv["traffic_bytes_per_launch"])
 

@@ -893,9 +893,9 @@ __global__ __launch_bounds__(256) void scan_resolve_kernel(ScanArgs a)
     }
 }
 
-// Dense query strands [n_sparse, n_qs): strands whose first-word filter
-// passes windows in most waves (short queries with high k, long queries with
-// k >= 16). Each lane counts its W windows' mismatches word by word, all
+// Dense query strands [n_sparse, n_qs): strands whose filter would pass a
+// window in 1/32 of the waves or more (short queries with high k, long
+// queries with k >= 16). Each lane counts its W windows' mismatches word by word, all
 // windows at once; after each 32-base word the wave stops with this strand
 // once no window of any lane is still within k (the paper's early exit, per
 // word). Windows within k after the last word are hits; plain lanes emit them
