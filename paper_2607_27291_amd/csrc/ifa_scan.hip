@@ -945,40 +945,56 @@ __device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, con
         lp = lnw;
     }
     if (!__any(plain && mn <= d.k)) return;
-    if (plain && mn <= d.k) {
-        uint32_t c = 0;
+    if constexpr (!kCompactHits<W>) {
+        // 32 windows per lane: count, emit and hash in place (a hit mask and
+        // list would cost a quarter of the occupancy)
+        if (plain && mn <= d.k) {
+            uint32_t c = 0;
 #pragma unroll
-        for (int b = 0; b < W; b++) c += m[b] <= d.k ? 1u : 0u;
-        cnt += c;
-        if (a.sink == kSinkRecords) {
+            for (int b = 0; b < W; b++) c += m[b] <= d.k ? 1u : 0u;
+            cnt += c;
+            if (a.sink == kSinkRecords) {
+                unsigned long long slot = atomicAdd(a.hit_count, (unsigned long long)c);
+#pragma unroll
+                for (int b = 0; b < W; b++) {
+                    if (m[b] <= d.k) {
+                        write_record(a, slot, d, contig, pos0 + b, m[b], 0u);
+                        slot++;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int b = 0; b < W; b++)
+                    if (m[b] <= d.k) dig += hit_hash(contig, pos0 + b, d.strand, m[b], 0u);
+            }
+        }
+        return;
+    }
+    // the lane's hits: bit b for window b
+    uint32_t hm = 0;
+    if (plain && mn <= d.k) {
+#pragma unroll
+        for (int b = 0; b < W; b++) hm |= (m[b] <= d.k ? 1u : 0u) << b;
+    }
+    const uint32_t c = __popc(hm);
+    cnt += c;
+    if (a.sink == kSinkRecords) {
+        if (hm) {
             unsigned long long slot = atomicAdd(a.hit_count, (unsigned long long)c);
 #pragma unroll
             for (int b = 0; b < W; b++) {
-                if (m[b] <= d.k) {
+                if ((hm >> b) & 1u) {
                     write_record(a, slot, d, contig, pos0 + b, m[b], 0u);
                     slot++;
                 }
             }
         }
-    }
-    if (a.sink == kSinkCountDigest && !kCompactHits<W>) {
-        if (plain && mn <= d.k) {
-#pragma unroll
-            for (int b = 0; b < W; b++)
-                if (m[b] <= d.k) dig += hit_hash(contig, pos0 + b, d.strand, m[b], 0u);
-        }
-    } else if (a.sink == kSinkCountDigest) {
+    } else {
         // Hash the hits with every lane busy: the lanes' hits are listed in
         // this wave's LDS area (slot = hits of lower lanes, from ballots of
         // the count's bits), then lane i hashes entries i, i + 64, ...
         // Hashing in place would run the hash for all 64 lanes at every
         // window any lane hits.
-        uint32_t hm = 0;
-        if (plain && mn <= d.k) {
-#pragma unroll
-            for (int b = 0; b < W; b++) hm |= (m[b] <= d.k ? 1u : 0u) << b;
-        }
-        const uint32_t c = __popc(hm);
         uint32_t off = 0, total = 0;
 #pragma unroll
         for (int j = 0; j < 6; j++) {   // c <= 32 < 2^6
