@@ -133,6 +133,7 @@ struct ScanArgs {
     const float *mq3_t;
     const uint32_t *mq3_w;
     uint32_t mq3_words;
+    uint32_t mq3_two_batches;   // batches [0, this) hold every two-word tile
     // matrix-core filters: batch of 32 strands of grid row 0 (the grid's y
     // dimension holds at most 65535 batches per launch)
     uint32_t batch0;

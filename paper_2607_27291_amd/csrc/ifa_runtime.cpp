@@ -248,6 +248,7 @@ struct ifa_ctx {
     const float *dq_mqt = nullptr, *dq_mq3t = nullptr;
     const uint32_t *dq_mq3w = nullptr;
     uint32_t mq3_words = 1;           // most prefix words of any three-class column tile
+    uint32_t mq3_two_batches = 0;     // leading batches holding a two-word tile
     uint32_t edge_pmin = 0;           // overhang kernel: pieces per wave (ScanArgs.edge_pmin)
     DevBuf<unsigned long long> d_qcount, d_qdigest;
     // indexed mode: parameters, MinHits cache, the query set's seeds and
@@ -476,6 +477,7 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.mq3_t = c->dq_mq3t;
     a.mq3_w = c->dq_mq3w;
     a.mq3_words = c->mq3_words;
+    a.mq3_two_batches = c->mq3_two_batches;
     a.edge_pmin = c->edge_pmin;
     if (c->indexed) {
         a.seed_info = c->d_seed_info.p;
@@ -1155,8 +1157,11 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     }
     std::vector<size_t> order(qs.size());
     for (size_t i = 0; i < order.size(); i++) order[i] = i;
+    // sparse strands filtered on two words first (all have L > 32, so min(L,
+    // 32) still never rises along the list), then L descending, then k
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
         if (dense[x] != dense[y]) return dense[x] < dense[y];
+        if (fw[x] != fw[y]) return fw[x] > fw[y];
         const QSDesc &a = qs[x], &b = qs[y];
         if (a.len != b.len) return a.len > b.len;
         return a.k < b.k;
@@ -1180,6 +1185,11 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
         build_mfma3_operands(qs, words, sorted_fw, n_sparse, mb3, mt3, mw3);
     }
     c->mq3_words = mw3.empty() ? 1u : *std::max_element(mw3.begin(), mw3.end());
+    // the tiles filtering on two words lead the list: their batches of 32
+    // strands (8 tiles) run the two-word kernel, the others the one-word one
+    uint32_t two_tiles = 0;
+    while (two_tiles < mw3.size() && mw3[two_tiles] == 2u) two_tiles++;
+    c->mq3_two_batches = (two_tiles + 7u) / 8u;
     // overhang kernel packing: 2 C window slots per piece and strand, C =
     // min(maxN, L - 1); the widest clip sets the pieces per wave of the grid
     uint32_t cmax = 0;

@@ -1446,23 +1446,32 @@ hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
     const VariantDesc &v = pick(a);
     if (v.enc == 1 || v.enc == 2) {
         // about v.waves waves over all batches of 32 strands (grid y), at
-        // most one per filter wave; each walks its share of the filter waves
+        // most one per filter wave; each walks its share of the filter waves.
+        // Three-class form: the leading batches that hold a two-word tile
+        // run the two-word kernel, the rest the one-word kernel (more waves
+        // per SIMD).
         const uint32_t waves = (a.w_end - a.w_begin + 31u) >> 5;
         const uint32_t wpg = v.wg / 64u;
         const uint32_t batches = (a.n_sparse + 31u) / 32u;
         const uint32_t want = (v.waves + wpg * batches - 1) / (wpg * batches);
         const uint32_t gx = max(1u, min((waves + wpg - 1) / wpg, want));
-        const bool two = v.enc == 2 && a.mq3_words >= 2;
-        const uint32_t lds =
-            v.enc == 1 ? mq_lds_bytes(min(16u, (a.n_sparse + 1u) / 2u))
-                       : mq3_lds_bytes(min(8u, (a.n_sparse + 3u) / 4u), v.wg, two ? 2 : 1);
-        for (uint32_t b0 = 0; b0 < batches; b0 += 65535u) {
-            ScanArgs part = a;
-            part.batch0 = b0;
-            hipLaunchKernelGGL(two ? v.filter2 : v.filter, dim3(gx, min(65535u, batches - b0)),
-                               dim3(v.wg), lds, s, part);
-            const hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
+        const uint32_t split =
+            v.enc == 2 && a.mq3_words >= 2 ? min(a.mq3_two_batches, batches) : 0u;
+        for (int part_nw = 2; part_nw >= 1; part_nw--) {
+            const uint32_t lo = part_nw == 2 ? 0u : split, hi = part_nw == 2 ? split : batches;
+            if (v.enc == 1 && part_nw == 2) continue;
+            const bool two = part_nw == 2;
+            const uint32_t lds =
+                v.enc == 1 ? mq_lds_bytes(min(16u, (a.n_sparse + 1u) / 2u))
+                           : mq3_lds_bytes(min(8u, (a.n_sparse + 3u) / 4u), v.wg, two ? 2 : 1);
+            for (uint32_t b0 = lo; b0 < hi; b0 += 65535u) {
+                ScanArgs part = a;
+                part.batch0 = b0;
+                hipLaunchKernelGGL(two ? v.filter2 : v.filter, dim3(gx, min(65535u, hi - b0)),
+                                   dim3(v.wg), lds, s, part);
+                const hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
         }
         return hipSuccess;
     }
