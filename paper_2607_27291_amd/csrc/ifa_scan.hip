@@ -770,32 +770,51 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
     const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
     const uint32_t stride = gridDim.x * (WG / 64u);
     const ifa_v16f zero = {};
-    for (uint32_t wave = blockIdx.x * (WG / 64u) + (threadIdx.x >> 6); wave < n_waves;
-         wave += stride) {
-        const uint32_t w0 = a.w_begin + 32u * wave;
-        const uint32_t lw = w0 + (l >> 1);
-        bool lane_n = false;
-        if (lw < a.w_end) lane_n = (a.nm[lw] | a.nm[min(lw + 1u, last)]) != 0u;
-        if (__any(lane_n)) {
+    // Lane j < kBlocks / 4 holds plane word j of a wave's stream (its four
+    // 8-base blocks); lane j <= 32 also N word j when a window start of the
+    // wave reads it (j = 0, or word j - 1 holds a window start). The words
+    // of a lane's next wave are loaded before the current wave's tiles run.
+    static_assert(kBlocks % 4u == 0u && kBlocks / 4u <= 64u, "one plane word per lane");
+    auto fetch = [&](uint32_t wv, uint32_t &ph, uint32_t &pl, uint32_t &pn) {
+        const uint32_t w0 = a.w_begin + 32u * wv, w = min(w0 + l, last);
+        ph = 0u;
+        pl = 0u;
+        pn = 0u;
+        if (l < kBlocks / 4u) {
+            ph = a.hi[w];
+            pl = a.lo[w];
+        }
+        if (l <= 32u && (l == 0u || w0 + l - 1u < a.w_end)) pn = a.nm[w];
+    };
+    uint32_t wave = blockIdx.x * (WG / 64u) + (threadIdx.x >> 6);
+    uint32_t nh = 0u, nl = 0u, nn = 0u;
+    if (wave < n_waves) fetch(wave, nh, nl, nn);
+    for (; wave < n_waves; wave += stride) {
+        const uint32_t ch = nh, cl = nl, cn = nn;
+        if (wave + stride < n_waves) fetch(wave + stride, nh, nl, nn);
+        if (__any(cn != 0u)) {
             if (l == 0u) {
                 if (a.batch0 + blockIdx.y == 0) atomicAdd(a.skip_count, 1u);
                 list_batch(a, wave, qb);
             }
             continue;
         }
-        // stage the indicator words of blocks l, l + 64, l + 128
+        // stage the indicator words of blocks 4j .. 4j + 3 (lane j)
+        if (l < kBlocks / 4u) {
+            const uint32_t m = 0x22222222u;
+            uint32_t v[12];
 #pragma unroll
-        for (uint32_t r = 0; r < 3; r++) {
-            const uint32_t b = l + 64u * r;
-            if (b < kBlocks) {
-                const uint32_t w = min(w0 + (b >> 2), last), sh = 8u * (b & 3u);
-                const uint32_t s1 = sp[(a.hi[w] >> sh) & 0xffu];
-                const uint32_t s0 = sp[(a.lo[w] >> sh) & 0xffu];
-                const uint32_t m = 0x22222222u;
-                flat[3u * b] = ~s1 & s0 & m;        // C (hi 0, lo 1)
-                flat[3u * b + 1u] = s1 & s0 & m;    // G (1, 1)
-                flat[3u * b + 2u] = s1 & ~s0 & m;   // T (1, 0)
+            for (uint32_t q = 0; q < 4; q++) {
+                const uint32_t s1 = sp[(ch >> (8u * q)) & 0xffu];
+                const uint32_t s0 = sp[(cl >> (8u * q)) & 0xffu];
+                v[3 * q] = ~s1 & s0 & m;           // C (hi 0, lo 1)
+                v[3 * q + 1] = s1 & s0 & m;        // G (1, 1)
+                v[3 * q + 2] = s1 & ~s0 & m;       // T (1, 0)
             }
+            uint4 *dst = reinterpret_cast<uint4 *>(flat + 12u * l);
+            dst[0] = make_uint4(v[0], v[1], v[2], v[3]);
+            dst[1] = make_uint4(v[4], v[5], v[6], v[7]);
+            dst[2] = make_uint4(v[8], v[9], v[10], v[11]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
