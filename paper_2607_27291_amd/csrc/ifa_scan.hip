@@ -733,8 +733,8 @@ static uint32_t mq_lds_bytes(uint32_t tiles)
 // k = 0..4 each give three indicator words (class C, G, T; nibble o = base
 // 8k + o, e2m1 1.0 or 0); slot z = 8h + 4t + d (K step t, lane half h,
 // register d) holds block z / 3, class z % 3; slot 15 meets only zero B
-// entries. A wave first writes the indicator words of its 1056-base stream
-// (blocks of 8 bases, three words each) to its own LDS area, where the slots
+// entries. A wave first writes the indicator words of its stream (m3_blocks
+// blocks of 8 bases, three words each) to its own LDS area, where the slots
 // of lane (g, h) in tile u are the 8 consecutive words from 3 (32u + g) + 8h.
 // mq3_t holds the match count minus nA that a column needs.
 // ---------------------------------------------------------------------------
