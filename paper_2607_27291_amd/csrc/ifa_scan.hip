@@ -931,8 +931,8 @@ template <int W>
 __device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, const Lane &ln,
                                              bool plain, uint32_t contig, uint32_t pos0,
                                              const uint32_t (&sh)[W], const uint32_t (&sl)[W],
-                                             uint32_t &cnt, uint64_t &dig, uint2 *hits,
-                                             const uint32_t *contigs)
+                                             uint32_t &cnt, uint64_t &dig, uint32_t *hits,
+                                             const uint32_t *lane_pos)
 {
     uint32_t m[W];
     uint32_t mn = 0xffffffffu;
@@ -989,15 +989,16 @@ __device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, con
         }
         return;
     }
-    // the lane's hits: bit b for window b
-    uint32_t hm = 0;
-    if (plain && mn <= d.k) {
-#pragma unroll
-        for (int b = 0; b < W; b++) hm |= (m[b] <= d.k ? 1u : 0u) << b;
-    }
-    const uint32_t c = __popc(hm);
-    cnt += c;
+    const bool live = plain && mn <= d.k;
     if (a.sink == kSinkRecords) {
+        // the lane's hits: bit b for window b
+        uint32_t hm = 0;
+        if (live) {
+#pragma unroll
+            for (int b = 0; b < W; b++) hm |= (m[b] <= d.k ? 1u : 0u) << b;
+        }
+        const uint32_t c = __popc(hm);
+        cnt += c;
         if (hm) {
             unsigned long long slot = atomicAdd(a.hit_count, (unsigned long long)c);
 #pragma unroll
@@ -1009,30 +1010,39 @@ __device__ __forceinline__ void dense_strand(const ScanArgs &a, const QS &d, con
             }
         }
     } else {
-        // Hash the hits with every lane busy: the lanes' hits are listed in
-        // this wave's LDS area (slot = hits of lower lanes, from ballots of
-        // the count's bits), then lane i hashes entries i, i + 64, ...
-        // Hashing in place would run the hash for all 64 lanes at every
-        // window any lane hits.
-        uint32_t off = 0, total = 0;
-#pragma unroll
-        for (int j = 0; j < 6; j++) {   // c <= 32 < 2^6
-            const uint64_t bj = __ballot((c >> j) & 1u);
-            off += __builtin_amdgcn_mbcnt_hi((uint32_t)(bj >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bj, 0u))
-                   << j;
-            total += (uint32_t)__popcll(bj) << j;
-        }
+        // Hash the hits with every lane busy: they are listed in this wave's
+        // LDS area window by window (the lanes hitting window b, from one
+        // ballot, take the slots after the hits of windows < b), then lane i
+        // hashes entries i, i + 64, ... Hashing in place would run the hash
+        // for all 64 lanes at every window any lane hits. An entry is
+        // m | lane << 16 | b << 24; the lane's contig and first position sit
+        // in LDS. The wave's hit total goes to lane 0's count (the query's
+        // count is a wave sum).
         const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t lane16 = lane << 16;
+        // one signed compare per window: lanes without a hit compare with -1
+        const int kk = live ? (int)d.k : -1;
+        uint32_t total = 0;   // wave-uniform
 #pragma unroll
-        for (int b = 0; b < W; b++)
-            if ((hm >> b) & 1u) hits[off++] = make_uint2(pos0 + (uint32_t)b, m[b] | (lane << 16));
+        for (int b = 0; b < W; b++) {
+            const bool hit = (int)m[b] <= kk;
+            const uint64_t mb = __ballot(hit);
+            if (mb == 0u) continue;
+            if (hit) {
+                const uint32_t slot = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, total));
+                hits[slot] = m[b] | lane16 | ((uint32_t)b << 24);
+            }
+            total += (uint32_t)__popcll(mb);
+        }
+        if (lane == 0u) cnt += total;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (uint32_t i = lane; i < total; i += 64u) {
-            const uint2 e = hits[i];
-            dig += hit_hash(contigs[e.y >> 16], e.x, d.strand, e.y & 0xffffu, 0u);
+            const uint32_t e = hits[i], hl = (e >> 16) & 0xffu;
+            dig += hit_hash(lane_pos[2u * hl], lane_pos[2u * hl + 1u] + (e >> 24), d.strand,
+                            e & 0xffffu, 0u);
         }
         // the next strand rewrites the list: every read is done first
         __builtin_amdgcn_wave_barrier();
@@ -1043,14 +1053,14 @@ template <int W>
 __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
 {
     // per wave: the hit list of the strand being hashed (at most 64 W hits)
-    // and the contig of every lane
-    __shared__ uint2 hit_lds[4][kCompactHits<W> ? 64 * W : 1];
-    __shared__ uint32_t contig_lds[4][kCompactHits<W> ? 64 : 1];
+    // and the contig and first position of every lane
+    __shared__ uint32_t hit_lds[4][kCompactHits<W> ? 64 * W : 1];
+    __shared__ uint32_t pos_lds[4][kCompactHits<W> ? 2 * 64 : 1];
     const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
     const Lane ln = make_lane<W>(a, gl);
     const uint32_t wave = gl >> 6;
-    uint2 *hits = hit_lds[threadIdx.x >> 6];
-    uint32_t *contigs = contig_lds[threadIdx.x >> 6];
+    uint32_t *hits = hit_lds[threadIdx.x >> 6];
+    uint32_t *lane_pos = pos_lds[threadIdx.x >> 6];
     uint32_t sh[W], sl[W];
 #pragma unroll
     for (int b = 0; b < W; b++) {
@@ -1067,7 +1077,8 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
         pos0 = (uint32_t)(pc.contig_off + (first - pc.start));
     }
     if (kCompactHits<W>) {
-        contigs[threadIdx.x & 63u] = contig;
+        lane_pos[2u * (threadIdx.x & 63u)] = contig;
+        lane_pos[2u * (threadIdx.x & 63u) + 1u] = pos0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1096,7 +1107,7 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
         // keep the hash keys of the W windows from being hoisted out of the
         // strand loop (32 more live registers, half the occupancy)
         asm volatile("" : "+v"(contig), "+v"(pos0));
-        dense_strand<W>(a, d, ln, plain, contig, pos0, sh, sl, cnt, dig, hits, contigs);
+        dense_strand<W>(a, d, ln, plain, contig, pos0, sh, sl, cnt, dig, hits, lane_pos);
     }
     if (a.sink == kSinkCountDigest && qid != 0xffffffffu) wave_add_stats(a, qid, cnt, dig, wave);
 }
