@@ -356,6 +356,37 @@ def test_dense_and_sparse_strands_with_work_list_overflow(ifa, orc, sink):
     assert len(want) > 1000
 
 
+def test_dense_strands_where_every_window_hits(ifa, orc):
+    """maxSubs >= L: every window of every plain lane is a hit, so the dense
+    kernel's per-wave hit list is full (64 lanes x W windows) for every
+    strand; N runs and contig ends send some lanes to the cold kernel.
+    Count+digest for one variant of each lane width."""
+    import synth
+    spec = synth.c2_spec(seed=91, total=1_200_000)
+    spec.n_param = 2e-3
+    spec.median = 60_000
+    ref = synth.gen_reference(spec)
+    rng = random.Random(91)
+    qs = [rand_dna(rng, L) for L in (6, 12, 18, 25, 32, 33, 47)]
+    ks = [len(q) + rng.randint(0, 3) for q in qs]
+    _, cnt, dig = orc.scan(qs, ref, ks, stats=True, records=False)
+    widths = {}
+    for v in range(ifa.ifa_variant_count()):
+        widths.setdefault(ifa.ifa_variant_info(v)["windows_per_lane"], v)
+    assert len(widths) >= 2
+    for w, v in sorted(widths.items()):
+        say(f"every window hits: variant {v} (W {w})")
+        with ifa.Scanner(chunk_bases=1 << 18, sink=ifa.IFA_SINK_COUNT_DIGEST) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries(qs, ks)
+            strands, filtered = ifa.ifa_query_partition(s.ctx)
+            assert filtered == 0
+            s.scan_chunk(ref)
+            gc, gd = s.query_stats()
+        assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), f"variant {v}"
+    assert int(cnt.sum()) > 10_000_000
+
+
 def matrix_variants(ifa):
     return [v for v in range(ifa.ifa_variant_count()) if ifa.ifa_variant_info(v)["encoding"] >= 1]
 
