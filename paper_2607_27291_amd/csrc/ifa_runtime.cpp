@@ -949,51 +949,67 @@ void validate_queries(uint32_t n, const uint8_t *const *seq, const uint32_t *len
 }
 
 // Pack every selected strand of n queries into descriptors and plane words,
-// appending to qs / words; query j gets qid qid_base + j.
+// appending to qs / words; query j gets qid qid_base + j. The offsets of every
+// query's descriptors and words come first, then blocks of queries are packed
+// on `threads` threads.
 void pack_query_strands(uint32_t strands, uint32_t n, const uint8_t *const *seq,
                         const uint32_t *len, const int32_t *max_subs, const int32_t *max_n,
                         uint32_t qid_base, std::vector<QSDesc> &qs, std::vector<uint32_t> &words,
-                        uint32_t &lmax)
+                        uint32_t &lmax, unsigned threads)
 {
+    const uint32_t ns = (strands & 1u) + ((strands >> 1) & 1u);
+    const size_t q0 = qs.size();
+    std::vector<size_t> woff(n + 1);
+    woff[0] = words.size();
     for (uint32_t j = 0; j < n; j++) {
-        const uint32_t L = len[j];
-        lmax = std::max(lmax, L);
-        uint8_t code[IFA_MAX_QUERY_LEN];
-        for (uint32_t i = 0; i < L; i++) code[i] = kCode.c[seq[j][i]];
-        for (uint32_t s = 0; s < 2; s++) {
-            if (!(strands & (1u << s))) continue;
-            QSDesc d{};
-            d.qid = qid_base + j;
-            d.len = (uint16_t)L;
-            d.strand = (uint8_t)s;
-            d.nw = (uint8_t)((L + 31) / 32);
-            d.k = (uint16_t)std::min<int64_t>(max_subs[j], L);
-            int64_t mn = max_n ? max_n[j] : (int64_t)(L / 4);
-            d.maxn = (uint16_t)std::min<int64_t>(mn, L);
-            d.woff = (uint32_t)words.size();
-            words.resize(words.size() + 3u * d.nw, 0u);
-            uint32_t *W = words.data() + d.woff;
-            for (uint32_t i = 0; i < L; i++) {
-                // strand 1: reverse complement; complementing flips the hi
-                // bit of the code (A<->T, C<->G), N stays N
-                uint32_t v = s == 0 ? code[i] : code[L - 1 - i];
-                if (s == 1 && v < 4) v ^= 2u;
-                uint32_t t = i >> 5, bit = 1u << (i & 31);
-                if (v == 4) {
-                    W[3 * t + 2] |= bit;
-                } else {
-                    if (v & 2) W[3 * t] |= bit;
-                    if (v & 1) W[3 * t + 1] |= bit;
-                }
-            }
-            d.qh0 = W[0];
-            d.ql0 = W[1];
-            d.qn0 = W[2];
-            // the filter counts mismatches over the first min(L, 32) bases
-            d.thr = d.k;
-            qs.push_back(d);
-        }
+        lmax = std::max(lmax, len[j]);
+        woff[j + 1] = woff[j] + (size_t)ns * 3u * ((len[j] + 31) / 32);
     }
+    qs.resize(q0 + (size_t)ns * n);
+    words.resize(woff[n], 0u);
+    const size_t block = 1024;
+    parallel_for(threads, (n + block - 1) / block, [&](size_t bi) {
+        const uint32_t j1 = (uint32_t)std::min<size_t>(n, (bi + 1) * block);
+        for (uint32_t j = (uint32_t)(bi * block); j < j1; j++) {
+            const uint32_t L = len[j];
+            uint8_t code[IFA_MAX_QUERY_LEN];
+            for (uint32_t i = 0; i < L; i++) code[i] = kCode.c[seq[j][i]];
+            uint32_t si = 0;
+            for (uint32_t s = 0; s < 2; s++) {
+                if (!(strands & (1u << s))) continue;
+                QSDesc d{};
+                d.qid = qid_base + j;
+                d.len = (uint16_t)L;
+                d.strand = (uint8_t)s;
+                d.nw = (uint8_t)((L + 31) / 32);
+                d.k = (uint16_t)std::min<int64_t>(max_subs[j], L);
+                int64_t mn = max_n ? max_n[j] : (int64_t)(L / 4);
+                d.maxn = (uint16_t)std::min<int64_t>(mn, L);
+                d.woff = (uint32_t)(woff[j] + (size_t)si * 3u * d.nw);
+                uint32_t *W = words.data() + d.woff;
+                for (uint32_t i = 0; i < L; i++) {
+                    // strand 1: reverse complement; complementing flips the hi
+                    // bit of the code (A<->T, C<->G), N stays N
+                    uint32_t v = s == 0 ? code[i] : code[L - 1 - i];
+                    if (s == 1 && v < 4) v ^= 2u;
+                    uint32_t t = i >> 5, bit = 1u << (i & 31);
+                    if (v == 4) {
+                        W[3 * t + 2] |= bit;
+                    } else {
+                        if (v & 2) W[3 * t] |= bit;
+                        if (v & 1) W[3 * t + 1] |= bit;
+                    }
+                }
+                d.qh0 = W[0];
+                d.ql0 = W[1];
+                d.qn0 = W[2];
+                // the filter counts mismatches over the first min(L, 32) bases
+                d.thr = d.k;
+                qs[q0 + (size_t)ns * j + si] = d;
+                si++;
+            }
+        }
+    });
 }
 
 // Make qs / words the context's query table. Partition: strands whose filter
@@ -1266,7 +1282,7 @@ void install_seeds(ifa_ctx *c, uint32_t n, const uint32_t *len, const int32_t *m
     std::vector<QSDesc> fq;
     std::vector<uint32_t> fw, foff(n);
     uint32_t lmax = 0;
-    pack_query_strands(1u, n, seq, len, max_subs, max_n, 0, fq, fw, lmax);
+    pack_query_strands(1u, n, seq, len, max_subs, max_n, 0, fq, fw, lmax, c->threads);
     for (uint32_t j = 0; j < n; j++) foff[j] = fq[j].woff;
     SeedBuild b;
     build_seeds(c->seedp, n, len, max_subs, c->h_qs, c->h_qwords, fw, foff, c->threads,
@@ -1500,7 +1516,8 @@ ifa_status ifa_load_queries(ifa_ctx *c, uint32_t n, const uint8_t *const *seq,
         std::vector<QSDesc> qs;
         std::vector<uint32_t> words;
         uint32_t lmax = 0;
-        pack_query_strands(c->cfg.strands, n, seq, len, max_subs, max_n, 0, qs, words, lmax);
+        pack_query_strands(c->cfg.strands, n, seq, len, max_subs, max_n, 0, qs, words, lmax,
+                           c->threads);
         c->indexed = indexed;
         install_queries(c, std::move(qs), std::move(words), n, lmax);
         if (indexed) install_seeds(c, n, len, max_subs, seq, max_n);
@@ -2137,7 +2154,7 @@ ifa_status ifa_server_submit(ifa_server *S, uint32_t n, const uint8_t *const *se
         r->id = S->next_id++;
         r->n_queries = n;
         pack_query_strands(c->cfg.strands, n, seq, len, max_subs, max_n, 0, r->qs, r->words,
-                           r->lmax);
+                           r->lmax, c->threads);
         r->est_hits = expected_hits(*r, c->resident_bases);
         if (request_id) *request_id = r->id;
         S->pending.push_back(std::move(r));

@@ -157,6 +157,80 @@ void parallel_for(size_t n, unsigned threads, F &&f)
     for (auto &th : pool) th.join();
 }
 
+// f(b) for every block b in [0, nb), blocks handed out one at a time to up to
+// `threads` threads
+template <class F>
+void parallel_blocks(size_t nb, unsigned threads, F &&f)
+{
+    const unsigned nt = (unsigned)std::max<size_t>(1, std::min<size_t>(threads, nb));
+    std::atomic<size_t> next{0};
+    auto run = [&]() {
+        for (size_t b; (b = next.fetch_add(1)) < nb;) f(b);
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nt; t++) pool.emplace_back(run);
+    run();
+    for (auto &th : pool) th.join();
+}
+
+// Stable counting sort of (keys[e], tags[e]) into buckets (key * golden) >>
+// (32 - bits): dir[b] = first entry of bucket b, dir[2^bits] = n; ent holds
+// (key, tag) pairs, a bucket's entries in input order. Two passes, both
+// parallel: a partition by the top bits of the bucket (per-slice counts, so
+// each slice scatters in input order), then each partition sorted on its own.
+void bucket_sort(const TableBuf &keys, const TableBuf &tags, uint32_t bits, unsigned threads,
+                 TableBuf &dir, TableBuf &ent)
+{
+    const size_t n = keys.size();
+    const uint32_t sh = 32 - bits;
+    const uint32_t pbits = std::min<uint32_t>(bits, 8), nparts = 1u << pbits;
+    const uint32_t lbits = bits - pbits;              // bucket bits inside a partition
+    auto bucket = [&](uint32_t key) { return (key * 0x9E3779B1u) >> sh; };
+    const size_t nslices = std::max<size_t>(1, std::min<size_t>(4 * threads, n / 4096 + 1));
+    // per slice and partition: entry count, then scatter offset
+    std::vector<size_t> off(nslices * nparts, 0);
+    parallel_blocks(nslices, threads, [&](size_t t) {
+        size_t *o = off.data() + t * nparts;
+        for (size_t e = n * t / nslices; e < n * (t + 1) / nslices; e++) o[bucket(keys[e]) >> lbits]++;
+    });
+    std::vector<size_t> pstart(nparts + 1, 0);
+    size_t acc = 0;
+    for (uint32_t p = 0; p < nparts; p++) {
+        pstart[p] = acc;
+        for (size_t t = 0; t < nslices; t++) {
+            const size_t c = off[t * nparts + p];
+            off[t * nparts + p] = acc;
+            acc += c;
+        }
+    }
+    pstart[nparts] = acc;
+    TableBuf k2(n), t2(n);
+    parallel_blocks(nslices, threads, [&](size_t t) {
+        size_t *o = off.data() + t * nparts;
+        for (size_t e = n * t / nslices; e < n * (t + 1) / nslices; e++) {
+            const size_t at = o[bucket(keys[e]) >> lbits]++;
+            k2[at] = keys[e];
+            t2[at] = tags[e];
+        }
+    });
+    dir.resize(((size_t)1 << bits) + 1);   // every bucket start is written below
+    ent.resize(2 * n);
+    parallel_blocks(nparts, threads, [&](size_t p) {
+        const size_t lo = pstart[p], hi = pstart[p + 1];
+        const uint32_t b0 = (uint32_t)p << lbits, nb = 1u << lbits;
+        std::vector<uint32_t> cnt(nb + 1, 0);
+        for (size_t e = lo; e < hi; e++) cnt[bucket(k2[e]) - b0 + 1]++;
+        for (uint32_t b = 0; b < nb; b++) cnt[b + 1] += cnt[b];
+        for (uint32_t b = 0; b < nb; b++) dir[b0 + b] = (uint32_t)(lo + cnt[b]);
+        for (size_t e = lo; e < hi; e++) {
+            const size_t at = lo + cnt[bucket(k2[e]) - b0]++;
+            ent[2 * at] = k2[e];
+            ent[2 * at + 1] = t2[e];
+        }
+    });
+    dir[(size_t)1 << bits] = (uint32_t)n;
+}
+
 }  // namespace
 
 void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
@@ -281,14 +355,12 @@ void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
         uint32_t bits = 4;
         while (bits < 24 && (1ull << bits) < 2 * n_ent) bits++;
         c.bits = bits;
-        const uint32_t sh = 32 - bits;
-        c.dir.assign((1u << bits) + 1, 0);
         // keys of every seed of this length, strands in order (each strand's
         // slice located by a prefix sum of its seed count), in parallel
         std::vector<size_t> first(qs.size() + 1, 0);
         for (size_t q = 0; q < qs.size(); q++)
             first[q + 1] = first[q] + (out.info[q].k == c.k ? nvalid[q] : 0);
-        std::vector<uint32_t> keys(n_ent), tags(n_ent);
+        TableBuf keys(n_ent), tags(n_ent);
         parallel_for(qs.size(), threads, [&](size_t q) {
             if (out.info[q].k != c.k) return;
             const QSDesc &d = qs[q];
@@ -300,15 +372,7 @@ void build_seeds(const SeedParams &P, uint32_t n_queries, const uint32_t *qlen,
                     tags[at_++] = ((uint32_t)q << 8) | i;
                 }
         });
-        for (size_t e = 0; e < n_ent; e++) c.dir[((keys[e] * 0x9E3779B1u) >> sh) + 1]++;
-        for (uint32_t b = 0; b < (1u << bits); b++) c.dir[b + 1] += c.dir[b];
-        std::vector<uint32_t> fill(c.dir.begin(), c.dir.end() - 1);
-        c.ent.assign(2 * keys.size(), 0);
-        for (size_t e = 0; e < keys.size(); e++) {
-            const uint32_t at_ = fill[(keys[e] * 0x9E3779B1u) >> sh]++;
-            c.ent[2 * (size_t)at_] = keys[e];
-            c.ent[2 * (size_t)at_ + 1] = tags[e];
-        }
+        bucket_sort(keys, tags, bits, threads, c.dir, c.ent);
     }
 }
 

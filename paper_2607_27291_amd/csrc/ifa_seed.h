@@ -2,7 +2,10 @@
 #pragma once
 #include <cstdint>
 #include <map>
+#include <memory>
+#include <new>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "ifa_dev.h"
@@ -25,6 +28,31 @@ struct SeedParams {
     uint32_t auto_queries = kAutoQueries;
 };
 
+// Allocator whose value-less construct leaves the element uninitialised: the
+// seed tables (hundreds of MB) are written whole after sizing, so zeroing
+// them first would only cost time.
+template <class T>
+struct DefaultInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = DefaultInitAlloc<U>;
+    };
+    DefaultInitAlloc() = default;
+    template <class U>
+    DefaultInitAlloc(const DefaultInitAlloc<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept
+    {
+        ::new ((void *)p) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a)
+    {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+using TableBuf = std::vector<uint32_t, DefaultInitAlloc<uint32_t>>;
+
 // MinHits results by (valid seeds, maxSubs, k) for the current parameters.
 using MinHitsCache = std::map<std::tuple<uint32_t, uint32_t, uint32_t>, int64_t>;
 
@@ -34,8 +62,8 @@ struct SeedBuild {
     std::vector<uint32_t> qthr;      // per query and strand: threshold (0: not scanned)
     struct Cfg {
         uint32_t k = 0, bits = 0;
-        std::vector<uint32_t> dir;   // 2^bits + 1 bucket starts
-        std::vector<uint32_t> ent;   // (key, strand << 8 | offset) pairs
+        TableBuf dir;                // 2^bits + 1 bucket starts
+        TableBuf ent;                // (key, strand << 8 | offset) pairs
     };
     std::vector<Cfg> cfg;
 };
