@@ -356,6 +356,45 @@ def test_dense_and_sparse_strands_with_work_list_overflow(ifa, orc, sink):
     assert len(want) > 1000
 
 
+@pytest.mark.parametrize("n_two,n_one", [(40, 0), (16, 20), (17, 20)])
+def test_two_word_batches_run_their_own_launch(ifa, orc, n_two, n_one):
+    """Strands filtered on a 64-base prefix (L 64, maxSubs 16) sort ahead of
+    the one-word ones (L 30, maxSubs 2), and the batches of 32 strands holding
+    them run the two-word filter while the rest run the one-word filter:
+    every batch two-word; two-word strands filling exactly one batch; and one
+    query more, so that a batch mixes both kinds."""
+    import synth
+    spec = synth.c2_spec(seed=95, total=800_000)
+    spec.n_param = 1e-3
+    ref = synth.gen_reference(spec)
+    rng = random.Random(95 + n_two + n_one)
+    qs = [rand_dna(rng, 64) for _ in range(n_two)] + [rand_dna(rng, 30) for _ in range(n_one)]
+    ks = [16] * n_two + [2] * n_one
+    buf = bytearray(ref.buf.tobytes())
+    for qi, q in enumerate(qs):          # near copies, so that both kinds have hits
+        c = rng.randrange(ref.n_contigs)
+        n = int(ref.lens[c])
+        p = int(ref.offs[c]) + rng.randint(0, n - len(q))
+        src = bytearray(q if qi % 2 else q.translate(COMP)[::-1])
+        for j in rng.sample(range(len(q)), ks[qi]):
+            src[j] = rng.choice(b"ACGT")
+        buf[p:p + len(q)] = src
+    ref = synth.Reference(np.frombuffer(bytes(buf), dtype=np.uint8).copy(), ref.offs, ref.lens)
+    want = orc.scan(qs, ref, ks)
+    assert len(want) >= len(qs)
+    for v in range(ifa.ifa_variant_count()):
+        if ifa.ifa_variant_info(v)["encoding"] != 2:
+            continue
+        say(f"two-word batches: {n_two} two-word, {n_one} one-word queries, variant {v}")
+        with ifa.Scanner(chunk_bases=1 << 18) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries(qs, ks)
+            strands, filtered = ifa.ifa_query_partition(s.ctx)
+            assert (strands, filtered) == (2 * len(qs), 2 * len(qs))
+            s.scan_chunk(ref)
+            assert_same(s.collect(), want, f"variant {v}")
+
+
 def test_dense_strands_where_every_window_hits(ifa, orc):
     """maxSubs >= L: every window of every plain lane is a hit, so the dense
     kernel's per-wave hit list is full (64 lanes x W windows) for every
