@@ -77,7 +77,9 @@ def parse():
     ap.add_argument("--read-len", type=int, default=150, help="idx: read length")
     ap.add_argument("--requests", type=int, default=50, help="c5: requests in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="c5: Poisson arrivals per second")
-    ap.add_argument("--chunk-bases", type=int, default=1 << 28, help="c5: resident chunk size")
+    ap.add_argument("--chunk-bases", type=int, default=None,
+                    help="device chunk size in bases (c2, c3: the library default 2^30 unless "
+                         "given; c5: 2^28 unless given)")
     ap.add_argument("--total", type=int, default=0, help="reference bases (0 = workload default)")
     ap.add_argument("--queries", type=int, default=0, help="query count (0 = workload default)")
     ap.add_argument("--ks", default="0,4,8", help="c2: maxSubs values, one pass each")
@@ -163,6 +165,11 @@ def calib_mfma():
             out[key] = round(t, 1)
             log(f"{key}: {t:.1f} TFLOP/s")
     return out
+
+
+def chunk_kw(args):
+    """Scanner keyword for an explicit --chunk-bases (else the library default)."""
+    return {"chunk_bases": args.chunk_bases} if args.chunk_bases else {}
 
 
 def choose_variant(ifa, s, args, queries, ks):
@@ -350,7 +357,7 @@ def run_c2(args):
         f"{len(w.plants)} planted copies ({time.time() - t0:.1f} s)")
     nq = len(w.queries)
 
-    s = ifa.Scanner(device=0, flags=scanner_flags(ifa, args))
+    s = ifa.Scanner(device=0, flags=scanner_flags(ifa, args), **chunk_kw(args))
     t0 = time.time()
     s.ref_load(w.ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
@@ -436,7 +443,8 @@ def run_c3(args):
     t0 = time.time()
     w = synth.c3_batched(total=total, n_queries=nq, median=args.median or 3e6)
     log(f"generated {w.ref.total / 1e9:.2f} Gbp, {nq} queries ({time.time() - t0:.1f} s)")
-    s = ifa.Scanner(device=0, sink=ifa.IFA_SINK_COUNT_DIGEST, flags=scanner_flags(ifa, args))
+    s = ifa.Scanner(device=0, sink=ifa.IFA_SINK_COUNT_DIGEST, flags=scanner_flags(ifa, args),
+                    **chunk_kw(args))
     s.ref_load(w.ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
     tune = choose_variant(ifa, s, args, w.queries, w.max_subs)
@@ -590,7 +598,7 @@ def run_c5(args):
     t0 = time.time()
     ref = synth.gen_reference(synth.c5_spec(total=total))
     log(f"generated {ref.total / 1e9:.1f} Gbp ({time.time() - t0:.1f} s)")
-    s = ifa.Scanner(device=0, chunk_bases=args.chunk_bases)
+    s = ifa.Scanner(device=0, chunk_bases=args.chunk_bases or (1 << 28))
     s.ref_load(ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
     del ref
