@@ -242,3 +242,31 @@ def test_auto_mode_follows_the_query_count(ifa, orc):
                 assert ifa.ifa_query_mode(s.ctx) == 0
                 want = orc.scan(qs[:n], contigs, ks[:n])
             assert_same(got, want, f"auto {n}")
+
+
+def test_indexed_many_queries(ifa, orc):
+    """2,000 reads cut from the reference with up to 4 substitutions: the seed
+    tables hold a few hundred thousand entries, so the host builds them in
+    many slices and every one of the 256 top-bit partitions. Seed lengths,
+    thresholds and hits match the oracle's."""
+    rng = random.Random(3600)
+    contigs = [rand_dna(rng, 60000) for _ in range(2)]
+    qs = []
+    for _ in range(2000):
+        c = rng.randrange(2)
+        L = rng.choice([60, 100])
+        p = rng.randint(0, 60000 - L)
+        q = bytearray(contigs[c][p:p + L])
+        for i in rng.sample(range(L), rng.randint(0, 4)):
+            q[i] = rng.choice(b"ACGT")
+        qs.append(bytes(q) if rng.random() < 0.5 else revcomp(bytes(q)))
+    ks = [rng.randint(0, 4) for _ in qs]
+    params = dict(iters=2000)
+    seeds, thr = oracle_seeds(orc, qs, ks, params)
+    want = orc.scan(qs, contigs, ks, seeds=seeds)
+    assert len(want) >= 1000
+    say("indexed mode, 2,000 queries")
+    k, gthr, got = run_indexed(ifa, qs, contigs, ks, params=params, chunk_bases=1 << 16)
+    assert list(k) == seeds["k"]
+    assert np.array_equal(gthr, thr)
+    assert_same(got, want, "2,000 queries")
