@@ -82,8 +82,26 @@ struct SeedTable {
     uint32_t bits;
     const uint32_t *dir;
     const uint2 *ent;
+    // presence bitmap of the table's keys: bit seed_bit(key) is set for every
+    // key of the table (a key absent from it needs no directory read)
+    const uint32_t *bm;
+    uint32_t key_bits;    // 2 (k - mask): bits of a key
+    uint32_t pad;
 };
-static_assert(sizeof(SeedTable) == 24, "SeedTable layout");
+static_assert(sizeof(SeedTable) == 40, "SeedTable layout");
+
+// Keys of up to kSeedBitmapBits bits index the presence bitmap directly (it
+// is exact); longer keys index it by the top kSeedBitmapBits bits of their
+// Fibonacci hash (a one-hash Bloom filter). Bitmap bits: 2^min(key_bits, 28).
+constexpr uint32_t kSeedBitmapBits = 28;
+__host__ __device__ inline uint32_t seed_bitmap_bits(uint32_t key_bits)
+{
+    return key_bits < kSeedBitmapBits ? key_bits : kSeedBitmapBits;
+}
+__host__ __device__ inline uint32_t seed_bit(uint32_t key, uint32_t key_bits)
+{
+    return key_bits <= kSeedBitmapBits ? key : (key * 0x9E3779B1u) >> (32u - kSeedBitmapBits);
+}
 
 // Work item of the sparse path: wave `wave` of the filter grid has at least
 // one candidate window for the query strands qb + j, j a set bit of `pending`.

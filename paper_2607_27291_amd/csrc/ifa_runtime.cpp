@@ -36,6 +36,8 @@ hipError_t launch_edge(const ScanArgs &a, hipStream_t s);
 hipError_t launch_seed(const ScanArgs &a, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
 hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s);
+hipError_t launch_seed_bitmap(const uint2 *ent, uint32_t n, uint32_t *bm, uint32_t words,
+                              uint32_t key_bits, hipStream_t s);
 uint32_t variant_count();
 uint32_t variant_default();
 void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg, uint32_t *enc);
@@ -258,7 +260,7 @@ struct ifa_ctx {
     MinHitsCache mh_cache;
     SeedBuild seeds;
     DevBuf<SeedInfo> d_seed_info;
-    DevBuf<uint32_t> d_seed_dir[kMaxSeedCfg], d_seed_ent[kMaxSeedCfg];
+    DevBuf<uint32_t> d_seed_dir[kMaxSeedCfg], d_seed_ent[kMaxSeedCfg], d_seed_bm[kMaxSeedCfg];
     DevBuf<SeedTable> d_seed_tab;     // [kMaxSeedCfg]
 
     // streaming
@@ -1322,6 +1324,15 @@ void install_seeds(ifa_ctx *c, uint32_t n, const uint32_t *len, const int32_t *m
         tab[i].bits = b.cfg[i].bits;
         tab[i].dir = c->d_seed_dir[i].p;
         tab[i].ent = reinterpret_cast<const uint2 *>(c->d_seed_ent[i].p);
+        // presence bitmap, built on the device from the uploaded entries
+        const uint32_t key_bits = 2u * (b.cfg[i].k - c->seedp.mask);
+        const size_t words = std::max<size_t>(1, ((size_t)1 << seed_bitmap_bits(key_bits)) / 32);
+        if (c->d_seed_bm[i].n < words) c->d_seed_bm[i].alloc(words, "seed presence bitmap");
+        hip_check(launch_seed_bitmap(tab[i].ent, (uint32_t)(b.cfg[i].ent.size() / 2),
+                                     c->d_seed_bm[i].p, (uint32_t)words, key_bits, c->comp_s),
+                  "seed presence bitmap");
+        tab[i].bm = c->d_seed_bm[i].p;
+        tab[i].key_bits = key_bits;
     }
     if (!c->d_seed_tab.p) c->d_seed_tab.alloc(kMaxSeedCfg, "seed table descriptors");
     hip_check(hipMemcpyAsync(c->d_seed_tab.p, tab, sizeof tab, hipMemcpyHostToDevice, c->comp_s),
@@ -1882,7 +1893,7 @@ ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
     b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
     b += c->d_seed_info.n * sizeof(SeedInfo) + c->d_seed_tab.n * sizeof(SeedTable);
     for (size_t i = 0; i < kMaxSeedCfg; i++)
-        b += (c->d_seed_dir[i].n + c->d_seed_ent[i].n) * sizeof(uint32_t);
+        b += (c->d_seed_dir[i].n + c->d_seed_ent[i].n + c->d_seed_bm[i].n) * sizeof(uint32_t);
     for (const auto &r : c->resident)
         b += r->planes.n * sizeof(uint32_t) + r->pieces.n * sizeof(Piece);
     *bytes = b;

@@ -1364,6 +1364,8 @@ __global__ __launch_bounds__(256) void scan_seed_kernel(ScanArgs a)
                 if (funnel(n1, n0, b) & unm) continue;
                 const uint32_t key = (squeeze_mask(funnel(h1, h0, b) & km, lo, a.seed_mask) << u) |
                                      squeeze_mask(funnel(l1, l0, b) & km, lo, a.seed_mask);
+                const uint32_t bit = seed_bit(key, tab.key_bits);
+                if (!((tab.bm[bit >> 5] >> (bit & 31u)) & 1u)) continue;
                 const uint32_t bk = (key * 0x9E3779B1u) >> (32u - bits);
                 const uint32_t e1 = dir[bk + 1];
                 for (uint32_t e = dir[bk]; e < e1; e++) {
@@ -1372,6 +1374,17 @@ __global__ __launch_bounds__(256) void scan_seed_kernel(ScanArgs a)
                 }
             }
         }
+    }
+}
+
+// Sets the presence bit of every key of a seed table's n entries (the
+// bitmap cleared before).
+__global__ void seed_bitmap_kernel(const uint2 *ent, uint32_t n, uint32_t *bm, uint32_t key_bits)
+{
+    const uint32_t lanes = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += lanes) {
+        const uint32_t bit = seed_bit(ent[i].x, key_bits);
+        atomicOr(&bm[bit >> 5], 1u << (bit & 31u));
     }
 }
 
@@ -1564,6 +1577,18 @@ hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(clear_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// Presence bitmap of a seed table: `words` 32-bit words (2^seed_bitmap_bits
+// bits, at least one word) cleared, then one bit set per entry.
+hipError_t launch_seed_bitmap(const uint2 *ent, uint32_t n, uint32_t *bm, uint32_t words,
+                              uint32_t key_bits, hipStream_t s)
+{
+    hipError_t e = launch_clear_u32(bm, words, s);
+    if (e != hipSuccess || n == 0) return e;
+    const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(seed_bitmap_kernel, dim3(blocks), dim3(256), 0, s, ent, n, bm, key_bits);
     return hipGetLastError();
 }
 
