@@ -110,6 +110,8 @@ def oracle_seeds(orc, qs, ks, params, strands=3):
     dict(iters=3000, prob_ppm=1_000_000),
     dict(iters=2000, mask=3, ks=(9, 11, 13), prob_ppm=990_000),
     dict(iters=2000, step=2, ks=(6, 8, 10)),
+    # keys of 30 and 32 bits: the presence bitmap is indexed by the key's hash
+    dict(iters=2000, ks=(15, 16), prob_ppm=1_000_000),
 ])
 def test_indexed_seeds_and_hits_match_oracle(ifa, orc, params):
     rng = random.Random(3100 + len(str(params)))
