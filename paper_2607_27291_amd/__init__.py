@@ -202,10 +202,30 @@ def _bytes(x) -> bytes:
 
 
 class _SeqArray:
-    """Pointer + length arrays over a list of byte sequences (kept alive)."""
+    """Pointer + length arrays over a list of byte sequences (kept alive).
+    A list of bytes objects of up to JOIN_BYTES in all is joined into one
+    buffer and its pointers are the buffer's address plus offsets; other
+    items are wrapped one by one (no copy)."""
+
+    JOIN_BYTES = 1 << 26
 
     def __init__(self, seqs, len_dtype):
         self.keep = []
+        lens = None
+        if isinstance(seqs, (list, tuple)) and seqs and all(type(x) is bytes for x in seqs):
+            lens = np.fromiter(map(len, seqs), dtype=np.uint64, count=len(seqs))
+            if int(lens.sum()) > self.JOIN_BYTES:
+                lens = None
+        if lens is not None:
+            buf = np.frombuffer(b"".join(seqs) or b"\0", dtype=np.uint8)
+            offs = np.zeros(len(seqs), dtype=np.uint64)
+            np.cumsum(lens[:-1], out=offs[1:])
+            addr = np.uint64(buf.ctypes.data) + offs
+            self.keep = [buf, addr]
+            self.n = len(seqs)
+            self.ptrs = addr.ctypes.data_as(ctypes.POINTER(ctypes.c_void_p))
+            self.lens = lens.astype(len_dtype)
+            return
         ptrs, lens = [], []
         for s in seqs:
             if isinstance(s, np.ndarray):
