@@ -88,3 +88,40 @@ def test_index_params_defaults_are_the_papers():
     assert (p.iters, p.prob_ppm, p.mask, p.step) == (200_000, 999_000, 0, 1)
     assert p.auto_queries >= 1
     assert ctypes.sizeof(ifa.IfaIndexParams) == 72
+
+
+def test_sequence_marshalling_paths_agree():
+    """The binding passes a list of bytes through one joined buffer (pointers
+    = its address + offsets) and any other sequence list item by item; both
+    must hand the C side the same bytes and lengths, empty items included,
+    and an oversized list must fall back to the item-by-item path."""
+    import ctypes
+    import random
+
+    import numpy as np
+    import paper_2607_27291_amd as m
+
+    rng = random.Random(17)
+    seqs = [bytes(rng.choice(b"ACGTN") for _ in range(rng.choice([0, 1, 5, 31, 32, 33, 150])))
+            for _ in range(500)]
+
+    def contents(sa):
+        ptrs = ctypes.cast(sa.ptrs, ctypes.POINTER(ctypes.c_void_p))
+        return [ctypes.string_at(ptrs[i], int(sa.lens[i])) if int(sa.lens[i]) else b""
+                for i in range(sa.n)]
+
+    joined = m._SeqArray(seqs, np.uint32)
+    assert isinstance(joined.keep[0], np.ndarray) and len(joined.keep) == 2
+    itemwise = m._SeqArray([bytearray(s) for s in seqs], np.uint32)
+    assert len(itemwise.keep) == len(seqs)
+    assert joined.n == itemwise.n == len(seqs)
+    assert np.array_equal(joined.lens, itemwise.lens) and joined.lens.dtype == np.uint32
+    assert contents(joined) == contents(itemwise) == seqs
+    old = m._SeqArray.JOIN_BYTES
+    try:
+        m._SeqArray.JOIN_BYTES = 100       # force the fallback for the same list
+        fallback = m._SeqArray(seqs, np.uint64)
+    finally:
+        m._SeqArray.JOIN_BYTES = old
+    assert len(fallback.keep) == len(seqs) and fallback.lens.dtype == np.uint64
+    assert contents(fallback) == seqs
