@@ -94,14 +94,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1,
                     help="scan kernel variant (default: autotuned on the workload's queries)")
-    ap.add_argument("--calib-valu", action="store_true",
-                    help="measure the issue rate of the scan's VALU instructions and exit")
     ap.add_argument("--graphs", action="store_true",
                     help="resident workloads: replay repeated passes from captured HIP graphs "
                          "(faster by a few percent; HIP events inside a graph overstate the "
                          "filter kernel's time, so the roofline figure is then conservative)")
-    ap.add_argument("--calib-mfma", action="store_true",
-                    help="measure the rate of the fp4 matrix-core instructions and exit")
     ap.add_argument("--tune-cache", default="",
                     help="autotuner cache file (a later run with the same queries reuses "
                          "its choice)")
@@ -122,49 +118,6 @@ def calib_copy():
         raise RuntimeError(f"calibration copy failed: HIP error {rc}")
     log(f"calib copy: 1 GiB read + 1 GiB write per launch, {ms.value:.3f} ms "
         f"({2 * (1 << 30) / ms.value / 1e6:.0f} GB/s)")
-
-
-def calib_valu():
-    """Issue rate of each instruction kind the filter uses (bitop3, alignbit,
-    bcnt, min3, xor): 16 independent chains per thread, 64 waves per CU."""
-    import ctypes
-    from paper_2607_27291_amd import build as b
-    L = ctypes.CDLL(b.CALIB_LIB)
-    L.ifa_calib_valu.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
-    L.ifa_calib_valu.restype = ctypes.c_double
-    out = {}
-    names = ["v_bitop3_b32", "v_alignbit_b32", "v_bcnt_u32_b32", "v_min3_u32", "v_xor_b32",
-             "v_bitop3_b32 (self chains)", "v_xor_b32 + v_bcnt_u32_b32 (self chains)"]
-    for op, name in enumerate(names):
-        for blocks in (256 * 8, 256 * 32):
-            g = L.ifa_calib_valu(op, blocks, 4096)
-            if g < 0:
-                raise RuntimeError(f"VALU probe {name} failed: HIP error {-g}")
-            key = f"{name} @{blocks // 256} blocks/CU"
-            out[key] = round(g / 1e3, 3)
-            log(f"{key}: {g / 1e3:.2f} T lane-ops/s")
-    return out
-
-
-def calib_mfma():
-    """Sustained rate of the fp4 (e2m1) MFMA instructions, four independent
-    accumulators per wave, at 8 and 32 workgroups of 256 threads per CU."""
-    import ctypes
-    from paper_2607_27291_amd import build as b
-    L = ctypes.CDLL(b.CALIB_LIB)
-    L.ifa_calib_mfma.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32]
-    L.ifa_calib_mfma.restype = ctypes.c_double
-    out = {}
-    for shape, name in enumerate(["v_mfma_scale_f32_32x32x64_f8f6f4 fp4",
-                                  "v_mfma_scale_f32_16x16x128_f8f6f4 fp4"]):
-        for blocks in (256 * 2, 256 * 8):
-            t = L.ifa_calib_mfma(shape, blocks, 2048)
-            if t < 0:
-                raise RuntimeError(f"MFMA probe {name} failed: HIP error {-t}")
-            key = f"{name} @{blocks // 256} blocks/CU"
-            out[key] = round(t, 1)
-            log(f"{key}: {t:.1f} TFLOP/s")
-    return out
 
 
 def chunk_kw(args):
@@ -763,12 +716,6 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is design-only)", file=sys.stderr)
         sys.exit(2)
-    if args.calib_valu:
-        print(json.dumps({"valu_peak_tops": calib_valu()}), flush=True)
-        return
-    if args.calib_mfma:
-        print(json.dumps({"mfma_fp4_tflops": calib_mfma()}), flush=True)
-        return
     if args.calib_copy:
         calib_copy()
     if args.workload == "c2":

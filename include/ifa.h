@@ -56,7 +56,9 @@ extern "C" {
 #endif
 
 #define IFA_ABI_VERSION 2u
-#define IFA_MAX_QUERY_LEN 256u
+/* Longest query: n_ref and the mismatch count of a window then fit the
+ * record's fields (n_ref is one byte). */
+#define IFA_MAX_QUERY_LEN 255u
 
 typedef struct ifa_ctx ifa_ctx;
 

@@ -29,7 +29,7 @@ __all__ = [
 ]
 
 IFA_ABI_VERSION = 2
-IFA_MAX_QUERY_LEN = 256
+IFA_MAX_QUERY_LEN = 255
 IFA_N_SEPARATE, IFA_N_AS_MISMATCH = 0, 1
 IFA_SINK_RECORDS, IFA_SINK_COUNT_DIGEST = 0, 1
 IFA_STRAND_FWD, IFA_STRAND_RC, IFA_STRAND_BOTH = 1, 2, 3

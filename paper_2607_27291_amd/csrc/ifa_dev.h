@@ -17,7 +17,7 @@
 
 namespace ifa {
 
-constexpr uint32_t kMaxLen = 256;          // longest query
+constexpr uint32_t kMaxLen = 256;          // layout bound: queries are at most 255 bases
 constexpr uint32_t kCarry = kMaxLen - 1;   // bases repeated at a split
 constexpr uint32_t kPadWords = 16;         // > (31 + kMaxLen) / 32 + 1
 constexpr uint32_t kMaxQWords = kMaxLen / 32;
@@ -113,8 +113,14 @@ struct WorkItem {
 };
 static_assert(sizeof(WorkItem) == 16, "WorkItem layout");
 
+// N-block flags of a chunk whose planes hold `total` words (padding
+// included): one byte per 32-word block, plus two so that a filter wave may
+// read the flags of the three blocks its words can touch.
+__host__ __device__ inline uint32_t nflag_blocks(uint32_t total) { return (total + 31u) / 32u + 2u; }
+
 struct ScanArgs {
     const uint32_t *hi, *lo, *nm, *em;
+    const uint8_t *nflag;     // per 32-word block: an N bit, or words past the data
     uint64_t chunk_len;       // bases in the chunk
     uint32_t own_from;        // a window is owned only if its last base >= own_from
     uint32_t w_begin, w_end;  // window-start words [w_begin, w_end) to scan

@@ -35,6 +35,8 @@ hipError_t launch_dense(const ScanArgs &a, hipStream_t s);
 hipError_t launch_edge(const ScanArgs &a, hipStream_t s);
 hipError_t launch_seed(const ScanArgs &a, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
+hipError_t launch_expand(uint32_t *planes, uint64_t stride, uint8_t *nflag, uint32_t used,
+                         uint32_t total, const uint4 *list, uint32_t n_list, hipStream_t s);
 hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s);
 hipError_t launch_seed_bitmap(const uint2 *ent, uint32_t n, uint32_t *bm, uint32_t words,
                               uint32_t key_bits, hipStream_t s);
@@ -165,7 +167,9 @@ struct PackTask {
 };
 
 struct Staging {
-    HostBuf<uint32_t> planes;       // 4 * plane_words
+    HostBuf<uint32_t> planes;       // hi, lo and nm planes of plane_words each
+    HostBuf<uint4> list;            // sparse N / piece-end words (seal)
+    uint32_t n_list = 0;
     std::vector<Piece> pieces;
     std::vector<PackTask> tasks;    // not yet packed
     uint64_t len = 0;               // bases used
@@ -193,6 +197,8 @@ struct PassGraph {
 
 struct DevChunk {
     DevBuf<uint32_t> planes;      // 4 planes of `stride` words each
+    DevBuf<uint8_t> nflag;        // N flag per 32-word block (nflag_blocks(stride))
+    DevBuf<uint4> sparse;         // the uploaded sparse N / piece-end list
     DevBuf<Piece> pieces;
     uint64_t stride = 0;
     uint64_t len = 0;
@@ -240,15 +246,22 @@ struct ifa_ctx {
     uint32_t n_sparse = 0;
     std::vector<uint32_t> h_qwords;
     // device query tables, uploaded together through a pinned staging arena:
-    // strand descriptors, packed words, the matrix-core filters' B operands
-    // and required match counts (four- and three-class forms)
+    // strand descriptors, packed words and the three-class filter's words per
+    // column tile
     DevBuf<uint8_t> d_qarena;
     HostBuf<uint8_t> h_qarena;
     const QSDesc *dq_qs = nullptr;
     const uint32_t *dq_words = nullptr;
+    const uint32_t *dq_mq3w = nullptr;
+    // the matrix-core filters' B operands and required match counts, one
+    // arena per form (index 0: four-class, 1: three-class), built when a
+    // pass first needs that form for the loaded query set
+    std::vector<uint8_t> h_fw;        // filter words of each strand (device order)
+    bool mq_ready[2] = {false, false};
+    DevBuf<uint8_t> d_mqarena[2];
+    HostBuf<uint8_t> h_mqarena[2];
     const uint4 *dq_mqb = nullptr, *dq_mq3b = nullptr;
     const float *dq_mqt = nullptr, *dq_mq3t = nullptr;
-    const uint32_t *dq_mq3w = nullptr;
     uint32_t mq3_words = 1;           // most prefix words of any three-class column tile
     uint32_t mq3_two_batches = 0;     // leading batches holding a two-word tile
     uint32_t edge_pmin = 0;           // overhang kernel: pieces per wave (ScanArgs.edge_pmin)
@@ -411,30 +424,82 @@ void pack_pending(ifa_ctx *c, Staging &s)
     c->st.pack_ms += now_ms() - t0;
 }
 
-// Finish the staging chunk: piece-end marks and padding words.
+// Grow a pinned list to hold n entries (its contents are not kept).
+void reserve_list(HostBuf<uint4> &l, size_t n)
+{
+    if (l.n < n) l.alloc(std::max<size_t>(n, l.n * 2), "pinned sparse list");
+}
+
+// The sparse list of a chunk: (word, nm, em, 0) for every used word that
+// holds an N bit or a piece end, in word order. nword: the sorted words with
+// an N bit and their nm values; ends: the sorted piece-end words and bits.
+uint32_t merge_sparse(const std::vector<std::pair<uint32_t, uint32_t>> &nword,
+                      const std::vector<std::pair<uint32_t, uint32_t>> &ends, HostBuf<uint4> &out)
+{
+    reserve_list(out, nword.size() + ends.size() + 1);
+    size_t i = 0, j = 0, n = 0;
+    while (i < nword.size() || j < ends.size()) {
+        uint4 e{0u, 0u, 0u, 0u};
+        if (j >= ends.size() || (i < nword.size() && nword[i].first < ends[j].first)) {
+            e.x = nword[i].first;
+            e.y = nword[i++].second;
+        } else if (i >= nword.size() || ends[j].first < nword[i].first) {
+            e.x = ends[j].first;
+            e.z = ends[j++].second;
+        } else {
+            e.x = nword[i].first;
+            e.y = nword[i++].second;
+            e.z = ends[j++].second;
+        }
+        out.p[n++] = e;
+    }
+    return (uint32_t)n;
+}
+
+// Piece-end words of a chunk (pieces sorted by start), the chunk tail's bits
+// past its last base included (they read as N and as piece ends).
+std::vector<std::pair<uint32_t, uint32_t>> piece_end_words(const std::vector<Piece> &pieces,
+                                                         uint64_t len)
+{
+    std::vector<std::pair<uint32_t, uint32_t>> ends;
+    auto add = [&](uint32_t w, uint32_t bits) {
+        if (!ends.empty() && ends.back().first == w) ends.back().second |= bits;
+        else ends.emplace_back(w, bits);
+    };
+    for (const Piece &p : pieces) {
+        const uint64_t last = p.start + p.len - 1;
+        add((uint32_t)(last >> 5), 1u << (last & 31));
+    }
+    if (len & 31) add((uint32_t)(len >> 5), ~((1u << (len & 31)) - 1u));
+    return ends;
+}
+
+// Finish the staging chunk: bits past the last base (hi = lo = 0, N) and the
+// sparse list of N and piece-end words. The device rebuilds its nm and em
+// planes and the padding from the list (upload).
 void seal(ifa_ctx *c, Staging &s)
 {
-    uint32_t *H = plane(c, s, 0), *Lo = plane(c, s, 1), *N = plane(c, s, 2), *E = plane(c, s, 3);
-    const uint64_t used_words = (s.len + 31) >> 5;
-    std::memset(E, 0, used_words * sizeof(uint32_t));
-    for (const Piece &p : s.pieces) {
-        uint64_t last = p.start + p.len - 1;
-        E[last >> 5] |= 1u << (last & 31);
-    }
+    uint32_t *H = plane(c, s, 0), *Lo = plane(c, s, 1), *N = plane(c, s, 2);
+    const uint64_t used = (s.len + 31) >> 5;
     if (s.len & 31) {
-        uint64_t w = s.len >> 5;
-        uint32_t tail = ~((1u << (s.len & 31)) - 1u);
+        const uint64_t w = s.len >> 5;
+        const uint32_t tail = ~((1u << (s.len & 31)) - 1u);
         H[w] &= ~tail;
         Lo[w] &= ~tail;
         N[w] |= tail;
-        E[w] |= tail;
     }
-    for (uint64_t w = used_words; w < used_words + kPadWords; w++) {
-        H[w] = 0;
-        Lo[w] = 0;
-        N[w] = 0xffffffffu;
-        E[w] = 0xffffffffu;
-    }
+    // words with an N bit, found in parallel over spans of the N plane
+    const uint64_t span = 1ull << 20;
+    const size_t parts = (size_t)((used + span - 1) / span);
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> found(parts);
+    parallel_for(c->threads, parts, [&](size_t i) {
+        const uint64_t w1 = std::min<uint64_t>(used, (i + 1) * span);
+        for (uint64_t w = i * span; w < w1; w++)
+            if (N[w]) found[i].emplace_back((uint32_t)w, N[w]);
+    });
+    std::vector<std::pair<uint32_t, uint32_t>> nword;
+    for (auto &f : found) nword.insert(nword.end(), f.begin(), f.end());
+    s.n_list = merge_sparse(nword, piece_end_words(s.pieces, s.len), s.list);
 }
 
 uint64_t words_with_pad(uint64_t len) { return ((len + 31) >> 5) + kPadWords; }
@@ -456,13 +521,17 @@ double binom_cdf(uint32_t n, double p, uint32_t k)
 // jobs: launch and retire
 // ---------------------------------------------------------------------------
 
+void ensure_filter_operands(ifa_ctx *c);
+
 ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
 {
+    ensure_filter_operands(c);
     ScanArgs a{};
     a.hi = ch.planes.p;
     a.lo = ch.planes.p + ch.stride;
     a.nm = ch.planes.p + 2 * ch.stride;
     a.em = ch.planes.p + 3 * ch.stride;
+    a.nflag = ch.nflag.p;
     a.chunk_len = ch.len;
     a.own_from = ch.own_from;
     a.w_begin = 0;
@@ -791,22 +860,44 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     c->st.chunks++;
 }
 
+// Copy the hi and lo planes of a chunk's `used` words and its sparse list to
+// device chunk d, then rebuild the nm and em planes, padding and N-block
+// flags there, all on `stream`. The host buffers must stay untouched until
+// the stream has passed this point.
+void upload_planes(const uint32_t *hi, const uint32_t *lo, uint64_t used, const uint4 *list,
+                   uint32_t n_list, DevChunk &d, hipStream_t stream)
+{
+    const uint64_t total = used + kPadWords;
+    if (d.stride < total) fail(IFA_E_INVALID, "device chunk too small");
+    if (d.nflag.n < nflag_blocks((uint32_t)d.stride))
+        d.nflag.alloc(nflag_blocks((uint32_t)d.stride), "N-block flags");
+    if (d.sparse.n < n_list) d.sparse.alloc(std::max<size_t>(n_list, 2 * d.sparse.n), "sparse list");
+    hip_check(hipMemcpyAsync(d.planes.p, hi, used * sizeof(uint32_t), hipMemcpyHostToDevice,
+                             stream),
+              "copy hi plane");
+    hip_check(hipMemcpyAsync(d.planes.p + d.stride, lo, used * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, stream),
+              "copy lo plane");
+    if (n_list)
+        hip_check(hipMemcpyAsync(d.sparse.p, list, n_list * sizeof(uint4), hipMemcpyHostToDevice,
+                                 stream),
+                  "copy sparse list");
+    hip_check(launch_expand(d.planes.p, d.stride, d.nflag.p, (uint32_t)used, (uint32_t)total,
+                            d.sparse.p, n_list, stream),
+              "expand chunk planes");
+}
+
 // Copy a sealed staging chunk into a device chunk on the copy stream.
 void upload(ifa_ctx *c, Staging &s, DevChunk &d, hipStream_t stream)
 {
-    const uint64_t words = words_with_pad(s.len);
     if (d.pieces.n < s.pieces.size() || d.pieces.p == nullptr)
         d.pieces.alloc(std::max<size_t>(s.pieces.size(), 1024), "device piece table");
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "event");
     hip_check(hipEventCreate(&e1), "event");
     hip_check(hipEventRecord(e0, stream), "event record");
-    if (d.stride < words) fail(IFA_E_INVALID, "device chunk too small");
-    for (int k = 0; k < 4; k++)
-        hip_check(hipMemcpyAsync(d.planes.p + (size_t)k * d.stride,
-                                 s.planes.p + (size_t)k * c->plane_words,
-                                 words * sizeof(uint32_t), hipMemcpyHostToDevice, stream),
-                  "copy chunk planes");
+    upload_planes(plane(c, s, 0), plane(c, s, 1), (s.len + 31) >> 5, s.list.p, s.n_list, d,
+                  stream);
     if (!s.pieces.empty())
         hip_check(hipMemcpyAsync(d.pieces.p, s.pieces.data(), s.pieces.size() * sizeof(Piece),
                                  hipMemcpyHostToDevice, stream),
@@ -943,7 +1034,7 @@ void validate_queries(uint32_t n, const uint8_t *const *seq, const uint32_t *len
     for (uint32_t j = 0; j < n; j++) {
         if (len[j] == 0 || len[j] > IFA_MAX_QUERY_LEN)
             fail(IFA_E_TOO_LONG, "query " + std::to_string(j) + " has length " +
-                                     std::to_string(len[j]) + " (allowed 1..256)");
+                                     std::to_string(len[j]) + " (allowed 1..255)");
         if (!seq[j]) fail(IFA_E_INVALID, "NULL query pointer");
         if (max_subs[j] < 0) fail(IFA_E_INVALID, "negative max_subs");
         if (max_n && max_n[j] < 0) fail(IFA_E_INVALID, "negative max_n");
@@ -1050,12 +1141,15 @@ uint64_t expected_work_items(const std::vector<QSDesc> &qs, const std::vector<ui
 // (= 2 hi + lo), else 0. need[c] = min(L, 32) - thr: the matches a window
 // must reach to remain a candidate (filter count <= thr).
 void build_mfma_operands(const std::vector<QSDesc> &qs, uint32_t n_sparse,
-                         std::vector<uint32_t> &b, std::vector<float> &need)
+                         std::vector<uint32_t> &b, std::vector<float> &need, unsigned threads)
 {
     const uint32_t n_tiles = (n_sparse + 1) / 2;
     b.assign((size_t)n_tiles * 3 * 64 * 4, 0u);
     need.assign((size_t)n_tiles * 32, 1e30f);
-    for (uint32_t nt = 0; nt < n_tiles; nt++) {
+    const uint32_t block = 4096;
+    parallel_for(threads, (n_tiles + block - 1) / block, [&](size_t bi) {
+    const uint32_t nt1 = (uint32_t)std::min<size_t>(n_tiles, (bi + 1) * block);
+    for (uint32_t nt = (uint32_t)(bi * block); nt < nt1; nt++) {
         for (uint32_t c = 0; c < 32; c++) {
             const uint32_t s = 2 * nt + c / 16, r = c % 16;
             if (s >= n_sparse) continue;
@@ -1073,6 +1167,7 @@ void build_mfma_operands(const std::vector<QSDesc> &qs, uint32_t n_sparse,
                     }
         }
     }
+    });
 }
 
 // Longest filter prefix, in 32-base words (the three-class matrix filter
@@ -1090,20 +1185,29 @@ constexpr uint32_t kFilterWords = 2;
 // there has the slot's class, -1.0 (code 0xA) when it is A, else 0; slot 15
 // stays 0. Layout: b[(((2 nt + w) * 2 + t) * 64 + lane) * 4 + d] (word 1 is
 // zero when W = 1). need[c] = Lf - thr - nA, nA = A bases among the first Lf.
+// Prefix words of each three-class column tile: the most any of its strands needs.
+void mfma3_tile_words(const std::vector<uint8_t> &fw, uint32_t n_sparse,
+                      std::vector<uint32_t> &words)
+{
+    const uint32_t n_tiles = (n_sparse + 3) / 4;
+    words.assign(n_tiles, 1u);
+    for (uint32_t nt = 0; nt < n_tiles; nt++)
+        for (uint32_t s = 4 * nt; s < std::min(n_sparse, 4 * nt + 4); s++)
+            words[nt] = std::max<uint32_t>(words[nt], fw[s]);
+}
+
 void build_mfma3_operands(const std::vector<QSDesc> &qs, const std::vector<uint32_t> &qw,
-                          const std::vector<uint8_t> &fw, uint32_t n_sparse,
-                          std::vector<uint32_t> &b, std::vector<float> &need,
-                          std::vector<uint32_t> &words)
+                          const std::vector<uint32_t> &words, uint32_t n_sparse,
+                          std::vector<uint32_t> &b, std::vector<float> &need, unsigned threads)
 {
     static const uint32_t kClass[3] = {1u, 3u, 2u};
     const uint32_t n_tiles = (n_sparse + 3) / 4;
     b.assign((size_t)n_tiles * kFilterWords * 2 * 64 * 4, 0u);
     need.assign((size_t)n_tiles * 32, 1e30f);
-    words.assign(n_tiles, 1u);
-    for (uint32_t nt = 0; nt < n_tiles; nt++)
-        for (uint32_t s = 4 * nt; s < std::min(n_sparse, 4 * nt + 4); s++)
-            words[nt] = std::max<uint32_t>(words[nt], fw[s]);
-    for (uint32_t nt = 0; nt < n_tiles; nt++) {
+    const uint32_t block = 2048;
+    parallel_for(threads, (n_tiles + block - 1) / block, [&](size_t bi) {
+    const uint32_t nt1 = (uint32_t)std::min<size_t>(n_tiles, (bi + 1) * block);
+    for (uint32_t nt = (uint32_t)(bi * block); nt < nt1; nt++) {
         for (uint32_t c = 0; c < 32; c++) {
             const uint32_t s = 4 * nt + c / 8, r = c % 8;
             if (s >= n_sparse) continue;
@@ -1144,6 +1248,7 @@ void build_mfma3_operands(const std::vector<QSDesc> &qs, const std::vector<uint3
                         }
         }
     }
+    });
 }
 
 // 32-base words of the strand's prefix a filter needs so that it passes a
@@ -1163,6 +1268,68 @@ uint32_t filter_words(const QSDesc &d)
         if (lf == d.len) break;
     }
     return 0;
+}
+
+// One part of a table upload: parts go at 256-byte offsets of one arena.
+struct TablePart {
+    const void *src;
+    size_t bytes;
+};
+
+// Copy `n` parts through the pinned staging `h` into the device arena `d`
+// (both grown as needed) with one copy on the compute stream, after the work
+// already queued there; off[i] gets part i's offset. Returns the arena.
+uint8_t *upload_tables(ifa_ctx *c, HostBuf<uint8_t> &h, DevBuf<uint8_t> &d, const TablePart *parts,
+                       int n, size_t *off, const char *what)
+{
+    size_t total = 0;
+    for (int i = 0; i < n; i++) {
+        off[i] = total;
+        total += (std::max<size_t>(parts[i].bytes, 16) + 255) & ~(size_t)255;
+    }
+    // the staging's previous upload is complete before it is rewritten
+    hip_check(hipStreamSynchronize(c->comp_s), "sync");
+    if (h.n < total) h.alloc(total, "pinned table staging");
+    if (d.n < total) d.alloc(total, what);
+    for (int i = 0; i < n; i++)
+        if (parts[i].bytes) std::memcpy(h.p + off[i], parts[i].src, parts[i].bytes);
+    hip_check(hipMemcpyAsync(d.p, h.p, total, hipMemcpyHostToDevice, c->comp_s), what);
+    return d.p;
+}
+
+// Build and upload the B operands and required counts of the matrix-core
+// filter form the context's variant uses, if the loaded query set does not
+// have them yet (brute-force sets with sparse strands only).
+void ensure_filter_operands(ifa_ctx *c)
+{
+    if (!c->have_queries || c->indexed || c->n_sparse == 0) return;
+    uint32_t wpl, qu, wg, enc;
+    variant_shape(c->variant, &wpl, &qu, &wg, &enc);
+    if (enc != 1 && enc != 2) return;
+    const int f = (int)enc - 1;
+    if (c->mq_ready[f]) return;
+    std::vector<uint32_t> b;
+    std::vector<float> need;
+    size_t off[2];
+    if (enc == 1) {
+        build_mfma_operands(c->h_qs, c->n_sparse, b, need, c->threads);
+    } else {
+        std::vector<uint32_t> mw3;
+        mfma3_tile_words(c->h_fw, c->n_sparse, mw3);
+        build_mfma3_operands(c->h_qs, c->h_qwords, mw3, c->n_sparse, b, need, c->threads);
+    }
+    const TablePart parts[2] = {{b.data(), b.size() * sizeof(uint32_t)},
+                                {need.data(), need.size() * sizeof(float)}};
+    uint8_t *base = upload_tables(c, c->h_mqarena[f], c->d_mqarena[f], parts, 2, off,
+                                  "matrix filter operands");
+    if (enc == 1) {
+        c->dq_mqb = reinterpret_cast<const uint4 *>(base + off[0]);
+        c->dq_mqt = reinterpret_cast<const float *>(base + off[1]);
+    } else {
+        c->dq_mq3b = reinterpret_cast<const uint4 *>(base + off[0]);
+        c->dq_mq3t = reinterpret_cast<const float *>(base + off[1]);
+    }
+    c->mq_ready[f] = true;
 }
 
 void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t> &&words,
@@ -1194,14 +1361,9 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
         if (!dense[i]) n_sparse++;
     }
     qs.swap(sorted);
-    std::vector<uint32_t> mb, mb3, mw3;
-    std::vector<float> mt, mt3;
-    // the matrix-core filters' operands serve brute-force passes only
+    std::vector<uint32_t> mw3;
     const bool indexed = c->indexed;
-    if (!indexed) {
-        build_mfma_operands(qs, n_sparse, mb, mt);
-        build_mfma3_operands(qs, words, sorted_fw, n_sparse, mb3, mt3, mw3);
-    }
+    if (!indexed) mfma3_tile_words(sorted_fw, n_sparse, mw3);
     c->mq3_words = mw3.empty() ? 1u : *std::max_element(mw3.begin(), mw3.end());
     // the tiles filtering on two words lead the list: their batches of 32
     // strands (8 tiles) run the two-word kernel, the others the one-word one
@@ -1214,38 +1376,16 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     for (const QSDesc &d : qs) cmax = std::max<uint32_t>(cmax, std::min<uint32_t>(d.maxn, d.len - 1u));
     c->edge_pmin = cmax == 0 ? 0u : (2u * cmax <= 64u ? 64u / (2u * cmax) : 1u);
     // one upload of every table: parts at 256-byte offsets in one arena
-    struct Part {
-        const void *src;
-        size_t bytes, off;
-    } parts[7] = {{qs.data(), qs.size() * sizeof(QSDesc), 0},
-                  {words.data(), words.size() * sizeof(uint32_t), 0},
-                  {mb.data(), mb.size() * sizeof(uint32_t), 0},
-                  {mt.data(), mt.size() * sizeof(float), 0},
-                  {mb3.data(), mb3.size() * sizeof(uint32_t), 0},
-                  {mt3.data(), mt3.size() * sizeof(float), 0},
-                  {mw3.data(), mw3.size() * sizeof(uint32_t), 0}};
-    size_t total = 0;
-    for (Part &pt : parts) {
-        pt.off = total;
-        total += (std::max<size_t>(pt.bytes, 16) + 255) & ~(size_t)255;
-    }
-    // the arena's previous upload is complete before it is rewritten
-    hip_check(hipStreamSynchronize(c->comp_s), "sync");
-    if (c->h_qarena.n < total) c->h_qarena.alloc(total, "pinned query staging");
-    if (c->d_qarena.n < total) c->d_qarena.alloc(total, "query tables");
-    for (const Part &pt : parts)
-        if (pt.bytes) std::memcpy(c->h_qarena.p + pt.off, pt.src, pt.bytes);
-    hip_check(hipMemcpyAsync(c->d_qarena.p, c->h_qarena.p, total, hipMemcpyHostToDevice,
-                             c->comp_s),
-              "upload query tables");
-    uint8_t *base = c->d_qarena.p;
-    c->dq_qs = reinterpret_cast<const QSDesc *>(base + parts[0].off);
-    c->dq_words = reinterpret_cast<const uint32_t *>(base + parts[1].off);
-    c->dq_mqb = reinterpret_cast<const uint4 *>(base + parts[2].off);
-    c->dq_mqt = reinterpret_cast<const float *>(base + parts[3].off);
-    c->dq_mq3b = reinterpret_cast<const uint4 *>(base + parts[4].off);
-    c->dq_mq3t = reinterpret_cast<const float *>(base + parts[5].off);
-    c->dq_mq3w = reinterpret_cast<const uint32_t *>(base + parts[6].off);
+    const TablePart parts[3] = {{qs.data(), qs.size() * sizeof(QSDesc)},
+                                {words.data(), words.size() * sizeof(uint32_t)},
+                                {mw3.data(), mw3.size() * sizeof(uint32_t)}};
+    size_t off[3];
+    uint8_t *base = upload_tables(c, c->h_qarena, c->d_qarena, parts, 3, off, "query tables");
+    c->dq_qs = reinterpret_cast<const QSDesc *>(base + off[0]);
+    c->dq_words = reinterpret_cast<const uint32_t *>(base + off[1]);
+    c->dq_mq3w = reinterpret_cast<const uint32_t *>(base + off[2]);
+    c->h_fw = std::move(sorted_fw);
+    c->mq_ready[0] = c->mq_ready[1] = false;
     if (c->cfg.sink == IFA_SINK_COUNT_DIGEST) {
         const size_t need = (size_t)std::max<uint32_t>(n_queries, 1) * kStripes;
         if (c->d_qcount.n < need) {
@@ -1258,7 +1398,7 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     // size the work lists for the expected load unless the caller fixed the
     // initial capacity (they grow on overflow either way)
     if (c->cfg.work_capacity == 0 && !indexed) {
-        const uint64_t est = expected_work_items(qs, sorted_fw, n_sparse, c->cfg.chunk_bases);
+        const uint64_t est = expected_work_items(qs, c->h_fw, n_sparse, c->cfg.chunk_bases);
         c->work_want =
             (uint32_t)std::min<uint64_t>(std::max<uint64_t>(est, c->work_want), 1ull << 28);
     }
@@ -1271,6 +1411,7 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     c->hits.clear();
     c->drain_pos = 0;
     c->hits_sorted = true;
+    ensure_filter_operands(c);
 }
 
 // Indexed mode: seeds of the query set just installed (c->h_qs, device
@@ -1440,7 +1581,7 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
         hip_check(hipStreamCreateWithFlags(&c->copy_s, hipStreamNonBlocking), "stream");
         hip_check(hipStreamCreateWithFlags(&c->comp_s, hipStreamNonBlocking), "stream");
         for (int i = 0; i < 2; i++) {
-            c->stage[i].planes.alloc(4 * c->plane_words, "pinned staging");
+            c->stage[i].planes.alloc(3 * c->plane_words, "pinned staging");
             hip_check(hipEventCreateWithFlags(&c->stage[i].copied, hipEventDisableTiming),
                       "event");
             c->slot[i].stride = c->plane_words;
@@ -1774,9 +1915,9 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
         ch.stride = words_with_pad(calib_bases);
         ch.planes.alloc(4 * ch.stride, "calibration chunk");
         ch.pieces.alloc(1, "calibration piece");
-        std::vector<uint32_t> host(4 * ch.stride, 0u);
-        uint64_t z = 0x243F6A8885A308D3ull;
         const uint64_t used = calib_bases >> 5;
+        std::vector<uint32_t> host(2 * used, 0u);
+        uint64_t z = 0x243F6A8885A308D3ull;
         for (uint64_t w = 0; w < used; w++) {
             z += 0x9E3779B97F4A7C15ull;
             uint64_t r = z;
@@ -1784,17 +1925,11 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
             r = (r ^ (r >> 27)) * 0x94D049BB133111EBull;
             r ^= r >> 31;
             host[w] = (uint32_t)r;
-            host[ch.stride + w] = (uint32_t)(r >> 32);
+            host[used + w] = (uint32_t)(r >> 32);
         }
-        uint32_t *E = host.data() + 3 * ch.stride, *N = host.data() + 2 * ch.stride;
-        E[(calib_bases - 1) >> 5] |= 1u << ((calib_bases - 1) & 31);
-        for (uint64_t w = used; w < ch.stride; w++) {
-            N[w] = 0xffffffffu;
-            E[w] = 0xffffffffu;
-        }
-        hip_check(hipMemcpyAsync(ch.planes.p, host.data(), host.size() * sizeof(uint32_t),
-                                 hipMemcpyHostToDevice, c->comp_s),
-                  "upload calibration chunk");
+        const uint4 end_word{(uint32_t)((calib_bases - 1) >> 5), 0u,
+                             1u << ((calib_bases - 1) & 31), 0u};
+        upload_planes(host.data(), host.data() + used, used, &end_word, 1, ch, c->comp_s);
         Piece pc{};
         pc.len = calib_bases;
         hip_check(hipMemcpyAsync(ch.pieces.p, &pc, sizeof pc, hipMemcpyHostToDevice, c->comp_s),
@@ -1889,7 +2024,7 @@ ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
         b += c->d_hits[i].n * sizeof(uint4) + c->work[i].n * sizeof(WorkItem);
     }
     b += c->d_ctr.n * sizeof(unsigned long long);
-    b += c->d_qarena.n;
+    b += c->d_qarena.n + c->d_mqarena[0].n + c->d_mqarena[1].n;
     b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
     b += c->d_seed_info.n * sizeof(SeedInfo) + c->d_seed_tab.n * sizeof(SeedTable);
     for (size_t i = 0; i < kMaxSeedCfg; i++)

@@ -771,9 +771,13 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
     const uint32_t stride = gridDim.x * (WG / 64u);
     const ifa_v16f zero = {};
     // Lane j < kBlocks / 4 holds plane word j of a wave's stream (its four
-    // 8-base blocks); lane j <= 32 also N word j when a window start of the
-    // wave reads it (j = 0, or word j - 1 holds a window start). The words
-    // of a lane's next wave are loaded before the current wave's tiles run.
+    // 8-base blocks). A window filtered on NW prefix words reads the words of
+    // its start .. start + NW, so the wave reads words w0 .. w0 + 31 + NW;
+    // lane j <= ((w0 + 31 + NW) >> 5) - (w0 >> 5) (at most 3 lanes) also
+    // holds the N flag of 32-word block (w0 >> 5) + j, so that any N the
+    // wave's windows read (and possibly some they do not) sends the wave to
+    // the exact path. The words of a lane's next wave are loaded before the
+    // current wave's tiles run.
     static_assert(kBlocks % 4u == 0u && kBlocks / 4u <= 64u, "one plane word per lane");
     auto fetch = [&](uint32_t wv, uint32_t &ph, uint32_t &pl, uint32_t &pn) {
         const uint32_t w0 = a.w_begin + 32u * wv, w = min(w0 + l, last);
@@ -784,7 +788,7 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
             ph = a.hi[w];
             pl = a.lo[w];
         }
-        if (l <= 32u && (l == 0u || w0 + l - 1u < a.w_end)) pn = a.nm[w];
+        if (l <= ((w0 + 31u + (uint32_t)NW) >> 5) - (w0 >> 5)) pn = a.nflag[(w0 >> 5) + l];
     };
     uint32_t wave = blockIdx.x * (WG / 64u) + (threadIdx.x >> 6);
     uint32_t nh = 0u, nl = 0u, nn = 0u;
@@ -1390,6 +1394,44 @@ __global__ void seed_bitmap_kernel(const uint2 *ent, uint32_t n, uint32_t *bm, u
 
 // Clears counters on the stream (a kernel, so the launch sequence can be
 // captured in a graph).
+// ---------------------------------------------------------------------------
+// Chunk expansion: the host uploads the hi and lo planes of a chunk's used
+// words and a sorted list of the words whose N or piece-end bits are not
+// all zero, (word, nm, em, 0); these kernels rebuild the dense nm and em
+// planes, the padding words (hi = lo = 0, nm = em = all ones), and one flag
+// byte per 32-word block: non-zero when the block holds an N bit or lies
+// past the used words.
+// ---------------------------------------------------------------------------
+
+__global__ void expand_fill_kernel(uint32_t *hi, uint32_t *lo, uint32_t *nm, uint32_t *em,
+                                   uint8_t *nflag, uint32_t used, uint32_t total,
+                                   uint32_t blocks)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < total; x += stride) {
+        const uint32_t v = x < used ? 0u : 0xffffffffu;
+        nm[x] = v;
+        em[x] = v;
+        if (x >= used) {
+            hi[x] = 0u;
+            lo[x] = 0u;
+        }
+    }
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < blocks; b += stride)
+        nflag[b] = (32ull * b + 31u >= used) ? 1u : 0u;
+}
+
+__global__ void expand_scatter_kernel(uint32_t *nm, uint32_t *em, uint8_t *nflag,
+                                      const uint4 *list, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 e = list[i];
+    nm[e.x] = e.y;
+    em[e.x] = e.z;
+    if (e.y) nflag[e.x >> 5] = 1u;
+}
+
 __global__ void clear_u64_kernel(unsigned long long *p, uint32_t n)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1563,6 +1605,23 @@ hipError_t launch_seed(const ScanArgs &a, hipStream_t s)
     const uint32_t words = a.w_end - a.w_begin;
     const uint32_t blocks = std::min<uint32_t>((words + 255) / 256, 4096);
     hipLaunchKernelGGL(scan_seed_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// Rebuild a chunk's nm and em planes, padding and N-block flags from the
+// sparse list (see expand_fill_kernel), on stream s after the planes' copy.
+hipError_t launch_expand(uint32_t *planes, uint64_t stride, uint8_t *nflag, uint32_t used,
+                         uint32_t total, const uint4 *list, uint32_t n_list, hipStream_t s)
+{
+    uint32_t *hi = planes, *lo = planes + stride, *nm = planes + 2 * stride, *em = planes + 3 * stride;
+    const uint32_t blocks = nflag_blocks(total);
+    const uint32_t grid = std::min<uint32_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(expand_fill_kernel, dim3(grid), dim3(256), 0, s, hi, lo, nm, em, nflag,
+                       used, total, blocks);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n_list == 0) return e;
+    hipLaunchKernelGGL(expand_scatter_kernel, dim3((n_list + 255) / 256), dim3(256), 0, s, nm, em,
+                       nflag, list, n_list);
     return hipGetLastError();
 }
 

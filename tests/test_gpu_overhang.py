@@ -93,7 +93,7 @@ def test_overhang_random_small_cases(ifa, orc, policy):
     rng = random.Random(2100 + policy)
     for trial in range(40):
         nq = rng.randint(1, 6)
-        qs = [rand_dna(rng, rng.choice([1, 2, 4, 7, 16, 31, 32, 33, 40, 64, 65, 100, 256]),
+        qs = [rand_dna(rng, rng.choice([1, 2, 4, 7, 16, 31, 32, 33, 40, 64, 65, 100, 255]),
                        b"ACGT" if rng.random() < 0.85 else b"ACGTN") for _ in range(nq)]
         contigs = _end_planted(rng, qs, rng.randint(0, 8), 0, 400,
                                rng.choice([b"ACGT", b"ACGT", b"ACGTN", b"acgtNNRY"]))

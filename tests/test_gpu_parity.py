@@ -98,7 +98,7 @@ def test_random_small_cases(ifa, orc, policy):
 def test_queries_of_every_length_and_threshold(ifa, orc):
     rng = random.Random(77)
     contigs = [rand_dna(rng, 3000, b"ACGTN") for _ in range(3)]
-    for L in (1, 2, 3, 8, 15, 31, 32, 33, 47, 64, 95, 96, 97, 128, 150, 200, 255, 256):
+    for L in (1, 2, 3, 8, 15, 31, 32, 33, 47, 64, 95, 96, 97, 128, 150, 200, 254, 255):
         # plant a few near copies so high-threshold and low-threshold hits exist
         q = rand_dna(rng, L)
         cs = []
@@ -209,6 +209,9 @@ def test_error_paths(ifa):
         assert e.value.status == 5
         with pytest.raises(ifa.IfaError) as e:
             s.load_queries([b"A" * 257], [0])
+        assert e.value.status == 5
+        with pytest.raises(ifa.IfaError) as e:
+            s.load_queries([b"A" * 256], [0])    # n_ref would not fit its byte
         assert e.value.status == 5
         with pytest.raises(ifa.IfaError) as e:
             s.load_queries([b"ACGT"], [-1])
@@ -607,3 +610,105 @@ def test_two_word_filter_prefix(ifa, orc, sink):
             else:
                 gc, gd = s.query_stats()
                 assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), f"variant {v}"
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_n_in_the_last_word_a_two_word_window_reads(ifa, orc, policy):
+    """A window filtered on two prefix words (L = 64) that starts in the last
+    8 starts of a 1024-window filter wave reads plane word w0 + 33 of the wave.
+    A reference N there must be seen (an N byte's own bits read as G), so each
+    copy below, with exactly k substitutions and one N at a strand base other
+    than G in that word, is a hit under the default N rule. Every three-class
+    matrix variant is run."""
+    rng = random.Random(9033)
+    L = 64
+    q = rand_dna(rng, L)
+    rc = q.translate(COMP)[::-1]
+    contig = bytearray(rand_dna(rng, 16 * 1024 + 200))
+    for i, s in enumerate(range(1016, 1024)):
+        start = 2048 * i + s
+        strand_seq = q if i % 2 == 0 else rc
+        # N at window offset o inside word 33 of the wave (base 1056 onwards)
+        choices = [o for o in range(1056 - s, L) if strand_seq[o] != ord("G")]
+        o = rng.choice(choices)
+        w = bytearray(strand_seq)
+        subs = rng.sample([x for x in range(L) if x != o], 16)
+        for x in subs:
+            w[x] = rng.choice([b for b in b"ACGT" if b != w[x]])
+        w[o] = ord("N")
+        contig[start:start + L] = w
+    k = 16 if policy == 0 else 17
+    want = orc.scan([q], [bytes(contig)], [k], policy=policy)
+    assert len(want) >= 8
+    vs = [v for v in range(ifa.ifa_variant_count()) if ifa.ifa_variant_info(v)["encoding"] == 2]
+    assert vs
+    for v in vs:
+        say(f"N in word 33: variant {v} policy {policy}")
+        with ifa.Scanner(n_policy=policy) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries([q], [k])
+            assert ifa.ifa_query_partition(s.ctx) == (2, 2)
+            s.scan_chunk([bytes(contig)])
+            assert_same(s.collect(), want, f"variant {v}")
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_longest_query_inside_an_n_run(ifa, orc, policy):
+    """The longest query (255 bases) over a run of 300 Ns: windows inside the
+    run have n_ref = 255, which must come back whole in the record and in the
+    digest. N_SEPARATE with maxN = 255 reports them (m = 0); N_AS_MISMATCH
+    with maxSubs = 255 reports them with m = 255."""
+    rng = random.Random(255)
+    L = 255
+    q = rand_dna(rng, L)
+    contig = rand_dna(rng, 700) + b"N" * 300 + rand_dna(rng, 700)
+    ks, mn = [L], [L]
+    say(f"L=255 over 300 Ns, policy {policy}")
+    want, cnt, dig = orc.scan([q], [contig], ks, mn, policy=policy, stats=True)
+    assert (want["n_ref"] == 255).sum() == 2 * 46
+    got = gpu_scan(ifa, [q], [contig], ks, mn, n_policy=policy)
+    assert_same(got, want, "L=255 in an N run")
+    with ifa.Scanner(n_policy=policy, sink=1) as s:
+        s.load_queries([q], ks, mn)
+        s.scan_chunk([contig])
+        gc, gd = s.query_stats()
+    assert np.array_equal(gc, cnt) and np.array_equal(gd, dig)
+
+
+def test_filter_launch_split_past_65535_batches(ifa, orc):
+    """The matrix-core filters take one batch of 32 sparse strands per grid
+    row, and a launch holds at most 65,535 rows: 1,050,000 queries of 32 bases
+    (2.1 M strands, 65,625 batches) make the host launch the filter in two
+    parts, the second starting at batch 65,535. Copies of queries from both
+    parts are planted in a small reference; the three-class and four-class
+    filters must both give the oracle's hits."""
+    n = 1_050_000
+    L, k = 32, 2
+    rng = np.random.default_rng(65535)
+    codes = np.frombuffer(b"ACGT", dtype=np.uint8)[rng.integers(0, 4, size=(n, L))]
+    qs = [codes[i].tobytes() for i in range(n)]
+    r = random.Random(65535)
+    contigs = [bytearray(rand_dna(r, 700)) for _ in range(2)]
+    planted = [0, 1, 31, 500_000, 1_048_560, 1_049_000] + list(range(n - 8, n))
+    for i, j in enumerate(planted):
+        c = contigs[i % 2]
+        p = 40 + 90 * (i // 2)
+        src = bytearray(qs[j] if i % 3 else qs[j].translate(COMP)[::-1])
+        for x in r.sample(range(L), i % 3):
+            src[x] = r.choice([b for b in b"ACGT" if b != src[x]])
+        c[p:p + L] = src
+    contigs = [bytes(c) for c in contigs]
+    ks = [k] * n
+    say(f"launch split: {n} queries, oracle")
+    want = orc.scan(qs, contigs, ks)
+    assert set(planted) <= set(want["query"].tolist())
+    for enc in (2, 1):
+        v = next(v for v in range(ifa.ifa_variant_count())
+                 if ifa.ifa_variant_info(v)["encoding"] == enc)
+        say(f"launch split: variant {v} (encoding {enc})")
+        with ifa.Scanner(chunk_bases=8192) as s:
+            ifa.ifa_set_variant(s.ctx, v)
+            s.load_queries(qs, ks)
+            assert ifa.ifa_query_partition(s.ctx) == (2 * n, 2 * n)
+            s.scan_chunk(contigs)
+            assert_same(s.collect(), want, f"variant {v}")

@@ -1,10 +1,14 @@
 """Parity at the workloads' own shapes, through the C ABI.
 
-Full-size runs are checked where the oracle cannot afford the whole job:
-every reported hit is re-evaluated window by window, every planted copy must
-be found, and the GPU's hits on a sample of contigs must equal the oracle's
-full scan of those contigs. Smaller shapes are compared whole.
+Full-size runs of the paper-scale (4 Gbp) and batched (1 Gbp) workloads are
+compared per query, as hit count and digest, with fixtures the oracle wrote
+(tests/golden/make_workload_goldens.py). Where no fixture exists the oracle
+checks what it can afford at run time: every reported hit re-evaluated window
+by window, every planted copy found, and the GPU's hits on a sample of
+contigs equal to the oracle's full scan of those contigs. Smaller shapes are
+compared whole.
 """
+import os
 import sys
 
 import numpy as np
@@ -32,37 +36,90 @@ def orc():
     return oracle
 
 
-def test_c2_full_size_sampled(ifa, orc):
-    """4 Gbp, 10 queries L30-36, maxSubs 8 (the benchmark's configuration):
-    all hits verified one by one, all planted copies found, and exact equality
-    with the oracle on 12 sampled contigs."""
+def test_c2_full_size_every_threshold(ifa):
+    """The paper-scale workload at full size (4 Gbp, 10 queries L30-36) at
+    maxSubs 0, 4 and 8: per-query hit count and digest of the records sink,
+    and of the count+digest sink, equal the oracle's over the whole 4 Gbp
+    (every contig, including those split across device chunks), and every
+    planted copy within the threshold is found."""
     import synth
-    say("c2 full size: generating 4 Gbp")
+    say("c2 every threshold: generating 4 Gbp")
     w = synth.c2_paper_scale(total=4_000_000_000)
-    k = 8
-    ks = [k] * len(w.queries)
+    head, rows = load_golden("c2_4gbp_count_digest.txt")
+    check_fingerprint(head, w.ref)
+    nq = len(w.queries)
+    gold = {}
+    for k, j, c, d in rows:
+        gold.setdefault(k, (np.zeros(nq, np.uint64), np.zeros(nq, np.uint64)))
+        gold[k][0][j], gold[k][1][j] = c, d
     with ifa.Scanner() as s:
         s.ref_load(w.ref)
-        s.load_queries(w.queries, ks)
+        for k in sorted(gold):
+            say(f"  records, maxSubs {k}")
+            s.load_queries(w.queries, [k] * nq)
+            s.scan_resident()
+            got = s.collect()
+            cnt, dig = records_digest(got, nq)
+            assert np.array_equal(cnt, gold[k][0]), (k, cnt, gold[k][0])
+            assert np.array_equal(dig, gold[k][1]), k
+            found = {(int(r["query"]), int(r["contig"]), int(r["pos"]), int(r["strand"]))
+                     for r in got}
+            for p in w.plants:
+                if p.subs <= k:
+                    assert (p.query, p.contig, p.pos, p.strand) in found
+    with ifa.Scanner(sink=ifa.IFA_SINK_COUNT_DIGEST) as s:
+        s.ref_load(w.ref)
+        for k in sorted(gold):
+            say(f"  count+digest, maxSubs {k}")
+            s.load_queries(w.queries, [k] * nq)
+            s.scan_resident()
+            gc, gd = s.query_stats()
+            assert np.array_equal(gc, gold[k][0]) and np.array_equal(gd, gold[k][1]), k
+
+
+def test_c3_all_queries_10mbp_of_the_1gbp_reference(ifa):
+    """All 10,000 batched queries (L 18-50, maxSubs 0-16) against a 10 Mbp
+    sample of whole contigs of the batched workload's 1 Gbp reference:
+    per-query count and digest equal the oracle's (fixture)."""
+    import re
+    import synth
+    w = synth.c3_batched(total=1_000_000_000)
+    head, rows = load_golden("c3_10mbp_count_digest.txt")
+    check_fingerprint(head, w.ref)
+    pick = [int(x) for x in re.search(r"whole contigs ([0-9,]+)", " ".join(head)).group(1).split(",")]
+    sub = w.ref.subset(pick)
+    say(f"c3 all queries x {sub.total / 1e6:.1f} Mbp ({len(pick)} contigs), count+digest")
+    with ifa.Scanner(sink=ifa.IFA_SINK_COUNT_DIGEST) as s:
+        s.load_queries(w.queries, w.max_subs)
+        s.scan_chunk(sub)
+        gc, gd = s.query_stats()
+    want_c = np.array([r[1] for r in rows], dtype=np.uint64)
+    want_d = np.array([r[2] for r in rows], dtype=np.uint64)
+    bad = np.nonzero((gc != want_c) | (gd != want_d))[0]
+    assert len(bad) == 0, f"{len(bad)} queries differ, first {bad[:5].tolist()}"
+    assert int(want_c.sum()) > 10 ** 9
+
+
+def test_c3_stratified_queries_full_1gbp(ifa):
+    """100 batched queries stratified over (L, maxSubs), leaving out pairs
+    expected to hit more than 1e7 times, against the whole 1 Gbp batched
+    reference: per-query count and digest equal the oracle's (fixture)."""
+    import synth
+    w = synth.c3_batched(total=1_000_000_000)
+    head, rows = load_golden("c3_100q_1gbp_count_digest.txt")
+    check_fingerprint(head, w.ref)
+    idx = [r[0] for r in rows]
+    qs = [w.queries[i] for i in idx]
+    ks = [w.max_subs[i] for i in idx]
+    assert ks == [r[1] for r in rows]
+    say(f"c3 stratified: {len(qs)} queries x 1 Gbp, count+digest")
+    with ifa.Scanner(sink=ifa.IFA_SINK_COUNT_DIGEST) as s:
+        s.ref_load(w.ref)
+        s.load_queries(qs, ks)
         s.scan_resident()
-        got = s.collect()
-    say(f"  {len(got)} hits")
-    # every hit is a true window with the reported counts
-    for r in got:
-        ok, m, nr = orc.eval_window(w.queries[r["query"]], k, w.ref.contig(int(r["contig"])),
-                                    int(r["pos"]), int(r["strand"]))
-        assert ok and m == r["mismatches"] and nr == r["n_ref"], r
-    found = {(int(r["query"]), int(r["contig"]), int(r["pos"]), int(r["strand"])) for r in got}
-    for p in w.plants:
-        if p.subs <= k:
-            assert (p.query, p.contig, p.pos, p.strand) in found
-    # completeness on a sample of contigs
-    rng = np.random.default_rng(2)
-    sample = sorted(rng.choice(w.ref.n_contigs, size=12, replace=False).tolist())
-    for c in sample:
-        want = orc.scan(w.queries, [w.ref.contig(c)], ks, first_ordinal=c)
-        mine = got[got["contig"] == c]
-        assert np.array_equal(mine, want), c
+        gc, gd = s.query_stats()
+    assert np.array_equal(gc, np.array([r[2] for r in rows], dtype=np.uint64))
+    assert np.array_equal(gd, np.array([r[3] for r in rows], dtype=np.uint64))
 
 
 def test_c3_all_queries_count_digest(ifa, orc):

@@ -391,3 +391,27 @@ def test_count_digest_matches_records(oracle_mod):
             d = (d + oracle_mod.hit_hash(int(r["contig"]), int(r["pos"]), int(r["strand"]),
                                          int(r["mismatches"]), int(r["n_ref"]))) % 2**64
         assert int(digests[j]) == d
+
+
+def test_fixture_digest_of_records_matches_the_oracle_sink(oracle_mod):
+    """The helper that reduces records to (count, digest) for the full-size
+    fixtures gives the oracle's own count+digest figures (C1 and a random
+    case with query Ns and reference N runs)."""
+    import os
+    import random
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from workload_fixtures import records_digest
+    import synth
+    w = synth.c1_tiny()
+    hits, cnt, dig = oracle_mod.scan(w.queries, w.ref, w.max_subs, stats=True)
+    c2, d2 = records_digest(hits, len(w.queries))
+    assert np.array_equal(c2, cnt) and np.array_equal(d2, dig)
+    rng = random.Random(17)
+    qs = [bytes(rng.choice(b"ACGTN") for _ in range(rng.randint(5, 40))) for _ in range(6)]
+    contigs = [bytes(rng.choice(b"ACGTNN") for _ in range(3000)) for _ in range(3)]
+    ks = [len(q) // 2 for q in qs]
+    hits, cnt, dig = oracle_mod.scan(qs, contigs, ks, stats=True, first_ordinal=7)
+    assert len(hits) > 100
+    c2, d2 = records_digest(hits, len(qs))
+    assert np.array_equal(c2, cnt) and np.array_equal(d2, dig)
