@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark: the brute-force gapless scan on one MI355X.
 
-Default workload (paper-scale single pass, the headline line): 10 queries of
-length 30-36 against a 4 Gbp synthetic reference (lognormal contigs, median
-3 Mbp; per-contig GC 35-65%; N runs covering 1e-4), one planted copy per query
-per 100 Mbp, at maxSubs 0, 4 and 8. The reference is packed and resident in
-device memory before timing starts. One step = three full passes (one per
-maxSubs) of the 10 queries over the 4 Gbp; each pass = the scan kernels, the
-hit drain from the device and the canonical sort of the records.
+Default workload (the default line): the paper-scale single pass -- 10
+queries of length 30-36 against a 4 Gbp synthetic reference (lognormal
+contigs, median 3 Mbp; per-contig GC 35-65%; N runs covering 1e-4), one
+planted copy per query per 100 Mbp, at maxSubs 0, 4 and 8. The reference is
+packed and resident in device memory before timing starts. One step = three
+full passes (one per maxSubs) of the 10 queries over the 4 Gbp; each pass =
+the scan kernels (replayed from captured HIP graphs), the hit drain from the
+device and the canonical sort of the records. Beside it, in the same JSON
+line (unless --only): the kernel's roofline (dense-equivalent and issued
+matrix-core fractions, HBM fraction, the op model's efficiency, measured
+traffic), the oracle on this host's cores (all threads and one thread), the
+same step end to end from host bytes, the batched scan (10,000 queries x 1 Gbp,
+count+digest) and the serving loop (Poisson trace, batched against serial,
+p50/p99, plus a run at 70% of the measured capacity).
 
 Other workloads (--workload):
   c3  batched scan: 10,000 queries, L 18-50, maxSubs 0-16 per query, against
@@ -15,6 +22,7 @@ Other workloads (--workload):
   c4  streaming: 100 queries, L 20-40, maxSubs 4, against a reference
       generated on the fly by host threads, packed and streamed through the
       pinned double buffer (never resident); one step = the whole reference.
+      --packed: the producer writes 2-bit planes and calls ifa_scan_packed.
   c5  serving loop: Poisson arrivals (200/s) of query sets of 1-1000
       queries (log-uniform), L 18-150, maxSubs 0-L/4, against 16 Gbp
       resident; continuous batching versus serial first-in-first-out scans
@@ -44,20 +52,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Gbp·query/s scanned (exact hits) + p50/p99 serving latency on 1 MI355X"
-# 32-bit VALU lane-ops/s: 256 CUs x 4 SIMDs x 32 lanes per clock (two wave64
-# VALU issues per 4 clocks) x 2.4 GHz = 78.6 T, the published fp32 vector
-# rate (157.3 TFLOP/s) counted in fused operations.
-PEAK_VALU_OPS = 256 * 4 * 32 * 2.4e9
-# Algorithmic VALU ops per window x query strand for the packed-word filter:
-# two v_bitop3_b32 (the mismatch bits of 32 bases), one v_bcnt_u32_b32 and
-# half a v_min3_u32 (threshold fold over the windows).
-OPS_PER_WINDOW_STRAND = 3.5
-# Dense fp4 (e2m1) matrix-core peak of MI355X.
-PEAK_FP4_FLOPS = 10.1e15
-# Algorithmic flops per window x query strand for the matrix-core filters:
-# the match count over 32 positions as a contraction of base-class codes,
-# 2 flops per position and class: 4 classes (encoding 1) or 3 (encoding 2).
-FLOPS_PER_WINDOW_STRAND = {1: 2 * 32 * 4, 2: 2 * 32 * 3}
+# Peaks of MI355X.
+PEAK_FP4_FLOPS = 10.1e15          # dense fp4 (e2m1) matrix cores
+PEAK_HBM_BYTES = 8.0e12           # HBM3E
+# 32-bit integer vector ALU: 256 CUs x 4 SIMDs x 16 lanes per clock (a wave64
+# instruction issues over 4 clocks on its SIMD) x 2.4 GHz = 39.3 T lane-ops/s.
+PEAK_VALU_INT32 = 256 * 4 * 16 * 2.4e9
+# The method's operation model for a packed-word scan: about 10 vector ops per
+# reference base x query (per 32-base word and strand: 2 XOR, 1 OR, 1 AND-NOT,
+# 1 popcount; two strands), and 0.25 byte of 2-bit reference read per base
+# and pass, shared by every query of the pass.
+OPS_PER_BPQ = 10
+BYTES_PER_BASE = 0.25
+# Algorithmic VALU ops per window x query strand and 32-base word of the
+# dense-strand kernels (the same five operations).
+OPS_PER_WINDOW_STRAND_WORD = 5
+# Matrix-core filters: flops per window x query strand of the match-count
+# contraction over one 32-base prefix word (32 positions x base classes x 2:
+# the dense-equivalent work), and the flops the instructions issue for it
+# (the banded operand's zeros included).
+FLOPS_DENSE = {1: 2 * 32 * 4, 2: 2 * 32 * 3}
+FLOPS_ISSUED = {1: 3 * 2 * 64 * 2, 2: 2 * 2 * 64 * 2}
 
 
 def log(*a):
@@ -76,6 +91,8 @@ def parse():
                     help="idx: substitutions per read = maxSubs, one query set each")
     ap.add_argument("--read-len", type=int, default=150, help="idx: read length")
     ap.add_argument("--requests", type=int, default=50, help="c5: requests in the trace")
+    ap.add_argument("--requests-70", type=int, default=20,
+                    help="c5: requests in the supplementary run at 70%% of capacity")
     ap.add_argument("--rate", type=float, default=200.0, help="c5: Poisson arrivals per second")
     ap.add_argument("--chunk-bases", type=int, default=None,
                     help="device chunk size in bases (c2, c3: the library default 2^30 unless "
@@ -83,21 +100,28 @@ def parse():
     ap.add_argument("--total", type=int, default=0, help="reference bases (0 = workload default)")
     ap.add_argument("--queries", type=int, default=0, help="query count (0 = workload default)")
     ap.add_argument("--ks", default="0,4,8", help="c2: maxSubs values, one pass each")
+    ap.add_argument("--packed", action="store_true",
+                    help="c4: the producer writes 2-bit planes and calls ifa_scan_packed")
     ap.add_argument("--overhang", action="store_true",
                     help="c2/c3: also report windows overhanging contig ends (soft clip)")
     ap.add_argument("--sam", action="store_true",
                     help="c2: also time the SAM text of one step's hits (host writer)")
     ap.add_argument("--median", type=float, default=0.0,
                     help="c2/c3: median contig length in bases (0 = the workload's 3 Mbp)")
-    ap.add_argument("--cpu-sample", type=int, default=250_000_000,
-                    help="c2: reference bases the oracle baseline scans per maxSubs (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=150_000_000,
+                    help="c2: reference bases the oracle baseline scans per maxSubs on all "
+                         "threads (0 = skip)")
+    ap.add_argument("--cpu-sample-1t", type=int, default=8_000_000,
+                    help="c2: reference bases of the one-thread oracle run")
+    ap.add_argument("--only", action="store_true",
+                    help="default workload: the paper-scale line alone (no end-to-end, "
+                         "batched or serving sub-records)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--variant", type=int, default=-1,
                     help="scan kernel variant (default: autotuned on the workload's queries)")
-    ap.add_argument("--graphs", action="store_true",
-                    help="resident workloads: replay repeated passes from captured HIP graphs "
-                         "(faster by a few percent; HIP events inside a graph overstate the "
-                         "filter kernel's time, so the roofline figure is then conservative)")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every pass eagerly (the default replays repeated resident "
+                         "passes from captured HIP graphs)")
     ap.add_argument("--tune-cache", default="",
                     help="autotuner cache file (a later run with the same queries reuses "
                          "its choice)")
@@ -125,17 +149,38 @@ def chunk_kw(args):
     return {"chunk_bases": args.chunk_bases} if args.chunk_bases else {}
 
 
-def choose_variant(ifa, s, args, queries, ks):
-    """Autotune the kernel variant on a 64 Mi-base calibration chunk with the
-    workload's queries, unless one is given."""
+def choose_variant(ifa, s, args, queries, ks, calib_bases=64 << 20, reps=5):
+    """Autotune the kernel variant on a calibration chunk (64 Mi random bases
+    by default) with the workload's queries, unless one is given."""
     if args.variant >= 0:
         ifa.ifa_set_variant(s.ctx, args.variant)
         return None
     s.load_queries(queries, ks)
-    chosen, ms = ifa.ifa_autotune(s.ctx, 64 << 20, 5, args.tune_cache or None)
+    chosen, ms = ifa.ifa_autotune(s.ctx, calib_bases, reps, args.tune_cache or None)
     log(f"autotune: variant {chosen} {ifa.ifa_variant_info(chosen)}; "
         f"ms per variant {[round(float(x), 4) for x in ms]}")
     return {"chosen": chosen, "ms": [round(float(x), 4) for x in ms]}
+
+
+def choose_variant_over(ifa, s, args, queries, ks_sets):
+    """Autotune over several threshold sets of the same queries (one pass each
+    in a step): every variant's median times are summed over the sets and the
+    fastest in total is chosen."""
+    if args.variant >= 0:
+        ifa.ifa_set_variant(s.ctx, args.variant)
+        return None
+    total = None
+    for ks in ks_sets:
+        s.load_queries(queries, ks)
+        _, ms = ifa.ifa_autotune(s.ctx, 64 << 20, 5, None)
+        ms = np.asarray(ms, dtype=np.float64)
+        total = ms if total is None else total + ms
+    best = int(np.argmin(total))
+    ifa.ifa_set_variant(s.ctx, best)
+    log(f"autotune over {len(ks_sets)} threshold sets: variant {best} "
+        f"{ifa.ifa_variant_info(best)}; summed ms {[round(float(x), 4) for x in total]}")
+    return {"chosen": best, "ms_summed": [round(float(x), 4) for x in total],
+            "threshold_sets": len(ks_sets)}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scan_filter_mfma3_c2_4gbp_hbm_traffic.md")
@@ -171,43 +216,89 @@ def profiled_traffic(kernel):
     return int(kv["traffic_bytes_per_launch"])
 
 
+def op_model(gbpq_s):
+    """The line's rate against the operation model's bound."""
+    bound = PEAK_VALU_INT32 / OPS_PER_BPQ / 1e9
+    return {"ops_per_bpq": OPS_PER_BPQ, "valu_peak_tops": round(PEAK_VALU_INT32 / 1e12, 2),
+            "bound_gbpq_s": round(bound, 1), "achieved_gbpq_s": round(gbpq_s, 1),
+            "efficiency": round(gbpq_s / bound, 4)}
+
+
 def roofline(ifa, st, sparse_strands, variant, traffic=False):
-    """Roofline of the filter kernel (the dominant one): its algorithmic work
-    per launch is the per-unit figure (OPS_PER_WINDOW_STRAND VALU ops, or
-    FLOPS_PER_WINDOW_STRAND matrix-core flops for the fp4 variants) x the
-    query strands it filters x the window starts it evaluated (counted by the
-    library: waves holding a reference N go whole to the resolve kernel and
-    are not counted), over its average launch time from HIP events on the
-    stream it runs on."""
-    launches = max(1, st["filter_launches"])
-    filter_ms_avg = st["filter_ms"] / launches
+    """Roofline of the filter kernel (the dominant one), its average time per
+    pass from HIP events on the stream it runs on (every filter launch of a
+    pass lies between two events).
+      * matrix-core filters (bound "mfma"): achieved = the dense-equivalent
+        flops of the match-count contraction per window x strand
+        (FLOPS_DENSE, one prefix word) x the sparse strands x the window
+        starts evaluated (waves sent whole to the exact path are not
+        counted) / time; issued_frac counts the flops the instructions issue;
+      * VALU filter (bound "alu"): OPS_PER_WINDOW_STRAND_WORD ops per window
+        x strand against the 32-bit vector peak;
+      * hbm_frac: BYTES_PER_BASE x the bases the passes covered / time,
+        against the HBM peak (the method's algorithmic reference traffic);
+      * traffic: HBM bytes per pass measured by rocprofv3 (FETCH_SIZE +
+        WRITE_SIZE, scaled by a copy kernel of known size) for this workload,
+        while the kernel source matches the profile."""
+    passes = max(1, st["filter_launches"])
+    filter_s = st["filter_ms"] * 1e-3
+    ms_avg = st["filter_ms"] / passes
     shape = ifa.ifa_variant_info(variant)
-    mfma = shape["encoding"] in FLOPS_PER_WINDOW_STRAND
-    per_unit = FLOPS_PER_WINDOW_STRAND[shape["encoding"]] if mfma else OPS_PER_WINDOW_STRAND
-    work_per_launch = per_unit * sparse_strands * st["filter_windows"] / launches
-    achieved = work_per_launch / (filter_ms_avg * 1e-3) / 1e12 if st["filter_launches"] else 0.0
-    peak = (PEAK_FP4_FLOPS if mfma else PEAK_VALU_OPS) / 1e12
+    enc = shape["encoding"]
     kernel = {0: "scan_filter_kernel", 1: "scan_filter_mfma_kernel",
-              2: "scan_filter_mfma3_kernel"}[shape["encoding"]]
+              2: "scan_filter_mfma3_kernel"}[enc]
+    ws = sparse_strands * st["filter_windows"]
+    if enc in FLOPS_DENSE:
+        achieved = FLOPS_DENSE[enc] * ws / filter_s / 1e12 if filter_s else 0.0
+        peak = PEAK_FP4_FLOPS / 1e12
+        bound, unit = "mfma", "TFLOP/s"
+        issued = FLOPS_ISSUED[enc] * ws / filter_s / 1e12 if filter_s else 0.0
+    else:
+        achieved = OPS_PER_WINDOW_STRAND_WORD * ws / filter_s / 1e12 if filter_s else 0.0
+        peak = PEAK_VALU_INT32 / 1e12
+        bound, unit = "alu", "TOP/s"
+        issued = None
+    hbm = BYTES_PER_BASE * st["bases"] / filter_s if filter_s else 0.0
     out = {
-        "bound": "mfma" if mfma else "alu",
+        "bound": bound,
         "achieved": round(achieved, 3),
         "peak": round(peak, 3),
-        "unit": "TFLOP/s" if mfma else "TOP/s",
+        "unit": unit,
         "frac": round(achieved / peak, 4),
         "traffic": None,
         "kernel": kernel,
+        "per_unit": (f"{FLOPS_DENSE[enc]} flops per window x query strand (dense-equivalent "
+                     "match-count contraction over a 32-base prefix)") if enc in FLOPS_DENSE
+                    else f"{OPS_PER_WINDOW_STRAND_WORD} ops per window x query strand",
+        "issued_frac": round(issued / peak, 4) if issued is not None else None,
+        "hbm_achieved_gbs": round(hbm / 1e9, 1),
+        "hbm_frac": round(hbm / PEAK_HBM_BYTES, 4),
+        "algorithmic_bytes_per_pass": int(BYTES_PER_BASE * st["bases"] / passes),
         "variant": variant,
         "variant_shape": shape,
-        "kernel_ms_avg": round(filter_ms_avg, 4),
-        "launches": st["filter_launches"],
-        "windows_per_launch": st["filter_windows"] // launches,
-        "work_items_per_launch": st["work_items"] // launches,
+        "kernel_ms_avg": round(ms_avg, 4),
+        "passes": st["filter_launches"],
+        "windows_per_pass": st["filter_windows"] // passes,
+        "work_items_per_pass": st["work_items"] // passes,
         "pass_ms_avg": round(st["kernel_ms"] / max(1, st["kernel_launches"]), 4),
     }
     if traffic:
-        out["traffic"] = profiled_traffic(kernel)
+        t = profiled_traffic(kernel)
+        out["traffic"] = t
+        if t:
+            out["traffic_over_algorithmic"] = round(t / max(1, out["algorithmic_bytes_per_pass"]), 3)
     return out
+
+
+def dense_roofline(st, dense_strands):
+    """The dense-strand kernels: OPS_PER_WINDOW_STRAND_WORD ops per window x
+    strand (one 32-base word) over their time, against the 32-bit VALU peak."""
+    ms = st["dense_ms"]
+    ach = OPS_PER_WINDOW_STRAND_WORD * st["bases"] * dense_strands / (ms * 1e-3) if ms else 0.0
+    return {"bound": "alu", "achieved": round(ach / 1e12, 3),
+            "peak": round(PEAK_VALU_INT32 / 1e12, 3), "unit": "TOP/s",
+            "frac": round(ach / PEAK_VALU_INT32, 4), "kernel": "scan_dense_kernel",
+            "ms_per_pass": round(ms / max(1, st["kernel_launches"]), 3)}
 
 
 def base_record(args, value, ms_per_step, config):
@@ -243,7 +334,7 @@ def device_sync():
 
 
 def scanner_flags(ifa, args):
-    return ((ifa.IFA_FLAG_GRAPHS if args.graphs else 0) |
+    return ((0 if args.eager else ifa.IFA_FLAG_GRAPHS) |
             (ifa.IFA_FLAG_OVERHANG if args.overhang else 0))
 
 
@@ -315,7 +406,7 @@ def run_c2(args):
     s.ref_load(w.ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
     log(f"resident: {bases / 1e9:.2f} Gbp in {chunks} device chunks ({time.time() - t0:.1f} s)")
-    tune = choose_variant(ifa, s, args, w.queries, [4] * nq)
+    tune = choose_variant_over(ifa, s, args, w.queries, [[k] * nq for k in ks])
     variant = ifa.ifa_get_variant(s.ctx)
 
     last_hits = []
@@ -356,31 +447,98 @@ def run_c2(args):
     out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant,
                                traffic=not args.total and not args.queries)
 
+    out["op_model"] = op_model(out["value"])
+    out["op_model_kernel_only"] = op_model(out["kernel_only_gbpq_s"])
     if not args.no_cpu and args.cpu_sample > 0:
-        import oracle
-        # bounded sample: the first contigs up to cpu_sample bases
-        acc, idx = 0, []
-        for i in range(w.ref.n_contigs):
-            if acc >= args.cpu_sample:
-                break
-            idx.append(i)
-            acc += int(w.ref.lens[i])
-        sub = w.ref.subset(idx)
-        threads = synth.default_threads()
-        t0 = time.perf_counter()
-        for k in ks:
-            oracle.scan(w.queries, sub, [k] * nq, threads=threads)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {
-            "value": round(sub.total * nq * len(ks) / dt / 1e9, 4),
-            "unit": "Gbp·query/s",
-            "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {len(idx)} contigs ({sub.total / 1e6:.0f} Mbp) x 10 queries x "
-                      f"maxSubs {'/'.join(map(str, ks))}, {dt:.1f} s",
-        }
+        out["cpu_baseline"] = cpu_baseline(w, ks, args.cpu_sample, args.cpu_sample_1t)
+    out["_workload"] = w
+    out["_variant"] = variant
     s.close()
     return out
+
+
+def oracle_sample(w, bases):
+    """The first contigs of the workload's reference up to `bases` bases."""
+    acc, idx = 0, []
+    for i in range(w.ref.n_contigs):
+        if acc >= bases:
+            break
+        idx.append(i)
+        acc += int(w.ref.lens[i])
+    return idx, w.ref.subset(idx)
+
+
+def cpu_baseline(w, ks, sample, sample_1t):
+    """The oracle (plain C, byte compare with early exit, threads over window
+    ranges) timed on this host on a bounded sample of the workload: the first
+    contigs, the same queries and maxSubs values; once with the threads a
+    one-GPU job gets here (all of the affinity set, at most 16) and once with
+    one thread (the per-core rate)."""
+    import oracle
+    import synth
+    nq = len(w.queries)
+    affinity = len(os.sched_getaffinity(0))
+    threads = synth.default_threads()
+    res = {}
+    for label, size, th in (("all", sample, threads), ("one", sample_1t, 1)):
+        idx, sub = oracle_sample(w, size)
+        t0 = time.perf_counter()
+        for k in ks:
+            oracle.scan(w.queries, sub, [k] * nq, threads=th)
+        dt = time.perf_counter() - t0
+        res[label] = (sub.total * nq * len(ks) / dt / 1e9, idx, sub.total, dt)
+    v, idx, tot, dt = res["all"]
+    v1, idx1, tot1, dt1 = res["one"]
+    return {
+        "value": round(v, 4),
+        "unit": "Gbp·query/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"first {len(idx)} contigs ({tot / 1e6:.0f} Mbp) x {nq} queries x maxSubs "
+                  f"{'/'.join(map(str, ks))}, {dt:.1f} s on {threads} threads",
+        "nproc": os.cpu_count(),
+        "affinity_cpus": affinity,
+        "threads": threads,
+        "one_thread": {"value": round(v1, 4), "unit": "Gbp·query/s",
+                       "sample": f"first {len(idx1)} contigs ({tot1 / 1e6:.1f} Mbp), {dt1:.1f} s"},
+    }
+
+
+def c2_end_to_end(args, w, ks, variant):
+    """The paper-scale step from host bytes: each maxSubs pass streams the 4
+    Gbp of contigs through ifa_scan_chunk (host packing, pinned double
+    buffer, copies, scan) and drains the hits; nothing is resident."""
+    import synth
+    import paper_2607_27291_amd as ifa
+    nq = len(w.queries)
+    s = ifa.Scanner(device=0, host_threads=synth.default_threads(), **chunk_kw(args))
+    ifa.ifa_set_variant(s.ctx, variant)
+
+    def step():
+        n = 0
+        for k in ks:
+            s.load_queries(w.queries, [k] * nq)
+            s.scan_chunk(w.ref)
+            n += len(s.collect())
+        return n
+
+    step()
+    device_sync()
+    ifa.ifa_reset_stats(s.ctx)
+    t0 = time.perf_counter()
+    reps = 2
+    for _ in range(reps):
+        hits = step()
+    device_sync()
+    dt = (time.perf_counter() - t0) / reps
+    st = ifa.ifa_get_stats(s.ctx)
+    s.close()
+    bpq = w.ref.total * nq * len(ks)
+    return {"gbpq_s": round(bpq / dt / 1e9, 3), "ms_per_step": round(dt * 1e3, 2),
+            "hits_per_step": hits, "steps": reps,
+            "pack_gbp_s": round(st["bases"] / max(st["pack_ms"] * 1e-3, 1e-9) / 1e9, 2),
+            "h2d_gb_s": round(st["bases"] * BYTES_PER_BASE / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 2),
+            "note": "host bytes in, hits out: packing and copies included"}
 
 
 # --------------------------------------------------------------------------
@@ -400,7 +558,8 @@ def run_c3(args):
                     **chunk_kw(args))
     s.ref_load(w.ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
-    tune = choose_variant(ifa, s, args, w.queries, w.max_subs)
+    tune = choose_variant(ifa, s, args, w.queries, w.max_subs,
+                          *((16 << 20, 3) if getattr(args, "sub", False) else (64 << 20, 5)))
     variant = ifa.ifa_get_variant(s.ctx)
 
     def step():
@@ -426,11 +585,15 @@ def run_c3(args):
     })
     out["kernel_only_gbpq_s"] = round(bpq * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
     out["filter_ms_per_step"] = round(st["filter_ms"] / args.steps, 3)
+    out["dense_ms_per_step"] = round(st["dense_ms"] / args.steps, 3)
     out["pass_ms_per_step"] = round(st["kernel_ms"] / args.steps, 3)
+    out["graph_launches"] = st["graph_launches"]
     out["autotune"] = tune
     add_overhang(out, args, st)
+    out["op_model"] = op_model(out["value"])
     # filter launches cover the sparse strands only; dense strands bypass it
     out["roofline"] = roofline(ifa, st, n_sparse, variant)
+    out["dense_roofline"] = dense_roofline(st, 2 * nq - n_sparse)
     s.close()
     return out
 
@@ -450,6 +613,8 @@ def run_c4(args):
     lens = synth.contig_lengths(spec)
     gcs = synth.contig_gc(spec, 0, len(lens))
     qs, ks = synth.c4_queries(n=nq)
+    if args.packed:
+        return run_c4_packed(args, spec, lens, gcs, qs, ks)
     batch_bases = 1 << 30
     # contig batches of about batch_bases each
     batches, cur, acc = [], [], 0
@@ -529,8 +694,90 @@ def run_c4(args):
     out["gpu_busy_frac"] = round(st["kernel_ms"] / (elapsed * 1e3), 4)
     out["producer_gbp_s"] = round(total * (args.steps + args.warmup) / max(gen_s[0], 1e-9) / 1e9, 3)
     out["pack_gbp_s"] = round(st["bases"] / max(st["pack_ms"] * 1e-3, 1e-9) / 1e9, 3)
-    # four bit planes per base (hi, lo, N, piece end): half a byte per base
-    out["h2d_gb_s"] = round(st["bases"] / 2 / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
+    # two bit planes per base (hi, lo) cross; N and piece ends as a sparse list
+    out["h2d_gb_s"] = round(st["bases"] * BYTES_PER_BASE / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
+    out["device_footprint_bytes"] = {"before": foot0, "after": foot1}
+    out["autotune"] = tune
+    out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant)
+    s.close()
+    return out
+
+
+def run_c4_packed(args, spec, lens, gcs, qs, ks):
+    """c4 with a producer that hands over 2-bit data: each batch of whole
+    contigs (at most one device chunk, 2^30 bases) is generated straight into
+    the two code planes and scanned with ifa_scan_packed."""
+    import synth
+    import paper_2607_27291_amd as ifa
+    total = int(lens.sum())
+    nq = len(qs)
+    cap = 1 << 30
+    batches, cur, acc = [], [], 0
+    for i, n in enumerate(lens):
+        if acc + int(n) > cap and cur:
+            batches.append(cur)
+            cur, acc = [], 0
+        cur.append(i)
+        acc += int(n)
+    if cur:
+        batches.append(cur)
+    threads = synth.default_threads()
+    log(f"c4 packed: {total / 1e9:.0f} Gbp in {len(lens)} contigs, {len(batches)} chunks, "
+        f"{nq} queries")
+    s = ifa.Scanner(device=0, host_threads=threads)
+    tune = choose_variant(ifa, s, args, qs, ks)
+    variant = ifa.ifa_get_variant(s.ctx)
+    s.load_queries(qs, ks)
+    foot0 = ifa.ifa_device_footprint(s.ctx)
+    words = (cap + 31) // 32
+    planes = [(np.empty(words, np.uint32), np.empty(words, np.uint32)) for _ in range(2)]
+
+    def gen_batch(b):
+        idx = batches[b]
+        hi, lo = planes[b % 2]
+        n = synth.fill_packed(spec, idx[0], lens[idx], gcs[idx], hi, lo, threads)
+        return n, hi, lo, lens[idx]
+
+    gen_s = [0.0]
+
+    def step():
+        s.load_queries(qs, ks)
+        nxt = {}
+
+        def produce(b):
+            t = time.perf_counter()
+            nxt[b] = gen_batch(b)
+            gen_s[0] += time.perf_counter() - t
+
+        th = threading.Thread(target=produce, args=(0,))
+        th.start()
+        for b in range(len(batches)):
+            th.join()
+            n, hi, lo, bl = nxt.pop(b)
+            # ifa_scan_packed copies the planes before it returns, so the
+            # producer may refill this buffer with batch b + 2
+            if b + 1 < len(batches):
+                th = threading.Thread(target=produce, args=(b + 1,))
+                th.start()
+            s.scan_packed(n, hi, lo, bl)
+        return len(s.collect())
+
+    elapsed, st, res = timed_steps(ifa, s, args, step)
+    foot1 = ifa.ifa_device_footprint(s.ctx)
+    bpq = total * nq
+    out = base_record(args, bpq * args.steps / elapsed / 1e9, elapsed * 1e3 / args.steps, {
+        "workload": f"terabase-style streaming: {nq} queries L20-40, maxSubs 4, vs "
+                    f"{total / 1e9:.0f} Gbp generated on the fly straight into 2-bit planes "
+                    "and streamed with ifa_scan_packed through pinned double buffers",
+        "reference_bases": total,
+        "queries": nq,
+        "contigs": len(lens),
+        "hits_per_step": res[-1],
+    })
+    out["kernel_only_gbpq_s"] = round(bpq * args.steps / (st["kernel_ms"] * 1e-3) / 1e9, 3)
+    out["gpu_busy_frac"] = round(st["kernel_ms"] / (elapsed * 1e3), 4)
+    out["producer_gbp_s"] = round(total * (args.steps + args.warmup) / max(gen_s[0], 1e-9) / 1e9, 3)
+    out["h2d_gb_s"] = round(st["bases"] * BYTES_PER_BASE / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
     out["device_footprint_bytes"] = {"before": foot0, "after": foot1}
     out["autotune"] = tune
     out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant)
@@ -568,7 +815,7 @@ def run_c5(args):
     mean_q = sum(len(r[1]) for r in trace) / len(trace)
     cap_req_s = res["batch"]["gbpq_per_s"] * 1e9 / (mean_q * bases)
     rate2 = 0.7 * cap_req_s
-    trace2 = synth.c5_trace(n_requests=args.requests, rate=rate2)
+    trace2 = synth.c5_trace(n_requests=args.requests_70, rate=rate2)
     log(f"replaying {len(trace2)} requests at {rate2:.3f}/s (70% of capacity), batch")
     res["batch_70pct"] = serve.replay(s, trace2, mode="batch", log=log)
     b = res["batch"]
@@ -589,6 +836,8 @@ def run_c5(args):
         for k, v in res.items()
     }
     out["serving"]["batch_70pct"]["rate_per_s"] = round(rate2, 4)
+    out["serving"]["batch_over_serial"] = round(res["batch"]["gbpq_per_s"] /
+                                                res["serial"]["gbpq_per_s"], 3)
     s.close()
     return out
 
@@ -710,6 +959,38 @@ def run_cross(args):
     return out
 
 
+def run_default(args):
+    """The paper-scale line (the driver's), and unless --only, beside it: the
+    same step end to end from host bytes, the batched scan (10,000 queries x
+    1 Gbp) and the serving loop (a trace of Poisson arrivals, batched against
+    serial), each measured on this GPU in the same run."""
+    import copy
+    out = run_c2(args)
+    w, variant = out.pop("_workload"), out.pop("_variant")
+    if args.only or args.total or args.queries:
+        return out
+    ks = [int(x) for x in args.ks.split(",")]
+    log("end to end: paper-scale step from host bytes")
+    out["end_to_end"] = c2_end_to_end(args, w, ks, variant)
+    del w
+    sub = copy.copy(args)
+    sub.sub = True
+    sub.steps, sub.warmup = 2, 1
+    log("batched scan: 10,000 queries x 1 Gbp")
+    c3 = run_c3(sub)
+    out["c3"] = {k: c3[k] for k in ("value", "unit", "ms_per_step", "config", "kernel_only_gbpq_s",
+                                   "filter_ms_per_step", "dense_ms_per_step", "pass_ms_per_step",
+                                   "graph_launches", "op_model", "roofline", "dense_roofline")}
+    out["c3"]["steps"], out["c3"]["warmup"] = sub.steps, sub.warmup
+    log("serving loop")
+    sub.requests = args.requests
+    sub.requests_70 = args.requests_70
+    c5 = run_c5(sub)
+    out["serving"] = {"value": c5["value"], "unit": c5["unit"], "config": c5["config"],
+                      **c5["serving"]}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -719,7 +1000,7 @@ def main():
     if args.calib_copy:
         calib_copy()
     if args.workload == "c2":
-        out = run_c2(args)
+        out = run_default(args)
     elif args.workload == "c3":
         out = run_c3(args)
     elif args.workload == "c4":

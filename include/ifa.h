@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define IFA_ABI_VERSION 2u
+#define IFA_ABI_VERSION 3u
 /* Longest query: n_ref and the mismatch count of a window then fit the
  * record's fields (n_ref is one byte). */
 #define IFA_MAX_QUERY_LEN 255u
@@ -80,11 +80,14 @@ typedef struct {
     int32_t device;         /* HIP device ordinal */
     uint64_t chunk_bases;   /* bases per device chunk; multiple of 32 in
                                [4096, 2^31]; fixes the device footprint */
-    uint64_t hit_capacity;  /* hit records per device hit buffer; 0 = auto
-                               (2^22). A full buffer never loses hits: the
-                               chunk is re-scanned in halves, and a buffer
-                               grows only if the 32 windows of one plane word
-                               x every query strand alone overflow it */
+    uint64_t hit_capacity;  /* hit records per device hit buffer (there are
+                               two); 0 = auto: 1/32 of the device memory free
+                               at ifa_create (hipMemGetInfo) over the two,
+                               within [2^20, 2^26] records each. A full buffer
+                               never loses hits: the chunk is re-scanned in
+                               halves, and a buffer grows only if the 32
+                               windows of one plane word x every query strand
+                               alone overflow it */
     uint32_t strands;       /* IFA_STRAND_* */
     uint32_t n_policy;      /* IFA_N_SEPARATE | IFA_N_AS_MISMATCH */
     uint32_t sink;          /* IFA_SINK_RECORDS | IFA_SINK_COUNT_DIGEST */
@@ -99,9 +102,12 @@ typedef struct {
     uint32_t flags;         /* IFA_FLAG_* bits; others must be 0 */
 } ifa_config;
 
-/* ifa_config.flags: replay each resident chunk's scan pass from a captured
- * HIP graph while its launch arguments repeat (the first pass with new
- * arguments runs eagerly; the second is captured). Results are identical. */
+/* ifa_config.flags: replay scan passes from captured HIP graphs, one per
+ * device chunk (resident chunk or stream slot), hit buffer and query-table
+ * set. A pass is captured the second time its launch structure (kernels,
+ * block sizes, LDS) repeats; later passes with other arguments (another
+ * streamed chunk, another query set) update the graph's kernel nodes before
+ * the replay. Results are identical. Set by ifa_config_default. */
 #define IFA_FLAG_GRAPHS 1u
 /* ifa_config.flags: also report the windows that overhang a contig end (see
  * the definition at the top). Off by default. */
@@ -164,12 +170,17 @@ typedef struct {
                                 resolve kernel and not counted) */
     uint64_t work_items;     /* work-list items the filter emitted */
     uint64_t graph_launches; /* scan passes replayed from a captured graph */
+    uint64_t graph_updates;  /* of those, replays whose kernel arguments were updated
+                                first (another streamed chunk or query set) */
     double edge_ms;          /* summed time of the overhanging-window kernel
                                 (IFA_FLAG_OVERHANG), HIP events on the compute stream */
+    double dense_ms;         /* summed time of the dense-strand kernels (or, in
+                                indexed mode, the seed kernel), HIP events */
 } ifa_stats;
 
 /* Fill *cfg with the defaults: device 0, 2^30-base chunks, automatic hit
- * capacity, both strands, IFA_N_SEPARATE, records sink, all host threads. */
+ * capacity, both strands, IFA_N_SEPARATE, records sink, all host threads,
+ * flags IFA_FLAG_GRAPHS. */
 void ifa_config_default(ifa_config *cfg);
 
 /* Create a context on cfg->device (cfg NULL = defaults). Allocates the fixed
@@ -199,6 +210,37 @@ ifa_status ifa_load_queries(ifa_ctx *ctx, uint32_t n, const uint8_t *const *seq,
  * Errors: IFA_E_STATE (no queries loaded), IFA_E_INVALID, IFA_E_DEVICE. */
 ifa_status ifa_scan_chunk(ifa_ctx *ctx, uint32_t n_contigs, const uint8_t *const *seq,
                           const uint64_t *len, uint32_t *first_ordinal);
+
+/* A chunk of whole contigs packed by the caller (a producer that already
+ * holds 2-bit data: the reference streams in on the fly, Methods, "Algorithm
+ * Design" and "Memory Management"). Contigs lie back to back from base 0;
+ * base x is bit x & 31 of word x >> 5 of the two code planes, with
+ * A = (hi 0, lo 0), C = (0, 1), G = (1, 1), T = (1, 0) (bits 2 and 1 of the
+ * base's ASCII letter, either case). Non-ACGT bases are given as N runs;
+ * their plane bits are ignored, as are bits past n_bases in the last word. */
+typedef struct {
+    uint64_t n_bases;             /* <= ifa_config.chunk_bases */
+    const uint32_t *hi, *lo;      /* ceil(n_bases / 32) words each */
+    uint32_t n_contigs;
+    uint32_t n_runs;
+    const uint64_t *contig_len;   /* n_contigs lengths (< 2^31) adding up to n_bases;
+                                     a contig of length 0 takes an ordinal only */
+    const uint64_t *run_start;    /* n_runs N runs: chunk offsets, ascending */
+    const uint32_t *run_len;      /* their lengths (>= 1); runs are disjoint and
+                                     inside the chunk */
+} ifa_packed_chunk;
+
+/* Scan one caller-packed chunk: the same hits (and ordinals) as
+ * ifa_scan_chunk of the same contigs as bytes, with every N-run base as 'N'.
+ * Contigs take global ordinals in order (*first_ordinal, may be NULL, gets
+ * the first); anything streamed by ifa_scan_chunk before is submitted first.
+ * The planes are copied to the library's pinned staging before the call
+ * returns; only the 2-bit planes and a list of the words holding an N or a
+ * contig end cross to the device, whose N and contig-end planes are rebuilt
+ * there. Errors: IFA_E_STATE (no queries loaded), IFA_E_INVALID (sizes, NULL
+ * pointers, runs out of order or outside the chunk, lengths that do not add
+ * up), IFA_E_DEVICE. */
+ifa_status ifa_scan_packed(ifa_ctx *ctx, const ifa_packed_chunk *chunk, uint32_t *first_ordinal);
 
 /* Wait for every submitted scan and hand out the hits found so far in
  * reference order: (contig, pos, strand, query) ascending, pos signed (Results, "Accuracy
@@ -323,24 +365,35 @@ ifa_status ifa_autotune(ifa_ctx *ctx, uint64_t calib_bases, uint32_t reps, const
  * concurrent requests shares the same kernel launches. A request admitted at
  * a step completes after one full revolution over the resident chunks; its
  * hits are exactly those of a plain scan of that query set alone (same
- * records, same reference order). Admission keeps the admitted query count
- * under max_active_queries and the admitted requests' expected hits (iid-base
- * binomial model) under hit_budget records; a request alone is always
- * admitted. A server borrows its context: the context must hold a resident
- * reference (ifa_ref_load), use the records sink, and must not be used for
- * other scans while the server exists.
+ * records, same reference order). Steps are pipelined: a step submits its
+ * chunk's scan, then waits for the previous step's scan and routes its hits
+ * (a step that submits nothing drains the last one), so a request completes
+ * within the step that submits its last chunk.
+ *
+ * Admission keeps the admitted query count under max_active_queries and the
+ * hits one step can produce under hit_budget records: a request reserves, per
+ * chunk, its expected hits on iid uniform bases (each base matches with
+ * probability 1/4: sum over strands of chunk bases x P(Bin(L, 3/4) <= k))
+ * plus six standard deviations and 1,024 records. The context's hit buffers
+ * grow to the admitted reservation; a request alone is always admitted (a
+ * chunk whose hits overflow is re-scanned in halves, as for any scan). A
+ * server borrows its context: the context must hold a resident reference
+ * (ifa_ref_load), use the records sink, and must not be used for other scans
+ * while the server exists.
  * ------------------------------------------------------------------------ */
 typedef struct ifa_server ifa_server;
 
 typedef struct {
     uint32_t max_active_queries;  /* default 4096 */
     uint32_t reserved;            /* must be 0 */
-    uint64_t hit_budget;          /* default 2^26 records */
+    uint64_t hit_budget;          /* records per step; 0 (default) = a quarter of the
+                                     device memory free at ifa_server_create
+                                     (hipMemGetInfo), over two 16-byte record buffers */
 } ifa_server_config;
 
 typedef struct {
     uint32_t pending;         /* submitted, not yet admitted */
-    uint32_t active;          /* admitted, scanning */
+    uint32_t active;          /* admitted, chunks left to scan */
     uint32_t active_queries;
     uint32_t done_waiting;    /* completed, hits not yet taken */
     uint64_t steps;
@@ -348,6 +401,10 @@ typedef struct {
     double step_ms;           /* host wall time inside steps */
     uint32_t cursor;          /* next resident chunk */
     uint32_t chunks;          /* resident chunks */
+    uint64_t hit_budget;      /* records per step in force */
+    uint64_t hits_reserved;   /* records reserved by the admitted requests */
+    uint32_t in_flight;       /* submitted scans whose hits are not routed yet */
+    uint32_t finishing;       /* requests with every chunk submitted, hits not all routed */
 } ifa_server_stats;
 
 void ifa_server_config_default(ifa_server_config *cfg);
@@ -361,9 +418,10 @@ ifa_status ifa_server_submit(ifa_server *srv, uint32_t n, const uint8_t *const *
                              const uint32_t *len, const int32_t *max_subs, const int32_t *max_n,
                              uint64_t *request_id);
 
-/* Admit what fits, then scan the chunk under the cursor for every admitted
- * request and advance the cursor. Blocks until the chunk's hits are routed.
- * Does nothing when no request is admitted. */
+/* Admit what fits, submit the scan of the chunk under the cursor for every
+ * admitted request and advance the cursor; then wait for the previous step's
+ * scan and route its hits (with no request admitted, only the latter). Does
+ * nothing when nothing is admitted or in flight. */
 ifa_status ifa_server_step(ifa_server *srv, uint32_t *n_active, uint32_t *n_done_waiting);
 
 /* The oldest completed request not yet taken: *request_id (0 if none) and

@@ -28,7 +28,7 @@ __all__ = [
     "SamWriter", "Scanner", "Server", "collect_all",
 ]
 
-IFA_ABI_VERSION = 2
+IFA_ABI_VERSION = 3
 IFA_MAX_QUERY_LEN = 255
 IFA_N_SEPARATE, IFA_N_AS_MISMATCH = 0, 1
 IFA_SINK_RECORDS, IFA_SINK_COUNT_DIGEST = 0, 1
@@ -39,6 +39,7 @@ IFA_FLAG_INDEXED = 4
 IFA_FLAG_AUTO_MODE = 8
 IFA_MAX_SEED_KS = 8
 
+IFA_OK, IFA_E_INVALID, IFA_E_NOMEM, IFA_E_DEVICE, IFA_E_STATE, IFA_E_TOO_LONG = range(6)
 STATUS = {0: "IFA_OK", 1: "IFA_E_INVALID", 2: "IFA_E_NOMEM", 3: "IFA_E_DEVICE",
           4: "IFA_E_STATE", 5: "IFA_E_TOO_LONG"}
 
@@ -61,7 +62,9 @@ class IfaStats(ctypes.Structure):
                 ("h2d_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
                 ("filter_ms", ctypes.c_double), ("filter_launches", ctypes.c_uint64),
                 ("filter_windows", ctypes.c_uint64), ("work_items", ctypes.c_uint64),
-                ("graph_launches", ctypes.c_uint64), ("edge_ms", ctypes.c_double)]
+                ("graph_launches", ctypes.c_uint64), ("graph_updates", ctypes.c_uint64),
+                ("edge_ms", ctypes.c_double),
+                ("dense_ms", ctypes.c_double)]
 
 
 class IfaIndexParams(ctypes.Structure):
@@ -81,7 +84,16 @@ class IfaServerStats(ctypes.Structure):
                 ("active_queries", ctypes.c_uint32), ("done_waiting", ctypes.c_uint32),
                 ("steps", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("step_ms", ctypes.c_double), ("cursor", ctypes.c_uint32),
-                ("chunks", ctypes.c_uint32)]
+                ("chunks", ctypes.c_uint32), ("hit_budget", ctypes.c_uint64),
+                ("hits_reserved", ctypes.c_uint64), ("in_flight", ctypes.c_uint32),
+                ("finishing", ctypes.c_uint32)]
+
+
+class IfaPackedChunk(ctypes.Structure):
+    _fields_ = [("n_bases", ctypes.c_uint64), ("hi", ctypes.c_void_p), ("lo", ctypes.c_void_p),
+                ("n_contigs", ctypes.c_uint32), ("n_runs", ctypes.c_uint32),
+                ("contig_len", ctypes.c_void_p), ("run_start", ctypes.c_void_p),
+                ("run_len", ctypes.c_void_p)]
 
 
 class IfaError(RuntimeError):
@@ -115,6 +127,8 @@ def lib():
         L.ifa_load_queries.restype = st
         L.ifa_scan_chunk.argtypes = [vp, u32, vp, vp, ctypes.POINTER(u32)]
         L.ifa_scan_chunk.restype = st
+        L.ifa_scan_packed.argtypes = [vp, ctypes.POINTER(IfaPackedChunk), ctypes.POINTER(u32)]
+        L.ifa_scan_packed.restype = st
         L.ifa_collect_hits.argtypes = [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.ifa_collect_hits.restype = st
         L.ifa_query_stats.argtypes = [vp, vp, vp]
@@ -290,6 +304,21 @@ def ifa_scan_chunk(ctx, contigs) -> int:
     first = ctypes.c_uint32()
     _check(ctx, lib().ifa_scan_chunk(ctx, n, ptrs, lens.ctypes.data, ctypes.byref(first)))
     del keep
+    return first.value
+
+
+def ifa_scan_packed(ctx, n_bases: int, hi, lo, contig_len, run_start=None, run_len=None) -> int:
+    """Scan a caller-packed chunk (see ifa_packed_chunk): hi / lo uint32
+    planes, contig lengths, optional N runs. Returns the first ordinal."""
+    hi = np.ascontiguousarray(hi, dtype=np.uint32)
+    lo = np.ascontiguousarray(lo, dtype=np.uint32)
+    cl = np.ascontiguousarray(contig_len, dtype=np.uint64)
+    rs = np.ascontiguousarray(run_start if run_start is not None else [], dtype=np.uint64)
+    rl = np.ascontiguousarray(run_len if run_len is not None else [], dtype=np.uint32)
+    pk = IfaPackedChunk(n_bases, hi.ctypes.data, lo.ctypes.data, len(cl), len(rs),
+                        cl.ctypes.data, rs.ctypes.data, rl.ctypes.data)
+    first = ctypes.c_uint32()
+    _check(ctx, lib().ifa_scan_packed(ctx, ctypes.byref(pk), ctypes.byref(first)))
     return first.value
 
 
@@ -583,7 +612,7 @@ class SamWriter:
 class Server:
     """Continuous-batching server over a Scanner's resident reference."""
 
-    def __init__(self, scanner, max_active_queries=4096, hit_budget=1 << 26):
+    def __init__(self, scanner, max_active_queries=4096, hit_budget=0):
         self.scanner = scanner
         cfg = ifa_server_config_default()
         cfg.max_active_queries = max_active_queries
@@ -636,7 +665,7 @@ class Scanner:
 
     def __init__(self, *, device=0, chunk_bases=1 << 30, hit_capacity=0,
                  strands=IFA_STRAND_BOTH, n_policy=IFA_N_SEPARATE, sink=IFA_SINK_RECORDS,
-                 host_threads=0, work_capacity=0, flags=0):
+                 host_threads=0, work_capacity=0, flags=IFA_FLAG_GRAPHS):
         cfg = ifa_config_default()
         cfg.device = device
         cfg.chunk_bases = chunk_bases
@@ -673,6 +702,9 @@ class Scanner:
 
     def scan_chunk(self, contigs) -> int:
         return ifa_scan_chunk(self.ctx, contigs)
+
+    def scan_packed(self, n_bases, hi, lo, contig_len, run_start=None, run_len=None) -> int:
+        return ifa_scan_packed(self.ctx, n_bases, hi, lo, contig_len, run_start, run_len)
 
     def collect(self) -> np.ndarray:
         return collect_all(self.ctx)

@@ -175,4 +175,13 @@ struct ScanArgs {
     unsigned long long *q_digest;
 };
 
+// A scan-kernel launch recorded instead of issued (the launch functions'
+// plan mode): kernel, grid, block, dynamic LDS and its one argument.
+struct ScanLaunch {
+    const void *func;
+    dim3 grid, block;
+    uint32_t lds;
+    ScanArgs args;
+};
+
 }  // namespace ifa

@@ -29,11 +29,12 @@
 #include "ifa_seed.h"
 
 namespace ifa {
-hipError_t launch_filter(const ScanArgs &a, hipStream_t s);
-hipError_t launch_resolve(const ScanArgs &a, hipStream_t s);
-hipError_t launch_dense(const ScanArgs &a, hipStream_t s);
-hipError_t launch_edge(const ScanArgs &a, hipStream_t s);
-hipError_t launch_seed(const ScanArgs &a, hipStream_t s);
+// (rec != nullptr: the launches are recorded in rec instead of issued)
+hipError_t launch_filter(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec = nullptr);
+hipError_t launch_resolve(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec = nullptr);
+hipError_t launch_dense(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec = nullptr);
+hipError_t launch_edge(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec = nullptr);
+hipError_t launch_seed(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec = nullptr);
 hipError_t launch_clear_u64(unsigned long long *p, uint32_t n, hipStream_t s);
 hipError_t launch_expand(uint32_t *planes, uint64_t stride, uint8_t *nflag, uint32_t used,
                          uint32_t total, const uint4 *list, uint32_t n_list, hipStream_t s);
@@ -183,14 +184,26 @@ struct Staging {
 // A captured scan pass of one resident chunk into one hit buffer: replayed
 // while the pass's launch arguments stay the same (the query tables' content
 // may change; their addresses and sizes may not).
+// A captured scan pass of one device chunk into one hit buffer with one
+// set of query tables. The pass is captured the second time its launch
+// structure (kernels, block sizes, LDS) repeats and replayed after that; when
+// only arguments or grid sizes differ (another streamed chunk, other query
+// counts) its kernel nodes are updated in place before the replay.
 struct PassGraph {
-    ScanArgs args{};              // arguments of the last eager or captured pass
-    bool seen = false;            // args held a pass that ran
+    ScanArgs args{};              // arguments the graph holds (or the last eager pass had)
+    std::vector<ScanLaunch> plan; // the scan-kernel launches of that pass
+    bool seen = false;            // plan holds a pass that ran
+    hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<hipGraphNode_t> knodes;   // the scan-kernel nodes, in plan order
     void reset()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
+        graph = nullptr;
+        knodes.clear();
+        plan.clear();
         seen = false;
     }
 };
@@ -206,11 +219,11 @@ struct DevChunk {
     uint32_t n_pieces = 0;
     hipEvent_t free_ev = nullptr;   // last kernel reading it finished
     bool resident = false;
-    PassGraph graph[2];             // per hit buffer (resident chunks)
+    PassGraph graph[2][2];          // per hit buffer and query-table set (resident chunks)
     ~DevChunk()
     {
-        graph[0].reset();
-        graph[1].reset();
+        for (auto &g : graph)
+            for (auto &x : g) x.reset();
     }
 };
 
@@ -218,7 +231,11 @@ struct DevChunk {
 struct Job {
     DevChunk *chunk = nullptr;
     int hitbuf = 0;
+    ScanArgs args{};                      // the pass's launch arguments (re-scans reuse
+                                          // them: the query tables they point to stay
+                                          // valid until the job is retired)
     hipEvent_t k0 = nullptr, kf = nullptr, k1 = nullptr;  // start / filter end / stop
+    hipEvent_t kd = nullptr;                              // dense kernels start
     hipEvent_t ke = nullptr;                              // overhang kernel start
     hipEvent_t done = nullptr;              // hit count copied to the host
     bool active = false;
@@ -248,8 +265,13 @@ struct ifa_ctx {
     // device query tables, uploaded together through a pinned staging arena:
     // strand descriptors, packed words and the three-class filter's words per
     // column tile
-    DevBuf<uint8_t> d_qarena;
-    HostBuf<uint8_t> h_qarena;
+    // Two sets of tables alternate between query sets (tab), so that a new
+    // set can be uploaded while passes of the previous one are still queued;
+    // `staged` marks the end of the last copy out of each pinned staging.
+    int tab = 0;
+    DevBuf<uint8_t> d_qarena[2];
+    HostBuf<uint8_t> h_qarena[2];
+    hipEvent_t qstaged[2] = {nullptr, nullptr};
     const QSDesc *dq_qs = nullptr;
     const uint32_t *dq_words = nullptr;
     const uint32_t *dq_mq3w = nullptr;
@@ -258,8 +280,9 @@ struct ifa_ctx {
     // pass first needs that form for the loaded query set
     std::vector<uint8_t> h_fw;        // filter words of each strand (device order)
     bool mq_ready[2] = {false, false};
-    DevBuf<uint8_t> d_mqarena[2];
-    HostBuf<uint8_t> h_mqarena[2];
+    DevBuf<uint8_t> d_mqarena[2][2];      // [tab][form]
+    HostBuf<uint8_t> h_mqarena[2][2];
+    hipEvent_t mqstaged[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     const uint4 *dq_mqb = nullptr, *dq_mq3b = nullptr;
     const float *dq_mqt = nullptr, *dq_mq3t = nullptr;
     uint32_t mq3_words = 1;           // most prefix words of any three-class column tile
@@ -523,9 +546,10 @@ double binom_cdf(uint32_t n, double p, uint32_t k)
 
 void ensure_filter_operands(ifa_ctx *c);
 
-ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
+// Launch arguments of a pass over chunk ch with the loaded queries, without
+// the hit, work-list and counter fields.
+ScanArgs chunk_args(ifa_ctx *c, const DevChunk &ch)
 {
-    ensure_filter_operands(c);
     ScanArgs a{};
     a.hi = ch.planes.p;
     a.lo = ch.planes.p + ch.stride;
@@ -560,6 +584,17 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.n_pieces = ch.n_pieces;
     a.sink = c->cfg.sink;
     a.variant = c->variant;
+    a.q_count = c->d_qcount.p;
+    a.q_digest = c->d_qdigest.p;
+    return a;
+}
+
+// Launch arguments of a pass over chunk ch into hit buffer hb (building the
+// matrix filter's operands first if the variant needs new ones).
+ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
+{
+    ensure_filter_operands(c);
+    ScanArgs a = chunk_args(c, ch);
     a.work = c->work[hb].p;
     a.work_count = reinterpret_cast<unsigned int *>(c->d_ctr.p + 2 * hb + 1);
     a.skip_count = a.work_count + 1;
@@ -567,8 +602,6 @@ ScanArgs make_args(ifa_ctx *c, const DevChunk &ch, int hb)
     a.hits = c->d_hits[hb].p;
     a.hit_count = c->d_ctr.p + 2 * hb;
     a.hit_cap = c->buf_cap[hb];
-    a.q_count = c->d_qcount.p;
-    a.q_digest = c->d_qdigest.p;
     return a;
 }
 
@@ -610,11 +643,12 @@ void copy_records(ifa_ctx *c, int hb, uint64_t n)
 // Timing events of one pass: t0 before the filter, t1 after it, te before
 // the overhanging-window kernel, t2 after the last scan kernel.
 struct PassEvents {
-    hipEvent_t t0 = nullptr, t1 = nullptr, te = nullptr, t2 = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr, td = nullptr, te = nullptr, t2 = nullptr;
     void create()
     {
         if (!t0) hip_check(hipEventCreate(&t0), "event");
         if (!t1) hip_check(hipEventCreate(&t1), "event");
+        if (!td) hip_check(hipEventCreate(&td), "event");
         if (!te) hip_check(hipEventCreate(&te), "event");
         if (!t2) hip_check(hipEventCreate(&t2), "event");
     }
@@ -622,9 +656,10 @@ struct PassEvents {
     {
         if (t0) (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
+        if (td) (void)hipEventDestroy(td);
         if (te) (void)hipEventDestroy(te);
         if (t2) (void)hipEventDestroy(t2);
-        t0 = t1 = te = t2 = nullptr;
+        t0 = t1 = td = te = t2 = nullptr;
     }
 };
 
@@ -632,30 +667,88 @@ struct PassEvents {
 // kernel, then resolve kernel over the work list) and, if `dense`, the dense
 // kernels and (with IFA_FLAG_OVERHANG) the overhanging windows. Counters are
 // cleared by kernels on the stream first.
+// (A null event in ev is not recorded.)
 void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, PassEvents &ev)
 {
+    auto mark = [&](hipEvent_t e) {
+        if (e) hip_check(hipEventRecord(e, c->comp_s), "event record");
+    };
     // the pass counters of a hit buffer are adjacent (hit count, then the
     // work and skip counts): one clear kernel
     hip_check(clear_hits ? launch_clear_u64(a.hit_count, 2, c->comp_s)
                          : launch_clear_u64(a.hit_count + 1, 1, c->comp_s),
               "clear pass counters");
-    hip_check(hipEventRecord(ev.t0, c->comp_s), "event record");
+    mark(ev.t0);
     if (c->indexed) {
         // indexed mode: seed lookups and their verification, one kernel
-        hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
+        mark(ev.t1);
+        mark(ev.td);
         if (dense) hip_check(launch_seed(a, c->comp_s), "seed launch");
-        hip_check(hipEventRecord(ev.te, c->comp_s), "event record");
-        hip_check(hipEventRecord(ev.t2, c->comp_s), "event record");
+        mark(ev.te);
+        mark(ev.t2);
         return;
     }
     hip_check(launch_filter(a, c->comp_s), "filter launch");
-    hip_check(hipEventRecord(ev.t1, c->comp_s), "event record");
+    mark(ev.t1);
     hip_check(launch_resolve(a, c->comp_s), "resolve launch");
+    mark(ev.td);
     if (dense) hip_check(launch_dense(a, c->comp_s), "dense launch");
-    hip_check(hipEventRecord(ev.te, c->comp_s), "event record");
+    mark(ev.te);
     if (dense && (c->cfg.flags & IFA_FLAG_OVERHANG))
         hip_check(launch_edge(a, c->comp_s), "overhang launch");
-    hip_check(hipEventRecord(ev.t2, c->comp_s), "event record");
+    mark(ev.t2);
+}
+
+// The scan-kernel launches enqueue_pass issues for a (the clear kernel and
+// events aside), in the same order.
+std::vector<ScanLaunch> plan_pass(const ifa_ctx *c, const ScanArgs &a, bool dense)
+{
+    std::vector<ScanLaunch> p;
+    if (c->indexed) {
+        if (dense) hip_check(launch_seed(a, nullptr, &p), "plan");
+        return p;
+    }
+    hip_check(launch_filter(a, nullptr, &p), "plan");
+    hip_check(launch_resolve(a, nullptr, &p), "plan");
+    if (dense) hip_check(launch_dense(a, nullptr, &p), "plan");
+    if (dense && (c->cfg.flags & IFA_FLAG_OVERHANG)) hip_check(launch_edge(a, nullptr, &p), "plan");
+    return p;
+}
+
+// Same kernels, blocks and LDS in the same order (grids and arguments may differ).
+bool same_structure(const std::vector<ScanLaunch> &x, const std::vector<ScanLaunch> &y)
+{
+    if (x.size() != y.size()) return false;
+    for (size_t i = 0; i < x.size(); i++)
+        if (x[i].func != y[i].func || x[i].block.x != y[i].block.x || x[i].lds != y[i].lds)
+            return false;
+    return true;
+}
+
+// The kernel nodes of a captured pass (a chain) after the first one (the
+// counter-clearing kernel), in order; empty if the graph is not such a chain.
+std::vector<hipGraphNode_t> chain_kernel_nodes(hipGraph_t g)
+{
+    std::vector<hipGraphNode_t> out;
+    size_t nr = 0;
+    if (hipGraphGetRootNodes(g, nullptr, &nr) != hipSuccess || nr != 1) return {};
+    hipGraphNode_t cur = nullptr;
+    if (hipGraphGetRootNodes(g, &cur, &nr) != hipSuccess) return {};
+    bool first = true;
+    while (cur) {
+        hipGraphNodeType t;
+        if (hipGraphNodeGetType(cur, &t) != hipSuccess) return {};
+        if (t == hipGraphNodeTypeKernel) {
+            if (!first) out.push_back(cur);
+            first = false;
+        }
+        size_t nd = 0;
+        if (hipGraphNodeGetDependentNodes(cur, nullptr, &nd) != hipSuccess || nd > 1) return {};
+        hipGraphNode_t next = nullptr;
+        if (nd == 1 && hipGraphNodeGetDependentNodes(cur, &next, &nd) != hipSuccess) return {};
+        cur = nd == 1 ? next : nullptr;
+    }
+    return out;
 }
 
 void enqueue_count_copies(ifa_ctx *c, int hb)
@@ -685,6 +778,7 @@ void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse, int hb, uint3
     c->st.kernel_ms += elapsed(ev.t0, ev.t2);
     c->st.kernel_launches++;
     if (c->cfg.flags & IFA_FLAG_OVERHANG) c->st.edge_ms += elapsed(ev.te, ev.t2);
+    c->st.dense_ms += elapsed(ev.td, ev.te);
     if (sparse) {
         c->st.filter_ms += elapsed(ev.t0, ev.t1);
         c->st.filter_launches++;
@@ -695,6 +789,18 @@ void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse, int hb, uint3
         c->st.filter_windows += starts > skipped ? starts - skipped : 0;
         c->st.work_items += host_work(c, hb);
     }
+}
+
+// A job's launch arguments with the hit buffer and work list of its hit
+// buffer as they are now (either may have grown since the job was submitted).
+ScanArgs job_args(const ifa_ctx *c, const Job &j)
+{
+    ScanArgs a = j.args;
+    a.work = c->work[j.hitbuf].p;
+    a.work_cap = c->work_cap[j.hitbuf];
+    a.hits = c->d_hits[j.hitbuf].p;
+    a.hit_cap = c->buf_cap[j.hitbuf];
+    return a;
 }
 
 // Make the work list of hit buffer hb at least work_want items long (the
@@ -709,15 +815,16 @@ void ensure_work_list(ifa_ctx *c, int hb)
 // After a pass whose resolve kernel found the work list too small (and so
 // did nothing), grow the list and run the sparse part again until it fits.
 // Its dense part is not repeated: it does not use the list.
-void settle_work_overflow(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t w1)
+void settle_work_overflow(ifa_ctx *c, const Job &j, uint32_t w0, uint32_t w1)
 {
+    const int hb = j.hitbuf;
     while (host_work(c, hb) > c->work_cap[hb]) {
         const uint64_t need = (uint64_t)host_work(c, hb);
         const uint64_t cap = std::min<uint64_t>(need + need / 4 + 1024, 0xffffffffull);
         // the other list grows before its next launch: both see the same load
         c->work_want = std::max<uint32_t>(c->work_want, (uint32_t)cap);
         ensure_work_list(c, hb);
-        ScanArgs a = make_args(c, ch, hb);
+        ScanArgs a = job_args(c, j);
         a.w_begin = w0;
         a.w_end = w1;
         PassEvents ev;
@@ -734,9 +841,10 @@ void settle_work_overflow(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, u
 // Re-scan word range [w0, w1) of a chunk whose hit buffer overflowed (the
 // records of the first pass are discarded); halves the range until every
 // part fits.
-void rescan_range(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t w1)
+void rescan_range(ifa_ctx *c, const Job &j, uint32_t w0, uint32_t w1)
 {
-    ScanArgs a = make_args(c, ch, hb);
+    const int hb = j.hitbuf;
+    ScanArgs a = job_args(c, j);
     a.w_begin = w0;
     a.w_end = w1;
     PassEvents ev;
@@ -744,10 +852,10 @@ void rescan_range(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t 
     enqueue_pass(c, a, true, true, ev);
     enqueue_count_copies(c, hb);
     hip_check(hipStreamSynchronize(c->comp_s), "sync");
-    add_pass_times(c, ev, c->n_sparse > 0, hb, w0, w1);
+    add_pass_times(c, ev, a.n_sparse > 0, hb, w0, w1);
     ev.destroy();
     c->st.rescans++;
-    settle_work_overflow(c, ch, hb, w0, w1);
+    settle_work_overflow(c, j, w0, w1);
     uint64_t n = host_hits(c, hb);
     if (n <= c->buf_cap[hb]) {
         copy_records(c, hb, n);
@@ -758,12 +866,12 @@ void rescan_range(ifa_ctx *c, const DevChunk &ch, int hb, uint32_t w0, uint32_t 
         // alone overflow the buffer, the buffer grows to fit them
         c->d_hits[hb].alloc(n, "grow hit buffer");
         c->buf_cap[hb] = n;
-        rescan_range(c, ch, hb, w0, w1);
+        rescan_range(c, j, w0, w1);
         return;
     }
     uint32_t mid = w0 + (w1 - w0) / 2;
-    rescan_range(c, ch, hb, w0, mid);
-    rescan_range(c, ch, hb, mid, w1);
+    rescan_range(c, j, w0, mid);
+    rescan_range(c, j, mid, w1);
 }
 
 void retire(ifa_ctx *c, Job &j)
@@ -773,19 +881,20 @@ void retire(ifa_ctx *c, Job &j)
     PassEvents ev;
     ev.t0 = j.k0;
     ev.t1 = j.kf;
+    ev.td = j.kd;
     ev.te = j.ke;
     ev.t2 = j.k1;
     const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
-    add_pass_times(c, ev, c->n_sparse > 0, j.hitbuf, 0, words);
-    settle_work_overflow(c, *j.chunk, j.hitbuf, 0, words);
+    add_pass_times(c, ev, j.args.n_sparse > 0, j.hitbuf, 0, words);
+    settle_work_overflow(c, j, 0, words);
     if (c->cfg.sink == IFA_SINK_RECORDS) {
         uint64_t n = host_hits(c, j.hitbuf);
         if (n <= c->buf_cap[j.hitbuf]) {
             copy_records(c, j.hitbuf, n);
         } else {
             uint32_t mid = words / 2;
-            rescan_range(c, *j.chunk, j.hitbuf, 0, mid);
-            rescan_range(c, *j.chunk, j.hitbuf, mid, words);
+            rescan_range(c, j, 0, mid);
+            rescan_range(c, j, mid, words);
         }
     }
     j.active = false;
@@ -808,14 +917,17 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     j.hitbuf = (int)(c->job_seq % 2);
     ensure_work_list(c, j.hitbuf);
     ScanArgs a = make_args(c, *ch, j.hitbuf);
+    j.args = a;
     if (!j.k0) hip_check(hipEventCreate(&j.k0), "event");
     if (!j.kf) hip_check(hipEventCreate(&j.kf), "event");
     if (!j.k1) hip_check(hipEventCreate(&j.k1), "event");
     if (!j.ke) hip_check(hipEventCreate(&j.ke), "event");
+    if (!j.kd) hip_check(hipEventCreate(&j.kd), "event");
     if (!j.done) hip_check(hipEventCreateWithFlags(&j.done, hipEventDisableTiming), "event");
     PassEvents ev;
     ev.t0 = j.k0;
     ev.t1 = j.kf;
+    ev.td = j.kd;
     ev.te = j.ke;
     ev.t2 = j.k1;
     // the pass and its counter copy (what a graph holds); the events the host
@@ -827,26 +939,49 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
         enqueue_count_copies(c, j.hitbuf);
     };
     PassGraph *pg = nullptr;
-    if ((c->cfg.flags & IFA_FLAG_GRAPHS) && ch->resident) {
-        pg = &ch->graph[j.hitbuf];
-        // a pass whose arguments repeat is captured once, then replayed
-        if (!pg->seen || std::memcmp(&pg->args, &a, sizeof a) != 0) {
+    std::vector<ScanLaunch> plan;
+    if (c->cfg.flags & IFA_FLAG_GRAPHS) {
+        pg = &ch->graph[j.hitbuf][c->tab];
+        plan = plan_pass(c, a, true);
+        if (!pg->seen || !same_structure(pg->plan, plan)) {
+            // first pass of this structure: run eagerly, capture the next one
             pg->reset();
             pg->args = a;
+            pg->plan = plan;
             pg->seen = true;
-            pg = nullptr;   // first time with these arguments: run eagerly
+            pg = nullptr;
         }
     }
     if (pg) {
         if (!pg->exec) {
-            hipGraph_t g = nullptr;
             hip_check(hipStreamBeginCapture(c->comp_s, hipStreamCaptureModeRelaxed),
                       "begin capture");
             enqueue();
-            hip_check(hipStreamEndCapture(c->comp_s, &g), "end capture");
-            const hipError_t e = hipGraphInstantiate(&pg->exec, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            hip_check(e, "instantiate pass graph");
+            hip_check(hipStreamEndCapture(c->comp_s, &pg->graph), "end capture");
+            hip_check(hipGraphInstantiate(&pg->exec, pg->graph, nullptr, nullptr, 0),
+                      "instantiate pass graph");
+            pg->knodes = chain_kernel_nodes(pg->graph);
+            pg->args = a;
+            pg->plan = plan;
+        } else if (std::memcmp(&pg->args, &a, sizeof a) != 0) {
+            // another chunk or query set of the same structure: point the
+            // captured kernels at it
+            if (pg->knodes.size() != plan.size()) fail(IFA_E_DEVICE, "pass graph layout");
+            for (size_t i = 0; i < plan.size(); i++) {
+                hipKernelNodeParams kp{};
+                void *kargs[] = {&plan[i].args};
+                kp.func = const_cast<void *>(plan[i].func);
+                kp.gridDim = plan[i].grid;
+                kp.blockDim = plan[i].block;
+                kp.sharedMemBytes = plan[i].lds;
+                kp.kernelParams = kargs;
+                kp.extra = nullptr;
+                hip_check(hipGraphExecKernelNodeSetParams(pg->exec, pg->knodes[i], &kp),
+                          "update pass graph");
+            }
+            pg->args = a;
+            pg->plan = plan;
+            c->st.graph_updates++;
         }
         hip_check(hipGraphLaunch(pg->exec, c->comp_s), "launch pass graph");
         c->st.graph_launches++;
@@ -918,6 +1053,8 @@ void reset_staging(Staging &s)
     s.packed_to = 0;
 }
 
+void submit_staging(ifa_ctx *c);
+
 // Submit the staging chunk being filled (if it holds any base) to the GPU.
 void flush_stream(ifa_ctx *c)
 {
@@ -928,6 +1065,14 @@ void flush_stream(ifa_ctx *c)
     }
     pack_pending(c, s);
     seal(c, s);
+    submit_staging(c);
+}
+
+// Upload the sealed staging chunk being filled to the next device slot, scan
+// it, and switch to the other staging buffer.
+void submit_staging(ifa_ctx *c)
+{
+    Staging &s = c->stage[c->cur];
     DevChunk &d = c->slot[c->chunk_seq % 2];
     // The device slot is reused. Its previous scan is retired first: an
     // overflowing hit buffer is re-scanned from this slot, so the slot must
@@ -1278,22 +1423,29 @@ struct TablePart {
 
 // Copy `n` parts through the pinned staging `h` into the device arena `d`
 // (both grown as needed) with one copy on the compute stream, after the work
-// already queued there; off[i] gets part i's offset. Returns the arena.
+// already queued there; off[i] gets part i's offset. `staged` marks the end
+// of the staging's last copy: it is waited for before the staging is
+// rewritten, and recorded again after this copy. Returns the arena.
 uint8_t *upload_tables(ifa_ctx *c, HostBuf<uint8_t> &h, DevBuf<uint8_t> &d, const TablePart *parts,
-                       int n, size_t *off, const char *what)
+                       int n, size_t *off, const char *what, hipEvent_t &staged)
 {
     size_t total = 0;
     for (int i = 0; i < n; i++) {
         off[i] = total;
         total += (std::max<size_t>(parts[i].bytes, 16) + 255) & ~(size_t)255;
     }
-    // the staging's previous upload is complete before it is rewritten
-    hip_check(hipStreamSynchronize(c->comp_s), "sync");
+    if (staged) hip_check(hipEventSynchronize(staged), "wait for table staging");
+    else hip_check(hipEventCreateWithFlags(&staged, hipEventDisableTiming), "event");
     if (h.n < total) h.alloc(total, "pinned table staging");
-    if (d.n < total) d.alloc(total, what);
+    if (d.n < total) {
+        // queued passes may still read the arena being replaced
+        hip_check(hipStreamSynchronize(c->comp_s), "sync");
+        d.alloc(total, what);
+    }
     for (int i = 0; i < n; i++)
         if (parts[i].bytes) std::memcpy(h.p + off[i], parts[i].src, parts[i].bytes);
     hip_check(hipMemcpyAsync(d.p, h.p, total, hipMemcpyHostToDevice, c->comp_s), what);
+    hip_check(hipEventRecord(staged, c->comp_s), "event record");
     return d.p;
 }
 
@@ -1320,8 +1472,9 @@ void ensure_filter_operands(ifa_ctx *c)
     }
     const TablePart parts[2] = {{b.data(), b.size() * sizeof(uint32_t)},
                                 {need.data(), need.size() * sizeof(float)}};
-    uint8_t *base = upload_tables(c, c->h_mqarena[f], c->d_mqarena[f], parts, 2, off,
-                                  "matrix filter operands");
+    const int t = c->tab;
+    uint8_t *base = upload_tables(c, c->h_mqarena[t][f], c->d_mqarena[t][f], parts, 2, off,
+                                  "matrix filter operands", c->mqstaged[t][f]);
     if (enc == 1) {
         c->dq_mqb = reinterpret_cast<const uint4 *>(base + off[0]);
         c->dq_mqt = reinterpret_cast<const float *>(base + off[1]);
@@ -1380,7 +1533,9 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
                                 {words.data(), words.size() * sizeof(uint32_t)},
                                 {mw3.data(), mw3.size() * sizeof(uint32_t)}};
     size_t off[3];
-    uint8_t *base = upload_tables(c, c->h_qarena, c->d_qarena, parts, 3, off, "query tables");
+    c->tab ^= 1;
+    uint8_t *base = upload_tables(c, c->h_qarena[c->tab], c->d_qarena[c->tab], parts, 3, off,
+                                  "query tables", c->qstaged[c->tab]);
     c->dq_qs = reinterpret_cast<const QSDesc *>(base + off[0]);
     c->dq_words = reinterpret_cast<const uint32_t *>(base + off[1]);
     c->dq_mq3w = reinterpret_cast<const uint32_t *>(base + off[2]);
@@ -1552,6 +1707,7 @@ void ifa_config_default(ifa_config *cfg)
     cfg->n_policy = IFA_N_SEPARATE;
     cfg->sink = IFA_SINK_RECORDS;
     cfg->host_threads = 0;
+    cfg->flags = IFA_FLAG_GRAPHS;
 }
 
 ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
@@ -1591,7 +1747,14 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
                       "event");
         }
         uint64_t cap = cfg.hit_capacity;
-        if (cap == 0) cap = 1ull << 22;
+        if (cap == 0) {
+            // 1/32 of the free device memory over the two record buffers,
+            // within [2^20, 2^26] records each
+            size_t free_b = 0, total_b = 0;
+            hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+            cap = free_b / 32 / (2 * sizeof(ifa_hit));
+            cap = std::min<uint64_t>(std::max<uint64_t>(cap, 1ull << 20), 1ull << 26);
+        }
         c->hit_cap = cap;
         if (cfg.sink == IFA_SINK_RECORDS) {
             for (int i = 0; i < 2; i++) {
@@ -1632,7 +1795,13 @@ void ifa_destroy(ifa_ctx *c)
         if (j.k1) (void)hipEventDestroy(j.k1);
         if (j.kf) (void)hipEventDestroy(j.kf);
         if (j.ke) (void)hipEventDestroy(j.ke);
+        if (j.kd) (void)hipEventDestroy(j.kd);
         if (j.done) (void)hipEventDestroy(j.done);
+    }
+    for (int t = 0; t < 2; t++) {
+        if (c->qstaged[t]) (void)hipEventDestroy(c->qstaged[t]);
+        for (int f = 0; f < 2; f++)
+            if (c->mqstaged[t][f]) (void)hipEventDestroy(c->mqstaged[t][f]);
     }
     for (int i = 0; i < 2; i++) {
         if (c->stage[i].copied) (void)hipEventDestroy(c->stage[i].copied);
@@ -1692,6 +1861,88 @@ ifa_status ifa_scan_chunk(ifa_ctx *c, uint32_t n_contigs, const uint8_t *const *
         append_contigs(c, n_contigs, seq, len, [&]() { flush_stream(c); });
         // caller memory must not be read after return
         pack_pending(c, c->stage[c->cur]);
+    });
+}
+
+ifa_status ifa_scan_packed(ifa_ctx *c, const ifa_packed_chunk *pk, uint32_t *first_ordinal)
+{
+    if (!c || !pk) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        if (!c->have_queries) fail(IFA_E_STATE, "no queries loaded");
+        const uint64_t n = pk->n_bases;
+        if (n > c->cfg.chunk_bases) fail(IFA_E_INVALID, "packed chunk larger than chunk_bases");
+        if (n > 0 && (!pk->hi || !pk->lo)) fail(IFA_E_INVALID, "NULL plane");
+        if (pk->n_contigs > 0 && !pk->contig_len) fail(IFA_E_INVALID, "NULL contig table");
+        if (pk->n_runs > 0 && (!pk->run_start || !pk->run_len)) fail(IFA_E_INVALID, "NULL N runs");
+        uint64_t sum = 0;
+        for (uint32_t i = 0; i < pk->n_contigs; i++) {
+            if (pk->contig_len[i] >= (1ull << 31)) fail(IFA_E_INVALID, "contig longer than 2^31 - 1");
+            sum += pk->contig_len[i];
+        }
+        if (sum != n) fail(IFA_E_INVALID, "contig lengths do not add up to n_bases");
+        for (uint32_t i = 0; i < pk->n_runs; i++) {
+            const uint64_t a = pk->run_start[i], len = pk->run_len[i];
+            if (len == 0 || a + len > n || (i > 0 && a < pk->run_start[i - 1] + pk->run_len[i - 1]))
+                fail(IFA_E_INVALID, "N runs must be non-empty, ascending, disjoint and in the chunk");
+        }
+        use_device(c);
+        if (first_ordinal) *first_ordinal = c->next_ordinal;
+        // what was streamed before goes first (ordinals stay in stream order)
+        flush_stream(c);
+        Staging &s = c->stage[c->cur];
+        // pieces: whole contigs back to back; empty contigs take an ordinal only
+        uint64_t at = 0;
+        for (uint32_t i = 0; i < pk->n_contigs; i++) {
+            const uint32_t ordinal = c->next_ordinal++;
+            const uint64_t len = pk->contig_len[i];
+            if (len == 0) continue;
+            Piece p{};
+            p.start = at;
+            p.len = len;
+            p.contig_off = 0;
+            p.contig = ordinal;
+            p.flags = kPieceContigStart | kPieceContigEnd;
+            s.pieces.push_back(p);
+            at += len;
+        }
+        if (n == 0) {
+            reset_staging(s);
+            return;
+        }
+        // the planes into pinned staging (the caller may reuse its buffers on
+        // return), bits past the last base cleared
+        const uint64_t used = (n + 31) >> 5, span = 1ull << 18;
+        uint32_t *H = plane(c, s, 0), *Lo = plane(c, s, 1);
+        parallel_for(c->threads, (size_t)((used + span - 1) / span), [&](size_t i) {
+            const uint64_t w0 = i * span, w1 = std::min<uint64_t>(used, w0 + span);
+            std::memcpy(H + w0, pk->hi + w0, (w1 - w0) * sizeof(uint32_t));
+            std::memcpy(Lo + w0, pk->lo + w0, (w1 - w0) * sizeof(uint32_t));
+        });
+        if (n & 31) {
+            const uint32_t keep = (1u << (n & 31)) - 1u;
+            H[used - 1] &= keep;
+            Lo[used - 1] &= keep;
+        }
+        // N words from the runs (and the chunk tail), then the sparse list
+        std::vector<std::pair<uint32_t, uint32_t>> nword;
+        auto add = [&](uint64_t w, uint32_t bits) {
+            if (!nword.empty() && nword.back().first == (uint32_t)w) nword.back().second |= bits;
+            else nword.emplace_back((uint32_t)w, bits);
+        };
+        for (uint32_t i = 0; i < pk->n_runs; i++) {
+            const uint64_t a = pk->run_start[i], b = a + pk->run_len[i];
+            for (uint64_t w = a >> 5; w <= (b - 1) >> 5; w++) {
+                const uint64_t lo = std::max(a, w << 5), hi = std::min(b, (w + 1) << 5);
+                add(w, (uint32_t)(((hi - lo) == 32 ? 0xffffffffull : ((1ull << (hi - lo)) - 1))
+                                  << (lo & 31)));
+            }
+        }
+        if (n & 31) add(n >> 5, ~((1u << (n & 31)) - 1u));
+        s.len = n;
+        s.own_from = 0;
+        s.packed_to = n;
+        s.n_list = merge_sparse(nword, piece_end_words(s.pieces, n), s.list);
+        submit_staging(c);
     });
 }
 
@@ -2024,7 +2275,8 @@ ifa_status ifa_device_footprint(const ifa_ctx *c, uint64_t *bytes)
         b += c->d_hits[i].n * sizeof(uint4) + c->work[i].n * sizeof(WorkItem);
     }
     b += c->d_ctr.n * sizeof(unsigned long long);
-    b += c->d_qarena.n + c->d_mqarena[0].n + c->d_mqarena[1].n;
+    for (int t = 0; t < 2; t++)
+        b += c->d_qarena[t].n + c->d_mqarena[t][0].n + c->d_mqarena[t][1].n;
     b += (c->d_qcount.n + c->d_qdigest.n) * sizeof(unsigned long long);
     b += c->d_seed_info.n * sizeof(SeedInfo) + c->d_seed_tab.n * sizeof(SeedTable);
     for (size_t i = 0; i < kMaxSeedCfg; i++)
@@ -2115,10 +2367,23 @@ ifa_status ifa_reset_stats(ifa_ctx *c)
 // of the query strands of every admitted request, so the work of different
 // requests overlaps in the same kernels. A request admitted at step s sees
 // the chunks s, s+1, ... (mod the chunk count) and completes after one full
-// revolution; its hits are then sorted into reference order. Admission keeps
-// the active query count under a cap (bounding step time) and the expected
-// hits of the active requests under a record budget (device and host memory
-// for hits); a request alone on the server is always admitted.
+// revolution; its hits are then sorted into reference order.
+//
+// Steps are pipelined: step t submits the scan of its chunk and only then
+// waits for the scan of step t - 1 and routes its hits to their requests, so
+// the host's routing and the next table build overlap the device's work. The
+// union query table is rebuilt only when the active set changes; the context
+// alternates between two sets of query tables, so a new table is uploaded
+// while the previous step's scan still reads the old one.
+//
+// Admission keeps the active query count under a cap (bounding step time)
+// and the hits one step can produce under a record budget: each request
+// reserves, per chunk, the binomial expectation of its hits on iid bases
+// plus six standard deviations and a floor of 1,024 records. The budget is
+// given, or (0) a quarter of the device memory free when the server is
+// created, spread over the context's two hit buffers. The hit buffers grow to
+// the admitted reservation. A request alone on the server is always admitted
+// (a chunk whose hits overflow the buffer is re-scanned in halves).
 
 namespace {
 
@@ -2128,9 +2393,17 @@ struct SrvRequest {
     std::vector<QSDesc> qs;           // qid = query index within the request
     std::vector<uint32_t> words;
     uint32_t lmax = 0;
-    uint32_t chunks_left = 0;
-    uint64_t est_hits = 0;
+    uint32_t chunks_left = 0;         // chunk scans still to submit
+    uint32_t routed_left = 0;         // chunk scans whose hits are not routed yet
+    double reserve = 0.0;             // hit records reserved per chunk
     std::vector<ifa_hit> hits;
+};
+
+// The installed union table: its requests in table order and the first
+// table query index of each.
+struct SrvTable {
+    std::vector<SrvRequest *> reqs;
+    std::vector<uint32_t> base;
 };
 
 }  // namespace
@@ -2138,12 +2411,16 @@ struct SrvRequest {
 struct ifa_server {
     ifa_ctx *ctx = nullptr;
     uint32_t max_active_queries = 0;
-    uint64_t hit_budget = 0;
+    uint64_t hit_budget = 0;          // records per step (both hit buffers hold it)
     std::deque<std::unique_ptr<SrvRequest>> pending;
-    std::vector<std::unique_ptr<SrvRequest>> active;
+    std::vector<std::unique_ptr<SrvRequest>> active;     // admitted, chunks left to scan
+    std::vector<std::unique_ptr<SrvRequest>> finishing;  // scanned, hits not all routed
     std::deque<std::unique_ptr<SrvRequest>> done;
     uint32_t active_queries = 0;
-    uint64_t active_est_hits = 0;
+    double active_reserve = 0.0;
+    bool table_dirty = true;          // the active set changed since the table was built
+    std::shared_ptr<SrvTable> table;  // installed union table
+    std::deque<std::shared_ptr<SrvTable>> inflight;   // tables of submitted, unrouted scans
     uint32_t cursor = 0;
     uint64_t next_id = 1;
     uint64_t steps = 0;
@@ -2153,13 +2430,25 @@ struct ifa_server {
 
 namespace {
 
-// Expected hits of a query set against `bases` reference bases for iid
-// uniform bases (each base matches with probability 1/4).
-uint64_t expected_hits(const SrvRequest &r, uint64_t bases)
+// Hit records a request reserves per chunk of `bases` reference bases: the
+// expected hits on iid uniform bases (each base matches with probability
+// 1/4), plus 6 standard deviations and a floor.
+double hit_reserve(const SrvRequest &r, uint64_t bases)
 {
-    double e = 0.0;
-    for (const QSDesc &d : r.qs) e += (double)bases * binom_cdf(d.len, 0.75, d.k);
-    return (uint64_t)(e + 1.0);
+    double e = 0.0, v = 0.0;
+    for (const QSDesc &d : r.qs) {
+        const double p = binom_cdf(d.len, 0.75, d.k);
+        e += (double)bases * p;
+        v += (double)bases * p * (1.0 - p);
+    }
+    return e + 6.0 * std::sqrt(v) + 1024.0;
+}
+
+uint64_t largest_chunk(const ifa_ctx *c)
+{
+    uint64_t m = 0;
+    for (const auto &d : c->resident) m = std::max<uint64_t>(m, d->len);
+    return m;
 }
 
 void server_admit(ifa_server *S)
@@ -2168,79 +2457,126 @@ void server_admit(ifa_server *S)
         SrvRequest &r = *S->pending.front();
         const bool alone = S->active.empty();
         if (!alone && (S->active_queries + r.n_queries > S->max_active_queries ||
-                       S->active_est_hits + r.est_hits > S->hit_budget))
+                       S->active_reserve + r.reserve > (double)S->hit_budget))
             break;
         r.chunks_left = (uint32_t)S->ctx->resident.size();
+        r.routed_left = r.chunks_left;
         S->active_queries += r.n_queries;
-        S->active_est_hits += r.est_hits;
+        S->active_reserve += r.reserve;
         S->active.push_back(std::move(S->pending.front()));
         S->pending.pop_front();
+        S->table_dirty = true;
     }
 }
 
-void server_step(ifa_server *S)
+// Install one query table for every active request: qid = the request's
+// table base + its local index.
+void server_install(ifa_server *S)
 {
     ifa_ctx *c = S->ctx;
-    server_admit(S);
-    if (S->active.empty()) return;
-    const double t0 = now_ms();
-    // one query table for every active request: qid = slot base + local index
+    std::shared_ptr<SrvTable> t = std::make_shared<SrvTable>();
     std::vector<QSDesc> qs;
     std::vector<uint32_t> words;
-    std::vector<uint32_t> owner;      // global qid -> index into active
-    std::vector<uint32_t> base;       // per active request: first global qid
-    uint32_t lmax = 0;
-    for (size_t i = 0; i < S->active.size(); i++) {
-        const SrvRequest &r = *S->active[i];
-        const uint32_t qb = (uint32_t)owner.size();
+    uint32_t lmax = 0, nq = 0;
+    for (auto &rp : S->active) {
+        const SrvRequest &r = *rp;
         const uint32_t wb = (uint32_t)words.size();
-        base.push_back(qb);
+        t->reqs.push_back(rp.get());
+        t->base.push_back(nq);
         for (QSDesc d : r.qs) {
-            d.qid += qb;
+            d.qid += nq;
             d.woff += wb;
             qs.push_back(d);
         }
         words.insert(words.end(), r.words.begin(), r.words.end());
-        owner.insert(owner.end(), r.n_queries, (uint32_t)i);
+        nq += r.n_queries;
         lmax = std::max(lmax, r.lmax);
     }
     c->indexed = false;   // serving runs brute-force passes
-    install_queries(c, std::move(qs), std::move(words), (uint32_t)owner.size(), lmax);
-    DevChunk *ch = c->resident[S->cursor].get();
-    c->st.bases += ch->len - ch->own_from;
-    submit_job(c, ch);
-    retire_all(c);
-    // route the chunk's hits to their requests
+    install_queries(c, std::move(qs), std::move(words), nq, lmax);
+    S->table = t;
+    S->table_dirty = false;
+}
+
+// Wait for the oldest submitted scan and route its hits to their requests;
+// requests whose last scan this was are complete.
+void server_route_oldest(ifa_server *S)
+{
+    ifa_ctx *c = S->ctx;
+    const std::shared_ptr<SrvTable> t = S->inflight.front();
+    S->inflight.pop_front();
+    const uint64_t seq = c->job_seq - 1 - S->inflight.size();   // that scan's job
+    retire(c, c->jobs[seq % 2]);
     for (const ifa_hit &h : c->hits) {
-        const uint32_t i = owner[h.query];
+        const size_t i = (size_t)(std::upper_bound(t->base.begin(), t->base.end(), h.query) -
+                                  t->base.begin()) - 1;
         ifa_hit local = h;
-        local.query = h.query - base[i];
-        S->active[i]->hits.push_back(local);
+        local.query = h.query - t->base[i];
+        t->reqs[i]->hits.push_back(local);
     }
     c->hits.clear();
     c->drain_pos = 0;
     c->hits_sorted = true;
-    S->cursor = (S->cursor + 1) % (uint32_t)c->resident.size();
-    S->steps++;
-    // requests that have seen every chunk are complete
+    for (SrvRequest *r : t->reqs) r->routed_left--;
     std::vector<std::unique_ptr<SrvRequest>> still;
-    for (auto &rp : S->active) {
-        if (--rp->chunks_left == 0) {
+    for (auto &rp : S->finishing) {
+        if (rp->routed_left == 0) {
             std::sort(rp->hits.begin(), rp->hits.end(), [](const ifa_hit &a, const ifa_hit &b) {
                 if (a.contig != b.contig) return a.contig < b.contig;
                 if (a.pos != b.pos) return a.pos < b.pos;
                 if (a.strand != b.strand) return a.strand < b.strand;
                 return a.query < b.query;
             });
-            S->active_queries -= rp->n_queries;
-            S->active_est_hits -= rp->est_hits;
             S->completed++;
             S->done.push_back(std::move(rp));
         } else {
             still.push_back(std::move(rp));
         }
     }
-    S->active.swap(still);
+    S->finishing.swap(still);
+}
+
+void server_step(ifa_server *S)
+{
+    ifa_ctx *c = S->ctx;
+    server_admit(S);
+    if (S->active.empty() && S->inflight.empty()) return;
+    const double t0 = now_ms();
+    if (!S->active.empty()) {
+        if (S->table_dirty) server_install(S);
+        // both hit buffers hold the admitted reservation (they only grow;
+        // neither is in use by an unretired scan of the other buffer)
+        const uint64_t want = (uint64_t)std::min(S->active_reserve, (double)S->hit_budget);
+        const int hb = (int)(c->job_seq % 2);
+        if (c->buf_cap[hb] < want) {
+            c->d_hits[hb].alloc(want, "grow hit buffer");
+            c->buf_cap[hb] = want;
+        }
+        DevChunk *ch = c->resident[S->cursor].get();
+        c->st.bases += ch->len - ch->own_from;
+        submit_job(c, ch);
+        S->inflight.push_back(S->table);
+        S->cursor = (S->cursor + 1) % (uint32_t)c->resident.size();
+        S->steps++;
+        // requests that have had every chunk submitted leave the active set
+        std::vector<std::unique_ptr<SrvRequest>> still;
+        for (auto &rp : S->active) {
+            if (--rp->chunks_left == 0) {
+                S->active_queries -= rp->n_queries;
+                S->active_reserve -= rp->reserve;
+                S->finishing.push_back(std::move(rp));
+                S->table_dirty = true;
+            } else {
+                still.push_back(std::move(rp));
+            }
+        }
+        S->active.swap(still);
+        if (S->active.empty()) S->active_reserve = 0.0;
+    }
+    // route the previous step's scan while this one runs (or, with nothing
+    // new submitted, drain the last one)
+    while (S->inflight.size() > 1 || (!S->inflight.empty() && S->active.empty()))
+        server_route_oldest(S);
     S->step_ms += now_ms() - t0;
 }
 
@@ -2253,7 +2589,7 @@ void ifa_server_config_default(ifa_server_config *cfg)
     if (!cfg) return;
     cfg->max_active_queries = 4096;
     cfg->reserved = 0;
-    cfg->hit_budget = 1ull << 26;
+    cfg->hit_budget = 0;
 }
 
 ifa_status ifa_server_create(ifa_ctx *c, const ifa_server_config *cfg_in, ifa_server **out)
@@ -2267,12 +2603,20 @@ ifa_status ifa_server_create(ifa_ctx *c, const ifa_server_config *cfg_in, ifa_se
         if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
         ifa_server_config cfg;
         if (cfg_in) cfg = *cfg_in; else ifa_server_config_default(&cfg);
-        if (cfg.max_active_queries == 0 || cfg.hit_budget == 0 || cfg.reserved != 0)
+        if (cfg.max_active_queries == 0 || cfg.reserved != 0)
             fail(IFA_E_INVALID, "bad server config");
+        uint64_t budget = cfg.hit_budget;
+        if (budget == 0) {
+            // a quarter of the free device memory, over the two hit buffers
+            use_device(c);
+            size_t free_b = 0, total_b = 0;
+            hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+            budget = std::max<uint64_t>(free_b / 4 / (2 * sizeof(ifa_hit)), 1u << 16);
+        }
         ifa_server *S = new ifa_server();
         S->ctx = c;
         S->max_active_queries = cfg.max_active_queries;
-        S->hit_budget = cfg.hit_budget;
+        S->hit_budget = budget;
         *out = S;
     });
 }
@@ -2281,8 +2625,17 @@ void ifa_server_destroy(ifa_server *S)
 {
     if (!S) return;
     if (S->ctx) {
-        (void)hipSetDevice(S->ctx->cfg.device);
-        if (S->ctx->comp_s) (void)hipStreamSynchronize(S->ctx->comp_s);
+        ifa_ctx *c = S->ctx;
+        (void)hipSetDevice(c->cfg.device);
+        // scans still in flight are retired and their hits dropped, so the
+        // context is left with nothing pending
+        (void)guarded(c, [&]() {
+            retire_all(c);
+            c->hits.clear();
+            c->drain_pos = 0;
+            c->hits_sorted = true;
+        });
+        if (c->comp_s) (void)hipStreamSynchronize(c->comp_s);
     }
     delete S;
 }
@@ -2301,7 +2654,7 @@ ifa_status ifa_server_submit(ifa_server *S, uint32_t n, const uint8_t *const *se
         r->n_queries = n;
         pack_query_strands(c->cfg.strands, n, seq, len, max_subs, max_n, 0, r->qs, r->words,
                            r->lmax, c->threads);
-        r->est_hits = expected_hits(*r, c->resident_bases);
+        r->reserve = hit_reserve(*r, largest_chunk(c));
         if (request_id) *request_id = r->id;
         S->pending.push_back(std::move(r));
     });
@@ -2361,6 +2714,10 @@ ifa_status ifa_server_info(const ifa_server *S, ifa_server_stats *out)
     out->step_ms = S->step_ms;
     out->cursor = S->cursor;
     out->chunks = (uint32_t)S->ctx->resident.size();
+    out->hit_budget = S->hit_budget;
+    out->hits_reserved = (uint64_t)S->active_reserve;
+    out->in_flight = (uint32_t)S->inflight.size();
+    out->finishing = (uint32_t)S->finishing.size();
     return IFA_OK;
 }
 

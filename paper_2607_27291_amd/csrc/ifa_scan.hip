@@ -36,6 +36,7 @@
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "ifa_dev.h"
 
@@ -603,6 +604,21 @@ __device__ __forceinline__ ifa_v8i onehot_operand(uint32_t hb, uint32_t lb)
     return r;
 }
 
+// The 8 XCDs of the chip take workgroups round-robin by linear workgroup id,
+// and each has its own L2. Filter waves read one 128-byte line past their own
+// (the first line of the next wave's words), so neighbouring waves on
+// different XCDs fetch that line twice from HBM. With gridDim.x a multiple of
+// 8 (the host rounds it), the x index is permuted so that each XCD holds a
+// contiguous run of x indices: xcd * (gridDim.x / 8) + the block's rank
+// within its XCD; the workgroups of one XCD then walk adjacent waves.
+__device__ __forceinline__ uint32_t xcd_local_x()
+{
+    const uint32_t g = gridDim.x;
+    if (g % 8u != 0u) return blockIdx.x;
+    const uint32_t lin = blockIdx.x + blockIdx.y * g;   // the dispatcher's order
+    return (lin % 8u) * (g / 8u) + blockIdx.x / 8u;
+}
+
 __device__ __forceinline__ ifa_v16f mfma_fp4(const ifa_v8i &a, const ifa_v8i &b, const ifa_v16f &c)
 {
     // cbsz = blgp = 4: both operands e2m1; E8M0 scales 127 = 1.0
@@ -635,7 +651,7 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma_kernel(ScanArgs a)
     const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
     const uint32_t stride = gridDim.x * (WG / 64u);
     const ifa_v16f zero = {};
-    for (uint32_t wave = blockIdx.x * (WG / 64u) + (threadIdx.x >> 6); wave < n_waves;
+    for (uint32_t wave = xcd_local_x() * (WG / 64u) + (threadIdx.x >> 6); wave < n_waves;
          wave += stride) {
         // lane l of a filter wave stands for plane word w0 + l / 2 (16
         // windows); the N test and the work items are those of the VALU filter
@@ -790,7 +806,7 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
         }
         if (l <= ((w0 + 31u + (uint32_t)NW) >> 5) - (w0 >> 5)) pn = a.nflag[(w0 >> 5) + l];
     };
-    uint32_t wave = blockIdx.x * (WG / 64u) + (threadIdx.x >> 6);
+    uint32_t wave = xcd_local_x() * (WG / 64u) + (threadIdx.x >> 6);
     uint32_t nh = 0u, nl = 0u, nn = 0u;
     if (wave < n_waves) fetch(wave, nh, nl, nn);
     for (; wave < n_waves; wave += stride) {
@@ -1511,6 +1527,18 @@ void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *w
     *enc = d.enc;
 }
 
+// Launch of a scan kernel, or (rec != nullptr) its record in a launch plan.
+static hipError_t go(void (*f)(ScanArgs), dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
+                     const ScanArgs &a, std::vector<ScanLaunch> *rec)
+{
+    if (rec) {
+        rec->push_back(ScanLaunch{reinterpret_cast<const void *>(f), grid, block, lds, a});
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL(f, grid, block, lds, s, a);
+    return hipGetLastError();
+}
+
 static const VariantDesc &pick(const ScanArgs &a)
 {
     return kVariantTable[a.variant < variant_count() ? a.variant : 0];
@@ -1525,7 +1553,7 @@ static uint64_t filter_lanes(const ScanArgs &a, const VariantDesc &v)
 
 // Sparse part, step 1: the filter kernel fills the work list (the caller
 // clears *work_count and *skip_count first).
-hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
+hipError_t launch_filter(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec)
 {
     if (a.w_end <= a.w_begin || a.n_sparse == 0) return hipSuccess;
     const VariantDesc &v = pick(a);
@@ -1539,7 +1567,10 @@ hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
         const uint32_t wpg = v.wg / 64u;
         const uint32_t batches = (a.n_sparse + 31u) / 32u;
         const uint32_t want = (v.waves + wpg * batches - 1) / (wpg * batches);
-        const uint32_t gx = max(1u, min((waves + wpg - 1) / wpg, want));
+        uint32_t gx = max(1u, min((waves + wpg - 1) / wpg, want));
+        // a multiple of 8 lets the kernel give each XCD a contiguous run of
+        // waves (xcd_local_x)
+        if (gx >= 8u) gx &= ~7u;
         const uint32_t split =
             v.enc == 2 && a.mq3_words >= 2 ? min(a.mq3_two_batches, batches) : 0u;
         for (int part_nw = 2; part_nw >= 1; part_nw--) {
@@ -1552,60 +1583,55 @@ hipError_t launch_filter(const ScanArgs &a, hipStream_t s)
             for (uint32_t b0 = lo; b0 < hi; b0 += 65535u) {
                 ScanArgs part = a;
                 part.batch0 = b0;
-                hipLaunchKernelGGL(two ? v.filter2 : v.filter, dim3(gx, min(65535u, hi - b0)),
-                                   dim3(v.wg), lds, s, part);
-                const hipError_t e = hipGetLastError();
+                const hipError_t e = go(two ? v.filter2 : v.filter,
+                                        dim3(gx, min(65535u, hi - b0)), dim3(v.wg), lds, s, part, rec);
                 if (e != hipSuccess) return e;
             }
         }
         return hipSuccess;
     }
     const uint64_t lanes = filter_lanes(a, v);
-    hipLaunchKernelGGL(v.filter, dim3((uint32_t)((lanes + v.wg - 1) / v.wg)), dim3(v.wg), 0, s, a);
-    return hipGetLastError();
+    return go(v.filter, dim3((uint32_t)((lanes + v.wg - 1) / v.wg)), dim3(v.wg), 0, s, a, rec);
 }
 
 // Sparse part, step 2: resolve the work list (a fixed grid, grid-stride).
-hipError_t launch_resolve(const ScanArgs &a, hipStream_t s)
+hipError_t launch_resolve(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec)
 {
     if (a.w_end <= a.w_begin || a.n_sparse == 0) return hipSuccess;
-    hipLaunchKernelGGL(pick(a).resolve, dim3(1024), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return go(pick(a).resolve, dim3(1024), dim3(256), 0, s, a, rec);
 }
 
 // Dense part: query strands [n_sparse, n_qs) on every lane (plain lanes in
 // the dense kernel, the others in the cold kernel).
-hipError_t launch_dense(const ScanArgs &a, hipStream_t s)
+hipError_t launch_dense(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec)
 {
     if (a.w_end <= a.w_begin || a.n_qs <= a.n_sparse) return hipSuccess;
     const VariantDesc &v = pick(a);
     const uint64_t lanes = filter_lanes(a, v);
     const dim3 grid((uint32_t)((lanes + 255) / 256));
-    hipLaunchKernelGGL(v.dense, grid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(v.dense_cold, grid, dim3(256), 0, s, a);
-    return hipGetLastError();
+    const hipError_t e = go(v.dense, grid, dim3(256), 0, s, a, rec);
+    if (e != hipSuccess) return e;
+    return go(v.dense_cold, grid, dim3(256), 0, s, a, rec);
 }
 
 // Overhanging windows of the word range: one wave per (block of pieces,
 // query strand) task, grid-stride.
-hipError_t launch_edge(const ScanArgs &a, hipStream_t s)
+hipError_t launch_edge(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec)
 {
     if (a.w_end <= a.w_begin || a.n_pieces == 0 || a.n_qs == 0 || a.edge_pmin == 0)
         return hipSuccess;
     const uint64_t tasks = (uint64_t)((a.n_pieces + a.edge_pmin - 1) / a.edge_pmin) * a.n_qs;
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((tasks + 3) / 4, 4096);
-    hipLaunchKernelGGL(scan_edge_kernel, dim3(blocks), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return go(scan_edge_kernel, dim3(blocks), dim3(256), 0, s, a, rec);
 }
 
 // Indexed mode: seed starts of the word range, grid-stride.
-hipError_t launch_seed(const ScanArgs &a, hipStream_t s)
+hipError_t launch_seed(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch> *rec)
 {
     if (a.w_end <= a.w_begin || a.seed_ncfg == 0) return hipSuccess;
     const uint32_t words = a.w_end - a.w_begin;
     const uint32_t blocks = std::min<uint32_t>((words + 255) / 256, 4096);
-    hipLaunchKernelGGL(scan_seed_kernel, dim3(blocks), dim3(256), 0, s, a);
-    return hipGetLastError();
+    return go(scan_seed_kernel, dim3(blocks), dim3(256), 0, s, a, rec);
 }
 
 // Rebuild a chunk's nm and em planes, padding and N-block flags from the

@@ -29,7 +29,7 @@ def nearest_rank(values, q):
     return v[k - 1]
 
 
-def replay(scanner, trace, *, mode="batch", max_active_queries=4096, hit_budget=1 << 26,
+def replay(scanner, trace, *, mode="batch", max_active_queries=4096, hit_budget=0,
            keep_hits=False, log=None):
     if mode not in ("batch", "serial"):
         raise ValueError("mode must be 'batch' or 'serial'")

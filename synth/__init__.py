@@ -39,6 +39,8 @@ def lib():
         L.synth_fill_many.argtypes = [u64, ctypes.c_int, dbl, u32, u32, u64, u64, vp, vp, vp, vp,
                                       ctypes.c_int]
         L.synth_fill_many.restype = ctypes.c_int
+        L.synth_fill_packed.argtypes = [u64, u64, u64, vp, vp, vp, vp, ctypes.c_int]
+        L.synth_fill_packed.restype = ctypes.c_int
         L.synth_queries.argtypes = [u64, u64, u64, u32, u32, vp, u64, vp]
         L.synth_set_simd.argtypes = [ctypes.c_int]
         L.synth_set_simd.restype = None
@@ -169,6 +171,27 @@ def fill_contigs(spec: RefSpec, first_contig: int, lens: np.ndarray, gcs: np.nda
                                out.ctypes.data, offs.ctypes.data, threads or default_threads())
     if rc != 0:
         raise MemoryError("synth_fill_many failed")
+
+
+def fill_packed(spec: RefSpec, first_contig: int, lens: np.ndarray, gcs: np.ndarray,
+                hi: np.ndarray, lo: np.ndarray, threads: int | None = None) -> int:
+    """The bases fill_contigs writes, as the two 2-bit code planes of a packed
+    chunk (contigs back to back from base 0; A=00 C=01 G=11 T=10 as hi, lo
+    bits); references without N only. hi / lo need ceil(total / 32) uint32
+    words each. Returns the total bases."""
+    assert spec.n_mode == N_NONE, "packed output covers references without N"
+    lens = np.ascontiguousarray(lens, dtype=np.uint64)
+    gcs = np.ascontiguousarray(gcs, dtype=np.float64)
+    total = int(lens.sum())
+    words = (total + 31) // 32
+    assert hi.dtype == np.uint32 and lo.dtype == np.uint32
+    assert hi.size >= words and lo.size >= words and hi.flags.c_contiguous and lo.flags.c_contiguous
+    rc = lib().synth_fill_packed(spec.seed, first_contig, len(lens), lens.ctypes.data,
+                                 gcs.ctypes.data, hi.ctypes.data, lo.ctypes.data,
+                                 threads or default_threads())
+    if rc != 0:
+        raise MemoryError("synth_fill_packed failed")
+    return total
 
 
 def gen_reference(spec: RefSpec, threads: int | None = None) -> Reference:

@@ -5,7 +5,9 @@
  * bases, N positions and query sequences. It holds none of the alignment
  * method's arithmetic (no window comparison, no mismatch counting, no
  * reverse complement of queries), and both the product path and the oracle
- * consume its output as plain ASCII bytes.
+ * consume its output as plain ASCII bytes. For a producer that hands the
+ * scan packed input, the same bases are also written as the two 2-bit code
+ * planes of that input format (synth_fill_packed).
  *
  * Randomness: SplitMix64 (Steele, Lea & Flood 2014), used two ways:
  *   - key(seed, stream, a, b) mixes four integers into a 64-bit state with the
@@ -22,6 +24,7 @@
 #include <string.h>
 #include <math.h>
 #include <pthread.h>
+#include <stdlib.h>
 #if defined(__x86_64__)
 #include <immintrin.h>
 #endif
@@ -342,8 +345,6 @@ static void *fill_worker(void *arg)
     return NULL;
 }
 
-#include <stdlib.h>
-
 int synth_fill_many(uint64_t seed, int n_mode, double n_param, uint32_t run_min, uint32_t run_max,
                     uint64_t first_contig, uint64_t n, const uint64_t *lens, const double *gcs,
                     uint8_t *out, const uint64_t *offs, int threads)
@@ -382,6 +383,171 @@ int synth_fill_many(uint64_t seed, int n_mode, double n_param, uint32_t run_min,
     for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
     pthread_mutex_destroy(&J.mu);
     free(is);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* 2-bit planes: the same bases as fill_range, written as two bit planes  */
+/* (for a producer that hands the scan packed data instead of bytes).      */
+/* Base x of a chunk is bit x & 31 of word x >> 5; A = (hi 0, lo 0),       */
+/* C = (0, 1), G = (1, 1), T = (1, 0). A random byte u gives G/C when its  */
+/* low 7 bits are below the GC threshold, and G or T when its top bit is   */
+/* set, so hi = the top bit and lo = (u & 0x7F) < thr.                     */
+/* ------------------------------------------------------------------ */
+
+/* OR the low cnt (<= 32) bits of v into bits [p, p + cnt) of a plane */
+static inline void put_bits(uint32_t *pl, uint64_t p, uint32_t v, uint32_t cnt)
+{
+    if (cnt < 32) v &= (1u << cnt) - 1u;
+    const uint64_t w = p >> 5;
+    const uint32_t sh = (uint32_t)(p & 31);
+    pl[w] |= v << sh;
+    if (sh && cnt > 32 - sh) pl[w + 1] |= v >> (32 - sh);
+}
+
+#if defined(__x86_64__)
+/* 4 draws from state s (not advanced): the hi / lo bits of their 32 bases */
+__attribute__((target("avx2"))) static inline void draws4_bits(uint64_t s, uint32_t thr,
+                                                               uint32_t *hb, uint32_t *lb)
+{
+    const __m256i g = _mm256_set_epi64x((long long)(4 * SYN_GAMMA), (long long)(3 * SYN_GAMMA),
+                                        (long long)(2 * SYN_GAMMA), (long long)SYN_GAMMA);
+    __m256i z = _mm256_add_epi64(_mm256_set1_epi64x((long long)s), g);
+    z = syn_mul64(_mm256_xor_si256(z, _mm256_srli_epi64(z, 30)), 0xBF58476D1CE4E5B9ULL);
+    z = syn_mul64(_mm256_xor_si256(z, _mm256_srli_epi64(z, 27)), 0x94D049BB133111EBULL);
+    z = _mm256_xor_si256(z, _mm256_srli_epi64(z, 31));
+    const __m256i low7 = _mm256_and_si256(z, _mm256_set1_epi8(0x7F));
+    const __m256i at = _mm256_cmpeq_epi8(_mm256_max_epu8(low7, _mm256_set1_epi8((char)thr)), low7);
+    *hb = (uint32_t)_mm256_movemask_epi8(z);
+    *lb = ~(uint32_t)_mm256_movemask_epi8(at);
+}
+#endif
+
+/* bases [x0, x0 + n) of contig c (length clen, GC gc), whose base 0 is base
+ * cstart of the chunk, into the chunk planes (bits ORed in; n_mode 0 only) */
+static void pack_range(const syn_spec *sp, uint64_t c, uint64_t clen, double gc, uint64_t cstart,
+                       uint64_t x0, uint64_t n, uint32_t *hi, uint32_t *lo)
+{
+    if (x0 >= clen) return;
+    if (x0 + n > clen) n = clen - x0;
+    const uint32_t thr = (uint32_t)(gc * 128.0 + 0.5);
+    uint64_t x = x0, end = x0 + n;
+    while (x < end) {
+        const uint64_t blk = x / SYN_BLOCK;
+        const uint64_t bstart = blk * SYN_BLOCK;
+        const uint64_t bend = bstart + SYN_BLOCK < end ? bstart + SYN_BLOCK : end;
+        syn_rng r = { syn_key(sp->seed, 3, c, blk) };
+        const uint64_t skip = (x - bstart) / 8;
+        r.s += skip * SYN_GAMMA;
+        uint64_t pos = bstart + skip * 8;
+        while (pos < bend) {
+#if defined(__x86_64__)
+            if (syn_simd && pos >= x && pos + 32 <= bend && __builtin_cpu_supports("avx2")) {
+                uint32_t hb, lb;
+                draws4_bits(r.s, thr, &hb, &lb);
+                r.s += 4 * SYN_GAMMA;
+                put_bits(hi, cstart + pos, hb, 32);
+                put_bits(lo, cstart + pos, lb, 32);
+                pos += 32;
+                continue;
+            }
+#endif
+            const uint64_t v = syn_next(&r);
+            uint32_t hb = 0, lb = 0;
+            for (uint32_t j = 0; j < 8; j++) {
+                const uint32_t u = (uint32_t)(v >> (8 * j)) & 0xFFu;
+                hb |= (u >> 7) << j;
+                lb |= ((u & 0x7Fu) < thr ? 1u : 0u) << j;
+            }
+            const uint64_t a = pos > x ? pos : x, b = pos + 8 < bend ? pos + 8 : bend;
+            put_bits(hi, cstart + a, hb >> (a - pos), (uint32_t)(b - a));
+            put_bits(lo, cstart + a, lb >> (a - pos), (uint32_t)(b - a));
+            pos += 8;
+        }
+        x = bend;
+    }
+}
+
+typedef struct {
+    const syn_spec *sp;
+    uint64_t first_contig, n;
+    const uint64_t *lens, *starts;   /* starts: chunk offset of each contig (prefix sums) */
+    const double *gcs;
+    uint32_t *hi, *lo;
+    uint64_t words, item_words, items;
+    volatile uint64_t next;
+    pthread_mutex_t mu;
+} pack_job;
+
+static void *pack_worker(void *arg)
+{
+    pack_job *J = (pack_job *)arg;
+    for (;;) {
+        pthread_mutex_lock(&J->mu);
+        const uint64_t it = J->next++;
+        pthread_mutex_unlock(&J->mu);
+        if (it >= J->items) break;
+        const uint64_t w0 = it * J->item_words;
+        const uint64_t w1 = w0 + J->item_words < J->words ? w0 + J->item_words : J->words;
+        memset(J->hi + w0, 0, (w1 - w0) * sizeof(uint32_t));
+        memset(J->lo + w0, 0, (w1 - w0) * sizeof(uint32_t));
+        const uint64_t b0 = 32 * w0, b1 = 32 * w1;
+        /* first contig ending after b0 */
+        uint64_t lo_i = 0, hi_i = J->n;
+        while (lo_i < hi_i) {
+            const uint64_t mid = (lo_i + hi_i) / 2;
+            if (J->starts[mid] + J->lens[mid] <= b0) lo_i = mid + 1; else hi_i = mid;
+        }
+        for (uint64_t i = lo_i; i < J->n && J->starts[i] < b1; i++) {
+            const uint64_t cs = J->starts[i], ce = cs + J->lens[i];
+            const uint64_t a = cs > b0 ? cs : b0, b = ce < b1 ? ce : b1;
+            if (a < b)
+                pack_range(J->sp, J->first_contig + i, J->lens[i], J->gcs[i], cs, a - cs, b - a,
+                           J->hi, J->lo);
+        }
+    }
+    return NULL;
+}
+
+/* hi / lo planes (ceil(total / 32) words each, written whole; bits past the
+ * last base 0) of contigs first_contig .. first_contig + n - 1 packed back
+ * to back from base 0. Only references without N (n_mode 0). */
+int synth_fill_packed(uint64_t seed, uint64_t first_contig, uint64_t n, const uint64_t *lens,
+                      const double *gcs, uint32_t *hi, uint32_t *lo, int threads)
+{
+    syn_spec sp = { seed, 0, 0.0, 0, 0 };
+    uint64_t *starts = (uint64_t *)malloc((n + 1) * sizeof(uint64_t));
+    if (!starts) return -1;
+    uint64_t acc = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        starts[i] = acc;
+        acc += lens[i];
+    }
+    starts[n] = acc;
+    pack_job J;
+    memset(&J, 0, sizeof J);
+    J.sp = &sp;
+    J.first_contig = first_contig;
+    J.n = n;
+    J.lens = lens;
+    J.starts = starts;
+    J.gcs = gcs;
+    J.hi = hi;
+    J.lo = lo;
+    J.words = (acc + 31) / 32;
+    J.item_words = 1ULL << 16;
+    J.items = (J.words + J.item_words - 1) / J.item_words;
+    pthread_mutex_init(&J.mu, NULL);
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    pthread_t th[256];
+    int started = 0;
+    for (int t = 1; t < threads; t++)
+        if (pthread_create(&th[started], NULL, pack_worker, &J) == 0) started++;
+    pack_worker(&J);
+    for (int t = 0; t < started; t++) pthread_join(th[t], NULL);
+    pthread_mutex_destroy(&J.mu);
+    free(starts);
     return 0;
 }
 

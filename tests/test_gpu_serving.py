@@ -42,11 +42,11 @@ def setup():
     s.close()
 
 
-def serve_all(ifa, s, batches, max_active_queries=4096):
+def serve_all(ifa, s, batches, max_active_queries=4096, hit_budget=0):
     """batches: list of lists of requests submitted together, one batch per
     step (later batches join a server already mid-revolution)."""
     out = {}
-    with ifa.Server(s, max_active_queries=max_active_queries) as srv:
+    with ifa.Server(s, max_active_queries=max_active_queries, hit_budget=hit_budget) as srv:
         ids = {}
         pending = list(batches)
         while pending or len(out) < sum(len(b) for b in batches):
@@ -97,3 +97,33 @@ def test_server_info_and_admission_cap(setup):
             srv.step()
             done += len(srv.completed())
         assert srv.info()["completed"] == 3
+
+
+def test_small_hit_budget_defers_admission_with_identical_results(setup):
+    """A hit budget below two requests' reservations (each reserves at least
+    1,024 records per chunk) admits one request at a time: the others wait,
+    and every request's hits equal its hits when served alone with the budget
+    sized from free device memory."""
+    ifa, ref, reqs, s = setup
+    items = list(enumerate(reqs[:5]))
+    say("serving: default budget (from free device memory)")
+    free = {}
+    for i, r in items:
+        free.update(serve_all(ifa, s, [[(i, r)]]))
+    say("serving: budget 2,000 records")
+    with ifa.Server(s, hit_budget=2000) as srv:
+        ids = {srv.submit(qs, ks): i for i, (qs, ks) in items}
+        srv.step()
+        info = srv.info()
+        assert info["hit_budget"] == 2000
+        assert info["active"] == 1 and info["pending"] == len(items) - 1
+        out = {}
+        while len(out) < len(items):
+            srv.step()
+            for rid, h in srv.completed():
+                out[ids[rid]] = h
+            assert srv.info()["active"] <= 1
+    for i, _ in items:
+        assert np.array_equal(out[i], free[i]), i
+    with ifa.Server(s) as srv:
+        assert srv.info()["hit_budget"] > 1 << 20     # sized from free device memory

@@ -16,6 +16,9 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from workload_fixtures import check_fingerprint, load_golden, records_digest  # noqa: E402
+
 
 def say(*a):
     print(*a, flush=True)

@@ -95,3 +95,32 @@ def test_vector_and_scalar_generators_agree(synth_mod):
     for g, w in zip(got, want):
         assert np.array_equal(g, w)
     assert np.array_equal(ref_v.buf, ref_s.buf)
+
+
+def test_packed_planes_hold_the_same_bases(synth_mod):
+    """fill_packed writes the bases fill_contigs writes, as the 2-bit code
+    planes of a packed chunk (hi = bit 2, lo = bit 1 of the ASCII letter),
+    with and without the AVX2 path, for contigs at unaligned offsets."""
+    import numpy as np
+    spec = synth_mod.c4_spec(total=30_000_000)
+    lens = np.array([5, 31, 32, 33, 4095, 4096, 4097, 100_003, 1_000_000, 77], dtype=np.uint64)
+    gcs = synth_mod.contig_gc(spec, 0, len(lens))
+    offs = np.zeros(len(lens), dtype=np.uint64)
+    offs[1:] = np.cumsum(lens)[:-1]
+    total = int(lens.sum())
+    buf = np.empty(total, dtype=np.uint8)
+    synth_mod.fill_contigs(spec, 3, lens, gcs, buf, offs)
+    words = (total + 31) // 32
+    bits = np.zeros(words * 32, dtype=np.uint8)
+    want = []
+    for b in (2, 1):
+        bits[:total] = (buf >> b) & 1
+        want.append(np.packbits(bits.reshape(-1, 8), axis=1, bitorder="little")
+                    .reshape(-1).view(np.uint32))
+    for simd in (True, False):
+        synth_mod.set_simd(simd)
+        hi = np.full(words, 0xDEADBEEF, dtype=np.uint32)
+        lo = np.full(words, 0xDEADBEEF, dtype=np.uint32)
+        assert synth_mod.fill_packed(spec, 3, lens, gcs, hi, lo, threads=3) == total
+        assert np.array_equal(hi, want[0]) and np.array_equal(lo, want[1]), simd
+    synth_mod.set_simd(True)
