@@ -279,6 +279,29 @@ ifa_status ifa_ref_load(ifa_ctx *ctx, uint32_t n_contigs, const uint8_t *const *
  * for ifa_scan_chunk. Errors: IFA_E_STATE (no queries or no resident chunk). */
 ifa_status ifa_scan_resident(ifa_ctx *ctx);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the scan of
+ * ifa_scan_resident with nothing allocated. The pass counters and the filter
+ * work list live in a fixed static device array of the library (16 MiB + 256
+ * bytes per device, held until the process ends) instead of context memory,
+ * and the hit records go straight to the caller's device buffer d_hits of cap
+ * records (records sink; in no particular order, each window once, the same
+ * set ifa_collect_hits would hand out after ifa_scan_resident). *n_hits gets
+ * the number of hits found. Synchronous: returns when the scan is done; no
+ * hits are left pending in the context. With the count+digest sink the hits
+ * go to the per-query counters as usual (read them with ifa_query_stats);
+ * d_hits may then be NULL and *n_hits is 0.
+ * The static array is shared by every context on the device and keeps the
+ * last call's contents (the call clears what it needs first): calls that
+ * overlap in time on one device race and must not be made.
+ * Errors: IFA_E_NOMEM when more than cap records were found (*n_hits gets the
+ * count needed; d_hits then holds cap of them); IFA_E_INVALID (NULL n_hits or
+ * d_hits, or more than 8 * 2^20 filtered query strands, which the static work
+ * list cannot hold); IFA_E_STATE (no queries, no resident reference, scans or
+ * hits pending, or the variant was changed after the queries were loaded so
+ * its matrix-filter operands would have to be built). */
+ifa_status ifa_scan_resident_into(ifa_ctx *ctx, ifa_hit *d_hits, uint64_t cap, uint64_t *n_hits);
+
 /* Free the resident reference. Errors: IFA_E_STATE while scans are pending. */
 ifa_status ifa_ref_release(ifa_ctx *ctx);
 

@@ -137,6 +137,8 @@ def lib():
         L.ifa_ref_load.restype = st
         L.ifa_scan_resident.argtypes = [vp]
         L.ifa_scan_resident.restype = st
+        L.ifa_scan_resident_into.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
+        L.ifa_scan_resident_into.restype = st
         L.ifa_ref_release.argtypes = [vp]
         L.ifa_ref_release.restype = st
         L.ifa_ref_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u32)]
@@ -349,6 +351,19 @@ def ifa_ref_load(ctx, contigs) -> int:
 
 def ifa_scan_resident(ctx):
     _check(ctx, lib().ifa_scan_resident(ctx))
+
+
+def ifa_scan_resident_into(ctx, d_hits: int, cap: int) -> int:
+    """Allocation-free resident scan: records go to the device buffer at
+    address d_hits (cap records). Returns the hit count; raises IfaError
+    (status IFA_E_NOMEM, .needed = the count) when it exceeds cap."""
+    n = ctypes.c_uint64()
+    status = lib().ifa_scan_resident_into(ctx, ctypes.c_void_p(d_hits), cap, ctypes.byref(n))
+    if status != IFA_OK:
+        err = IfaError(status, ifa_last_error(ctx))
+        err.needed = n.value
+        raise err
+    return n.value
 
 
 def ifa_ref_release(ctx):

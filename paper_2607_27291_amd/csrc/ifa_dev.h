@@ -21,6 +21,12 @@ constexpr uint32_t kMaxLen = 256;          // layout bound: queries are at most 
 constexpr uint32_t kCarry = kMaxLen - 1;   // bases repeated at a split
 constexpr uint32_t kPadWords = 16;         // > (31 + kMaxLen) / 32 + 1
 constexpr uint32_t kMaxQWords = kMaxLen / 32;
+// Static scratch of the allocation-free entry point: kScratchCounterBytes of
+// pass counters (hit count u64, work count u32, skipped waves u32), then
+// kScratchWorkItems work-list items.
+constexpr uint32_t kScratchCounterBytes = 256;
+constexpr uint32_t kScratchWorkItems = 1u << 20;
+constexpr uint64_t kScratchBytes = kScratchCounterBytes + 16ull * kScratchWorkItems;
 // count+digest accumulators are striped: query q adds into slot
 // q * kStripes + (workgroup % kStripes); the host sums the stripes
 constexpr uint32_t kStripes = 64;

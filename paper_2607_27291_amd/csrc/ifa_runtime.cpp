@@ -41,6 +41,7 @@ hipError_t launch_expand(uint32_t *planes, uint64_t stride, uint8_t *nflag, uint
 hipError_t launch_clear_u32(unsigned int *p, uint32_t n, hipStream_t s);
 hipError_t launch_seed_bitmap(const uint2 *ent, uint32_t n, uint32_t *bm, uint32_t words,
                               uint32_t key_bits, hipStream_t s);
+void *scratch_address(int device, hipError_t *err);
 uint32_t variant_count();
 uint32_t variant_default();
 void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *wg, uint32_t *enc);
@@ -326,6 +327,9 @@ struct ifa_ctx {
     // resident reference
     std::vector<std::unique_ptr<DevChunk>> resident;
     uint64_t resident_bases = 0;
+
+    // device address of the static scratch array (allocation-free entry point)
+    uint8_t *scratch = nullptr;
 
     // stats
     ifa_stats st{};
@@ -1693,6 +1697,46 @@ void cache_store(const char *path, const std::string &key, uint32_t v, double ms
 // C ABI
 // ===========================================================================
 
+namespace {
+
+// A pass of the allocation-free scan over words [w0, w1) of chunk ch: the
+// work list and pass counters live in the static scratch array, records go to
+// d_hits (cap records; the hit count, cleared by the caller, runs on past
+// cap). The dense part runs once (dense = true); the sparse part runs again on
+// halves of the range while the static work list overflows (its resolve
+// kernel then does nothing).
+void static_pass(ifa_ctx *c, const DevChunk &ch, uint32_t w0, uint32_t w1, bool dense,
+                 ifa_hit *d_hits, uint64_t cap)
+{
+    unsigned long long *ctr = reinterpret_cast<unsigned long long *>(c->scratch);
+    ScanArgs a = chunk_args(c, ch);
+    a.w_begin = w0;
+    a.w_end = w1;
+    a.work = reinterpret_cast<WorkItem *>(c->scratch + kScratchCounterBytes);
+    a.work_count = reinterpret_cast<unsigned int *>(ctr + 1);
+    a.skip_count = a.work_count + 1;
+    a.work_cap = kScratchWorkItems;
+    a.hits = reinterpret_cast<uint4 *>(d_hits);
+    a.hit_count = ctr;
+    a.hit_cap = cap;
+    PassEvents none;
+    enqueue_pass(c, a, false, dense, none);
+    if (c->n_sparse == 0 || c->indexed) return;
+    hip_check(hipMemcpyAsync(c->h_ctr.p, ctr, 2 * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, c->comp_s),
+              "copy pass counters");
+    hip_check(hipStreamSynchronize(c->comp_s), "sync");
+    const uint32_t items = reinterpret_cast<const unsigned int *>(c->h_ctr.p + 1)[0];
+    if (items <= kScratchWorkItems) return;
+    // one filter wave's items always fit (checked by the caller)
+    if (w1 - w0 <= 32u) fail(IFA_E_DEVICE, "static work list overflow");
+    const uint32_t mid = w0 + (w1 - w0) / 2;
+    static_pass(c, ch, w0, mid, false, d_hits, cap);
+    static_pass(c, ch, mid, w1, false, d_hits, cap);
+}
+
+}  // namespace
+
 extern "C" {
 
 void ifa_config_default(ifa_config *cfg)
@@ -1767,6 +1811,9 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
             c->work[i].alloc(wcap, "work list");
             c->work_cap[i] = wcap;
         }
+        hipError_t se = hipSuccess;
+        c->scratch = static_cast<uint8_t *>(scratch_address(cfg.device, &se));
+        hip_check(se, "static scratch address");
         c->d_ctr.alloc(4, "pass counters");
         c->h_ctr.alloc(4, "pinned pass counters");
         hip_check(hipMemset(c->d_ctr.p, 0, 4 * sizeof(unsigned long long)), "memset");
@@ -2068,6 +2115,47 @@ ifa_status ifa_scan_resident(ifa_ctx *c)
             c->st.bases += d->len - d->own_from;
             submit_job(c, d.get());
         }
+    });
+}
+
+ifa_status ifa_scan_resident_into(ifa_ctx *c, ifa_hit *d_hits, uint64_t cap, uint64_t *n_hits)
+{
+    if (!c || !n_hits) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        *n_hits = 0;
+        if (!c->have_queries) fail(IFA_E_STATE, "no queries loaded");
+        if (c->resident.empty()) fail(IFA_E_STATE, "no resident reference");
+        if (!nothing_pending(c)) fail(IFA_E_STATE, "scans or hits pending; collect hits first");
+        if (c->cfg.sink == IFA_SINK_RECORDS && cap > 0 && !d_hits)
+            fail(IFA_E_INVALID, "NULL hit buffer");
+        uint32_t wpl, qu, wg, enc;
+        variant_shape(c->variant, &wpl, &qu, &wg, &enc);
+        if ((enc == 1 || enc == 2) && c->n_sparse > 0 && !c->indexed && !c->mq_ready[enc - 1])
+            fail(IFA_E_STATE, "the variant's filter operands are not built: choose the variant "
+                              "before loading the queries");
+        // a single filter wave lists at most 4 items per batch of 32 strands
+        // (waves holding an N); the static list must hold one wave's items
+        if (4ull * ((c->n_sparse + 31) / 32) > kScratchWorkItems)
+            fail(IFA_E_INVALID, "too many filtered query strands for the static scratch (at most " +
+                                    std::to_string(8ull * kScratchWorkItems) + ")");
+        use_device(c);
+        unsigned long long *ctr = reinterpret_cast<unsigned long long *>(c->scratch);
+        // the hit count runs over every chunk: records append to d_hits
+        hip_check(launch_clear_u64(ctr, 2, c->comp_s), "clear pass counters");
+        for (auto &d : c->resident) {
+            static_pass(c, *d, 0, (uint32_t)((d->len + 31) >> 5), true, d_hits, cap);
+            c->st.bases += d->len - d->own_from;
+            c->st.chunks++;
+        }
+        hip_check(hipMemcpyAsync(c->h_ctr.p, ctr, sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, c->comp_s),
+                  "copy hit count");
+        hip_check(hipStreamSynchronize(c->comp_s), "sync");
+        const uint64_t n = c->cfg.sink == IFA_SINK_RECORDS ? c->h_ctr.p[0] : 0;
+        *n_hits = n;
+        if (n > cap)
+            fail(IFA_E_NOMEM, "hit buffer holds " + std::to_string(cap) + " records, " +
+                                  std::to_string(n) + " needed");
     });
 }
 

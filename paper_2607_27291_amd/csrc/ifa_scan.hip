@@ -37,6 +37,7 @@
 #include <algorithm>
 #include <climits>
 #include <vector>
+#include <mutex>
 
 #include "ifa_dev.h"
 
@@ -1458,6 +1459,49 @@ __global__ void clear_u32_kernel(unsigned int *p, uint32_t n)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Static scratch for the allocation-free scan entry point: the pass counters
+// (hit count, work count, skipped waves) and the filter work list of a pass,
+// in a fixed device array instead of memory the context allocates. Every
+// device holds its own copy. Host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (scratch_address): the array's
+// name in host code is a host-side stand-in, not a device address.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices];
+}  // namespace
+
+// Address of `scratch` on `device` (looked up once per device, with that
+// device current); nullptr and the HIP error in *err when the lookup fails.
+void *scratch_address(int device, hipError_t *err)
+{
+    *err = hipSuccess;
+    if (device < 0 || device >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void *ptr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess) {
+            *err = e;
+            return nullptr;
+        }
+        g_scratch[device] = ptr;
+    }
+    return g_scratch[device];
 }
 
 // ---------------------------------------------------------------------------
