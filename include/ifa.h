@@ -356,7 +356,9 @@ ifa_status ifa_query_mode(const ifa_ctx *ctx, uint32_t *indexed);
 /* Kernel variants: tile shapes of the scan kernel (windows per lane, query
  * strands per loop iteration, workgroup size) and the arithmetic of the
  * filter kernel (encoding 0: vector-ALU bit operations; 1: fp4 matrix cores
- * on four-class one-hot codes; 2: fp4 matrix cores on three-class codes).
+ * on four-class one-hot codes; 2: fp4 matrix cores on three-class codes; 3:
+ * as 2, and the dense query strands of at most 32 bases are counted on the
+ * matrix cores too, on waves without an N or a contig end).
  * Every variant computes the same hits; they differ only in speed. Any
  * output pointer may be NULL. A new context starts with a three-class
  * matrix-core variant; ifa_get_variant names it. */

@@ -167,6 +167,13 @@ struct ScanArgs {
     // matrix-core filters: batch of 32 strands of grid row 0 (the grid's y
     // dimension holds at most 65535 batches per launch)
     uint32_t batch0;
+    // dense strands [dm_first, n_qs) (all of at most 32 bases) are counted on
+    // the matrix cores on clean waves (n_qs: none): three-class operands of
+    // one word, four strands per column tile, dm_b[(2 tile + K step) * 64 +
+    // lane], dm_t[32 tile + column] = L - k - nA (the exact hit bound)
+    const uint4 *dm_b;
+    const float *dm_t;
+    uint32_t dm_first;
     // overhang kernel: pieces per wave for the strand with the widest clip
     // (64 / (2 C) lanes each, at least 1); 0 = no strand can overhang
     uint32_t edge_pmin;

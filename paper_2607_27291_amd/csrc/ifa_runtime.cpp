@@ -286,6 +286,12 @@ struct ifa_ctx {
     hipEvent_t mqstaged[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     const uint4 *dq_mqb = nullptr, *dq_mq3b = nullptr;
     const float *dq_mqt = nullptr, *dq_mq3t = nullptr;
+    // dense strands counted on the matrix cores on clean waves (three-class
+    // variants): [n_dm0, n_qs), all of at most 32 bases, and their operands
+    uint32_t n_dm0 = 0;
+    bool dm_ready = false;
+    const uint4 *dq_dmb = nullptr;
+    const float *dq_dmt = nullptr;
     uint32_t mq3_words = 1;           // most prefix words of any three-class column tile
     uint32_t mq3_two_batches = 0;     // leading batches holding a two-word tile
     uint32_t edge_pmin = 0;           // overhang kernel: pieces per wave (ScanArgs.edge_pmin)
@@ -590,6 +596,14 @@ ScanArgs chunk_args(ifa_ctx *c, const DevChunk &ch)
     a.variant = c->variant;
     a.q_count = c->d_qcount.p;
     a.q_digest = c->d_qdigest.p;
+    a.dm_first = a.n_qs;
+    uint32_t wpl, qu, wg, enc;
+    variant_shape(c->variant, &wpl, &qu, &wg, &enc);
+    if (enc == 3 && !c->indexed && c->n_dm0 < a.n_qs && c->dm_ready) {
+        a.dm_first = c->n_dm0;
+        a.dm_b = c->dq_dmb;
+        a.dm_t = c->dq_dmt;
+    }
     return a;
 }
 
@@ -1458,26 +1472,46 @@ uint8_t *upload_tables(ifa_ctx *c, HostBuf<uint8_t> &h, DevBuf<uint8_t> &d, cons
 // have them yet (brute-force sets with sparse strands only).
 void ensure_filter_operands(ifa_ctx *c)
 {
-    if (!c->have_queries || c->indexed || c->n_sparse == 0) return;
+    if (!c->have_queries || c->indexed) return;
     uint32_t wpl, qu, wg, enc;
     variant_shape(c->variant, &wpl, &qu, &wg, &enc);
-    if (enc != 1 && enc != 2) return;
-    const int f = (int)enc - 1;
-    if (c->mq_ready[f]) return;
-    std::vector<uint32_t> b;
-    std::vector<float> need;
-    size_t off[2];
+    if (enc < 1 || enc > 3) return;
+    const uint32_t n_qs = (uint32_t)c->h_qs.size();
+    const bool dense = enc == 3 && c->n_dm0 < n_qs;
+    if (c->n_sparse == 0 && !dense) return;
+    const int f = enc == 1 ? 0 : 1;
+    if (c->mq_ready[f] && (!dense || c->dm_ready)) return;
+    std::vector<uint32_t> b, db;
+    std::vector<float> need, dneed;
+    size_t off[4];
     if (enc == 1) {
         build_mfma_operands(c->h_qs, c->n_sparse, b, need, c->threads);
     } else {
         std::vector<uint32_t> mw3;
         mfma3_tile_words(c->h_fw, c->n_sparse, mw3);
         build_mfma3_operands(c->h_qs, c->h_qwords, mw3, c->n_sparse, b, need, c->threads);
+        if (dense) {
+            // the dense strands of at most 32 bases: one-word tiles, their
+            // bound the exact hit test (thr = k)
+            std::vector<QSDesc> dq(c->h_qs.begin() + c->n_dm0, c->h_qs.end());
+            std::vector<uint32_t> one((dq.size() + 3) / 4, 1u);
+            build_mfma3_operands(dq, c->h_qwords, one, (uint32_t)dq.size(), db, dneed, c->threads);
+            // keep only the first word's operands of each tile (2 K steps)
+            std::vector<uint32_t> packed;
+            packed.reserve(one.size() * 2 * 64 * 4);
+            for (size_t nt = 0; nt < one.size(); nt++) {
+                const size_t base = nt * kFilterWords * 2 * 64 * 4;
+                packed.insert(packed.end(), db.begin() + base, db.begin() + base + 2 * 64 * 4);
+            }
+            db.swap(packed);
+        }
     }
-    const TablePart parts[2] = {{b.data(), b.size() * sizeof(uint32_t)},
-                                {need.data(), need.size() * sizeof(float)}};
+    const TablePart parts[4] = {{b.data(), b.size() * sizeof(uint32_t)},
+                                {need.data(), need.size() * sizeof(float)},
+                                {db.data(), db.size() * sizeof(uint32_t)},
+                                {dneed.data(), dneed.size() * sizeof(float)}};
     const int t = c->tab;
-    uint8_t *base = upload_tables(c, c->h_mqarena[t][f], c->d_mqarena[t][f], parts, 2, off,
+    uint8_t *base = upload_tables(c, c->h_mqarena[t][f], c->d_mqarena[t][f], parts, 4, off,
                                   "matrix filter operands", c->mqstaged[t][f]);
     if (enc == 1) {
         c->dq_mqb = reinterpret_cast<const uint4 *>(base + off[0]);
@@ -1485,6 +1519,9 @@ void ensure_filter_operands(ifa_ctx *c)
     } else {
         c->dq_mq3b = reinterpret_cast<const uint4 *>(base + off[0]);
         c->dq_mq3t = reinterpret_cast<const float *>(base + off[1]);
+        c->dq_dmb = reinterpret_cast<const uint4 *>(base + off[2]);
+        c->dq_dmt = reinterpret_cast<const float *>(base + off[3]);
+        c->dm_ready = dense;
     }
     c->mq_ready[f] = true;
 }
@@ -1545,6 +1582,7 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     c->dq_mq3w = reinterpret_cast<const uint32_t *>(base + off[2]);
     c->h_fw = std::move(sorted_fw);
     c->mq_ready[0] = c->mq_ready[1] = false;
+    c->dm_ready = false;
     if (c->cfg.sink == IFA_SINK_COUNT_DIGEST) {
         const size_t need = (size_t)std::max<uint32_t>(n_queries, 1) * kStripes;
         if (c->d_qcount.n < need) {
@@ -1561,6 +1599,13 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
         c->work_want =
             (uint32_t)std::min<uint64_t>(std::max<uint64_t>(est, c->work_want), 1ull << 28);
     }
+    uint32_t n_dm0 = (uint32_t)qs.size();
+    for (uint32_t i = n_sparse; i < (uint32_t)qs.size(); i++)
+        if (qs[i].len <= 32u) {
+            n_dm0 = i;
+            break;
+        }
+    c->n_dm0 = indexed ? (uint32_t)qs.size() : n_dm0;
     c->h_qs = std::move(qs);
     c->n_sparse = n_sparse;
     c->h_qwords = std::move(words);
@@ -2130,7 +2175,7 @@ ifa_status ifa_scan_resident_into(ifa_ctx *c, ifa_hit *d_hits, uint64_t cap, uin
             fail(IFA_E_INVALID, "NULL hit buffer");
         uint32_t wpl, qu, wg, enc;
         variant_shape(c->variant, &wpl, &qu, &wg, &enc);
-        if ((enc == 1 || enc == 2) && c->n_sparse > 0 && !c->indexed && !c->mq_ready[enc - 1])
+        if (enc >= 1 && c->n_sparse > 0 && !c->indexed && !c->mq_ready[enc == 1 ? 0 : 1])
             fail(IFA_E_STATE, "the variant's filter operands are not built: choose the variant "
                               "before loading the queries");
         // a single filter wave lists at most 4 items per batch of 32 strands
@@ -2291,8 +2336,12 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
             scratch_qc.alloc(need, "tuning query counters");
             scratch_qd.alloc(need, "tuning query digests");
         }
+        // the work list holds what a variant's filter lists (it grows and the
+        // variant is timed again when it overflows: an overflowing list skips
+        // the resolve kernel, which would flatter a weak filter)
+        uint32_t work_cap = 1u << 16;
         DevBuf<WorkItem> scratch_work;
-        scratch_work.alloc(1u << 16, "tuning work list");
+        scratch_work.alloc(work_cap, "tuning work list");
         DevBuf<unsigned int> scratch_wc;
         scratch_wc.alloc(2, "tuning work counters");
         hipEvent_t e0, e1;
@@ -2309,17 +2358,27 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
             a.hit_cap = 1024;
             a.q_count = scratch_qc.p;
             a.q_digest = scratch_qd.p;
-            a.work = scratch_work.p;
             a.work_count = scratch_wc.p;
             a.skip_count = scratch_wc.p + 1;
-            a.work_cap = 1u << 16;
             auto pass = [&]() {
                 hip_check(launch_clear_u32(a.work_count, 2, c->comp_s), "clear");
                 hip_check(launch_filter(a, c->comp_s), "tuning launch");
                 hip_check(launch_resolve(a, c->comp_s), "tuning launch");
                 hip_check(launch_dense(a, c->comp_s), "tuning launch");
             };
-            pass();   // warm up
+            for (;;) {
+                a.work = scratch_work.p;
+                a.work_cap = work_cap;
+                pass();   // warm up, and the list's need
+                unsigned int items = 0;
+                hip_check(hipMemcpyAsync(&items, scratch_wc.p, sizeof items,
+                                         hipMemcpyDeviceToHost, c->comp_s),
+                          "copy tuning work count");
+                hip_check(hipStreamSynchronize(c->comp_s), "sync tuning pass");
+                if (items <= work_cap || work_cap >= (1u << 28)) break;
+                work_cap = (uint32_t)std::min<uint64_t>(2ull * items, 1ull << 28);
+                scratch_work.alloc(work_cap, "tuning work list");
+            }
             std::vector<float> t(reps);
             for (uint32_t r = 0; r < reps; r++) {
                 hip_check(hipEventRecord(e0, c->comp_s), "event record");

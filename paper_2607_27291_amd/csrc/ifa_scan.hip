@@ -909,6 +909,195 @@ static uint32_t mq3_lds_bytes(uint32_t tiles, uint32_t wg, int nw)
            (wg / 64u) * 3u * m3_blocks(nw) * 4u;
 }
 
+// ---------------------------------------------------------------------------
+// Dense strands on the matrix cores.
+//
+// For a query strand of L <= 32 bases the three-class contraction over its
+// whole length is the exact match count of every window: with need = L - k -
+// nA (nA = A bases of the strand), a window is a hit iff its value D reaches
+// need, and its mismatches are m = k + need - D. So on a clean wave -- no N
+// and no piece end in the words its windows read, every window owned and
+// inside the chunk and the scanned range, all in one piece -- the dense
+// strands [dm_first, n_qs) (all of L <= 32) are counted here, four per column
+// tile, with the filter's staging and operand layout; their hits are emitted
+// by each lane from a 32-bit hit mask per pair of row tiles (the lane holds
+// one strand's column: 16 rows of two row tiles), with the values D - need
+// of the lane's rows parked in LDS bytes. The VALU dense kernels take those
+// strands only on waves that are not clean.
+//
+// Grid: x = workgroups walking waves (XCD-aware), y = dense column tile.
+// ---------------------------------------------------------------------------
+
+// Is the 1024-window wave whose window starts begin at word w0 clean (see
+// above) for strands of at most 32 bases? Windows start in words w0 ..
+// w0 + 31 and read up to word w0 + 32. Called by all 64 lanes.
+__device__ __forceinline__ bool wave_is_clean(const ScanArgs &a, uint32_t w0)
+{
+    const uint32_t l = threadIdx.x & 63u;
+    if (w0 + 32u > a.w_end || 32ull * w0 < (uint64_t)a.own_from ||
+        32ull * (w0 + 33u) > a.chunk_len)
+        return false;
+    uint32_t bad = 0;
+    if (l <= 32u) bad = a.nm[w0 + l] | a.em[w0 + l];
+    return !__any(bad != 0u);
+}
+
+template <int WG>
+__global__ __launch_bounds__(WG) void scan_dense_mfma3_kernel(ScanArgs a)
+{
+    constexpr uint32_t kBlocks = m3_blocks(1), kWords = 3 * kBlocks;
+    extern __shared__ uint4 lds[];
+    const uint32_t nt = blockIdx.y;                                 // dense column tile
+    uint4 *sb = lds;                                                // [2 K steps][64]
+    float *st = reinterpret_cast<float *>(lds + 128u);              // [32]
+    uint32_t *sp = reinterpret_cast<uint32_t *>(st + 32u);          // [256]
+    const uint32_t wid = threadIdx.x >> 6;
+    uint32_t *flat = sp + 256u + wid * (kWords + 512u);             // this wave's words
+    uint32_t *ebuf = flat + kWords;                                 // [8][64 lanes] packed bytes
+    for (uint32_t i = threadIdx.x; i < 128u; i += WG) sb[i] = a.dm_b[128u * nt + i];
+    for (uint32_t i = threadIdx.x; i < 32u; i += WG) st[i] = a.dm_t[32u * nt + i];
+    for (uint32_t i = threadIdx.x; i < 256u; i += WG) sp[i] = kSpread.v[i];
+    __syncthreads();
+
+    const uint32_t l = threadIdx.x & 63u;
+    const uint32_t g = l & 31u, h = l >> 5;
+    // the lane's column: strand 4 nt + g / 8 of the dense MFMA range, shift
+    // g % 8 (the four descriptors are read wave-uniformly, then selected)
+    const uint32_t sq = a.dm_first + 4u * nt + (g >> 3);
+    const bool col_ok = sq < a.n_qs;
+    QS d;
+    {
+        const uint32_t q0 = a.dm_first + 4u * nt;
+        const QS e0 = load_qs(a, q0);
+        const QS e1 = load_qs(a, min(q0 + 1u, a.n_qs - 1u));
+        const QS e2 = load_qs(a, min(q0 + 2u, a.n_qs - 1u));
+        const QS e3 = load_qs(a, min(q0 + 3u, a.n_qs - 1u));
+        const uint32_t s = g >> 3;
+        d = s == 0u ? e0 : s == 1u ? e1 : s == 2u ? e2 : e3;
+    }
+    const float need = st[g];
+    const uint32_t shift = g & 7u;
+    const uint32_t last = (uint32_t)((a.chunk_len + 31) >> 5) + kPadWords - 1;
+    const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
+    const uint32_t stride = gridDim.x * (WG / 64u);
+    const ifa_v16f zero = {};
+    const ifa_v8i B0 = {(int)sb[l].x, (int)sb[l].y, (int)sb[l].z, (int)sb[l].w, 0, 0, 0, 0};
+    const ifa_v8i B1 = {(int)sb[64u + l].x, (int)sb[64u + l].y, (int)sb[64u + l].z,
+                        (int)sb[64u + l].w, 0, 0, 0, 0};
+    uint32_t cnt = 0;
+    uint64_t dig = 0;
+    for (uint32_t wave = xcd_local_x() * (WG / 64u) + wid; wave < n_waves; wave += stride) {
+        const uint32_t w0 = a.w_begin + 32u * wave;
+        if (!wave_is_clean(a, w0)) continue;
+        // contig and position of the wave's first window (one piece)
+        uint32_t contig = 0, pos0 = 0;
+        {
+            const uint64_t first = 32ull * w0;
+            const Piece pc = a.pieces[find_piece(a, first)];
+            contig = pc.contig;
+            pos0 = (uint32_t)(pc.contig_off + (first - pc.start));
+        }
+        // stage the indicator words of blocks 4j .. 4j + 3 (lane j)
+        if (l < kBlocks / 4u) {
+            const uint32_t w = min(w0 + l, last);
+            const uint32_t ch = a.hi[w], cl = a.lo[w];
+            const uint32_t m = 0x22222222u;
+            uint32_t v[12];
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) {
+                const uint32_t s1 = sp[(ch >> (8u * q)) & 0xffu];
+                const uint32_t s0 = sp[(cl >> (8u * q)) & 0xffu];
+                v[3 * q] = ~s1 & s0 & m;           // C (hi 0, lo 1)
+                v[3 * q + 1] = s1 & s0 & m;        // G (1, 1)
+                v[3 * q + 2] = s1 & ~s0 & m;       // T (1, 0)
+            }
+            uint4 *dst = reinterpret_cast<uint4 *>(flat + 12u * l);
+            dst[0] = make_uint4(v[0], v[1], v[2], v[3]);
+            dst[1] = make_uint4(v[4], v[5], v[6], v[7]);
+            dst[2] = make_uint4(v[8], v[9], v[10], v[11]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int p = 0; p < 2; p++) {
+            ifa_v8i A[2][2];
+#pragma unroll
+            for (int uu = 0; uu < 2; uu++) {
+                const uint32_t *f = flat + 3u * (32u * (2 * p + uu) + g) + 8u * h;
+#pragma unroll
+                for (int t = 0; t < 2; t++)
+                    A[uu][t] = ifa_v8i{(int)f[4 * t], (int)f[4 * t + 1], (int)f[4 * t + 2],
+                                       (int)f[4 * t + 3], 0, 0, 0, 0};
+            }
+            ifa_v16f d0 = mfma_fp4(A[0][0], B0, zero);
+            ifa_v16f d1 = mfma_fp4(A[1][0], B0, zero);
+            d0 = mfma_fp4(A[0][1], B1, d0);
+            d1 = mfma_fp4(A[1][1], B1, d1);
+            // hit mask: bit i for row i of row tile 2p, bit 16 + i of 2p + 1
+            uint32_t hm = 0;
+#pragma unroll
+            for (int i = 0; i < 16; i++) {
+                hm |= (d0[i] >= need ? 1u : 0u) << i;
+                hm |= (d1[i] >= need ? 1u : 0u) << (16 + i);
+            }
+            if (!col_ok) hm = 0;
+            if (!__any(hm != 0u)) continue;
+            // D - need of the lane's 32 rows as bytes (only hit rows are read)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                uint32_t b0 = 0, b1 = 0;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    b0 |= ((uint32_t)(int)(d0[4 * q + e] - need) & 0xffu) << (8 * e);
+                    b1 |= ((uint32_t)(int)(d1[4 * q + e] - need) & 0xffu) << (8 * e);
+                }
+                ebuf[64u * q + l] = b0;            // dword q of lane l (bank-friendly)
+                ebuf[64u * (4u + q) + l] = b1;
+            }
+            unsigned long long slot = 0;
+            if (a.sink == kSinkRecords && hm)
+                slot = atomicAdd(a.hit_count, (unsigned long long)__popc(hm));
+            while (hm) {
+                const uint32_t i = __builtin_ctz(hm);
+                hm &= hm - 1u;
+                const uint32_t ii = i & 15u;
+                // window of row ii: row tile 2p + i / 16, group 8 (ii / 4) + 4 h + ii % 4
+                const uint32_t win = 256u * (2u * (uint32_t)p + (i >> 4)) +
+                                     8u * (8u * (ii >> 2) + 4u * h + (ii & 3u)) + shift;
+                const uint32_t m = d.k - ((ebuf[64u * (i >> 2) + l] >> (8u * (i & 3u))) & 0xffu);
+                if (a.sink == kSinkRecords) {
+                    write_record(a, slot, d, contig, pos0 + win, m, 0u);
+                    slot++;
+                } else {
+                    cnt += 1;
+                    dig += hit_hash(contig, pos0 + win, d.strand, m, 0u);
+                }
+            }
+        }
+        // the next wave rewrites this wave's words: all reads done first
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (a.sink == kSinkCountDigest) {
+        // each lane holds one strand's column: sum per strand of the tile
+#pragma unroll
+        for (uint32_t s = 0; s < 4u; s++) {
+            const uint32_t q = a.dm_first + 4u * nt + s;
+            if (q >= a.n_qs) break;
+            const bool mine = (g >> 3) == s;
+            const QS ds = load_qs(a, q);
+            wave_add_stats(a, ds.qid, mine ? cnt : 0u, mine ? dig : 0ull,
+                           blockIdx.x * (WG / 64u) + wid);
+        }
+    }
+}
+
+// LDS bytes of the dense matrix kernel (one column tile per workgroup).
+static uint32_t dm3_lds_bytes(uint32_t wg)
+{
+    return 128u * 16u + 32u * 4u + 256u * 4u + (wg / 64u) * (3u * m3_blocks(1) + 512u) * 4u;
+}
+
 // One wave per work item (grid-stride). Does nothing when the filter kernel
 // overflowed the list: the host then grows it and runs the sparse part again.
 template <int W>
@@ -1105,13 +1294,17 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     uint32_t cur_len = 32;
+    // on a clean wave the strands from dm_first on are counted on the matrix
+    // cores (scan_dense_mfma3_kernel)
+    const uint32_t q_end =
+        a.dm_first < a.n_qs && wave_is_clean(a, a.w_begin + 32u * wave) ? a.dm_first : a.n_qs;
     // both strands of a query are adjacent: their counts are summed before
     // the wave-wide reduction
     uint32_t cnt = 0, qid = 0xffffffffu;
     uint64_t dig = 0;
     // the next strand's descriptor is loaded while this one runs
     QS nxt = load_qs(a, a.n_sparse);
-    for (uint32_t q = a.n_sparse; q < a.n_qs; q++) {
+    for (uint32_t q = a.n_sparse; q < q_end; q++) {
         const QS d = nxt;
         if (q + 1u < a.n_qs) nxt = load_qs(a, q + 1u);
         if (d.qid != qid) {
@@ -1144,7 +1337,9 @@ __global__ __launch_bounds__(256) void scan_dense_cold_kernel(ScanArgs a)
     const bool cold = ln.active && !lane_is_plain(a, ln);
     if (!__any(cold)) return;
     const uint32_t wave = gl >> 6;
-    for (uint32_t q = a.n_sparse; q < a.n_qs; q++) {
+    const uint32_t q_end =
+        a.dm_first < a.n_qs && wave_is_clean(a, a.w_begin + 32u * wave) ? a.dm_first : a.n_qs;
+    for (uint32_t q = a.n_sparse; q < q_end; q++) {
         const QS d = load_qs(a, q);
         uint32_t cnt = 0;
         uint64_t dig = 0;
@@ -1520,25 +1715,34 @@ struct VariantDesc {
     uint32_t enc;       // filter arithmetic: 0 = VALU bit ops, 1 = fp4 matrix cores
                         // (four classes), 2 = fp4 matrix cores (three classes)
     uint32_t waves;     // matrix-core filter: waves launched over all batches
+    uint32_t dmfma;     // 1: dense strands of at most 32 bases on the matrix cores
+                        // (clean waves; three-class filters only)
 };
 
 #define IFA_V(W, QU, WG)                                                                 \
     {                                                                                    \
         scan_filter_kernel<W, QU, WG>, scan_filter_kernel<W, QU, WG>,                    \
             scan_resolve_kernel<W>, scan_dense_kernel<W>, scan_dense_cold_kernel<W>, W, QU,  \
-            WG, 0, 0                                                                     \
+            WG, 0, 0, 0                                                                  \
     }
 // matrix-core filters: waves of 16 windows per lane, resolved by the W = 16 kernels
 #define IFA_VM3(WG, WAVES)                                                               \
     {                                                                                    \
         scan_filter_mfma3_kernel<WG, 1>, scan_filter_mfma3_kernel<WG, 2>,                \
             scan_resolve_kernel<16>, scan_dense_kernel<16>, scan_dense_cold_kernel<16>, 16,  \
-            4, WG, 2, WAVES                                                              \
+            4, WG, 2, WAVES, 0                                                           \
+    }
+// the same, with dense strands of at most 32 bases on the matrix cores
+#define IFA_VM3D(WG, WAVES)                                                              \
+    {                                                                                    \
+        scan_filter_mfma3_kernel<WG, 1>, scan_filter_mfma3_kernel<WG, 2>,                \
+            scan_resolve_kernel<16>, scan_dense_kernel<16>, scan_dense_cold_kernel<16>, 16,  \
+            4, WG, 2, WAVES, 1                                                           \
     }
 #define IFA_VM(WG, WAVES)                                                                \
     {                                                                                    \
         scan_filter_mfma_kernel<WG>, scan_filter_mfma_kernel<WG>, scan_resolve_kernel<16>, \
-            scan_dense_kernel<16>, scan_dense_cold_kernel<16>, 16, 2, WG, 1, WAVES       \
+            scan_dense_kernel<16>, scan_dense_cold_kernel<16>, 16, 2, WG, 1, WAVES, 0    \
     }
 static const VariantDesc kVariantTable[] = {
     IFA_V(32, 1, 256),   // 0
@@ -1551,10 +1755,12 @@ static const VariantDesc kVariantTable[] = {
     IFA_VM(512, 16384),  IFA_VM(512, 65536),  IFA_VM(1024, 65536),
     IFA_VM3(512, 32768), IFA_VM3(256, 32768), IFA_VM3(1024, 32768),
     IFA_VM3(512, 65536), IFA_VM3(256, 16384),
+    IFA_VM3D(256, 32768), IFA_VM3D(512, 32768),
 };
 #undef IFA_V
 #undef IFA_VM
 #undef IFA_VM3
+#undef IFA_VM3D
 
 uint32_t variant_count() { return sizeof(kVariantTable) / sizeof(kVariantTable[0]); }
 
@@ -1568,7 +1774,8 @@ void variant_shape(uint32_t v, uint32_t *windows, uint32_t *qunroll, uint32_t *w
     *windows = d.windows;
     *qunroll = d.qunroll;
     *wg = d.wg;
-    *enc = d.enc;
+    // encoding 3: the three-class filter with dense strands on the matrix cores
+    *enc = d.enc + d.dmfma;
 }
 
 // Launch of a scan kernel, or (rec != nullptr) its record in a launch plan.
@@ -1653,9 +1860,26 @@ hipError_t launch_dense(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch
     const VariantDesc &v = pick(a);
     const uint64_t lanes = filter_lanes(a, v);
     const dim3 grid((uint32_t)((lanes + 255) / 256));
-    const hipError_t e = go(v.dense, grid, dim3(256), 0, s, a, rec);
+    hipError_t e = go(v.dense, grid, dim3(256), 0, s, a, rec);
     if (e != hipSuccess) return e;
-    return go(v.dense_cold, grid, dim3(256), 0, s, a, rec);
+    e = go(v.dense_cold, grid, dim3(256), 0, s, a, rec);
+    if (e != hipSuccess || a.dm_first >= a.n_qs) return e;
+    // one-word dense strands on the matrix cores, clean waves only: one
+    // column tile of 4 strands per grid row, about 2^15 waves in all
+    const uint32_t tiles = (a.n_qs - a.dm_first + 3u) / 4u;
+    const uint32_t waves = (a.w_end - a.w_begin + 31u) >> 5;
+    uint32_t gx = max(1u, min((waves + 3u) / 4u, (32768u / 4u + tiles - 1u) / tiles));
+    if (gx >= 8u) gx &= ~7u;
+    for (uint32_t t0 = 0; t0 < tiles; t0 += 65535u) {
+        ScanArgs part = a;
+        part.dm_first = a.dm_first + 4u * t0;
+        part.dm_b = a.dm_b + 128u * t0;
+        part.dm_t = a.dm_t + 32u * t0;
+        e = go(scan_dense_mfma3_kernel<256>, dim3(gx, min(65535u, tiles - t0)), dim3(256),
+               dm3_lds_bytes(256), s, part, rec);
+        if (e != hipSuccess) return e;
+    }
+    return e;
 }
 
 // Overhanging windows of the word range: one wave per (block of pieces,

@@ -84,6 +84,7 @@ def replay(scanner, trace, *, mode="batch", max_active_queries=4096, hit_budget=
         "mean_s": sum(lat) / n,
         "steps": steps,
         "step_ms_total": info["step_ms"],
+        "hit_budget": info["hit_budget"],
         "latencies_s": lat,
         "hits": n_hits,
         "hit_records": hits,

@@ -386,7 +386,7 @@ def test_two_word_batches_run_their_own_launch(ifa, orc, n_two, n_one):
     want = orc.scan(qs, ref, ks)
     assert len(want) >= len(qs)
     for v in range(ifa.ifa_variant_count()):
-        if ifa.ifa_variant_info(v)["encoding"] != 2:
+        if ifa.ifa_variant_info(v)["encoding"] not in (2, 3):
             continue
         say(f"two-word batches: {n_two} two-word, {n_one} one-word queries, variant {v}")
         with ifa.Scanner(chunk_bases=1 << 18) as s:
@@ -501,7 +501,7 @@ def test_matrix_core_filter_emits_what_the_valu_filter_emits(ifa):
             st = s.stats()
             seen[v] = (st["work_items"], st["filter_windows"], info["encoding"])
     word = {x[:2] for x in seen.values() if x[2] < 2}
-    block = {x[:2] for x in seen.values() if x[2] == 2}
+    block = {x[:2] for x in seen.values() if x[2] >= 2}
     assert len(word) == 1 and len(block) == 1, seen
     (_, w_word), (_, w_block) = word.pop(), block.pop()
     assert 0.98 * w_word <= w_block <= w_word, seen
@@ -692,7 +692,8 @@ def test_n_in_the_last_word_a_two_word_window_reads(ifa, orc, policy):
     k = 16 if policy == 0 else 17
     want = orc.scan([q], [bytes(contig)], [k], policy=policy)
     assert len(want) >= 8
-    vs = [v for v in range(ifa.ifa_variant_count()) if ifa.ifa_variant_info(v)["encoding"] == 2]
+    vs = [v for v in range(ifa.ifa_variant_count())
+          if ifa.ifa_variant_info(v)["encoding"] in (2, 3)]
     assert vs
     for v in vs:
         say(f"N in word 33: variant {v} policy {policy}")
@@ -764,3 +765,55 @@ def test_filter_launch_split_past_65535_batches(ifa, orc):
             assert ifa.ifa_query_partition(s.ctx) == (2 * n, 2 * n)
             s.scan_chunk(contigs)
             assert_same(s.collect(), want, f"variant {v}")
+
+
+@pytest.mark.parametrize("sink", [0, 1])
+def test_dense_strands_on_matrix_cores(ifa, orc, sink):
+    """Dense strands of at most 32 bases are counted on the matrix cores on
+    clean waves (no N or contig end among the words their windows read) and
+    by the VALU kernels elsewhere; longer dense strands always by the VALU
+    kernels. Short high-threshold queries (hit rates from 1e-4 to ~1) against
+    contigs with N runs and many contig ends, in small chunks (carried
+    prefixes), records with a small hit buffer (re-scans) and count+digest:
+    every three-class variant and a VALU variant equal the oracle."""
+    rng = random.Random(4422)
+    contigs = []
+    for i in range(10):
+        n = rng.choice([900, 5000, 33_000, 70_000])
+        c = bytearray(rand_dna(rng, n))
+        for _ in range(rng.randint(0, 3)):
+            p = rng.randrange(0, n - 1)
+            c[p:p + rng.randint(1, 120)] = b"N" * len(c[p:p + 120])
+        contigs.append(bytes(c[:n]))
+    qs, ks = [], []
+    for L, k in ((18, 16), (18, 12), (20, 10), (24, 12), (24, 9), (28, 14), (31, 15),
+                 (32, 16), (32, 13), (36, 16), (37, 17), (19, 11), (22, 8), (26, 10)):
+        for _ in range(3):
+            qs.append(rand_dna(rng, L, b"ACGT" if rng.random() < 0.9 else b"ACGTN"))
+            ks.append(k)
+    if sink == 0:
+        want = orc.scan(qs, contigs, ks)
+    else:
+        _, cnt, dig = orc.scan(qs, contigs, ks, stats=True, records=False)
+    vs = [v for v in range(ifa.ifa_variant_count()) if ifa.ifa_variant_info(v)["encoding"] == 3]
+    assert vs, "no variant with dense strands on the matrix cores"
+    vs.append(next(v for v in range(ifa.ifa_variant_count())
+                   if ifa.ifa_variant_info(v)["encoding"] == 2))
+    vs.append(next(v for v in range(ifa.ifa_variant_count())
+                   if ifa.ifa_variant_info(v)["encoding"] == 0
+                   and ifa.ifa_variant_info(v)["windows_per_lane"] == 16))
+    for v in vs:
+        for chunk, hcap in ((1 << 20, 0), (1 << 16, 20_000)):
+            say(f"dense on matrix cores: variant {v} sink {sink} chunk {chunk} hcap {hcap}")
+            with ifa.Scanner(chunk_bases=chunk, sink=sink,
+                             hit_capacity=hcap if sink == 0 else 0) as s:
+                ifa.ifa_set_variant(s.ctx, v)
+                s.load_queries(qs, ks)
+                n_strands, n_filtered = ifa.ifa_query_partition(s.ctx)
+                assert n_filtered < n_strands
+                s.scan_chunk(contigs)
+                if sink == 0:
+                    assert_same(s.collect(), want, f"variant {v} chunk {chunk}")
+                else:
+                    gc, gd = s.query_stats()
+                    assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), f"variant {v}"
