@@ -326,12 +326,12 @@ def ifa_scan_packed(ctx, n_bases: int, hi, lo, contig_len, run_start=None, run_l
 
 def ifa_collect_hits(ctx, cap: int):
     """One call: returns (hits array of at most cap records, n_remaining)."""
-    out = np.zeros(max(cap, 1), dtype=HIT_DTYPE)
+    out = np.empty(max(cap, 1), dtype=HIT_DTYPE)
     nw = ctypes.c_uint64()
     nr = ctypes.c_uint64()
     _check(ctx, lib().ifa_collect_hits(ctx, out.ctypes.data, cap, ctypes.byref(nw),
                                        ctypes.byref(nr)))
-    return out[:nw.value].copy(), nr.value
+    return (out if nw.value == len(out) else out[:nw.value].copy()), nr.value
 
 
 def ifa_query_stats(ctx, n_queries: int):
@@ -665,13 +665,15 @@ class Server:
 
 
 def collect_all(ctx, batch: int = 1 << 20) -> np.ndarray:
-    """Drain every held hit (two-call pattern over ifa_collect_hits)."""
+    """Drain every held hit (two-call pattern over ifa_collect_hits: a call
+    with cap 0 gives the count, then batches of at most `batch` records)."""
+    _, rem = ifa_collect_hits(ctx, 0)
     parts = []
-    while True:
-        h, rem = ifa_collect_hits(ctx, batch)
+    while rem:
+        h, rem = ifa_collect_hits(ctx, min(rem, batch))
         parts.append(h)
-        if rem == 0:
-            break
+    if not parts:
+        return np.zeros(0, dtype=HIT_DTYPE)
     return np.concatenate(parts) if len(parts) > 1 else parts[0]
 
 

@@ -135,6 +135,9 @@ struct ScanArgs {
     uint32_t n_qs;            // query strands; [0, n_sparse) filtered, the rest dense
     uint32_t n_sparse;
     uint32_t policy;
+    // strands per work item when a filter wave lists a whole batch for the
+    // resolve kernel (a wave holding an N): 1, 2, 4 or 8
+    uint32_t list_per;
     const uint32_t *qwords;
     const Piece *pieces;
     uint32_t n_pieces;

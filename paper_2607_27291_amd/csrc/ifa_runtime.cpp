@@ -575,6 +575,11 @@ ScanArgs chunk_args(ifa_ctx *c, const DevChunk &ch)
     a.n_qs = (uint32_t)c->h_qs.size();
     a.n_sparse = c->n_sparse;
     a.policy = c->cfg.n_policy;
+    // a wave holding an N goes to the resolve kernel with every sparse
+    // strand; with few strands (one or two batches) those waves are most of
+    // its work and each one's strands serialise in one resolve wave, so they
+    // are split finer to spread them over more waves
+    a.list_per = a.n_sparse <= 64u ? 2u : 8u;
     a.qwords = c->dq_words;
     a.mq_b = c->dq_mqb;
     a.mq_t = c->dq_mqt;

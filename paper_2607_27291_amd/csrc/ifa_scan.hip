@@ -501,19 +501,21 @@ __device__ __forceinline__ void filter_lane(const ScanArgs &a, const Lane &ln, u
 }
 
 // Work items for a wave that holds an N: every strand of the batch at qb is
-// listed, as items of up to 8 strands so that different resolve waves share
+// listed, as items of list_per strands so that different resolve waves share
 // the batch (these items carry all their strands, unlike filtered ones).
 __device__ __forceinline__ void list_batch(const ScanArgs &a, uint32_t wave, uint32_t qb)
 {
     const uint32_t nb = min(32u, a.n_sparse - qb);
     const uint32_t all = nb == 32u ? 0xffffffffu : ((1u << nb) - 1u);
-    const unsigned int idx = atomicAdd(a.work_count, (nb + 7u) / 8u);
-    for (uint32_t p = 0; 8u * p < nb; p++) {
+    const uint32_t per = a.list_per;
+    const uint32_t items = (nb + per - 1u) / per;
+    const unsigned int idx = atomicAdd(a.work_count, items);
+    for (uint32_t p = 0; p < items; p++) {
         if (idx + p < a.work_cap) {
             WorkItem it;
             it.wave = wave;
             it.qb = qb;
-            it.pending = all & (0xffu << (8u * p));
+            it.pending = all & (((1u << per) - 1u) << (per * p));
             it.pad = 0;
             a.work[idx + p] = it;
         }

@@ -56,6 +56,9 @@ def replay(scanner, trace, *, mode="batch", max_active_queries=4096, hit_budget=
             if in_flight:
                 srv.step()
                 steps += 1
+                if log and steps % 500 == 0:
+                    log(f"  {mode}: step {steps}, {done}/{n} requests done, {i} arrived "
+                        f"at {time.perf_counter() - t0:.1f} s")
             elif i < n:
                 time.sleep(max(0.0, trace[i][0] - (time.perf_counter() - t0)))
             for rid, h in srv.completed():
