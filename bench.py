@@ -800,7 +800,8 @@ def run_c5(args):
     t0 = time.time()
     ref = synth.gen_reference(synth.c5_spec(total=total))
     log(f"generated {ref.total / 1e9:.1f} Gbp ({time.time() - t0:.1f} s)")
-    s = ifa.Scanner(device=0, chunk_bases=args.chunk_bases or (1 << 28))
+    s = ifa.Scanner(device=0, chunk_bases=args.chunk_bases or (1 << 28),
+                    flags=scanner_flags(ifa, args) & ~ifa.IFA_FLAG_OVERHANG)
     s.ref_load(ref)
     bases, chunks = ifa.ifa_ref_info(s.ctx)
     del ref
@@ -833,6 +834,7 @@ def run_c5(args):
         "requests": args.requests,
         "queries": b["queries"],
         "variant": variant,
+        "graphs": not args.eager,
     })
     out["steps"] = 1
     out["warmup"] = 0

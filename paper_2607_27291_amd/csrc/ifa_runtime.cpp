@@ -558,6 +558,13 @@ void ensure_filter_operands(ifa_ctx *c);
 
 // Launch arguments of a pass over chunk ch with the loaded queries, without
 // the hit, work-list and counter fields.
+// Strands per work item when a filter wave hands a whole batch to the
+// resolve kernel (a wave holding an N). With few strands (one or two
+// batches) such waves are most of the resolve kernel's work and the strands
+// of an item run one after another in one resolve wave, so they are split
+// finer to spread them over more waves.
+uint32_t list_per(uint32_t n_sparse) { return n_sparse <= 64u ? 2u : 8u; }
+
 ScanArgs chunk_args(ifa_ctx *c, const DevChunk &ch)
 {
     ScanArgs a{};
@@ -575,11 +582,7 @@ ScanArgs chunk_args(ifa_ctx *c, const DevChunk &ch)
     a.n_qs = (uint32_t)c->h_qs.size();
     a.n_sparse = c->n_sparse;
     a.policy = c->cfg.n_policy;
-    // a wave holding an N goes to the resolve kernel with every sparse
-    // strand; with few strands (one or two batches) those waves are most of
-    // its work and each one's strands serialise in one resolve wave, so they
-    // are split finer to spread them over more waves
-    a.list_per = a.n_sparse <= 64u ? 2u : 8u;
+    a.list_per = list_per(a.n_sparse);
     a.qwords = c->dq_words;
     a.mq_b = c->dq_mqb;
     a.mq_t = c->dq_mqt;
@@ -1011,7 +1014,9 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     } else {
         enqueue();
     }
-    hip_check(hipEventRecord(ch->free_ev, c->comp_s), "event record");
+    // a streamed chunk's slot may be refilled once this pass is done (the
+    // copy stream waits for free_ev); resident chunks are never refilled
+    if (!ch->resident) hip_check(hipEventRecord(ch->free_ev, c->comp_s), "event record");
     hip_check(hipEventRecord(j.done, c->comp_s), "event record");
     j.active = true;
     c->job_seq++;
@@ -1472,53 +1477,70 @@ uint8_t *upload_tables(ifa_ctx *c, HostBuf<uint8_t> &h, DevBuf<uint8_t> &d, cons
     return d.p;
 }
 
-// Build and upload the B operands and required counts of the matrix-core
-// filter form the context's variant uses, if the loaded query set does not
-// have them yet (brute-force sets with sparse strands only).
-void ensure_filter_operands(ifa_ctx *c)
-{
-    if (!c->have_queries || c->indexed) return;
-    uint32_t wpl, qu, wg, enc;
-    variant_shape(c->variant, &wpl, &qu, &wg, &enc);
-    if (enc < 1 || enc > 3) return;
-    const uint32_t n_qs = (uint32_t)c->h_qs.size();
-    const bool dense = enc == 3 && c->n_dm0 < n_qs;
-    if (c->n_sparse == 0 && !dense) return;
-    const int f = enc == 1 ? 0 : 1;
-    if (c->mq_ready[f] && (!dense || c->dm_ready)) return;
+// The B operands and required counts of the matrix-core filter form a
+// variant uses, for the loaded query set: form 0 (four-class, encoding 1) or
+// 1 (three-class, encodings 2 and 3; with encoding 3 also the one-word
+// operands of the dense strands of at most 32 bases).
+struct FilterOperands {
+    int form = -1;            // -1: the variant needs none
+    bool dense = false;
     std::vector<uint32_t> b, db;
     std::vector<float> need, dneed;
-    size_t off[4];
+};
+
+FilterOperands build_filter_operands(const ifa_ctx *c)
+{
+    FilterOperands op;
+    if (c->indexed) return op;
+    uint32_t wpl, qu, wg, enc;
+    variant_shape(c->variant, &wpl, &qu, &wg, &enc);
+    if (enc < 1 || enc > 3) return op;
+    const uint32_t n_qs = (uint32_t)c->h_qs.size();
+    const bool dense = enc == 3 && c->n_dm0 < n_qs;
+    if (c->n_sparse == 0 && !dense) return op;
+    const int f = enc == 1 ? 0 : 1;
+    if (c->mq_ready[f] && (!dense || c->dm_ready)) return op;
+    op.form = f;
+    op.dense = dense;
     if (enc == 1) {
-        build_mfma_operands(c->h_qs, c->n_sparse, b, need, c->threads);
+        build_mfma_operands(c->h_qs, c->n_sparse, op.b, op.need, c->threads);
     } else {
         std::vector<uint32_t> mw3;
         mfma3_tile_words(c->h_fw, c->n_sparse, mw3);
-        build_mfma3_operands(c->h_qs, c->h_qwords, mw3, c->n_sparse, b, need, c->threads);
+        build_mfma3_operands(c->h_qs, c->h_qwords, mw3, c->n_sparse, op.b, op.need, c->threads);
         if (dense) {
             // the dense strands of at most 32 bases: one-word tiles, their
             // bound the exact hit test (thr = k)
             std::vector<QSDesc> dq(c->h_qs.begin() + c->n_dm0, c->h_qs.end());
             std::vector<uint32_t> one((dq.size() + 3) / 4, 1u);
-            build_mfma3_operands(dq, c->h_qwords, one, (uint32_t)dq.size(), db, dneed, c->threads);
+            std::vector<uint32_t> db;
+            build_mfma3_operands(dq, c->h_qwords, one, (uint32_t)dq.size(), db, op.dneed,
+                                 c->threads);
             // keep only the first word's operands of each tile (2 K steps)
-            std::vector<uint32_t> packed;
-            packed.reserve(one.size() * 2 * 64 * 4);
+            op.db.reserve(one.size() * 2 * 64 * 4);
             for (size_t nt = 0; nt < one.size(); nt++) {
                 const size_t base = nt * kFilterWords * 2 * 64 * 4;
-                packed.insert(packed.end(), db.begin() + base, db.begin() + base + 2 * 64 * 4);
+                op.db.insert(op.db.end(), db.begin() + base, db.begin() + base + 2 * 64 * 4);
             }
-            db.swap(packed);
         }
     }
-    const TablePart parts[4] = {{b.data(), b.size() * sizeof(uint32_t)},
-                                {need.data(), need.size() * sizeof(float)},
-                                {db.data(), db.size() * sizeof(uint32_t)},
-                                {dneed.data(), dneed.size() * sizeof(float)}};
-    const int t = c->tab;
-    uint8_t *base = upload_tables(c, c->h_mqarena[t][f], c->d_mqarena[t][f], parts, 4, off,
-                                  "matrix filter operands", c->mqstaged[t][f]);
-    if (enc == 1) {
+    return op;
+}
+
+// The four upload parts of op (operands, counts, dense operands, dense counts).
+void filter_operand_parts(const FilterOperands &op, TablePart *parts)
+{
+    parts[0] = {op.b.data(), op.b.size() * sizeof(uint32_t)};
+    parts[1] = {op.need.data(), op.need.size() * sizeof(float)};
+    parts[2] = {op.db.data(), op.db.size() * sizeof(uint32_t)};
+    parts[3] = {op.dneed.data(), op.dneed.size() * sizeof(float)};
+}
+
+// Point the context at operands uploaded to base + off[0..3].
+void set_filter_operands(ifa_ctx *c, const FilterOperands &op, const uint8_t *base,
+                         const size_t *off)
+{
+    if (op.form == 0) {
         c->dq_mqb = reinterpret_cast<const uint4 *>(base + off[0]);
         c->dq_mqt = reinterpret_cast<const float *>(base + off[1]);
     } else {
@@ -1526,9 +1548,28 @@ void ensure_filter_operands(ifa_ctx *c)
         c->dq_mq3t = reinterpret_cast<const float *>(base + off[1]);
         c->dq_dmb = reinterpret_cast<const uint4 *>(base + off[2]);
         c->dq_dmt = reinterpret_cast<const float *>(base + off[3]);
-        c->dm_ready = dense;
+        c->dm_ready = op.dense;
     }
-    c->mq_ready[f] = true;
+    c->mq_ready[op.form] = true;
+}
+
+// Build and upload the matrix-core filter operands of the context's variant
+// if the loaded query set does not have them yet (the variant changed after
+// the queries were loaded; install_queries uploads those of the variant in
+// use with the query tables).
+void ensure_filter_operands(ifa_ctx *c)
+{
+    if (!c->have_queries) return;
+    const FilterOperands op = build_filter_operands(c);
+    if (op.form < 0) return;
+    TablePart parts[4];
+    filter_operand_parts(op, parts);
+    size_t off[4];
+    const int t = c->tab;
+    const uint8_t *base = upload_tables(c, c->h_mqarena[t][op.form], c->d_mqarena[t][op.form],
+                                        parts, 4, off, "matrix filter operands",
+                                        c->mqstaged[t][op.form]);
+    set_filter_operands(c, op, base, off);
 }
 
 void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t> &&words,
@@ -1574,20 +1615,45 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     uint32_t cmax = 0;
     for (const QSDesc &d : qs) cmax = std::max<uint32_t>(cmax, std::min<uint32_t>(d.maxn, d.len - 1u));
     c->edge_pmin = cmax == 0 ? 0u : (2u * cmax <= 64u ? 64u / (2u * cmax) : 1u);
-    // one upload of every table: parts at 256-byte offsets in one arena
-    const TablePart parts[3] = {{qs.data(), qs.size() * sizeof(QSDesc)},
-                                {words.data(), words.size() * sizeof(uint32_t)},
-                                {mw3.data(), mw3.size() * sizeof(uint32_t)}};
-    size_t off[3];
+    uint32_t n_dm0 = (uint32_t)qs.size();
+    for (uint32_t i = n_sparse; i < (uint32_t)qs.size(); i++)
+        if (qs[i].len <= 32u) {
+            n_dm0 = i;
+            break;
+        }
+    c->n_dm0 = indexed ? (uint32_t)qs.size() : n_dm0;
+    if (c->cfg.work_capacity == 0 && !indexed) {
+        // size the work lists for the expected load unless the caller fixed
+        // the initial capacity (they grow on overflow either way)
+        const uint64_t est = expected_work_items(qs, sorted_fw, n_sparse, c->cfg.chunk_bases);
+        c->work_want =
+            (uint32_t)std::min<uint64_t>(std::max<uint64_t>(est, c->work_want), 1ull << 28);
+    }
+    c->h_qs = std::move(qs);
+    c->h_fw = std::move(sorted_fw);
+    c->n_sparse = n_sparse;
+    c->h_qwords = std::move(words);
+    c->n_queries = n_queries;
+    c->lmax = std::max<uint32_t>(lmax, 1);
+    c->have_queries = false;   // until the tables are on the device
+    c->mq_ready[0] = c->mq_ready[1] = false;
+    c->dm_ready = false;
+    // one upload of every table, the variant's filter operands included:
+    // parts at 256-byte offsets in one arena
+    const FilterOperands op = build_filter_operands(c);
+    TablePart parts[7] = {{c->h_qs.data(), c->h_qs.size() * sizeof(QSDesc)},
+                          {c->h_qwords.data(), c->h_qwords.size() * sizeof(uint32_t)},
+                          {mw3.data(), mw3.size() * sizeof(uint32_t)}};
+    const int n_parts = op.form < 0 ? 3 : 7;
+    if (op.form >= 0) filter_operand_parts(op, parts + 3);
+    size_t off[7];
     c->tab ^= 1;
-    uint8_t *base = upload_tables(c, c->h_qarena[c->tab], c->d_qarena[c->tab], parts, 3, off,
-                                  "query tables", c->qstaged[c->tab]);
+    const uint8_t *base = upload_tables(c, c->h_qarena[c->tab], c->d_qarena[c->tab], parts,
+                                        n_parts, off, "query tables", c->qstaged[c->tab]);
     c->dq_qs = reinterpret_cast<const QSDesc *>(base + off[0]);
     c->dq_words = reinterpret_cast<const uint32_t *>(base + off[1]);
     c->dq_mq3w = reinterpret_cast<const uint32_t *>(base + off[2]);
-    c->h_fw = std::move(sorted_fw);
-    c->mq_ready[0] = c->mq_ready[1] = false;
-    c->dm_ready = false;
+    if (op.form >= 0) set_filter_operands(c, op, base, off + 3);
     if (c->cfg.sink == IFA_SINK_COUNT_DIGEST) {
         const size_t need = (size_t)std::max<uint32_t>(n_queries, 1) * kStripes;
         if (c->d_qcount.n < need) {
@@ -1597,30 +1663,10 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
         hip_check(launch_clear_u64(c->d_qcount.p, (uint32_t)need, c->comp_s), "clear counters");
         hip_check(launch_clear_u64(c->d_qdigest.p, (uint32_t)need, c->comp_s), "clear digests");
     }
-    // size the work lists for the expected load unless the caller fixed the
-    // initial capacity (they grow on overflow either way)
-    if (c->cfg.work_capacity == 0 && !indexed) {
-        const uint64_t est = expected_work_items(qs, c->h_fw, n_sparse, c->cfg.chunk_bases);
-        c->work_want =
-            (uint32_t)std::min<uint64_t>(std::max<uint64_t>(est, c->work_want), 1ull << 28);
-    }
-    uint32_t n_dm0 = (uint32_t)qs.size();
-    for (uint32_t i = n_sparse; i < (uint32_t)qs.size(); i++)
-        if (qs[i].len <= 32u) {
-            n_dm0 = i;
-            break;
-        }
-    c->n_dm0 = indexed ? (uint32_t)qs.size() : n_dm0;
-    c->h_qs = std::move(qs);
-    c->n_sparse = n_sparse;
-    c->h_qwords = std::move(words);
-    c->n_queries = n_queries;
-    c->lmax = std::max<uint32_t>(lmax, 1);
-    c->have_queries = true;
     c->hits.clear();
     c->drain_pos = 0;
     c->hits_sorted = true;
-    ensure_filter_operands(c);
+    c->have_queries = true;
 }
 
 // Indexed mode: seeds of the query set just installed (c->h_qs, device
@@ -2183,9 +2229,11 @@ ifa_status ifa_scan_resident_into(ifa_ctx *c, ifa_hit *d_hits, uint64_t cap, uin
         if (enc >= 1 && c->n_sparse > 0 && !c->indexed && !c->mq_ready[enc == 1 ? 0 : 1])
             fail(IFA_E_STATE, "the variant's filter operands are not built: choose the variant "
                               "before loading the queries");
-        // a single filter wave lists at most 4 items per batch of 32 strands
-        // (waves holding an N); the static list must hold one wave's items
-        if (4ull * ((c->n_sparse + 31) / 32) > kScratchWorkItems)
+        // a single filter wave lists at most 32 / list_per items per batch of
+        // 32 strands (waves holding an N); the static list must hold one
+        // wave's items
+        const uint64_t per = list_per(c->n_sparse);
+        if ((32u + per - 1u) / per * ((c->n_sparse + 31) / 32) > kScratchWorkItems)
             fail(IFA_E_INVALID, "too many filtered query strands for the static scratch (at most " +
                                     std::to_string(8ull * kScratchWorkItems) + ")");
         use_device(c);

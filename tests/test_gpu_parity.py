@@ -817,3 +817,40 @@ def test_dense_strands_on_matrix_cores(ifa, orc, sink):
                 else:
                     gc, gd = s.query_stats()
                     assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), f"variant {v}"
+
+
+def test_variant_chosen_after_loading_builds_its_operands(ifa, orc):
+    """The query tables carry the matrix-filter operands of the variant in use
+    when the queries are loaded; a variant chosen afterwards builds its own
+    (four-class, three-class, three-class with dense strands on the matrix
+    cores) on its first scan. One load, then every encoding in turn and back
+    to the first, each scan equal to the oracle."""
+    rng = random.Random(2718)
+    contigs = []
+    for _ in range(6):
+        n = rng.choice([4000, 30_000, 90_000])
+        c = bytearray(rand_dna(rng, n))
+        p, r = rng.randrange(0, n - 200), rng.randint(1, 150)
+        c[p:p + r] = b"N" * r
+        contigs.append(bytes(c))
+    qs, ks = [], []
+    for L, k in ((34, 3), (40, 5), (30, 2), (64, 9), (20, 9), (24, 11), (31, 14), (50, 14)):
+        for _ in range(3):
+            qs.append(rand_dna(rng, L))
+            ks.append(k)
+    want = orc.scan(qs, contigs, ks)
+    by_enc = {}
+    for v in range(ifa.ifa_variant_count()):
+        by_enc.setdefault(ifa.ifa_variant_info(v)["encoding"], v)
+    order = [by_enc[e] for e in sorted(by_enc)]
+    order += [order[0], order[-1], by_enc.get(2, order[0])]
+    with ifa.Scanner(chunk_bases=1 << 18) as s:
+        ifa.ifa_set_variant(s.ctx, order[0])
+        s.load_queries(qs, ks)
+        for v in order:
+            say(f"variant {v} (encoding {ifa.ifa_variant_info(v)['encoding']}) after loading")
+            ifa.ifa_set_variant(s.ctx, v)
+            first = s.scan_chunk(contigs)   # contigs take new ordinals each call
+            got = s.collect()
+            got["contig"] -= first
+            assert_same(got, want, f"variant {v} chosen after loading")
