@@ -8,6 +8,7 @@ the library has not been built.
 from __future__ import annotations
 
 import ctypes
+import itertools
 import os
 
 import numpy as np
@@ -225,9 +226,25 @@ class _SeqArray:
 
     JOIN_BYTES = 1 << 26
 
+    SMALL = 1024
+
     def __init__(self, seqs, len_dtype):
         self.keep = []
         lens = None
+        if (isinstance(seqs, (list, tuple)) and 0 < len(seqs) <= self.SMALL
+                and all(type(x) is bytes for x in seqs)):
+            # a short list (a query set): plain ctypes arrays over the joined
+            # bytes, whose buffer the pointers address directly
+            joined = b"".join(seqs)
+            base = ctypes.cast(ctypes.c_char_p(joined), ctypes.c_void_p).value
+            ln = [len(x) for x in seqs]
+            arr = (ctypes.c_void_p * len(seqs))(
+                *[base + o for o in itertools.accumulate(ln[:-1], initial=0)])
+            self.keep = [joined, arr]
+            self.n = len(seqs)
+            self.ptrs = ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p))
+            self.lens = np.array(ln, dtype=len_dtype)
+            return
         if isinstance(seqs, (list, tuple)) and seqs and all(type(x) is bytes for x in seqs):
             lens = np.fromiter(map(len, seqs), dtype=np.uint64, count=len(seqs))
             if int(lens.sum()) > self.JOIN_BYTES:

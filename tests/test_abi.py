@@ -91,10 +91,12 @@ def test_index_params_defaults_are_the_papers():
 
 
 def test_sequence_marshalling_paths_agree():
-    """The binding passes a list of bytes through one joined buffer (pointers
-    = its address + offsets) and any other sequence list item by item; both
-    must hand the C side the same bytes and lengths, empty items included,
-    and an oversized list must fall back to the item-by-item path."""
+    """The binding passes a short list of bytes (a query set) through ctypes
+    arrays over one joined bytes object, a longer one through one joined
+    numpy buffer (pointers = its address + offsets) and any other sequence
+    list item by item; all must hand the C side the same bytes and lengths,
+    empty items included, and an oversized long list must fall back to the
+    item-by-item path."""
     import ctypes
     import random
 
@@ -103,20 +105,25 @@ def test_sequence_marshalling_paths_agree():
 
     rng = random.Random(17)
     seqs = [bytes(rng.choice(b"ACGTN") for _ in range(rng.choice([0, 1, 5, 31, 32, 33, 150])))
-            for _ in range(500)]
+            for _ in range(m._SeqArray.SMALL + 300)]
 
     def contents(sa):
         ptrs = ctypes.cast(sa.ptrs, ctypes.POINTER(ctypes.c_void_p))
         return [ctypes.string_at(ptrs[i], int(sa.lens[i])) if int(sa.lens[i]) else b""
                 for i in range(sa.n)]
 
+    short = seqs[:500]
+    small = m._SeqArray(short, np.uint32)
+    assert type(small.keep[0]) is bytes and len(small.keep) == 2
     joined = m._SeqArray(seqs, np.uint32)
     assert isinstance(joined.keep[0], np.ndarray) and len(joined.keep) == 2
     itemwise = m._SeqArray([bytearray(s) for s in seqs], np.uint32)
     assert len(itemwise.keep) == len(seqs)
-    assert joined.n == itemwise.n == len(seqs)
+    assert joined.n == itemwise.n == len(seqs) and small.n == len(short)
     assert np.array_equal(joined.lens, itemwise.lens) and joined.lens.dtype == np.uint32
+    assert np.array_equal(small.lens, itemwise.lens[:500]) and small.lens.dtype == np.uint32
     assert contents(joined) == contents(itemwise) == seqs
+    assert contents(small) == short
     old = m._SeqArray.JOIN_BYTES
     try:
         m._SeqArray.JOIN_BYTES = 100       # force the fallback for the same list
