@@ -73,6 +73,11 @@ OPS_PER_WINDOW_STRAND_WORD = 5
 # (the banded operand's zeros included): K steps of 64 products x 2 per output.
 FLOPS_DENSE = {1: 2 * 32 * 4, 2: 2 * 32 * 3, 3: 2 * 32 * 3}
 FLOPS_ISSUED = {1: 3 * 64 * 2, 2: 2 * 64 * 2, 3: 2 * 64 * 2}
+# Three-class tiles that run the first K step alone (maxSubs 0 and alike)
+# test the window at shift r of a group on its first 16 - r bases, 12.5 on
+# average over the 8 shifts, and issue one K step.
+FLOPS_DENSE_HALF = 2 * 12.5 * 3
+FLOPS_ISSUED_HALF = 1 * 64 * 2
 
 
 def log(*a):
@@ -226,15 +231,16 @@ def op_model(gbpq_s):
             "efficiency": round(gbpq_s / bound, 4)}
 
 
-def roofline(ifa, st, sparse_strands, variant, traffic=False):
+def roofline(ifa, st, variant, traffic=False):
     """Roofline of the filter kernel (the dominant one), its average time per
     pass from HIP events on the stream it runs on (every filter launch of a
     pass lies between two events).
       * matrix-core filters (bound "mfma"): achieved = the dense-equivalent
         flops of the match-count contraction per window x strand
-        (FLOPS_DENSE, one prefix word) x the sparse strands x the window
-        starts evaluated (waves sent whole to the exact path are not
-        counted) / time; issued_frac counts the flops the instructions issue;
+        (FLOPS_DENSE, one prefix word; FLOPS_DENSE_HALF in half-step tiles)
+        x the (window start, filtered strand) pairs the passes evaluated
+        (waves sent whole to the exact path are not counted) / time;
+        issued_frac counts the flops the instructions issue;
       * VALU filter (bound "alu"): OPS_PER_WINDOW_STRAND_WORD ops per window
         x strand against the 32-bit vector peak;
       * hbm_frac: BYTES_PER_BASE x the bases the passes covered / time,
@@ -249,12 +255,17 @@ def roofline(ifa, st, sparse_strands, variant, traffic=False):
     enc = shape["encoding"]
     kernel = {0: "scan_filter_kernel", 1: "scan_filter_mfma_kernel",
               2: "scan_filter_mfma3_kernel", 3: "scan_filter_mfma3_kernel"}[enc]
-    ws = sparse_strands * st["filter_windows"]
+    # window x strand pairs the filter evaluated, over every pass (each pass
+    # with its own query set), and those of half-step tiles
+    ws = st["filter_strand_windows"]
+    ws_half = st["filter_half_strand_windows"]
     if enc in FLOPS_DENSE:
-        achieved = FLOPS_DENSE[enc] * ws / filter_s / 1e12 if filter_s else 0.0
+        flops = FLOPS_DENSE[enc] * (ws - ws_half) + FLOPS_DENSE_HALF * ws_half
+        flops_issued = FLOPS_ISSUED[enc] * (ws - ws_half) + FLOPS_ISSUED_HALF * ws_half
+        achieved = flops / filter_s / 1e12 if filter_s else 0.0
         peak = PEAK_FP4_FLOPS / 1e12
         bound, unit = "mfma", "TFLOP/s"
-        issued = FLOPS_ISSUED[enc] * ws / filter_s / 1e12 if filter_s else 0.0
+        issued = flops_issued / filter_s / 1e12 if filter_s else 0.0
     else:
         achieved = OPS_PER_WINDOW_STRAND_WORD * ws / filter_s / 1e12 if filter_s else 0.0
         peak = PEAK_VALU_INT32 / 1e12
@@ -270,8 +281,11 @@ def roofline(ifa, st, sparse_strands, variant, traffic=False):
         "traffic": None,
         "kernel": kernel,
         "per_unit": (f"{FLOPS_DENSE[enc]} flops per window x query strand (dense-equivalent "
-                     "match-count contraction over a 32-base prefix)") if enc in FLOPS_DENSE
+                     "match-count contraction over a 32-base prefix; "
+                     f"{FLOPS_DENSE_HALF:g} in half-step tiles, which test 16 - shift bases)")
+                    if enc in FLOPS_DENSE
                     else f"{OPS_PER_WINDOW_STRAND_WORD} ops per window x query strand",
+        "half_step_share": round(ws_half / ws, 4) if ws else 0.0,
         "issued_frac": round(issued / peak, 4) if issued is not None else None,
         "hbm_achieved_gbs": round(hbm / 1e9, 1),
         "hbm_frac": round(hbm / PEAK_HBM_BYTES, 4),
@@ -446,7 +460,7 @@ def run_c2(args):
     out["autotune"] = tune
     out["graph_launches"] = st["graph_launches"]
     # the committed traffic figure is for this workload at its default size
-    out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant,
+    out["roofline"] = roofline(ifa, st, variant,
                                traffic=not args.total and not args.queries)
 
     out["op_model"] = op_model(out["value"])
@@ -594,7 +608,7 @@ def run_c3(args):
     add_overhang(out, args, st)
     out["op_model"] = op_model(out["value"])
     # filter launches cover the sparse strands only; dense strands bypass it
-    out["roofline"] = roofline(ifa, st, n_sparse, variant)
+    out["roofline"] = roofline(ifa, st, variant)
     out["dense_roofline"] = dense_roofline(st, 2 * nq - n_sparse)
     s.close()
     return out
@@ -700,7 +714,7 @@ def run_c4(args):
     out["h2d_gb_s"] = round(st["bases"] * BYTES_PER_BASE / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
     out["device_footprint_bytes"] = {"before": foot0, "after": foot1}
     out["autotune"] = tune
-    out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant)
+    out["roofline"] = roofline(ifa, st, variant)
     s.close()
     return out
 
@@ -782,7 +796,7 @@ def run_c4_packed(args, spec, lens, gcs, qs, ks):
     out["h2d_gb_s"] = round(st["bases"] * BYTES_PER_BASE / max(st["h2d_ms"] * 1e-3, 1e-9) / 1e9, 3)
     out["device_footprint_bytes"] = {"before": foot0, "after": foot1}
     out["autotune"] = tune
-    out["roofline"] = roofline(ifa, st, ifa.ifa_sparse_count(s.ctx), variant)
+    out["roofline"] = roofline(ifa, st, variant)
     s.close()
     return out
 

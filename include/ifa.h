@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define IFA_ABI_VERSION 3u
+#define IFA_ABI_VERSION 4u
 /* Longest query: n_ref and the mismatch count of a window then fit the
  * record's fields (n_ref is one byte). */
 #define IFA_MAX_QUERY_LEN 255u
@@ -176,6 +176,12 @@ typedef struct {
                                 (IFA_FLAG_OVERHANG), HIP events on the compute stream */
     double dense_ms;         /* summed time of the dense-strand kernels (or, in
                                 indexed mode, the seed kernel), HIP events */
+    uint64_t filter_strand_windows;      /* sum over filter launches of the window
+                                            starts evaluated x the filtered strands */
+    uint64_t filter_half_strand_windows; /* of those, for strands in three-class tiles
+                                            that run the first K step alone (maxSubs 0
+                                            and similar: their windows tested on their
+                                            first 16 - shift bases) */
 } ifa_stats;
 
 /* Fill *cfg with the defaults: device 0, 2^30-base chunks, automatic hit

@@ -29,7 +29,7 @@ reported. Readings where the paper is silent (SAM v1.6 field meanings):
 from __future__ import annotations
 
 N_SEPARATE, N_AS_MISMATCH = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 _NORM = {ord(c): c for c in "ACGT"}
 _NORM.update({ord(c.lower()): c for c in "ACGT"})

@@ -29,7 +29,7 @@ __all__ = [
     "SamWriter", "Scanner", "Server", "collect_all",
 ]
 
-IFA_ABI_VERSION = 3
+IFA_ABI_VERSION = 4
 IFA_MAX_QUERY_LEN = 255
 IFA_N_SEPARATE, IFA_N_AS_MISMATCH = 0, 1
 IFA_SINK_RECORDS, IFA_SINK_COUNT_DIGEST = 0, 1
@@ -65,7 +65,8 @@ class IfaStats(ctypes.Structure):
                 ("filter_windows", ctypes.c_uint64), ("work_items", ctypes.c_uint64),
                 ("graph_launches", ctypes.c_uint64), ("graph_updates", ctypes.c_uint64),
                 ("edge_ms", ctypes.c_double),
-                ("dense_ms", ctypes.c_double)]
+                ("dense_ms", ctypes.c_double), ("filter_strand_windows", ctypes.c_uint64),
+                ("filter_half_strand_windows", ctypes.c_uint64)]
 
 
 class IfaIndexParams(ctypes.Structure):

@@ -239,6 +239,7 @@ struct Job {
     hipEvent_t kd = nullptr;                              // dense kernels start
     hipEvent_t ke = nullptr;                              // overhang kernel start
     hipEvent_t done = nullptr;              // hit count copied to the host
+    uint32_t n_half = 0;                    // filtered strands in half-step tiles
     bool active = false;
 };
 
@@ -294,6 +295,7 @@ struct ifa_ctx {
     const float *dq_dmt = nullptr;
     uint32_t mq3_words = 1;           // most prefix words of any three-class column tile
     uint32_t mq3_two_batches = 0;     // leading batches holding a two-word tile
+    uint32_t n_half_strands = 0;      // sparse strands in half-step three-class tiles
     uint32_t edge_pmin = 0;           // overhang kernel: pieces per wave (ScanArgs.edge_pmin)
     DevBuf<unsigned long long> d_qcount, d_qdigest;
     // indexed mode: parameters, MinHits cache, the query set's seeds and
@@ -798,9 +800,10 @@ uint32_t host_skip(const ifa_ctx *c, int hb)
 // Book the times of a finished pass over words [w0, w1) whose counters are
 // on the host. The filter evaluated every window start of the range except
 // those of the waves it handed to the resolve kernel.
-void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse, int hb, uint32_t w0,
+void add_pass_times(ifa_ctx *c, const PassEvents &ev, const Job &j, int hb, uint32_t w0,
                     uint32_t w1)
 {
+    const bool sparse = j.args.n_sparse > 0;
     c->st.kernel_ms += elapsed(ev.t0, ev.t2);
     c->st.kernel_launches++;
     if (c->cfg.flags & IFA_FLAG_OVERHANG) c->st.edge_ms += elapsed(ev.te, ev.t2);
@@ -812,7 +815,10 @@ void add_pass_times(ifa_ctx *c, const PassEvents &ev, bool sparse, int hb, uint3
         variant_shape(c->variant, &wpl, &qu, &wg, &enc);
         const uint64_t starts = 32ull * (w1 - w0);
         const uint64_t skipped = 64ull * wpl * host_skip(c, hb);
-        c->st.filter_windows += starts > skipped ? starts - skipped : 0;
+        const uint64_t evaluated = starts > skipped ? starts - skipped : 0;
+        c->st.filter_windows += evaluated;
+        c->st.filter_strand_windows += evaluated * j.args.n_sparse;
+        c->st.filter_half_strand_windows += evaluated * j.n_half;
         c->st.work_items += host_work(c, hb);
     }
 }
@@ -858,7 +864,7 @@ void settle_work_overflow(ifa_ctx *c, const Job &j, uint32_t w0, uint32_t w1)
         enqueue_pass(c, a, false, false, ev);
         enqueue_count_copies(c, hb);
         hip_check(hipStreamSynchronize(c->comp_s), "sync");
-        add_pass_times(c, ev, true, hb, w0, w1);
+        add_pass_times(c, ev, j, hb, w0, w1);
         ev.destroy();
         c->st.rescans++;
     }
@@ -878,7 +884,7 @@ void rescan_range(ifa_ctx *c, const Job &j, uint32_t w0, uint32_t w1)
     enqueue_pass(c, a, true, true, ev);
     enqueue_count_copies(c, hb);
     hip_check(hipStreamSynchronize(c->comp_s), "sync");
-    add_pass_times(c, ev, a.n_sparse > 0, hb, w0, w1);
+    add_pass_times(c, ev, j, hb, w0, w1);
     ev.destroy();
     c->st.rescans++;
     settle_work_overflow(c, j, w0, w1);
@@ -911,7 +917,7 @@ void retire(ifa_ctx *c, Job &j)
     ev.te = j.ke;
     ev.t2 = j.k1;
     const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
-    add_pass_times(c, ev, j.args.n_sparse > 0, j.hitbuf, 0, words);
+    add_pass_times(c, ev, j, j.hitbuf, 0, words);
     settle_work_overflow(c, j, 0, words);
     if (c->cfg.sink == IFA_SINK_RECORDS) {
         uint64_t n = host_hits(c, j.hitbuf);
@@ -944,6 +950,11 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     ensure_work_list(c, j.hitbuf);
     ScanArgs a = make_args(c, *ch, j.hitbuf);
     j.args = a;
+    {
+        uint32_t wpl, qu, wg, enc;
+        variant_shape(c->variant, &wpl, &qu, &wg, &enc);
+        j.n_half = enc == 2 || enc == 3 ? c->n_half_strands : 0u;
+    }
     if (!j.k0) hip_check(hipEventCreate(&j.k0), "event");
     if (!j.kf) hip_check(hipEventCreate(&j.kf), "event");
     if (!j.k1) hip_check(hipEventCreate(&j.k1), "event");
@@ -1284,6 +1295,37 @@ void pack_query_strands(uint32_t strands, uint32_t n, const uint8_t *const *seq,
 // descending (the kernels mask their cached slices in place as L drops),
 // then by k. n_queries sizes the
 // count+digest accumulators, which this resets.
+// The first K step of a one-word three-class tile holds the 8-base blocks 0
+// and 1 of each group's segment in all three classes (and block 2 in two),
+// so on its own it tests the window at shift r (0..7) of a group on the
+// strand's first min(L, 16 - r) bases. A tile whose strands all pass a
+// 1024-window wave that way less than kHalfWaveRate of the time runs that
+// step alone (half the matrix work; maxSubs 0 qualifies from L = 16 on).
+constexpr double kHalfWaveRate = 1.0 / 1024.0;
+
+// Mean over the 8 shifts of P(a random window passes the half-step filter).
+double half_step_rate(const QSDesc &d)
+{
+    const uint32_t lf = std::min<uint32_t>(d.len, 32u);
+    double p = 0.0;
+    for (uint32_t r = 0; r < 8; r++) p += binom_cdf(std::min<uint32_t>(lf, 16u - r), 0.75, d.thr);
+    return p / 8.0;
+}
+
+bool half_step_ok(const QSDesc &d, uint8_t fw)
+{
+    return fw == 1 && half_step_rate(d) * 1024.0 < kHalfWaveRate;
+}
+
+// P(a random window passes the strand's filter): on its first
+// min(L, 32 fw) bases, or the half step.
+double window_pass_rate(const QSDesc &d, uint8_t fw, bool half)
+{
+    if (half) return half_step_rate(d);
+    const uint32_t lf = std::min<uint32_t>(d.len, 32u * std::max<uint32_t>(fw, 1u));
+    return binom_cdf(lf, 0.75, d.thr);
+}
+
 // Expected work items the filter emits per chunk of chunk_bases uniform
 // random bases, for sparse strands qs[0, n_sparse): an item is one (wave,
 // batch of 32 strands) with a candidate among the wave's windows (64 lanes x
@@ -1297,8 +1339,7 @@ uint64_t expected_work_items(const std::vector<QSDesc> &qs, const std::vector<ui
     for (uint32_t b = 0; b < n_sparse; b += 32) {
         double log_none = 0.0;
         for (uint32_t s = b; s < std::min<uint32_t>(n_sparse, b + 32); s++) {
-            const uint32_t lf = std::min<uint32_t>(qs[s].len, 32u * std::max<uint32_t>(fw[s], 1u));
-            const double p = binom_cdf(lf, 0.75, qs[s].thr);
+            const double p = window_pass_rate(qs[s], fw[s], half_step_ok(qs[s], fw[s]));
             log_none += 1024.0 * std::log1p(-std::min(p, 1.0 - 1e-12));
         }
         items += waves * -std::expm1(log_none);
@@ -1349,15 +1390,17 @@ constexpr uint32_t kFilterWords = 2;
 
 // Operands of the three-class matrix-core filter: tile nt holds strands
 // 4nt .. 4nt+3, column c = 8 (strand - 4nt) + shift r, and filters on the
-// first Lf = min(L, 32 W) bases of each, W = words[nt] = the most prefix words
-// (filter_words) any of its strands needs. For word w < W, lane l (column
-// l % 32, half h = l / 32), K step t, register d the slot is z = 8h + 4t + d:
-// segment block k = z / 3 and class z % 3 (C, G, T; codes 1, 3, 2); nibble o
-// is segment base i = 8k + o and query base j = 32w + i - r. The value is
-// +1.0 (e2m1 code 2) when 32w <= j < min(32(w + 1), Lf) and the query base
-// there has the slot's class, -1.0 (code 0xA) when it is A, else 0; slot 15
-// stays 0. Layout: b[(((2 nt + w) * 2 + t) * 64 + lane) * 4 + d] (word 1 is
-// zero when W = 1). need[c] = Lf - thr - nA, nA = A bases among the first Lf.
+// first Lf = min(L, 32 W) bases of each, W = words[nt] & 0xff = the most
+// prefix words (filter_words) any of its strands needs; a half-step tile
+// (words[nt] & kHalfTile) on the first Lt = min(Lf, 16 - r) only, else Lt =
+// Lf. For word w < W, lane l (column l % 32, half h = l / 32), K step t,
+// register d the slot is z = 8t + 4h + d: segment block k = z / 3 and class
+// z % 3 (C, G, T; codes 1, 3, 2); nibble o is segment base i = 8k + o and
+// query base j = 32w + i - r. The value is +1.0 (e2m1 code 2) when 32w <= j <
+// min(32(w + 1), Lt) and the query base there has the slot's class, -1.0
+// (code 0xA) when it is A, else 0; slot 15 stays 0. Layout:
+// b[(((2 nt + w) * 2 + t) * 64 + lane) * 4 + d] (word 1 is zero when W = 1).
+// need[c] = Lt - thr - nA, nA = A bases among the first Lt.
 // Prefix words of each three-class column tile: the most any of its strands needs.
 void mfma3_tile_words(const std::vector<uint8_t> &fw, uint32_t n_sparse,
                       std::vector<uint32_t> &words)
@@ -1367,6 +1410,23 @@ void mfma3_tile_words(const std::vector<uint8_t> &fw, uint32_t n_sparse,
     for (uint32_t nt = 0; nt < n_tiles; nt++)
         for (uint32_t s = 4 * nt; s < std::min(n_sparse, 4 * nt + 4); s++)
             words[nt] = std::max<uint32_t>(words[nt], fw[s]);
+}
+
+// Per three-class column tile of the sparse strands: the prefix words it
+// filters on, plus kHalfTile when every strand of the tile qualifies for the
+// half step (see half_step_ok).
+constexpr uint32_t kHalfTile = 0x100u;
+
+void mfma3_tile_meta(const std::vector<QSDesc> &qs, const std::vector<uint8_t> &fw,
+                     uint32_t n_sparse, std::vector<uint32_t> &meta)
+{
+    mfma3_tile_words(fw, n_sparse, meta);
+    for (uint32_t nt = 0; nt < meta.size(); nt++) {
+        bool half = meta[nt] == 1u;
+        for (uint32_t s = 4 * nt; half && s < std::min(n_sparse, 4 * nt + 4); s++)
+            half = half_step_ok(qs[s], fw[s]);
+        if (half) meta[nt] |= kHalfTile;
+    }
 }
 
 void build_mfma3_operands(const std::vector<QSDesc> &qs, const std::vector<uint32_t> &qw,
@@ -1385,7 +1445,12 @@ void build_mfma3_operands(const std::vector<QSDesc> &qs, const std::vector<uint3
             const uint32_t s = 4 * nt + c / 8, r = c % 8;
             if (s >= n_sparse) continue;
             const QSDesc &d = qs[s];
-            const uint32_t lf = std::min<uint32_t>(d.len, 32u * words[nt]);
+            const bool half = (words[nt] & kHalfTile) != 0u;
+            const uint32_t nw = words[nt] & 0xffu;
+            const uint32_t lf = std::min<uint32_t>(d.len, 32u * nw);
+            // bases the column tests: a half-step column at shift r only its
+            // first min(lf, 16 - r)
+            const uint32_t lt = half ? std::min<uint32_t>(lf, 16u - r) : lf;
             // the strand's bases 0 .. lf-1 (lf <= 64) from its packed words
             uint8_t code[64], isn[64];
             for (uint32_t j = 0; j < lf; j++) {
@@ -1397,20 +1462,22 @@ void build_mfma3_operands(const std::vector<QSDesc> &qs, const std::vector<uint3
                 isn[j] = (uint8_t)((qn >> bit) & 1u);
             }
             uint32_t n_a = 0;
-            for (uint32_t j = 0; j < lf; j++)
+            for (uint32_t j = 0; j < lt; j++)
                 if (!isn[j] && code[j] == 0u) n_a++;
-            need[32 * nt + c] = (float)lf - (float)d.thr - (float)n_a;
-            for (uint32_t w = 0; w < words[nt]; w++)
+            need[32 * nt + c] = (float)lt - (float)d.thr - (float)n_a;
+            for (uint32_t w = 0; w < nw; w++)
                 for (uint32_t h = 0; h < 2; h++)
                     for (uint32_t t = 0; t < 2; t++)
                         for (uint32_t dd = 0; dd < 4; dd++) {
-                            const uint32_t z = 8 * h + 4 * t + dd;
+                            // K step t holds slots 8t .. 8t + 7, lane half h
+                            // four of them
+                            const uint32_t z = 8 * t + 4 * h + dd;
                             if (z >= 15) continue;
                             const uint32_t k = z / 3, cls = kClass[z % 3];
                             uint32_t word = 0;
                             for (uint32_t o = 0; o < 8; o++) {
                                 const int32_t j = (int32_t)(32 * w + 8 * k + o) - (int32_t)r;
-                                if (j < (int32_t)(32 * w) || j >= (int32_t)std::min(32 * w + 32, lf))
+                                if (j < (int32_t)(32 * w) || j >= (int32_t)std::min(32 * w + 32, lt))
                                     continue;
                                 if (isn[j]) continue;
                                 if (code[j] == cls) word |= 0x2u << (4 * o);
@@ -1506,7 +1573,7 @@ FilterOperands build_filter_operands(const ifa_ctx *c)
         build_mfma_operands(c->h_qs, c->n_sparse, op.b, op.need, c->threads);
     } else {
         std::vector<uint32_t> mw3;
-        mfma3_tile_words(c->h_fw, c->n_sparse, mw3);
+        mfma3_tile_meta(c->h_qs, c->h_fw, c->n_sparse, mw3);
         build_mfma3_operands(c->h_qs, c->h_qwords, mw3, c->n_sparse, op.b, op.need, c->threads);
         if (dense) {
             // the dense strands of at most 32 bases: one-word tiles, their
@@ -1603,13 +1670,17 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     qs.swap(sorted);
     std::vector<uint32_t> mw3;
     const bool indexed = c->indexed;
-    if (!indexed) mfma3_tile_words(sorted_fw, n_sparse, mw3);
-    c->mq3_words = mw3.empty() ? 1u : *std::max_element(mw3.begin(), mw3.end());
+    if (!indexed) mfma3_tile_meta(qs, sorted_fw, n_sparse, mw3);
+    c->mq3_words = 1;
+    for (uint32_t m : mw3) c->mq3_words = std::max(c->mq3_words, m & 0xffu);
     // the tiles filtering on two words lead the list: their batches of 32
     // strands (8 tiles) run the two-word kernel, the others the one-word one
     uint32_t two_tiles = 0;
-    while (two_tiles < mw3.size() && mw3[two_tiles] == 2u) two_tiles++;
+    while (two_tiles < mw3.size() && (mw3[two_tiles] & 0xffu) == 2u) two_tiles++;
     c->mq3_two_batches = (two_tiles + 7u) / 8u;
+    c->n_half_strands = 0;
+    for (uint32_t nt = 0; nt < mw3.size(); nt++)
+        if (mw3[nt] & kHalfTile) c->n_half_strands += std::min<uint32_t>(4u, n_sparse - 4u * nt);
     // overhang kernel packing: 2 C window slots per piece and strand, C =
     // min(maxN, L - 1); the widest clip sets the pieces per wave of the grid
     uint32_t cmax = 0;

@@ -402,7 +402,7 @@ __device__ __forceinline__ bool filter_cand_words(const ScanArgs &a, const QS &d
 // three-class matrix column tile; 1 for dense strands.
 __device__ __forceinline__ uint32_t strand_filter_words(const ScanArgs &a, uint32_t q)
 {
-    return q < a.n_sparse ? a.mq3_w[q >> 2] : 1u;
+    return q < a.n_sparse ? a.mq3_w[q >> 2] & 0xffu : 1u;
 }
 
 // Lane state of filter-grid lane `gl` (relative to w_begin).
@@ -750,12 +750,14 @@ static uint32_t mq_lds_bytes(uint32_t tiles)
 // Tile: 32 groups x 8 windows = 256 window starts; four tiles per filter wave.
 // Column tile: 4 strands x 8 shifts. K layout: the segment's 8-base blocks
 // k = 0..4 each give three indicator words (class C, G, T; nibble o = base
-// 8k + o, e2m1 1.0 or 0); slot z = 8h + 4t + d (K step t, lane half h,
+// 8k + o, e2m1 1.0 or 0); slot z = 8t + 4h + d (K step t, lane half h,
 // register d) holds block z / 3, class z % 3; slot 15 meets only zero B
-// entries. A wave first writes the indicator words of its stream (m3_blocks
-// blocks of 8 bases, three words each) to its own LDS area, where the slots
-// of lane (g, h) in tile u are the 8 consecutive words from 3 (32u + g) + 8h.
-// mq3_t holds the match count minus nA that a column needs.
+// entries. K step 0 thus holds blocks 0 and 1 in every class: a half-step
+// tile (flag 0x100 in mq3_w) runs it alone and tests the window at shift r
+// on its first 16 - r bases. A wave first writes the indicator words of its
+// stream (m3_blocks blocks of 8 bases, three words each) to its own LDS
+// area; the slots of lane (g, h) in tile u are words 3 (32u + g) + 4h + 8t
+// + d. mq3_t holds the match count minus nA that a column needs.
 // ---------------------------------------------------------------------------
 
 // 8-base blocks a wave stages: its 1024 windows read up to base
@@ -848,11 +850,11 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
         for (int w = 0; w < NW; w++)
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                const uint32_t *f = flat + 3u * (32u * u + g + 4u * w) + 8u * h;
+                const uint32_t *f = flat + 3u * (32u * u + g + 4u * w) + 4u * h;
 #pragma unroll
                 for (int t = 0; t < 2; t++)
-                    A[w][u][t] = ifa_v8i{(int)f[4 * t], (int)f[4 * t + 1], (int)f[4 * t + 2],
-                                         (int)f[4 * t + 3], 0, 0, 0, 0};
+                    A[w][u][t] = ifa_v8i{(int)f[8 * t], (int)f[8 * t + 1], (int)f[8 * t + 2],
+                                         (int)f[8 * t + 3], 0, 0, 0, 0};
             }
         uint32_t pending = 0;   // wave-uniform
         for (uint32_t nt = 0; nt < tn; nt++) {
@@ -860,7 +862,11 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
             const ifa_v8i B0 = {(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, 0, 0, 0, 0};
             const ifa_v8i B1 = {(int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w, 0, 0, 0, 0};
             ifa_v8i B2 = {}, B3 = {};
-            const bool two = NW == 2 && __builtin_amdgcn_readfirstlane(sw[nt]) == 2u;
+            const uint32_t meta = __builtin_amdgcn_readfirstlane(sw[nt]);
+            const bool two = NW == 2 && (meta & 0xffu) == 2u;
+            // half-step tile: the first K step alone (the windows' first
+            // 16 - shift bases)
+            const bool half = (meta >> 8) != 0u;
             if (two) {
                 const uint4 v2 = sb[(4u * nt + 2u) * 64u + l], v3 = sb[(4u * nt + 3u) * 64u + l];
                 B2 = ifa_v8i{(int)v2.x, (int)v2.y, (int)v2.z, (int)v2.w, 0, 0, 0, 0};
@@ -872,8 +878,10 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
             for (int p = 0; p < 2; p++) {
                 ifa_v16f d0 = mfma_fp4(A[0][2 * p][0], B0, zero);
                 ifa_v16f d1 = mfma_fp4(A[0][2 * p + 1][0], B0, zero);
-                d0 = mfma_fp4(A[0][2 * p][1], B1, d0);
-                d1 = mfma_fp4(A[0][2 * p + 1][1], B1, d1);
+                if (!half) {
+                    d0 = mfma_fp4(A[0][2 * p][1], B1, d0);
+                    d1 = mfma_fp4(A[0][2 * p + 1][1], B1, d1);
+                }
                 if (two) {
                     d0 = mfma_fp4(A[NW - 1][2 * p][0], B2, d0);
                     d1 = mfma_fp4(A[NW - 1][2 * p + 1][0], B2, d1);
@@ -1026,11 +1034,11 @@ __global__ __launch_bounds__(WG) void scan_dense_mfma3_kernel(ScanArgs a)
             ifa_v8i A[2][2];
 #pragma unroll
             for (int uu = 0; uu < 2; uu++) {
-                const uint32_t *f = flat + 3u * (32u * (2 * p + uu) + g) + 8u * h;
+                const uint32_t *f = flat + 3u * (32u * (2 * p + uu) + g) + 4u * h;
 #pragma unroll
                 for (int t = 0; t < 2; t++)
-                    A[uu][t] = ifa_v8i{(int)f[4 * t], (int)f[4 * t + 1], (int)f[4 * t + 2],
-                                       (int)f[4 * t + 3], 0, 0, 0, 0};
+                    A[uu][t] = ifa_v8i{(int)f[8 * t], (int)f[8 * t + 1], (int)f[8 * t + 2],
+                                       (int)f[8 * t + 3], 0, 0, 0, 0};
             }
             ifa_v16f d0 = mfma_fp4(A[0][0], B0, zero);
             ifa_v16f d1 = mfma_fp4(A[1][0], B0, zero);

@@ -854,3 +854,56 @@ def test_variant_chosen_after_loading_builds_its_operands(ifa, orc):
             got = s.collect()
             got["contig"] -= first
             assert_same(got, want, f"variant {v} chosen after loading")
+
+
+@pytest.mark.parametrize("sink", [0, 1])
+def test_half_step_tiles_for_exact_match_queries(ifa, orc, sink):
+    """Column tiles whose strands all have maxSubs 0 (and enough length) run
+    the first K step of the three-class contraction alone, testing the
+    window at shift r of each 8-window group on its first 16 - r bases.
+    Planted exact copies at every shift and around wave and chunk edges, N
+    runs, queries with an N, and sets mixing maxSubs 0 with maxSubs 1-2 (so
+    that some tiles run half and others both steps) must equal the oracle
+    for every three-class variant."""
+    rng = random.Random(1616)
+    lens = [16, 17, 20, 24, 31, 32, 33, 40, 48, 64]
+    qs = [rand_dna(rng, L) for L in lens for _ in range(2)]
+    qs.append(rand_dna(rng, 30)[:12] + b"N" + rand_dna(rng, 17))
+    contigs = []
+    for i in range(8):
+        n = rng.choice([3000, 40_000, 70_000])
+        c = bytearray(rand_dna(rng, n))
+        for _ in range(rng.randint(0, 2)):
+            p, r = rng.randrange(0, n - 300), rng.randint(1, 200)
+            c[p:p + r] = b"N" * r
+        # exact copies (or reverse complements) at every offset mod 8 and
+        # around 1024-base wave edges
+        for j in range(12):
+            q = qs[rng.randrange(len(qs))]
+            if rng.random() < 0.5:
+                q = q.translate(COMP)[::-1]
+            p = rng.choice([1024 * rng.randrange(1, n // 1024 or 2) - rng.randrange(0, 40),
+                            rng.randrange(0, n - len(q))])
+            p = max(0, min(p, n - len(q)))
+            c[p:p + len(q)] = q
+        contigs.append(bytes(c))
+    sets = {"all maxSubs 0": [0] * len(qs),
+            "mixed": [rng.choice([0, 0, 0, 1, 2]) for _ in qs]}
+    vs = [v for v in range(ifa.ifa_variant_count()) if ifa.ifa_variant_info(v)["encoding"] >= 2]
+    for name, ks in sets.items():
+        if sink == 0:
+            want = orc.scan(qs, contigs, ks)
+        else:
+            _, cnt, dig = orc.scan(qs, contigs, ks, stats=True, records=False)
+        for v in vs:
+            say(f"half-step tiles: {name}, variant {v}, sink {sink}")
+            with ifa.Scanner(chunk_bases=1 << 16, sink=sink) as s:
+                ifa.ifa_set_variant(s.ctx, v)
+                s.load_queries(qs, ks)
+                s.scan_chunk(contigs)
+                if sink == 0:
+                    assert_same(s.collect(), want, f"{name} variant {v}")
+                else:
+                    gc, gd = s.query_stats()
+                    assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), \
+                        f"{name} variant {v} stats"
