@@ -163,7 +163,8 @@ typedef struct {
     double h2d_ms;           /* summed host-to-device copy time of chunks */
     double pack_ms;          /* host wall time spent packing contigs */
     double filter_ms;        /* summed time of the filter kernel alone (the hot
-                                loop), HIP events on the compute stream */
+                                loop) over the timed passes (timed_filter_passes),
+                                HIP events on the compute stream */
     uint64_t filter_launches;/* filter kernel launches */
     uint64_t filter_windows; /* window starts the filter kernel evaluated (those of
                                 waves holding a reference N are passed whole to the
@@ -173,15 +174,22 @@ typedef struct {
     uint64_t graph_updates;  /* of those, replays whose kernel arguments were updated
                                 first (another streamed chunk or query set) */
     double edge_ms;          /* summed time of the overhanging-window kernel
-                                (IFA_FLAG_OVERHANG), HIP events on the compute stream */
+                                (IFA_FLAG_OVERHANG) over the timed passes, HIP events */
     double dense_ms;         /* summed time of the dense-strand kernels (or, in
-                                indexed mode, the seed kernel), HIP events */
+                                indexed mode, the seed kernel) over the timed passes,
+                                HIP events */
     uint64_t filter_strand_windows;      /* sum over filter launches of the window
                                             starts evaluated x the filtered strands */
     uint64_t filter_half_strand_windows; /* of those, for strands in three-class tiles
                                             that run the first K step alone (maxSubs 0
                                             and similar: their windows tested on their
                                             first 16 - shift bases) */
+    uint64_t timed_passes;   /* passes whose kernels were timed one by one: those
+                                launched eagerly (a pass replayed from a captured graph
+                                is timed as a whole, in kernel_ms, by events around the
+                                graph launch; events recorded inside a graph misreport
+                                the time of the kernels between them) */
+    uint64_t timed_filter_passes; /* of those, passes with a filter launch */
 } ifa_stats;
 
 /* Fill *cfg with the defaults: device 0, 2^30-base chunks, automatic hit
@@ -316,6 +324,13 @@ ifa_status ifa_ref_info(const ifa_ctx *ctx, uint64_t *bases, uint32_t *chunks);
 
 /* Counters (see ifa_stats). ifa_get_stats waits for submitted work first. */
 ifa_status ifa_get_stats(ifa_ctx *ctx, ifa_stats *out);
+
+/* Turn the capture and replay of scan passes as HIP graphs (IFA_FLAG_GRAPHS)
+ * on (enable != 0) or off for the context's later scans; graphs captured so
+ * far are kept. With it off every pass is launched eagerly and its kernels
+ * are timed one by one in the statistics. Waits for submitted work first.
+ * Errors: IFA_E_INVALID (ctx NULL). */
+ifa_status ifa_set_graphs(ifa_ctx *ctx, int enable);
 ifa_status ifa_reset_stats(ifa_ctx *ctx);
 
 /* Query strands of the loaded set (*n_strands) and how many of them take the

@@ -66,7 +66,8 @@ class IfaStats(ctypes.Structure):
                 ("graph_launches", ctypes.c_uint64), ("graph_updates", ctypes.c_uint64),
                 ("edge_ms", ctypes.c_double),
                 ("dense_ms", ctypes.c_double), ("filter_strand_windows", ctypes.c_uint64),
-                ("filter_half_strand_windows", ctypes.c_uint64)]
+                ("filter_half_strand_windows", ctypes.c_uint64),
+                ("timed_passes", ctypes.c_uint64), ("timed_filter_passes", ctypes.c_uint64)]
 
 
 class IfaIndexParams(ctypes.Structure):
@@ -149,6 +150,8 @@ def lib():
         L.ifa_get_stats.restype = st
         L.ifa_reset_stats.argtypes = [vp]
         L.ifa_reset_stats.restype = st
+        L.ifa_set_graphs.argtypes = [vp, ctypes.c_int]
+        L.ifa_set_graphs.restype = st
         L.ifa_variant_count.argtypes = []
         L.ifa_variant_count.restype = u32
         L.ifa_variant_info.argtypes = [u32, ctypes.POINTER(u32), ctypes.POINTER(u32),
@@ -403,6 +406,10 @@ def ifa_get_stats(ctx) -> dict:
 
 def ifa_reset_stats(ctx):
     _check(ctx, lib().ifa_reset_stats(ctx))
+
+
+def ifa_set_graphs(ctx, enable: bool):
+    _check(ctx, lib().ifa_set_graphs(ctx, 1 if enable else 0))
 
 
 def ifa_variant_count() -> int:

@@ -240,6 +240,7 @@ struct Job {
     hipEvent_t ke = nullptr;                              // overhang kernel start
     hipEvent_t done = nullptr;              // hit count copied to the host
     uint32_t n_half = 0;                    // filtered strands in half-step tiles
+    bool split_timed = false;               // kf, kd, ke recorded (eager launches)
     bool active = false;
 };
 
@@ -801,15 +802,21 @@ uint32_t host_skip(const ifa_ctx *c, int hb)
 // on the host. The filter evaluated every window start of the range except
 // those of the waves it handed to the resolve kernel.
 void add_pass_times(ifa_ctx *c, const PassEvents &ev, const Job &j, int hb, uint32_t w0,
-                    uint32_t w1)
+                    uint32_t w1, bool split_timed)
 {
     const bool sparse = j.args.n_sparse > 0;
     c->st.kernel_ms += elapsed(ev.t0, ev.t2);
     c->st.kernel_launches++;
-    if (c->cfg.flags & IFA_FLAG_OVERHANG) c->st.edge_ms += elapsed(ev.te, ev.t2);
-    c->st.dense_ms += elapsed(ev.td, ev.te);
+    if (split_timed) {
+        c->st.timed_passes++;
+        if (c->cfg.flags & IFA_FLAG_OVERHANG) c->st.edge_ms += elapsed(ev.te, ev.t2);
+        c->st.dense_ms += elapsed(ev.td, ev.te);
+        if (sparse) {
+            c->st.filter_ms += elapsed(ev.t0, ev.t1);
+            c->st.timed_filter_passes++;
+        }
+    }
     if (sparse) {
-        c->st.filter_ms += elapsed(ev.t0, ev.t1);
         c->st.filter_launches++;
         uint32_t wpl, qu, wg, enc;
         variant_shape(c->variant, &wpl, &qu, &wg, &enc);
@@ -864,7 +871,7 @@ void settle_work_overflow(ifa_ctx *c, const Job &j, uint32_t w0, uint32_t w1)
         enqueue_pass(c, a, false, false, ev);
         enqueue_count_copies(c, hb);
         hip_check(hipStreamSynchronize(c->comp_s), "sync");
-        add_pass_times(c, ev, j, hb, w0, w1);
+        add_pass_times(c, ev, j, hb, w0, w1, true);
         ev.destroy();
         c->st.rescans++;
     }
@@ -884,7 +891,7 @@ void rescan_range(ifa_ctx *c, const Job &j, uint32_t w0, uint32_t w1)
     enqueue_pass(c, a, true, true, ev);
     enqueue_count_copies(c, hb);
     hip_check(hipStreamSynchronize(c->comp_s), "sync");
-    add_pass_times(c, ev, j, hb, w0, w1);
+    add_pass_times(c, ev, j, hb, w0, w1, true);
     ev.destroy();
     c->st.rescans++;
     settle_work_overflow(c, j, w0, w1);
@@ -917,7 +924,7 @@ void retire(ifa_ctx *c, Job &j)
     ev.te = j.ke;
     ev.t2 = j.k1;
     const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
-    add_pass_times(c, ev, j, j.hitbuf, 0, words);
+    add_pass_times(c, ev, j, j.hitbuf, 0, words, j.split_timed);
     settle_work_overflow(c, j, 0, words);
     if (c->cfg.sink == IFA_SINK_RECORDS) {
         uint64_t n = host_hits(c, j.hitbuf);
@@ -967,12 +974,16 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     ev.td = j.kd;
     ev.te = j.ke;
     ev.t2 = j.k1;
-    // the pass and its counter copy (what a graph holds); the events the host
-    // waits on are recorded on the stream after it, never inside a graph: a
-    // host wait on an event recorded by a graph node has returned before a
-    // replay finished
-    auto enqueue = [&]() {
-        enqueue_pass(c, a, true, true, ev);
+    // the pass and its counter copy (what a graph holds). No event is
+    // recorded inside a graph: a host wait on an event recorded by a graph
+    // node has returned before a replay finished, and timing events recorded
+    // by graph nodes read 10-15 % longer than the kernels between them
+    // (against rocprofv3's kernel trace and the step's own wall time). A
+    // replayed pass is timed as a whole by events around the graph launch;
+    // its kernels are timed one by one only when launched eagerly.
+    PassEvents none;
+    auto enqueue = [&](PassEvents &e) {
+        enqueue_pass(c, a, true, true, e);
         enqueue_count_copies(c, j.hitbuf);
     };
     PassGraph *pg = nullptr;
@@ -993,7 +1004,7 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
         if (!pg->exec) {
             hip_check(hipStreamBeginCapture(c->comp_s, hipStreamCaptureModeRelaxed),
                       "begin capture");
-            enqueue();
+            enqueue(none);
             hip_check(hipStreamEndCapture(c->comp_s, &pg->graph), "end capture");
             hip_check(hipGraphInstantiate(&pg->exec, pg->graph, nullptr, nullptr, 0),
                       "instantiate pass graph");
@@ -1020,10 +1031,14 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
             pg->plan = plan;
             c->st.graph_updates++;
         }
+        hip_check(hipEventRecord(j.k0, c->comp_s), "event record");
         hip_check(hipGraphLaunch(pg->exec, c->comp_s), "launch pass graph");
+        hip_check(hipEventRecord(j.k1, c->comp_s), "event record");
         c->st.graph_launches++;
+        j.split_timed = false;
     } else {
-        enqueue();
+        enqueue(ev);
+        j.split_timed = true;
     }
     // a streamed chunk's slot may be refilled once this pass is done (the
     // copy stream waits for free_ev); resident chunks are never refilled
@@ -2358,6 +2373,17 @@ ifa_status ifa_get_stats(ifa_ctx *c, ifa_stats *out)
         use_device(c);
         retire_all(c);
         *out = c->st;
+    });
+}
+
+ifa_status ifa_set_graphs(ifa_ctx *c, int enable)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        use_device(c);
+        retire_all(c);
+        if (enable) c->cfg.flags |= IFA_FLAG_GRAPHS;
+        else c->cfg.flags &= ~IFA_FLAG_GRAPHS;
     });
 }
 

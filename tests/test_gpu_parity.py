@@ -907,3 +907,39 @@ def test_half_step_tiles_for_exact_match_queries(ifa, orc, sink):
                     gc, gd = s.query_stats()
                     assert np.array_equal(gc, cnt) and np.array_equal(gd, dig), \
                         f"{name} variant {v} stats"
+
+
+def test_graphs_switched_off_and_on_time_every_eager_pass(ifa, orc):
+    """Replayed passes are timed as a whole; turning graph capture off makes
+    every later pass eager, with its kernels timed one by one, and on again
+    resumes the replays. Results stay those of the oracle throughout."""
+    import synth
+    spec = synth.c2_spec(seed=77, total=2_000_000)
+    ref = synth.gen_reference(spec)
+    rng = random.Random(77)
+    qs = [rand_dna(rng, rng.choice([28, 32, 36])) for _ in range(6)]
+    ks = [rng.randint(0, 4) for _ in qs]
+    want = orc.scan(qs, ref, ks)
+    with ifa.Scanner(chunk_bases=1 << 20) as s:
+        s.ref_load(ref)
+        s.load_queries(qs, ks)
+        _, chunks = ifa.ifa_ref_info(s.ctx)
+        for i in range(3):
+            s.scan_resident()
+            assert_same(s.collect(), want, f"graph pass {i}")
+        st = s.stats()
+        assert st["graph_launches"] > 0
+        assert st["timed_passes"] == st["kernel_launches"] - st["graph_launches"]
+        ifa.ifa_set_graphs(s.ctx, False)
+        ifa.ifa_reset_stats(s.ctx)
+        for i in range(2):
+            s.scan_resident()
+            assert_same(s.collect(), want, f"eager pass {i}")
+        st = s.stats()
+        assert st["graph_launches"] == 0 and st["timed_passes"] == st["kernel_launches"] == 2 * chunks
+        assert st["timed_filter_passes"] == 2 * chunks and st["filter_ms"] > 0
+        ifa.ifa_set_graphs(s.ctx, True)
+        ifa.ifa_reset_stats(s.ctx)
+        s.scan_resident()
+        assert_same(s.collect(), want, "graphs on again")
+        assert s.stats()["graph_launches"] > 0
