@@ -314,17 +314,21 @@ def roofline(ifa, st, variant, traffic=False, st_k=None):
     return out
 
 
-def dense_roofline(st, dense_strands):
+def dense_roofline(st, dense_strands, matrix=False):
     """The dense-strand kernels: OPS_PER_WINDOW_STRAND_WORD ops per window x
     strand (one 32-base word) over their time, against the 32-bit VALU peak;
-    st's timed passes only (pass kernel_timing's statistics)."""
+    st's timed passes only (pass kernel_timing's statistics). With `matrix`
+    (a variant that counts the low-hit-rate strands of at most 32 bases on
+    the matrix cores) the time covers both kinds of dense kernel, and the
+    rate is the VALU operation model's equivalent."""
     ms = st["dense_ms"]
     timed = max(1, st["timed_passes"])
     bases = st["bases"] * timed / max(1, st["kernel_launches"])
     ach = OPS_PER_WINDOW_STRAND_WORD * bases * dense_strands / (ms * 1e-3) if ms else 0.0
     return {"bound": "alu", "achieved": round(ach / 1e12, 3),
             "peak": round(PEAK_VALU_INT32 / 1e12, 3), "unit": "TOP/s",
-            "frac": round(ach / PEAK_VALU_INT32, 4), "kernel": "scan_dense_kernel",
+            "frac": round(ach / PEAK_VALU_INT32, 4),
+            "kernel": "scan_dense_kernel + scan_dense_mfma3_kernel" if matrix else "scan_dense_kernel",
             "ms_per_pass": round(ms / timed, 3)}
 
 
@@ -646,7 +650,8 @@ def run_c3(args):
     out["filter_ms_per_pass"] = round(tk["filter_ms"] / max(1, tk["timed_filter_passes"]), 3)
     out["dense_ms_per_pass"] = round(tk["dense_ms"] / max(1, tk["timed_passes"]), 3)
     out["roofline"] = roofline(ifa, st, variant, st_k=st_k)
-    out["dense_roofline"] = dense_roofline(tk, 2 * nq - n_sparse)
+    out["dense_roofline"] = dense_roofline(tk, 2 * nq - n_sparse,
+                                           matrix=ifa.ifa_variant_info(variant)["encoding"] == 3)
     s.close()
     return out
 

@@ -177,6 +177,15 @@ struct ScanArgs {
     const uint4 *dm_b;
     const float *dm_t;
     uint32_t dm_first;
+    // dense strands [dense_seam, n_qs) are those the encoding-3 variants may
+    // count on the matrix cores; the dense strands come by L descending on
+    // either side of the seam, so the VALU dense kernel runs each side in a
+    // launch of its own: strands [dense_begin, dense_end), and with
+    // dense_unclean only the waves that are not clean (those the matrix
+    // kernel leaves out)
+    uint32_t dense_seam;
+    uint32_t dense_begin, dense_end;
+    uint32_t dense_unclean;
     // overhang kernel: pieces per wave for the strand with the widest clip
     // (64 / (2 C) lanes each, at least 1); 0 = no strand can overhang
     uint32_t edge_pmin;

@@ -608,6 +608,10 @@ ScanArgs chunk_args(ifa_ctx *c, const DevChunk &ch)
     a.q_count = c->d_qcount.p;
     a.q_digest = c->d_qdigest.p;
     a.dm_first = a.n_qs;
+    a.dense_seam = std::min<uint32_t>(std::max<uint32_t>(c->n_dm0, a.n_sparse), a.n_qs);
+    a.dense_begin = a.n_sparse;
+    a.dense_end = a.n_qs;
+    a.dense_unclean = 0;
     uint32_t wpl, qu, wg, enc;
     variant_shape(c->variant, &wpl, &qu, &wg, &enc);
     if (enc == 3 && !c->indexed && c->n_dm0 < a.n_qs && c->dm_ready) {
@@ -1318,6 +1322,19 @@ void pack_query_strands(uint32_t strands, uint32_t n, const uint8_t *const *seq,
 // step alone (half the matrix work; maxSubs 0 qualifies from L = 16 on).
 constexpr double kHalfWaveRate = 1.0 / 1024.0;
 
+// Dense strands the encoding-3 variants count on the matrix cores (on clean
+// waves): at most 32 bases, so that one prefix word holds the whole strand,
+// and a random window hit rate of at most kDenseMatrixRate, so that their
+// hits, listed per accumulator register, stay few. The others (short strands
+// with high maxSubs) stay on the VALU kernels, whose hit list serves every
+// lane when nearly every window hits.
+constexpr double kDenseMatrixRate = 0.02;
+
+bool dense_matrix_ok(const QSDesc &d)
+{
+    return d.len <= 32u && binom_cdf(d.len, 0.75, d.k) <= kDenseMatrixRate;
+}
+
 // Mean over the 8 shifts of P(a random window passes the half-step filter).
 double half_step_rate(const QSDesc &d)
 {
@@ -1657,17 +1674,21 @@ void ensure_filter_operands(ifa_ctx *c)
 void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t> &&words,
                      uint32_t n_queries, uint32_t lmax)
 {
-    std::vector<uint8_t> fw(qs.size()), dense(qs.size());
+    const bool indexed = c->indexed;
+    std::vector<uint8_t> fw(qs.size()), dense(qs.size()), dm(qs.size());
     for (size_t i = 0; i < qs.size(); i++) {
         fw[i] = (uint8_t)filter_words(qs[i]);
         dense[i] = fw[i] == 0;
+        dm[i] = dense[i] && !indexed && dense_matrix_ok(qs[i]);
     }
     std::vector<size_t> order(qs.size());
     for (size_t i = 0; i < order.size(); i++) order[i] = i;
     // sparse strands filtered on two words first (all have L > 32, so min(L,
-    // 32) still never rises along the list), then L descending, then k
+    // 32) still never rises along the list), then L descending, then k; the
+    // dense strands the matrix cores may count last among the dense ones
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
         if (dense[x] != dense[y]) return dense[x] < dense[y];
+        if (dm[x] != dm[y]) return dm[x] < dm[y];
         if (fw[x] != fw[y]) return fw[x] > fw[y];
         const QSDesc &a = qs[x], &b = qs[y];
         if (a.len != b.len) return a.len > b.len;
@@ -1684,7 +1705,6 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     }
     qs.swap(sorted);
     std::vector<uint32_t> mw3;
-    const bool indexed = c->indexed;
     if (!indexed) mfma3_tile_meta(qs, sorted_fw, n_sparse, mw3);
     c->mq3_words = 1;
     for (uint32_t m : mw3) c->mq3_words = std::max(c->mq3_words, m & 0xffu);
@@ -1701,13 +1721,10 @@ void install_queries(ifa_ctx *c, std::vector<QSDesc> &&qs, std::vector<uint32_t>
     uint32_t cmax = 0;
     for (const QSDesc &d : qs) cmax = std::max<uint32_t>(cmax, std::min<uint32_t>(d.maxn, d.len - 1u));
     c->edge_pmin = cmax == 0 ? 0u : (2u * cmax <= 64u ? 64u / (2u * cmax) : 1u);
-    uint32_t n_dm0 = (uint32_t)qs.size();
-    for (uint32_t i = n_sparse; i < (uint32_t)qs.size(); i++)
-        if (qs[i].len <= 32u) {
-            n_dm0 = i;
-            break;
-        }
-    c->n_dm0 = indexed ? (uint32_t)qs.size() : n_dm0;
+    uint32_t n_dm0 = n_sparse;
+    for (size_t i : order)
+        if (dense[i] && !dm[i]) n_dm0++;
+    c->n_dm0 = n_dm0;   // [n_dm0, size): the matrix-counted dense strands
     if (c->cfg.work_capacity == 0 && !indexed) {
         // size the work lists for the expected load unless the caller fixed
         // the initial capacity (they grow on overflow either way)

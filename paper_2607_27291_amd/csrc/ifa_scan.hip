@@ -925,18 +925,30 @@ static uint32_t mq3_lds_bytes(uint32_t tiles, uint32_t wg, int nw)
 // For a query strand of L <= 32 bases the three-class contraction over its
 // whole length is the exact match count of every window: with need = L - k -
 // nA (nA = A bases of the strand), a window is a hit iff its value D reaches
-// need, and its mismatches are m = k + need - D. So on a clean wave -- no N
+// need, and its mismatches are m = k - (D - need). So on a clean wave -- no N
 // and no piece end in the words its windows read, every window owned and
 // inside the chunk and the scanned range, all in one piece -- the dense
-// strands [dm_first, n_qs) (all of L <= 32) are counted here, four per column
-// tile, with the filter's staging and operand layout; their hits are emitted
-// by each lane from a 32-bit hit mask per pair of row tiles (the lane holds
-// one strand's column: 16 rows of two row tiles), with the values D - need
-// of the lane's rows parked in LDS bytes. The VALU dense kernels take those
-// strands only on waves that are not clean.
+// strands [dm_first, n_qs) (all of L <= 32, chosen by the host for their low
+// random-window hit rate) are counted here, with the filter's staging and
+// operand layout. A workgroup holds a batch of kDmTiles column tiles (four
+// strands each) in LDS, and each wave stages its stream once for all of them.
+// Hits are listed per accumulator register, in blocks of kDmBlock registers:
+// the block's ballots (lanes whose value reaches need) come first, then, after
+// a flush if the block's hits could overflow the wave's LDS list, each
+// register with hits is listed, the hitting lanes taking slots total + mbcnt.
+// Only the flush at a block's start and the one at the wave's end are
+// inlined, so the loop stays small. The list is hashed (or written out as
+// records) with every lane busy, into LDS copies of the per-strand sums that
+// go to the query's accumulators when the workgroup ends. The VALU dense
+// kernels take those strands only on waves that are not clean.
 //
-// Grid: x = workgroups walking waves (XCD-aware), y = dense column tile.
+// Grid: x = workgroups walking waves (XCD-aware), y = batch of column tiles.
 // ---------------------------------------------------------------------------
+
+constexpr uint32_t kDmTiles = 8;     // column tiles per batch (32 strands)
+constexpr uint32_t kDmBlock = 8;     // accumulator registers listed per block
+constexpr uint32_t kDmList = 64u * kDmBlock;   // hit-list entries per wave
+constexpr uint32_t kDmReps = 8;      // copies of each strand's sums in LDS
 
 // Is the 1024-window wave whose window starts begin at word w0 clean (see
 // above) for strands of at most 32 bases? Windows start in words w0 ..
@@ -952,50 +964,103 @@ __device__ __forceinline__ bool wave_is_clean(const ScanArgs &a, uint32_t w0)
     return !__any(bad != 0u);
 }
 
+// LDS state of a dense matrix workgroup (one batch of kDmTiles column tiles).
+struct DmShared {
+    const float *need;              // [tile][32 columns] need of the column's strand
+    const uint32_t *kq;             // [32] k | strand << 16 per strand of the batch
+    const uint32_t *qid;            // [32] caller's query index per strand
+    uint32_t *cnt;                  // [32][kDmReps] hit counts
+    unsigned long long *dig;        // [32][kDmReps] digests
+};
+
+// Hash (or write out as records) the `total` hits listed in a wave's list,
+// with every lane. An entry is D | lane << 8 | register << 14 | row tile << 18
+// | tile << 21: the lane that held the value gives its column (strand
+// 4 tile + column / 8 of the batch, shift column % 8), and the mismatches are
+// k - (D - need). Counts and digests go to one of kDmReps copies of the
+// strand's sums (by lane), so that lanes hashing hits of one strand do not
+// queue on one LDS address. Called by all 64 lanes of the wave.
+__device__ __forceinline__ void dm_flush(const ScanArgs &a, const uint32_t *list, uint32_t total,
+                                         uint32_t contig, uint32_t pos0, const DmShared &sh)
+{
+    const uint32_t l = threadIdx.x & 63u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    unsigned long long base = 0;
+    if (a.sink == kSinkRecords) {
+        if (l == 0u) base = atomicAdd(a.hit_count, (unsigned long long)total);
+        base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+               (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+    }
+    for (uint32_t e = l; e < total; e += 64u) {
+        const uint32_t ent = list[e];
+        const uint32_t el = (ent >> 8) & 63u, i = (ent >> 14) & 15u;
+        const uint32_t u = (ent >> 18) & 7u, nt = ent >> 21;
+        const uint32_t col = el & 31u, eh = el >> 5;
+        const uint32_t qb = 4u * nt + (col >> 3);            // strand in the batch
+        const uint32_t kq = sh.kq[qb];
+        // window of register i: row tile u, group 8 (i / 4) + 4 h + i % 4
+        const uint32_t win = 256u * u + 8u * (8u * (i >> 2) + 4u * eh + (i & 3u)) + (col & 7u);
+        const uint32_t m = (kq & 0xffffu) + (uint32_t)sh.need[32u * nt + col] - (ent & 0xffu);
+        if (a.sink == kSinkRecords) {
+            if (base + e < a.hit_cap)
+                a.hits[base + e] = make_uint4(sh.qid[qb], contig, pos0 + win, (kq >> 16) | (m << 16));
+        } else {
+            const uint32_t rep = kDmReps * qb + (l & (kDmReps - 1u));
+            atomicAdd(&sh.cnt[rep], 1u);
+            atomicAdd(&sh.dig[rep], (unsigned long long)hit_hash(contig, pos0 + win, kq >> 16, m, 0u));
+        }
+    }
+    // the list is rewritten next: every read is done first
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int WG>
 __global__ __launch_bounds__(WG) void scan_dense_mfma3_kernel(ScanArgs a)
 {
     constexpr uint32_t kBlocks = m3_blocks(1), kWords = 3 * kBlocks;
     extern __shared__ uint4 lds[];
-    const uint32_t nt = blockIdx.y;                                 // dense column tile
-    uint4 *sb = lds;                                                // [2 K steps][64]
-    float *st = reinterpret_cast<float *>(lds + 128u);              // [32]
-    uint32_t *sp = reinterpret_cast<uint32_t *>(st + 32u);          // [256]
+    const uint32_t n_dm = a.n_qs - a.dm_first;                      // strands on the matrix cores
+    const uint32_t n_tiles = (n_dm + 3u) / 4u;
+    const uint32_t t0 = kDmTiles * blockIdx.y;                      // first tile of the batch
+    const uint32_t tn = min(n_tiles, t0 + kDmTiles) - t0;
+    const uint32_t nq = min(4u * tn, n_dm - 4u * t0);               // strands of the batch
+    uint4 *sb = lds;                                                // [tile][2 K steps][64]
+    float *st = reinterpret_cast<float *>(lds + 128u * kDmTiles);   // [tile][32] need
+    unsigned long long *sdig =
+        reinterpret_cast<unsigned long long *>(st + 32u * kDmTiles); // [32][kDmReps]
+    uint32_t *scnt = reinterpret_cast<uint32_t *>(sdig + 32u * kDmReps); // [32][kDmReps]
+    uint32_t *skq = scnt + 32u * kDmReps;                           // [32]
+    uint32_t *sqid = skq + 32u;                                     // [32]
+    uint32_t *sp = sqid + 32u;                                      // [256]
     const uint32_t wid = threadIdx.x >> 6;
-    uint32_t *flat = sp + 256u + wid * (kWords + 512u);             // this wave's words
-    uint32_t *ebuf = flat + kWords;                                 // [8][64 lanes] packed bytes
-    for (uint32_t i = threadIdx.x; i < 128u; i += WG) sb[i] = a.dm_b[128u * nt + i];
-    for (uint32_t i = threadIdx.x; i < 32u; i += WG) st[i] = a.dm_t[32u * nt + i];
+    uint32_t *flat = sp + 256u + wid * (kWords + kDmList);          // this wave's words
+    uint32_t *list = flat + kWords;                                 // this wave's hit list
+    for (uint32_t i = threadIdx.x; i < 128u * tn; i += WG) sb[i] = a.dm_b[128u * t0 + i];
+    for (uint32_t i = threadIdx.x; i < 32u * tn; i += WG) st[i] = a.dm_t[32u * t0 + i];
+    for (uint32_t i = threadIdx.x; i < 32u * kDmReps; i += WG) {
+        sdig[i] = 0ull;
+        scnt[i] = 0u;
+    }
+    for (uint32_t i = threadIdx.x; i < nq; i += WG) {
+        const QS d = load_qs(a, a.dm_first + 4u * t0 + i);
+        skq[i] = d.k | (d.strand << 16);
+        sqid[i] = d.qid;
+    }
     for (uint32_t i = threadIdx.x; i < 256u; i += WG) sp[i] = kSpread.v[i];
     __syncthreads();
+    const DmShared sh{st, skq, sqid, scnt, sdig};
 
     const uint32_t l = threadIdx.x & 63u;
     const uint32_t g = l & 31u, h = l >> 5;
-    // the lane's column: strand 4 nt + g / 8 of the dense MFMA range, shift
-    // g % 8 (the four descriptors are read wave-uniformly, then selected)
-    const uint32_t sq = a.dm_first + 4u * nt + (g >> 3);
-    const bool col_ok = sq < a.n_qs;
-    QS d;
-    {
-        const uint32_t q0 = a.dm_first + 4u * nt;
-        const QS e0 = load_qs(a, q0);
-        const QS e1 = load_qs(a, min(q0 + 1u, a.n_qs - 1u));
-        const QS e2 = load_qs(a, min(q0 + 2u, a.n_qs - 1u));
-        const QS e3 = load_qs(a, min(q0 + 3u, a.n_qs - 1u));
-        const uint32_t s = g >> 3;
-        d = s == 0u ? e0 : s == 1u ? e1 : s == 2u ? e2 : e3;
-    }
-    const float need = st[g];
-    const uint32_t shift = g & 7u;
     const uint32_t last = (uint32_t)((a.chunk_len + 31) >> 5) + kPadWords - 1;
     const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
     const uint32_t stride = gridDim.x * (WG / 64u);
     const ifa_v16f zero = {};
-    const ifa_v8i B0 = {(int)sb[l].x, (int)sb[l].y, (int)sb[l].z, (int)sb[l].w, 0, 0, 0, 0};
-    const ifa_v8i B1 = {(int)sb[64u + l].x, (int)sb[64u + l].y, (int)sb[64u + l].z,
-                        (int)sb[64u + l].w, 0, 0, 0, 0};
-    uint32_t cnt = 0;
-    uint64_t dig = 0;
+    // piece of the last wave walked: waves come in increasing order, so the
+    // next wave's piece is found by stepping forward from it
+    uint32_t pidx = 0xffffffffu;
     for (uint32_t wave = xcd_local_x() * (WG / 64u) + wid; wave < n_waves; wave += stride) {
         const uint32_t w0 = a.w_begin + 32u * wave;
         if (!wave_is_clean(a, w0)) continue;
@@ -1003,7 +1068,12 @@ __global__ __launch_bounds__(WG) void scan_dense_mfma3_kernel(ScanArgs a)
         uint32_t contig = 0, pos0 = 0;
         {
             const uint64_t first = 32ull * w0;
-            const Piece pc = a.pieces[find_piece(a, first)];
+            if (pidx == 0xffffffffu) {
+                pidx = find_piece(a, first);
+            } else {
+                while (pidx + 1u < a.n_pieces && a.pieces[pidx + 1u].start <= first) pidx++;
+            }
+            const Piece pc = a.pieces[pidx];
             contig = pc.contig;
             pos0 = (uint32_t)(pc.contig_off + (first - pc.start));
         }
@@ -1029,83 +1099,90 @@ __global__ __launch_bounds__(WG) void scan_dense_mfma3_kernel(ScanArgs a)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        ifa_v8i A[4][2];
 #pragma unroll
-        for (int p = 0; p < 2; p++) {
-            ifa_v8i A[2][2];
+        for (int u = 0; u < 4; u++) {
+            const uint32_t *f = flat + 3u * (32u * u + g) + 4u * h;
 #pragma unroll
-            for (int uu = 0; uu < 2; uu++) {
-                const uint32_t *f = flat + 3u * (32u * (2 * p + uu) + g) + 4u * h;
+            for (int t = 0; t < 2; t++)
+                A[u][t] = ifa_v8i{(int)f[8 * t], (int)f[8 * t + 1], (int)f[8 * t + 2],
+                                  (int)f[8 * t + 3], 0, 0, 0, 0};
+        }
+        uint32_t total = 0;   // wave-uniform: entries in the list
+        for (uint32_t nt = 0; nt < tn; nt++) {
+            const uint4 v0 = sb[(2u * nt) * 64u + l], v1 = sb[(2u * nt + 1u) * 64u + l];
+            const ifa_v8i B0 = {(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, 0, 0, 0, 0};
+            const ifa_v8i B1 = {(int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w, 0, 0, 0, 0};
+            // columns past the last strand never hit (their need is huge)
+            const float need = st[32u * nt + g];
+            const uint32_t lane_ent = (l << 8) | (nt << 21);
 #pragma unroll
-                for (int t = 0; t < 2; t++)
-                    A[uu][t] = ifa_v8i{(int)f[8 * t], (int)f[8 * t + 1], (int)f[8 * t + 2],
-                                       (int)f[8 * t + 3], 0, 0, 0, 0};
-            }
-            ifa_v16f d0 = mfma_fp4(A[0][0], B0, zero);
-            ifa_v16f d1 = mfma_fp4(A[1][0], B0, zero);
-            d0 = mfma_fp4(A[0][1], B1, d0);
-            d1 = mfma_fp4(A[1][1], B1, d1);
-            // hit mask: bit i for row i of row tile 2p, bit 16 + i of 2p + 1
-            uint32_t hm = 0;
+            for (int p = 0; p < 2; p++) {
+                ifa_v16f d0 = mfma_fp4(A[2 * p][0], B0, zero);
+                ifa_v16f d1 = mfma_fp4(A[2 * p + 1][0], B0, zero);
+                d0 = mfma_fp4(A[2 * p][1], B1, d0);
+                d1 = mfma_fp4(A[2 * p + 1][1], B1, d1);
+                // blocks of kDmBlock registers: all their ballots first, then
+                // (after a flush if the list could overflow) the listing
 #pragma unroll
-            for (int i = 0; i < 16; i++) {
-                hm |= (d0[i] >= need ? 1u : 0u) << i;
-                hm |= (d1[i] >= need ? 1u : 0u) << (16 + i);
-            }
-            if (!col_ok) hm = 0;
-            if (!__any(hm != 0u)) continue;
-            // D - need of the lane's 32 rows as bytes (only hit rows are read)
+                for (int b = 0; b < 32 / (int)kDmBlock; b++) {
+                    uint64_t mb[kDmBlock];
+                    uint32_t sum = 0;
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                uint32_t b0 = 0, b1 = 0;
+                    for (int j = 0; j < (int)kDmBlock; j++) {
+                        const int r = (int)kDmBlock * b + j;
+                        mb[j] = __ballot((r < 16 ? d0[r & 15] : d1[r & 15]) >= need);
+                        sum += (uint32_t)__popcll(mb[j]);
+                    }
+                    if (sum == 0u) continue;
+                    if (total + sum > kDmList) {
+                        dm_flush(a, list, total, contig, pos0, sh);
+                        total = 0;
+                    }
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    b0 |= ((uint32_t)(int)(d0[4 * q + e] - need) & 0xffu) << (8 * e);
-                    b1 |= ((uint32_t)(int)(d1[4 * q + e] - need) & 0xffu) << (8 * e);
-                }
-                ebuf[64u * q + l] = b0;            // dword q of lane l (bank-friendly)
-                ebuf[64u * (4u + q) + l] = b1;
-            }
-            unsigned long long slot = 0;
-            if (a.sink == kSinkRecords && hm)
-                slot = atomicAdd(a.hit_count, (unsigned long long)__popc(hm));
-            while (hm) {
-                const uint32_t i = __builtin_ctz(hm);
-                hm &= hm - 1u;
-                const uint32_t ii = i & 15u;
-                // window of row ii: row tile 2p + i / 16, group 8 (ii / 4) + 4 h + ii % 4
-                const uint32_t win = 256u * (2u * (uint32_t)p + (i >> 4)) +
-                                     8u * (8u * (ii >> 2) + 4u * h + (ii & 3u)) + shift;
-                const uint32_t m = d.k - ((ebuf[64u * (i >> 2) + l] >> (8u * (i & 3u))) & 0xffu);
-                if (a.sink == kSinkRecords) {
-                    write_record(a, slot, d, contig, pos0 + win, m, 0u);
-                    slot++;
-                } else {
-                    cnt += 1;
-                    dig += hit_hash(contig, pos0 + win, d.strand, m, 0u);
+                    for (int j = 0; j < (int)kDmBlock; j++) {
+                        const int r = (int)kDmBlock * b + j;
+                        const float v = r < 16 ? d0[r & 15] : d1[r & 15];
+                        if (mb[j] == 0u) continue;
+                        if (v >= need) {
+                            const uint32_t slot = __builtin_amdgcn_mbcnt_hi(
+                                (uint32_t)(mb[j] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb[j], total));
+                            list[slot] = __builtin_amdgcn_cvt_pk_u8_f32(
+                                v, 0u, lane_ent | ((uint32_t)(r & 15) << 14) | ((uint32_t)(2 * p + (r >> 4)) << 18));
+                        }
+                        total += (uint32_t)__popcll(mb[j]);
+                    }
                 }
             }
         }
+        if (total) dm_flush(a, list, total, contig, pos0, sh);
         // the next wave rewrites this wave's words: all reads done first
         __builtin_amdgcn_wave_barrier();
     }
     if (a.sink == kSinkCountDigest) {
-        // each lane holds one strand's column: sum per strand of the tile
+        __syncthreads();
+        // one addition per strand of the batch to its query's accumulators
+        for (uint32_t i = threadIdx.x; i < nq; i += WG) {
+            uint32_t c = 0;
+            unsigned long long s = 0;
 #pragma unroll
-        for (uint32_t s = 0; s < 4u; s++) {
-            const uint32_t q = a.dm_first + 4u * nt + s;
-            if (q >= a.n_qs) break;
-            const bool mine = (g >> 3) == s;
-            const QS ds = load_qs(a, q);
-            wave_add_stats(a, ds.qid, mine ? cnt : 0u, mine ? dig : 0ull,
-                           blockIdx.x * (WG / 64u) + wid);
+            for (uint32_t j = 0; j < kDmReps; j++) {
+                c += scnt[kDmReps * i + j];
+                s += sdig[kDmReps * i + j];
+            }
+            if (c == 0u) continue;
+            const uint32_t slot = sqid[i] * kStripes + blockIdx.x % kStripes;
+            atomicAdd(&a.q_count[slot], (unsigned long long)c);
+            atomicAdd(&a.q_digest[slot], s);
         }
     }
 }
 
-// LDS bytes of the dense matrix kernel (one column tile per workgroup).
+// LDS bytes of the dense matrix kernel (one batch of kDmTiles column tiles).
 static uint32_t dm3_lds_bytes(uint32_t wg)
 {
-    return 128u * 16u + 32u * 4u + 256u * 4u + (wg / 64u) * (3u * m3_blocks(1) + 512u) * 4u;
+    return kDmTiles * (128u * 16u + 32u * 4u) + 32u * kDmReps * (8u + 4u) + 2u * 32u * 4u +
+           256u * 4u + (wg / 64u) * (3u * m3_blocks(1) + kDmList) * 4u;
 }
 
 // One wave per work item (grid-stride). Does nothing when the filter kernel
@@ -1140,8 +1217,9 @@ __global__ __launch_bounds__(256) void scan_resolve_kernel(ScanArgs a)
 // word). Windows within k after the last word are hits; plain lanes emit them
 // here. Other lanes (N, piece end, carried prefix, chunk tail) are left to
 // scan_dense_cold_kernel, so that their code does not weigh on this loop's
-// registers. Dense strands come sorted by L descending so the cached word-0
-// slices can be masked in place.
+// registers. Dense strands come sorted by L descending (those counted on the
+// matrix cores last, again by L descending), so the cached word-0 slices can
+// be masked in place and are rebuilt once at that seam.
 // Count+digest in the dense kernel: list the hits in LDS and hash them with
 // every lane busy (W = 16); at W = 32 the list would halve the occupancy.
 template <int W>
@@ -1279,6 +1357,9 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
     const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
     const Lane ln = make_lane<W>(a, gl);
     const uint32_t wave = gl >> 6;
+    // the launch for the matrix-counted strands takes only the waves the
+    // matrix kernel leaves out
+    if (a.dense_unclean && wave_is_clean(a, a.w_begin + 32u * wave)) return;
     uint32_t *hits = hit_lds[threadIdx.x >> 6];
     uint32_t *lane_pos = pos_lds[threadIdx.x >> 6];
     uint32_t sh[W], sl[W];
@@ -1304,19 +1385,19 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     uint32_t cur_len = 32;
-    // on a clean wave the strands from dm_first on are counted on the matrix
-    // cores (scan_dense_mfma3_kernel)
-    const uint32_t q_end =
-        a.dm_first < a.n_qs && wave_is_clean(a, a.w_begin + 32u * wave) ? a.dm_first : a.n_qs;
+    // strands [dense_begin, dense_end): with strands counted on the matrix
+    // cores, the others in one launch and those in a second one (waves the
+    // matrix kernel leaves out), each range by L descending
+    const uint32_t q_end = a.dense_end;
     // both strands of a query are adjacent: their counts are summed before
     // the wave-wide reduction
     uint32_t cnt = 0, qid = 0xffffffffu;
     uint64_t dig = 0;
     // the next strand's descriptor is loaded while this one runs
-    QS nxt = load_qs(a, a.n_sparse);
-    for (uint32_t q = a.n_sparse; q < q_end; q++) {
+    QS nxt = load_qs(a, a.dense_begin);
+    for (uint32_t q = a.dense_begin; q < q_end; q++) {
         const QS d = nxt;
-        if (q + 1u < a.n_qs) nxt = load_qs(a, q + 1u);
+        if (q + 1u < q_end) nxt = load_qs(a, q + 1u);
         if (d.qid != qid) {
             if (a.sink == kSinkCountDigest && qid != 0xffffffffu)
                 wave_add_stats(a, qid, cnt, dig, wave);
@@ -1765,7 +1846,7 @@ static const VariantDesc kVariantTable[] = {
     IFA_VM(512, 16384),  IFA_VM(512, 65536),  IFA_VM(1024, 65536),
     IFA_VM3(512, 32768), IFA_VM3(256, 32768), IFA_VM3(1024, 32768),
     IFA_VM3(512, 65536), IFA_VM3(256, 16384),
-    IFA_VM3D(256, 32768), IFA_VM3D(512, 32768),
+    IFA_VM3D(256, 32768), IFA_VM3D(512, 32768), IFA_VM3D(512, 65536),
 };
 #undef IFA_V
 #undef IFA_VM
@@ -1870,22 +1951,42 @@ hipError_t launch_dense(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch
     const VariantDesc &v = pick(a);
     const uint64_t lanes = filter_lanes(a, v);
     const dim3 grid((uint32_t)((lanes + 255) / 256));
-    hipError_t e = go(v.dense, grid, dim3(256), 0, s, a, rec);
-    if (e != hipSuccess) return e;
+    // each side of the seam by L descending, in a launch of its own; with
+    // the matrix kernel counting [dm_first = seam, n_qs) on clean waves, the
+    // second launch takes only the waves it leaves out
+    hipError_t e = hipSuccess;
+    const uint32_t seam = a.dense_seam;
+    if (seam > a.n_sparse) {
+        ScanArgs part = a;
+        part.dense_begin = a.n_sparse;
+        part.dense_end = seam;
+        e = go(v.dense, grid, dim3(256), 0, s, part, rec);
+        if (e != hipSuccess) return e;
+    }
+    if (seam < a.n_qs) {
+        ScanArgs part = a;
+        part.dense_begin = seam;
+        part.dense_end = a.n_qs;
+        part.dense_unclean = a.dm_first < a.n_qs ? 1u : 0u;
+        e = go(v.dense, grid, dim3(256), 0, s, part, rec);
+        if (e != hipSuccess) return e;
+    }
     e = go(v.dense_cold, grid, dim3(256), 0, s, a, rec);
     if (e != hipSuccess || a.dm_first >= a.n_qs) return e;
     // one-word dense strands on the matrix cores, clean waves only: one
-    // column tile of 4 strands per grid row, about 2^15 waves in all
+    // batch of kDmTiles column tiles (32 strands) per grid row, about 2^15
+    // waves in all
     const uint32_t tiles = (a.n_qs - a.dm_first + 3u) / 4u;
+    const uint32_t batches = (tiles + kDmTiles - 1u) / kDmTiles;
     const uint32_t waves = (a.w_end - a.w_begin + 31u) >> 5;
-    uint32_t gx = max(1u, min((waves + 3u) / 4u, (32768u / 4u + tiles - 1u) / tiles));
+    uint32_t gx = max(1u, min((waves + 3u) / 4u, (32768u / 4u + batches - 1u) / batches));
     if (gx >= 8u) gx &= ~7u;
-    for (uint32_t t0 = 0; t0 < tiles; t0 += 65535u) {
+    for (uint32_t b0 = 0; b0 < batches; b0 += 65535u) {
         ScanArgs part = a;
-        part.dm_first = a.dm_first + 4u * t0;
-        part.dm_b = a.dm_b + 128u * t0;
-        part.dm_t = a.dm_t + 32u * t0;
-        e = go(scan_dense_mfma3_kernel<256>, dim3(gx, min(65535u, tiles - t0)), dim3(256),
+        part.dm_first = a.dm_first + 4u * kDmTiles * b0;
+        part.dm_b = a.dm_b + 128u * kDmTiles * b0;
+        part.dm_t = a.dm_t + 32u * kDmTiles * b0;
+        e = go(scan_dense_mfma3_kernel<256>, dim3(gx, min(65535u, batches - b0)), dim3(256),
                dm3_lds_bytes(256), s, part, rec);
         if (e != hipSuccess) return e;
     }
