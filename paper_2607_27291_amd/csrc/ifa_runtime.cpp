@@ -1327,8 +1327,9 @@ constexpr double kHalfWaveRate = 1.0 / 1024.0;
 // and a random window hit rate of at most kDenseMatrixRate, so that their
 // hits, listed per accumulator register, stay few. The others (short strands
 // with high maxSubs) stay on the VALU kernels, whose hit list serves every
-// lane when nearly every window hits.
-constexpr double kDenseMatrixRate = 0.02;
+// lane when nearly every window hits. (On 10,000 queries of 18-50 bases with
+// maxSubs 0-16, limits of 0.02 and 0.2 gave 1 % and 4 % slower passes.)
+constexpr double kDenseMatrixRate = 0.05;
 
 bool dense_matrix_ok(const QSDesc &d)
 {
