@@ -164,7 +164,10 @@ typedef struct {
     double pack_ms;          /* host wall time spent packing contigs */
     double filter_ms;        /* summed time of the filter kernel alone (the hot
                                 loop) over the timed passes (timed_filter_passes),
-                                HIP events on the compute stream */
+                                HIP events on the compute stream; in a pass that
+                                also has dense strands, the dense kernels run
+                                beside it on a second stream, so this time and
+                                dense_ms overlap */
     uint64_t filter_launches;/* filter kernel launches */
     uint64_t filter_windows; /* window starts the filter kernel evaluated (those of
                                 waves holding a reference N are passed whole to the

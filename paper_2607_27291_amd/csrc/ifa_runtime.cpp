@@ -18,6 +18,7 @@
 #include <cstring>
 #include <deque>
 #include <functional>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -236,11 +237,11 @@ struct Job {
                                           // them: the query tables they point to stay
                                           // valid until the job is retired)
     hipEvent_t k0 = nullptr, kf = nullptr, k1 = nullptr;  // start / filter end / stop
-    hipEvent_t kd = nullptr;                              // dense kernels start
+    hipEvent_t kd = nullptr, kx = nullptr;                // dense kernels start / end
     hipEvent_t ke = nullptr;                              // overhang kernel start
     hipEvent_t done = nullptr;              // hit count copied to the host
     uint32_t n_half = 0;                    // filtered strands in half-step tiles
-    bool split_timed = false;               // kf, kd, ke recorded (eager launches)
+    bool split_timed = false;               // kf, kd, kx, ke recorded (eager launches)
     bool active = false;
 };
 
@@ -253,6 +254,10 @@ struct ifa_ctx {
     uint64_t plane_words = 0;
 
     hipStream_t copy_s = nullptr, comp_s = nullptr;
+    // the dense kernels of a pass that also has filtered strands run on
+    // dense_s, beside the filter and resolve kernels (fork and join events)
+    hipStream_t dense_s = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
     // kernel variant (autotuner or caller's choice)
     uint32_t variant = variant_default();
@@ -673,15 +678,18 @@ void copy_records(ifa_ctx *c, int hb, uint64_t n)
     c->st.hits += n;
 }
 
-// Timing events of one pass: t0 before the filter, t1 after it, te before
+// Timing events of one pass: t0 before the filter, t1 after it, td and tx
+// before and after the dense kernels (on the stream they run on), te before
 // the overhanging-window kernel, t2 after the last scan kernel.
 struct PassEvents {
-    hipEvent_t t0 = nullptr, t1 = nullptr, td = nullptr, te = nullptr, t2 = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr, td = nullptr, tx = nullptr, te = nullptr,
+               t2 = nullptr;
     void create()
     {
         if (!t0) hip_check(hipEventCreate(&t0), "event");
         if (!t1) hip_check(hipEventCreate(&t1), "event");
         if (!td) hip_check(hipEventCreate(&td), "event");
+        if (!tx) hip_check(hipEventCreate(&tx), "event");
         if (!te) hip_check(hipEventCreate(&te), "event");
         if (!t2) hip_check(hipEventCreate(&t2), "event");
     }
@@ -690,46 +698,67 @@ struct PassEvents {
         if (t0) (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
         if (td) (void)hipEventDestroy(td);
+        if (tx) (void)hipEventDestroy(tx);
         if (te) (void)hipEventDestroy(te);
         if (t2) (void)hipEventDestroy(t2);
-        t0 = t1 = td = te = t2 = nullptr;
+        t0 = t1 = td = tx = te = t2 = nullptr;
     }
 };
 
 // Enqueue one pass of the scan over a's word range: the sparse part (filter
 // kernel, then resolve kernel over the work list) and, if `dense`, the dense
 // kernels and (with IFA_FLAG_OVERHANG) the overhanging windows. Counters are
-// cleared by kernels on the stream first.
+// cleared by kernels on the stream first. With both parts, the dense kernels
+// run on the side stream, forked after the clear and joined before the
+// overhanging windows: the filter keeps the matrix cores busy and the dense
+// kernels the vector ALUs, so the two overlap on each CU. They share only
+// the pass counters and query sums, which both update atomically.
 // (A null event in ev is not recorded.)
 void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, PassEvents &ev)
 {
-    auto mark = [&](hipEvent_t e) {
-        if (e) hip_check(hipEventRecord(e, c->comp_s), "event record");
+    auto mark = [&](hipEvent_t e, hipStream_t s) {
+        if (e) hip_check(hipEventRecord(e, s), "event record");
     };
     // the pass counters of a hit buffer are adjacent (hit count, then the
     // work and skip counts): one clear kernel
     hip_check(clear_hits ? launch_clear_u64(a.hit_count, 2, c->comp_s)
                          : launch_clear_u64(a.hit_count + 1, 1, c->comp_s),
               "clear pass counters");
-    mark(ev.t0);
+    hipStream_t cs = c->comp_s;
+    mark(ev.t0, cs);
     if (c->indexed) {
         // indexed mode: seed lookups and their verification, one kernel
-        mark(ev.t1);
-        mark(ev.td);
-        if (dense) hip_check(launch_seed(a, c->comp_s), "seed launch");
-        mark(ev.te);
-        mark(ev.t2);
+        mark(ev.t1, cs);
+        mark(ev.td, cs);
+        if (dense) hip_check(launch_seed(a, cs), "seed launch");
+        mark(ev.tx, cs);
+        mark(ev.te, cs);
+        mark(ev.t2, cs);
         return;
     }
-    hip_check(launch_filter(a, c->comp_s), "filter launch");
-    mark(ev.t1);
-    hip_check(launch_resolve(a, c->comp_s), "resolve launch");
-    mark(ev.td);
-    if (dense) hip_check(launch_dense(a, c->comp_s), "dense launch");
-    mark(ev.te);
+    const bool side = dense && a.n_sparse > 0 && a.n_sparse < a.n_qs;
+    if (side) {
+        hip_check(hipEventRecord(c->fork_ev, cs), "fork");
+        hip_check(hipStreamWaitEvent(c->dense_s, c->fork_ev, 0), "fork");
+        mark(ev.td, c->dense_s);
+        hip_check(launch_dense(a, c->dense_s), "dense launch");
+        mark(ev.tx, c->dense_s);
+        hip_check(hipEventRecord(c->join_ev, c->dense_s), "join");
+    }
+    hip_check(launch_filter(a, cs), "filter launch");
+    mark(ev.t1, cs);
+    hip_check(launch_resolve(a, cs), "resolve launch");
+    if (side) {
+        hip_check(hipStreamWaitEvent(cs, c->join_ev, 0), "join");
+    } else {
+        mark(ev.td, cs);
+        if (dense) hip_check(launch_dense(a, cs), "dense launch");
+        mark(ev.tx, cs);
+    }
+    mark(ev.te, cs);
     if (dense && (c->cfg.flags & IFA_FLAG_OVERHANG))
-        hip_check(launch_edge(a, c->comp_s), "overhang launch");
-    mark(ev.t2);
+        hip_check(launch_edge(a, cs), "overhang launch");
+    mark(ev.t2, cs);
 }
 
 // The scan-kernel launches enqueue_pass issues for a (the clear kernel and
@@ -758,29 +787,61 @@ bool same_structure(const std::vector<ScanLaunch> &x, const std::vector<ScanLaun
     return true;
 }
 
-// The kernel nodes of a captured pass (a chain) after the first one (the
-// counter-clearing kernel), in order; empty if the graph is not such a chain.
-std::vector<hipGraphNode_t> chain_kernel_nodes(hipGraph_t g)
+// The scan-kernel nodes of a captured pass in plan order, or empty if the
+// graph does not hold the plan. The graph is a chain, or (dense kernels on
+// the side stream) a fork after the counter-clearing kernel into the filter
+// and resolve kernels on one branch and the dense kernels on the other, then
+// a join. Nodes are taken in dependency order; among the ready ones, the
+// kernel the plan names next (the two branches launch different kernels).
+std::vector<hipGraphNode_t> plan_kernel_nodes(hipGraph_t g, const std::vector<ScanLaunch> &plan)
 {
-    std::vector<hipGraphNode_t> out;
-    size_t nr = 0;
-    if (hipGraphGetRootNodes(g, nullptr, &nr) != hipSuccess || nr != 1) return {};
-    hipGraphNode_t cur = nullptr;
-    if (hipGraphGetRootNodes(g, &cur, &nr) != hipSuccess) return {};
-    bool first = true;
-    while (cur) {
-        hipGraphNodeType t;
-        if (hipGraphNodeGetType(cur, &t) != hipSuccess) return {};
-        if (t == hipGraphNodeTypeKernel) {
-            if (!first) out.push_back(cur);
-            first = false;
-        }
+    size_t n = 0;
+    if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess) return {};
+    std::vector<hipGraphNode_t> nodes(n);
+    if (n && hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return {};
+    std::map<hipGraphNode_t, size_t> pending;   // dependencies not yet taken
+    std::vector<hipGraphNode_t> ready;
+    for (hipGraphNode_t x : nodes) {
         size_t nd = 0;
-        if (hipGraphNodeGetDependentNodes(cur, nullptr, &nd) != hipSuccess || nd > 1) return {};
-        hipGraphNode_t next = nullptr;
-        if (nd == 1 && hipGraphNodeGetDependentNodes(cur, &next, &nd) != hipSuccess) return {};
-        cur = nd == 1 ? next : nullptr;
+        if (hipGraphNodeGetDependencies(x, nullptr, &nd) != hipSuccess) return {};
+        pending[x] = nd;
+        if (nd == 0) ready.push_back(x);
     }
+    auto take = [&](size_t i) -> bool {
+        hipGraphNode_t x = ready[i];
+        ready.erase(ready.begin() + (std::ptrdiff_t)i);
+        size_t nd = 0;
+        if (hipGraphNodeGetDependentNodes(x, nullptr, &nd) != hipSuccess) return false;
+        std::vector<hipGraphNode_t> dep(nd);
+        if (nd && hipGraphNodeGetDependentNodes(x, dep.data(), &nd) != hipSuccess) return false;
+        for (hipGraphNode_t y : dep)
+            if (--pending[y] == 0) ready.push_back(y);
+        return true;
+    };
+    std::vector<hipGraphNode_t> out;
+    bool first = true;   // the counter-clearing kernel is not in the plan
+    while (!ready.empty()) {
+        bool moved = false;
+        for (size_t i = 0; i < ready.size() && !moved; i++) {
+            hipGraphNodeType t;
+            if (hipGraphNodeGetType(ready[i], &t) != hipSuccess) return {};
+            if (t != hipGraphNodeTypeKernel || first) {
+                first = first && t != hipGraphNodeTypeKernel;
+                if (!take(i)) return {};
+                moved = true;
+                continue;
+            }
+            hipKernelNodeParams kp{};
+            if (hipGraphKernelNodeGetParams(ready[i], &kp) != hipSuccess) return {};
+            if (out.size() < plan.size() && kp.func == plan[out.size()].func) {
+                out.push_back(ready[i]);
+                if (!take(i)) return {};
+                moved = true;
+            }
+        }
+        if (!moved) return {};
+    }
+    if (out.size() != plan.size()) return {};
     return out;
 }
 
@@ -814,7 +875,7 @@ void add_pass_times(ifa_ctx *c, const PassEvents &ev, const Job &j, int hb, uint
     if (split_timed) {
         c->st.timed_passes++;
         if (c->cfg.flags & IFA_FLAG_OVERHANG) c->st.edge_ms += elapsed(ev.te, ev.t2);
-        c->st.dense_ms += elapsed(ev.td, ev.te);
+        c->st.dense_ms += elapsed(ev.td, ev.tx);
         if (sparse) {
             c->st.filter_ms += elapsed(ev.t0, ev.t1);
             c->st.timed_filter_passes++;
@@ -925,6 +986,7 @@ void retire(ifa_ctx *c, Job &j)
     ev.t0 = j.k0;
     ev.t1 = j.kf;
     ev.td = j.kd;
+    ev.tx = j.kx;
     ev.te = j.ke;
     ev.t2 = j.k1;
     const uint32_t words = (uint32_t)((j.chunk->len + 31) >> 5);
@@ -971,11 +1033,13 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     if (!j.k1) hip_check(hipEventCreate(&j.k1), "event");
     if (!j.ke) hip_check(hipEventCreate(&j.ke), "event");
     if (!j.kd) hip_check(hipEventCreate(&j.kd), "event");
+    if (!j.kx) hip_check(hipEventCreate(&j.kx), "event");
     if (!j.done) hip_check(hipEventCreateWithFlags(&j.done, hipEventDisableTiming), "event");
     PassEvents ev;
     ev.t0 = j.k0;
     ev.t1 = j.kf;
     ev.td = j.kd;
+    ev.tx = j.kx;
     ev.te = j.ke;
     ev.t2 = j.k1;
     // the pass and its counter copy (what a graph holds). No event is
@@ -1012,7 +1076,7 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
             hip_check(hipStreamEndCapture(c->comp_s, &pg->graph), "end capture");
             hip_check(hipGraphInstantiate(&pg->exec, pg->graph, nullptr, nullptr, 0),
                       "instantiate pass graph");
-            pg->knodes = chain_kernel_nodes(pg->graph);
+            pg->knodes = plan_kernel_nodes(pg->graph, plan);
             pg->args = a;
             pg->plan = plan;
         } else if (std::memcmp(&pg->args, &a, sizeof a) != 0) {
@@ -1980,6 +2044,9 @@ ifa_status ifa_create(const ifa_config *cfg_in, ifa_ctx **out)
         c->plane_words = words_with_pad(cfg.chunk_bases);
         hip_check(hipStreamCreateWithFlags(&c->copy_s, hipStreamNonBlocking), "stream");
         hip_check(hipStreamCreateWithFlags(&c->comp_s, hipStreamNonBlocking), "stream");
+        hip_check(hipStreamCreateWithFlags(&c->dense_s, hipStreamNonBlocking), "stream");
+        hip_check(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming), "event");
+        hip_check(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming), "event");
         for (int i = 0; i < 2; i++) {
             c->stage[i].planes.alloc(3 * c->plane_words, "pinned staging");
             hip_check(hipEventCreateWithFlags(&c->stage[i].copied, hipEventDisableTiming),
@@ -2033,6 +2100,7 @@ void ifa_destroy(ifa_ctx *c)
     (void)hipSetDevice(c->cfg.device);
     if (c->comp_s) (void)hipStreamSynchronize(c->comp_s);
     if (c->copy_s) (void)hipStreamSynchronize(c->copy_s);
+    if (c->dense_s) (void)hipStreamSynchronize(c->dense_s);
     for (auto &pr : c->h2d_pending) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
@@ -2043,6 +2111,7 @@ void ifa_destroy(ifa_ctx *c)
         if (j.kf) (void)hipEventDestroy(j.kf);
         if (j.ke) (void)hipEventDestroy(j.ke);
         if (j.kd) (void)hipEventDestroy(j.kd);
+        if (j.kx) (void)hipEventDestroy(j.kx);
         if (j.done) (void)hipEventDestroy(j.done);
     }
     for (int t = 0; t < 2; t++) {
@@ -2057,8 +2126,11 @@ void ifa_destroy(ifa_ctx *c)
     for (auto &r : c->resident)
         if (r->free_ev) (void)hipEventDestroy(r->free_ev);
     c->resident.clear();
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+    if (c->join_ev) (void)hipEventDestroy(c->join_ev);
     if (c->copy_s) (void)hipStreamDestroy(c->copy_s);
     if (c->comp_s) (void)hipStreamDestroy(c->comp_s);
+    if (c->dense_s) (void)hipStreamDestroy(c->dense_s);
     delete c;
 }
 
