@@ -550,6 +550,62 @@ def test_resident_graph_replays_match_eager(ifa, orc, sink):
 
 
 @pytest.mark.parametrize("sink", [0, 1])
+def test_forked_pass_graphs_with_dense_strands(ifa, orc, sink):
+    """Passes holding both filtered and dense strands run the dense kernels on
+    a second stream beside the filter; their captured graphs fork and join.
+    Streamed chunks replayed with the kernel nodes pointed at each new chunk,
+    for two query sets in turn, give the oracle's results, for the default
+    variant, a VALU variant and the variant that counts dense strands on the
+    matrix cores."""
+    import synth
+    spec = synth.c2_spec(seed=88, total=2_200_000)
+    spec.n_param = 2e-3
+    spec.median = 80_000
+    ref = synth.gen_reference(spec)
+    contigs = [ref.contig(i) for i in range(ref.n_contigs)]
+    rng = random.Random(88)
+    shape = [(18, 10), (20, 9), (22, 8), (24, 12), (30, 14), (31, 3), (36, 5), (40, 7), (64, 9)]
+    sets = []
+    for _ in range(2):
+        qs = [rand_dna(rng, L) for L, _ in shape for _ in range(2)]
+        ks = [k for _, k in shape for _ in range(2)]
+        sets.append((qs, ks))
+    order = [0, 1, 0]
+    want = []
+    for rep, i in enumerate(order):
+        # each scan of a context numbers its contigs after the earlier ones
+        first = rep * len(contigs)
+        if sink == 0:
+            want.append(orc.scan(sets[i][0], contigs, sets[i][1], first_ordinal=first))
+        else:
+            _, cnt, dig = orc.scan(sets[i][0], contigs, sets[i][1], stats=True, records=False,
+                                   first_ordinal=first)
+            want.append((cnt, dig))
+    info = [ifa.ifa_variant_info(v) for v in range(ifa.ifa_variant_count())]
+    variants = [None, next(v for v, x in enumerate(info) if x["encoding"] == 0),
+                next(v for v, x in enumerate(info) if x["encoding"] == 3)]
+    for v in variants:
+        with ifa.Scanner(chunk_bases=1 << 17, sink=sink, flags=ifa.IFA_FLAG_GRAPHS) as s:
+            if v is None:
+                v = ifa.ifa_get_variant(s.ctx)
+            ifa.ifa_set_variant(s.ctx, v)
+            for rep, i in enumerate(order):
+                say(f"forked pass graphs: variant {v} sink {sink} rep {rep} set {i}")
+                s.load_queries(*sets[i])
+                strands, filtered = ifa.ifa_query_partition(s.ctx)
+                assert 0 < filtered < strands
+                s.scan_chunk(contigs)
+                if sink == 0:
+                    assert_same(s.collect(), want[rep], f"variant {v} rep {rep}")
+                else:
+                    gc, gd = s.query_stats()
+                    assert np.array_equal(gc, want[rep][0]) and \
+                        np.array_equal(gd, want[rep][1]), f"variant {v} rep {rep}"
+            st = s.stats()
+            assert st["graph_launches"] > 0 and st["graph_updates"] > 0, (v, st)
+
+
+@pytest.mark.parametrize("sink", [0, 1])
 def test_streamed_graph_replays_match_eager(ifa, orc, sink):
     """Streamed chunks (two stream slots, two hit buffers) replayed from
     captured pass graphs whose kernel nodes are pointed at each new chunk
