@@ -1419,23 +1419,47 @@ __global__ __launch_bounds__(256) void scan_dense_kernel(ScanArgs a)
 
 // Dense query strands on the lanes scan_dense_kernel leaves out (an N, a
 // piece end, the carried prefix or the chunk tail among their bases): the
-// exact serial test. Waves without such a lane return at once.
+// exact serial test. Waves without such a lane return at once. Such lanes are
+// few and scattered (one to a few per wave), so the wave's lanes take the
+// strands (lane j: strands n_sparse + j, + 64, ...) and each tests its strand
+// against the windows of every cold lane of the wave in turn, whose words are
+// broadcast; count+digest sums go to the query's stripe once per strand.
 template <int W>
 __global__ __launch_bounds__(256) void scan_dense_cold_kernel(ScanArgs a)
 {
     const uint32_t gl = blockIdx.x * 256u + threadIdx.x;
-    Lane ln = make_lane<W>(a, gl);
-    const bool cold = ln.active && !lane_is_plain(a, ln);
-    if (!__any(cold)) return;
+    const Lane ln = make_lane<W>(a, gl);
+    const uint64_t cold = __ballot(ln.active && !lane_is_plain(a, ln));
+    if (cold == 0u) return;
+    const uint32_t l = threadIdx.x & 63u;
     const uint32_t wave = gl >> 6;
     const uint32_t q_end =
         a.dm_first < a.n_qs && wave_is_clean(a, a.w_begin + 32u * wave) ? a.dm_first : a.n_qs;
-    for (uint32_t q = a.n_sparse; q < q_end; q++) {
-        const QS d = load_qs(a, q);
+    for (uint32_t q0 = a.n_sparse; q0 < q_end; q0 += 64u) {
+        const bool on = q0 + l < q_end;
+        const QS d = load_qs(a, on ? q0 + l : q0);
         uint32_t cnt = 0;
         uint64_t dig = 0;
-        if (cold && filter_cand_words<W>(a, d, ln, 1u)) exact_serial<W>(a, d, ln, cnt, dig);
-        if (a.sink == kSinkCountDigest) wave_add_stats(a, d.qid, cnt, dig, wave);
+        for (uint64_t rest = cold; rest != 0u; rest &= rest - 1u) {
+            const int c = (int)__builtin_ctzll(rest);
+            Lane lc;
+            lc.w = (uint32_t)__builtin_amdgcn_readlane((int)ln.w, c);
+            lc.off = (uint32_t)__builtin_amdgcn_readlane((int)ln.off, c);
+            lc.h0 = (uint32_t)__builtin_amdgcn_readlane((int)ln.h0, c);
+            lc.h1 = (uint32_t)__builtin_amdgcn_readlane((int)ln.h1, c);
+            lc.l0 = (uint32_t)__builtin_amdgcn_readlane((int)ln.l0, c);
+            lc.l1 = (uint32_t)__builtin_amdgcn_readlane((int)ln.l1, c);
+            lc.n0 = (uint32_t)__builtin_amdgcn_readlane((int)ln.n0, c);
+            lc.n1 = (uint32_t)__builtin_amdgcn_readlane((int)ln.n1, c);
+            lc.active = true;
+            lc.plain = 0;
+            if (on && filter_cand_words<W>(a, d, lc, 1u)) exact_serial<W>(a, d, lc, cnt, dig);
+        }
+        if (a.sink == kSinkCountDigest && on && cnt != 0u) {
+            const uint32_t slot = d.qid * kStripes + wave % kStripes;
+            atomicAdd(&a.q_count[slot], (unsigned long long)cnt);
+            atomicAdd(&a.q_digest[slot], (unsigned long long)dig);
+        }
     }
 }
 
