@@ -297,9 +297,9 @@ def roofline(ifa, st, variant, traffic=False, st_k=None):
         "variant": variant,
         "variant_shape": shape,
         "kernel_ms_avg": round(ms_avg, 4),
-        "kernel_timing": ("eager launches after the timed region, HIP events around each "
-                          "kernel" if st_k is not None else "HIP events around each kernel "
-                          "of the timed region's eager passes"),
+        "kernel_timing": ("eager launches after the timed region, one kernel at a time, "
+                          "HIP events around each kernel" if st_k is not None else
+                          "HIP events around each kernel of the timed region's eager passes"),
         "timed_launches": tk["timed_filter_passes"],
         "passes": st["filter_launches"],
         "windows_per_pass": st["filter_windows"] // passes,
@@ -418,16 +418,17 @@ def timed_steps(ifa, s, args, step):
 
 
 def kernel_timing(ifa, s, args, step, steps=1):
-    """Statistics whose passes have their kernels timed one by one. The
-    timed region replays passes from captured HIP graphs, and a replayed
-    pass is timed only as a whole: events recorded inside a graph read the
-    kernels between them 10-15 % long. So the dominant kernel's time per
-    launch comes from `steps` more steps launched eagerly (the same kernels,
-    launch shapes and inputs), right after the timed region. With --eager
-    the timed region's own statistics serve."""
-    if args.eager:
-        return None
+    """Statistics whose passes have their kernels timed one by one, each
+    alone on the device. The timed region replays passes from captured HIP
+    graphs, and a replayed pass is timed only as a whole: events recorded
+    inside a graph read the kernels between them 10-15 % long. In a pass with
+    both filtered and dense strands the dense kernels run beside the filter,
+    so each one's own time would cover the other's work too. So the kernels'
+    times per launch come from `steps` more steps launched eagerly and one
+    kernel at a time (the same kernels, launch shapes and inputs), right
+    after the timed region."""
     ifa.ifa_set_graphs(s.ctx, False)
+    ifa.ifa_set_overlap(s.ctx, False)
     try:
         ifa.ifa_reset_stats(s.ctx)
         for _ in range(steps):
@@ -435,7 +436,8 @@ def kernel_timing(ifa, s, args, step, steps=1):
         device_sync()
         return ifa.ifa_get_stats(s.ctx)
     finally:
-        ifa.ifa_set_graphs(s.ctx, True)
+        ifa.ifa_set_overlap(s.ctx, True)
+        ifa.ifa_set_graphs(s.ctx, not args.eager)
 
 
 # --------------------------------------------------------------------------

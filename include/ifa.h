@@ -334,6 +334,15 @@ ifa_status ifa_get_stats(ifa_ctx *ctx, ifa_stats *out);
  * are timed one by one in the statistics. Waits for submitted work first.
  * Errors: IFA_E_INVALID (ctx NULL). */
 ifa_status ifa_set_graphs(ifa_ctx *ctx, int enable);
+
+/* Run the dense-strand kernels of a pass that also has filtered strands on a
+ * second stream beside the filter and resolve kernels (enable != 0, the
+ * default), or after them on one stream. Results are identical; beside each
+ * other the kernels share the device, so each one's time in the statistics
+ * covers the other's work too, and with it off each kernel is timed alone.
+ * Passes captured in the other arrangement are captured again. Waits for
+ * submitted work first. Errors: IFA_E_INVALID (ctx NULL). */
+ifa_status ifa_set_overlap(ifa_ctx *ctx, int enable);
 ifa_status ifa_reset_stats(ifa_ctx *ctx);
 
 /* Query strands of the loaded set (*n_strands) and how many of them take the

@@ -19,7 +19,8 @@ __all__ = [
     "IfaError", "HIT_DTYPE", "lib", "ifa_config_default", "ifa_create", "ifa_destroy",
     "ifa_load_queries", "ifa_scan_chunk", "ifa_collect_hits", "ifa_last_error",
     "ifa_query_stats", "ifa_ref_load", "ifa_scan_resident", "ifa_ref_release", "ifa_ref_info",
-    "ifa_get_stats", "ifa_reset_stats", "ifa_variant_count", "ifa_variant_info",
+    "ifa_get_stats", "ifa_reset_stats", "ifa_set_graphs", "ifa_set_overlap",
+    "ifa_variant_count", "ifa_variant_info",
     "ifa_set_variant", "ifa_get_variant", "ifa_autotune", "ifa_query_partition",
     "ifa_device_footprint", "ifa_server_config_default", "ifa_server_create",
     "ifa_server_destroy", "ifa_server_submit", "ifa_server_step", "ifa_server_poll",
@@ -152,6 +153,8 @@ def lib():
         L.ifa_reset_stats.restype = st
         L.ifa_set_graphs.argtypes = [vp, ctypes.c_int]
         L.ifa_set_graphs.restype = st
+        L.ifa_set_overlap.argtypes = [vp, ctypes.c_int]
+        L.ifa_set_overlap.restype = st
         L.ifa_variant_count.argtypes = []
         L.ifa_variant_count.restype = u32
         L.ifa_variant_info.argtypes = [u32, ctypes.POINTER(u32), ctypes.POINTER(u32),
@@ -410,6 +413,10 @@ def ifa_reset_stats(ctx):
 
 def ifa_set_graphs(ctx, enable: bool):
     _check(ctx, lib().ifa_set_graphs(ctx, 1 if enable else 0))
+
+
+def ifa_set_overlap(ctx, enable: bool):
+    _check(ctx, lib().ifa_set_overlap(ctx, 1 if enable else 0))
 
 
 def ifa_variant_count() -> int:

@@ -198,6 +198,7 @@ struct PassGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<hipGraphNode_t> knodes;   // the scan-kernel nodes, in plan order
+    bool forked = false;          // dense kernels on the second stream
     void reset()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -207,6 +208,7 @@ struct PassGraph {
         knodes.clear();
         plan.clear();
         seen = false;
+        forked = false;
     }
 };
 
@@ -258,6 +260,7 @@ struct ifa_ctx {
     // dense_s, beside the filter and resolve kernels (fork and join events)
     hipStream_t dense_s = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    bool overlap = true;   // ifa_set_overlap
 
     // kernel variant (autotuner or caller's choice)
     uint32_t variant = variant_default();
@@ -705,6 +708,13 @@ struct PassEvents {
     }
 };
 
+// Does a pass over a (with its dense part if `dense`) run the dense kernels
+// on the second stream?
+bool forks(const ifa_ctx *c, const ScanArgs &a, bool dense)
+{
+    return c->overlap && !c->indexed && dense && a.n_sparse > 0 && a.n_sparse < a.n_qs;
+}
+
 // Enqueue one pass of the scan over a's word range: the sparse part (filter
 // kernel, then resolve kernel over the work list) and, if `dense`, the dense
 // kernels and (with IFA_FLAG_OVERHANG) the overhanging windows. Counters are
@@ -736,7 +746,7 @@ void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, Pa
         mark(ev.t2, cs);
         return;
     }
-    const bool side = dense && a.n_sparse > 0 && a.n_sparse < a.n_qs;
+    const bool side = forks(c, a, dense);
     if (side) {
         hip_check(hipEventRecord(c->fork_ev, cs), "fork");
         hip_check(hipStreamWaitEvent(c->dense_s, c->fork_ev, 0), "fork");
@@ -1059,12 +1069,13 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
     if (c->cfg.flags & IFA_FLAG_GRAPHS) {
         pg = &ch->graph[j.hitbuf][c->tab];
         plan = plan_pass(c, a, true);
-        if (!pg->seen || !same_structure(pg->plan, plan)) {
+        if (!pg->seen || !same_structure(pg->plan, plan) || pg->forked != forks(c, a, true)) {
             // first pass of this structure: run eagerly, capture the next one
             pg->reset();
             pg->args = a;
             pg->plan = plan;
             pg->seen = true;
+            pg->forked = forks(c, a, true);
             pg = nullptr;
         }
     }
@@ -2474,6 +2485,16 @@ ifa_status ifa_set_graphs(ifa_ctx *c, int enable)
         retire_all(c);
         if (enable) c->cfg.flags |= IFA_FLAG_GRAPHS;
         else c->cfg.flags &= ~IFA_FLAG_GRAPHS;
+    });
+}
+
+ifa_status ifa_set_overlap(ifa_ctx *c, int enable)
+{
+    if (!c) return IFA_E_INVALID;
+    return guarded(c, [&]() {
+        use_device(c);
+        retire_all(c);
+        c->overlap = enable != 0;
     });
 }
 

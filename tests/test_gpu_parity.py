@@ -605,6 +605,38 @@ def test_forked_pass_graphs_with_dense_strands(ifa, orc, sink):
             assert st["graph_launches"] > 0 and st["graph_updates"] > 0, (v, st)
 
 
+def test_overlap_switched_off_and_on(ifa, orc):
+    """ifa_set_overlap: passes with both filtered and dense strands give the
+    oracle's hits with the dense kernels beside the filter and after it, from
+    captured graphs (captured again when the arrangement changes) and
+    eagerly."""
+    import synth
+    spec = synth.c2_spec(seed=99, total=1_500_000)
+    spec.n_param = 2e-3
+    spec.median = 70_000
+    ref = synth.gen_reference(spec)
+    rng = random.Random(99)
+    shape = [(18, 10), (21, 9), (26, 12), (33, 4), (40, 6), (64, 8)]
+    qs = [rand_dna(rng, L) for L, _ in shape for _ in range(3)]
+    ks = [k for _, k in shape for _ in range(3)]
+    want = orc.scan(qs, ref, ks)
+    with ifa.Scanner(chunk_bases=1 << 19, flags=ifa.IFA_FLAG_GRAPHS) as s:
+        s.ref_load(ref)
+        s.load_queries(qs, ks)
+        strands, filtered = ifa.ifa_query_partition(s.ctx)
+        assert 0 < filtered < strands
+        for graphs in (True, False):
+            ifa.ifa_set_graphs(s.ctx, graphs)
+            for overlap in (True, False, True):
+                ifa.ifa_set_overlap(s.ctx, overlap)
+                for i in range(3):
+                    say(f"overlap {overlap} graphs {graphs} pass {i}")
+                    s.scan_resident()
+                    assert_same(s.collect(), want, f"overlap {overlap} graphs {graphs} pass {i}")
+            if graphs:
+                assert s.stats()["graph_launches"] > 0
+
+
 @pytest.mark.parametrize("sink", [0, 1])
 def test_streamed_graph_replays_match_eager(ifa, orc, sink):
     """Streamed chunks (two stream slots, two hit buffers) replayed from
