@@ -1088,6 +1088,12 @@ void submit_job(ifa_ctx *c, DevChunk *ch)
             hip_check(hipGraphInstantiate(&pg->exec, pg->graph, nullptr, nullptr, 0),
                       "instantiate pass graph");
             pg->knodes = plan_kernel_nodes(pg->graph, plan);
+            // a captured pass whose kernel nodes cannot be matched to its plan
+            // could not be pointed at another chunk or query set later
+            if (pg->knodes.size() != plan.size()) {
+                pg->reset();
+                fail(IFA_E_DEVICE, "pass graph layout");
+            }
             pg->args = a;
             pg->plan = plan;
         } else if (std::memcmp(&pg->args, &a, sizeof a) != 0) {
