@@ -766,8 +766,11 @@ __host__ __device__ constexpr uint32_t m3_blocks(int nw) { return 136u + 4u * (u
 
 // NW: most prefix words (32 bases each) of the launch's column tiles; tile nt
 // filters on mq3_w[nt] <= NW of them, each adding two K steps to its sums.
+// The one-word form keeps four waves per SIMD with the pipeline's second set
+// of accumulators (at most 128 VGPRs).
 template <int WG, int NW>
-__global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(NW == 1 ? 4 : 1)))
+void scan_filter_mfma3_kernel(ScanArgs a)
 {
     constexpr uint32_t kBlocks = m3_blocks(NW), kWords = 3 * kBlocks;
     extern __shared__ uint4 lds[];
@@ -791,6 +794,8 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
     const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
     const uint32_t stride = gridDim.x * (WG / 64u);
     const ifa_v16f zero = {};
+    bool any_half = false;   // a tile of the batch runs the first K step alone
+    for (uint32_t i = 0; i < tn; i++) any_half = any_half || (sw[i] >> 8) != 0u;
     // Lane j < kBlocks / 4 holds plane word j of a wave's stream (its four
     // 8-base blocks). A window filtered on NW prefix words reads the words of
     // its start .. start + NW, so the wave reads words w0 .. w0 + 31 + NW;
@@ -857,6 +862,74 @@ __global__ __launch_bounds__(WG) void scan_filter_mfma3_kernel(ScanArgs a)
                                          (int)f[8 * t + 3], 0, 0, 0, 0};
             }
         uint32_t pending = 0;   // wave-uniform
+        if (NW == 1 && !any_half) {
+            // One-word tiles that all run both K steps: a software pipeline
+            // over two sets of accumulators. The p1 MFMAs of tile nt run
+            // while the p0 counts of tile nt are folded, and the p0 MFMAs of
+            // tile nt + 1 while the p1 counts of tile nt are folded, so that
+            // each wave keeps the matrix core busy during its own fold.
+            auto ldB = [&](uint32_t nt, ifa_v8i &B0, ifa_v8i &B1, float &nd) {
+                const uint4 v0 = sb[(4u * nt) * 64u + l], v1 = sb[(4u * nt + 1u) * 64u + l];
+                B0 = ifa_v8i{(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, 0, 0, 0, 0};
+                B1 = ifa_v8i{(int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w, 0, 0, 0, 0};
+                nd = st[32u * nt + g];
+            };
+            ifa_v8i cB0, cB1, nB0, nB1;
+            float cneed, nneed;
+            ldB(0, cB0, cB1, cneed);
+            ifa_v16f a0 = mfma_fp4(A[0][0][0], cB0, zero);
+            ifa_v16f a1 = mfma_fp4(A[0][1][0], cB0, zero);
+            a0 = mfma_fp4(A[0][0][1], cB1, a0);
+            a1 = mfma_fp4(A[0][1][1], cB1, a1);
+            for (uint32_t nt = 0; nt + 1u < tn; nt++) {
+                const uint32_t nn = nt + 1u;
+                ldB(nn, nB0, nB1, nneed);
+                ifa_v16f b0 = mfma_fp4(A[0][2][0], cB0, zero);
+                ifa_v16f b1 = mfma_fp4(A[0][3][0], cB0, zero);
+                b0 = mfma_fp4(A[0][2][1], cB1, b0);
+                b1 = mfma_fp4(A[0][3][1], cB1, b1);
+                float mx = -1e30f;
+#pragma unroll
+                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(a0[i], a1[i]), mx);
+                a0 = mfma_fp4(A[0][0][0], nB0, zero);
+                a1 = mfma_fp4(A[0][1][0], nB0, zero);
+                a0 = mfma_fp4(A[0][0][1], nB1, a0);
+                a1 = mfma_fp4(A[0][1][1], nB1, a1);
+#pragma unroll
+                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(b0[i], b1[i]), mx);
+                const uint64_t m = __ballot(mx >= cneed);
+#pragma unroll
+                for (uint32_t q = 0; q < 4; q++)
+                    if (m & (0x000000ff000000ffull << (8u * q))) pending |= 1u << (4u * nt + q);
+                cB0 = nB0;
+                cB1 = nB1;
+                cneed = nneed;
+                // the order above, interleaved: each MFMA followed by a few
+                // VALU instructions of the fold that does not wait on it
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+                }
+            }
+            {
+                // the last tile: its p1 MFMAs beside the fold of its p0 counts
+                const uint32_t nt = tn - 1u;
+                ifa_v16f b0 = mfma_fp4(A[0][2][0], cB0, zero);
+                ifa_v16f b1 = mfma_fp4(A[0][3][0], cB0, zero);
+                b0 = mfma_fp4(A[0][2][1], cB1, b0);
+                b1 = mfma_fp4(A[0][3][1], cB1, b1);
+                float mx = -1e30f;
+#pragma unroll
+                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(a0[i], a1[i]), mx);
+#pragma unroll
+                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(b0[i], b1[i]), mx);
+                const uint64_t m = __ballot(mx >= cneed);
+#pragma unroll
+                for (uint32_t q = 0; q < 4; q++)
+                    if (m & (0x000000ff000000ffull << (8u * q))) pending |= 1u << (4u * nt + q);
+            }
+        } else
         for (uint32_t nt = 0; nt < tn; nt++) {
             const uint4 v0 = sb[(4u * nt) * 64u + l], v1 = sb[(4u * nt + 1u) * 64u + l];
             const ifa_v8i B0 = {(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, 0, 0, 0, 0};
