@@ -34,10 +34,12 @@
 // Variants (template parameters, chosen by the autotuner): windows per lane
 // W, query strands per filter iteration QU, and workgroup size.
 #include <hip/hip_runtime.h>
+
 #include <algorithm>
 #include <climits>
 #include <vector>
 #include <mutex>
+#include <type_traits>
 
 #include "ifa_dev.h"
 
@@ -794,8 +796,13 @@ void scan_filter_mfma3_kernel(ScanArgs a)
     const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
     const uint32_t stride = gridDim.x * (WG / 64u);
     const ifa_v16f zero = {};
-    bool any_half = false;   // a tile of the batch runs the first K step alone
-    for (uint32_t i = 0; i < tn; i++) any_half = any_half || (sw[i] >> 8) != 0u;
+    // tiles of the batch that run the first K step alone: none, or all
+    bool all_full = true, all_half = true;
+    for (uint32_t i = 0; i < tn; i++) {
+        const bool hf = (sw[i] >> 8) != 0u;
+        all_full = all_full && !hf;
+        all_half = all_half && hf;
+    }
     // Lane j < kBlocks / 4 holds plane word j of a wave's stream (its four
     // 8-base blocks). A window filtered on NW prefix words reads the words of
     // its start .. start + NW, so the wave reads words w0 .. w0 + 31 + NW;
@@ -862,73 +869,79 @@ void scan_filter_mfma3_kernel(ScanArgs a)
                                          (int)f[8 * t + 3], 0, 0, 0, 0};
             }
         uint32_t pending = 0;   // wave-uniform
-        if (NW == 1 && !any_half) {
-            // One-word tiles that all run both K steps: a software pipeline
-            // over two sets of accumulators. The p1 MFMAs of tile nt run
-            // while the p0 counts of tile nt are folded, and the p0 MFMAs of
-            // tile nt + 1 while the p1 counts of tile nt are folded, so that
-            // each wave keeps the matrix core busy during its own fold.
+        // One-word batches whose tiles all run both K steps, or all the
+        // first alone: a software pipeline over two sets of accumulators. The
+        // p1 MFMAs of tile nt run while the p0 counts of tile nt are folded,
+        // and the p0 MFMAs of tile nt + 1 while the p1 counts of tile nt are
+        // folded, so that each wave keeps the matrix core busy during its own
+        // fold.
+        auto pipeline = [&](auto half_tag) {
+            constexpr bool kHalf = decltype(half_tag)::value;
             auto ldB = [&](uint32_t nt, ifa_v8i &B0, ifa_v8i &B1, float &nd) {
-                const uint4 v0 = sb[(4u * nt) * 64u + l], v1 = sb[(4u * nt + 1u) * 64u + l];
+                const uint4 v0 = sb[(4u * nt) * 64u + l];
                 B0 = ifa_v8i{(int)v0.x, (int)v0.y, (int)v0.z, (int)v0.w, 0, 0, 0, 0};
-                B1 = ifa_v8i{(int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w, 0, 0, 0, 0};
+                if (!kHalf) {
+                    const uint4 v1 = sb[(4u * nt + 1u) * 64u + l];
+                    B1 = ifa_v8i{(int)v1.x, (int)v1.y, (int)v1.z, (int)v1.w, 0, 0, 0, 0};
+                }
                 nd = st[32u * nt + g];
             };
-            ifa_v8i cB0, cB1, nB0, nB1;
-            float cneed, nneed;
-            ldB(0, cB0, cB1, cneed);
-            ifa_v16f a0 = mfma_fp4(A[0][0][0], cB0, zero);
-            ifa_v16f a1 = mfma_fp4(A[0][1][0], cB0, zero);
-            a0 = mfma_fp4(A[0][0][1], cB1, a0);
-            a1 = mfma_fp4(A[0][1][1], cB1, a1);
-            for (uint32_t nt = 0; nt + 1u < tn; nt++) {
-                const uint32_t nn = nt + 1u;
-                ldB(nn, nB0, nB1, nneed);
-                ifa_v16f b0 = mfma_fp4(A[0][2][0], cB0, zero);
-                ifa_v16f b1 = mfma_fp4(A[0][3][0], cB0, zero);
-                b0 = mfma_fp4(A[0][2][1], cB1, b0);
-                b1 = mfma_fp4(A[0][3][1], cB1, b1);
-                float mx = -1e30f;
-#pragma unroll
-                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(a0[i], a1[i]), mx);
-                a0 = mfma_fp4(A[0][0][0], nB0, zero);
-                a1 = mfma_fp4(A[0][1][0], nB0, zero);
-                a0 = mfma_fp4(A[0][0][1], nB1, a0);
-                a1 = mfma_fp4(A[0][1][1], nB1, a1);
-#pragma unroll
-                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(b0[i], b1[i]), mx);
-                const uint64_t m = __ballot(mx >= cneed);
+            // the counts of row tiles 2p and 2p + 1 of a column tile
+            auto counts = [&](int p, const ifa_v8i &B0, const ifa_v8i &B1, ifa_v16f &d0,
+                              ifa_v16f &d1) {
+                d0 = mfma_fp4(A[0][2 * p][0], B0, zero);
+                d1 = mfma_fp4(A[0][2 * p + 1][0], B0, zero);
+                if (!kHalf) {
+                    d0 = mfma_fp4(A[0][2 * p][1], B1, d0);
+                    d1 = mfma_fp4(A[0][2 * p + 1][1], B1, d1);
+                }
+            };
+            auto mark = [&](uint32_t nt, float mx, float need) {
+                const uint64_t m = __ballot(mx >= need);
 #pragma unroll
                 for (uint32_t q = 0; q < 4; q++)
                     if (m & (0x000000ff000000ffull << (8u * q))) pending |= 1u << (4u * nt + q);
+            };
+            ifa_v8i cB0 = {}, cB1 = {}, nB0 = {}, nB1 = {};
+            float cneed, nneed;
+            ifa_v16f a0, a1, b0, b1;
+            ldB(0, cB0, cB1, cneed);
+            counts(0, cB0, cB1, a0, a1);
+            for (uint32_t nt = 0; nt + 1u < tn; nt++) {
+                ldB(nt + 1u, nB0, nB1, nneed);
+                counts(1, cB0, cB1, b0, b1);
+                float mx = -1e30f;
+#pragma unroll
+                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(a0[i], a1[i]), mx);
+                counts(0, nB0, nB1, a0, a1);
+#pragma unroll
+                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(b0[i], b1[i]), mx);
+                mark(nt, mx, cneed);
                 cB0 = nB0;
                 cB1 = nB1;
                 cneed = nneed;
-                // the order above, interleaved: each MFMA followed by a few
-                // VALU instructions of the fold that does not wait on it
+                // the order above, interleaved: each MFMA followed by VALU
+                // instructions of the fold that does not wait on it
+                constexpr int kMfma = kHalf ? 4 : 8;
 #pragma unroll
-                for (int i = 0; i < 8; i++) {
+                for (int i = 0; i < kMfma; i++) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x002, 4, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 32 / kMfma, 0);
                 }
             }
-            {
-                // the last tile: its p1 MFMAs beside the fold of its p0 counts
-                const uint32_t nt = tn - 1u;
-                ifa_v16f b0 = mfma_fp4(A[0][2][0], cB0, zero);
-                ifa_v16f b1 = mfma_fp4(A[0][3][0], cB0, zero);
-                b0 = mfma_fp4(A[0][2][1], cB1, b0);
-                b1 = mfma_fp4(A[0][3][1], cB1, b1);
-                float mx = -1e30f;
+            // the last tile: its p1 MFMAs beside the fold of its p0 counts
+            counts(1, cB0, cB1, b0, b1);
+            float mx = -1e30f;
 #pragma unroll
-                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(a0[i], a1[i]), mx);
+            for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(a0[i], a1[i]), mx);
 #pragma unroll
-                for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(b0[i], b1[i]), mx);
-                const uint64_t m = __ballot(mx >= cneed);
-#pragma unroll
-                for (uint32_t q = 0; q < 4; q++)
-                    if (m & (0x000000ff000000ffull << (8u * q))) pending |= 1u << (4u * nt + q);
-            }
+            for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(b0[i], b1[i]), mx);
+            mark(tn - 1u, mx, cneed);
+        };
+        if (NW == 1 && all_full) {
+            pipeline(std::false_type{});
+        } else if (NW == 1 && all_half) {
+            pipeline(std::true_type{});
         } else
         for (uint32_t nt = 0; nt < tn; nt++) {
             const uint4 v0 = sb[(4u * nt) * 64u + l], v1 = sb[(4u * nt + 1u) * 64u + l];
