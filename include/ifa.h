@@ -403,10 +403,12 @@ ifa_status ifa_get_variant(const ifa_ctx *ctx, uint32_t *v);
 
 /* Autotuner: time every variant on a calibration chunk of calib_bases
  * uniform random bases (0 = 64 Mi) with the loaded queries, median of reps
- * launches (0 = 3), and select the fastest for this context. cache_path (may
- * be NULL): a text file of "key variant ms" lines keyed by device
- * architecture, query-strand count band, longest query in words and threshold
- * band; a cached key is used without timing, a new result is appended.
+ * launches (0 = 3), and select the fastest for this context. Each pass is
+ * timed as a scan runs it (dense kernels beside the filter while
+ * ifa_set_overlap is on). cache_path (may be NULL): a text file of
+ * "key variant ms" lines keyed by device architecture, query-strand count
+ * band, longest query in words, threshold band and the overlap setting; a
+ * cached key is used without timing, a new result is appended.
  * *chosen (may be NULL) gets the variant; ms_per_variant (may be NULL) gets
  * ifa_variant_count() medians (-1 when taken from the cache). Hits found on
  * the calibration chunk are discarded. Errors: IFA_E_STATE (no queries, or

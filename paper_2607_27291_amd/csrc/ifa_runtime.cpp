@@ -1942,7 +1942,7 @@ std::string tune_key(ifa_ctx *c)
     }
     return arch + "|q2^" + std::to_string(band) + "|w" + std::to_string(nw) + "|k" +
            std::to_string(kmin / 4) + "-" + std::to_string(kmax / 4) + "|v" +
-           std::to_string(ifa::variant_count());
+           std::to_string(ifa::variant_count()) + (c->overlap ? "|o" : "");
 }
 
 bool cache_lookup(const char *path, const std::string &key, uint32_t *v)
@@ -2627,11 +2627,23 @@ ifa_status ifa_autotune(ifa_ctx *c, uint64_t calib_bases, uint32_t reps, const c
             a.q_digest = scratch_qd.p;
             a.work_count = scratch_wc.p;
             a.skip_count = scratch_wc.p + 1;
+            // the kernels as a pass runs them: with the overlap on (and both
+            // kinds of strand), the dense kernels beside the filter
             auto pass = [&]() {
                 hip_check(launch_clear_u32(a.work_count, 2, c->comp_s), "clear");
+                const bool side = forks(c, a, true);
+                if (side) {
+                    hip_check(hipEventRecord(c->fork_ev, c->comp_s), "fork");
+                    hip_check(hipStreamWaitEvent(c->dense_s, c->fork_ev, 0), "fork");
+                    hip_check(launch_dense(a, c->dense_s), "tuning launch");
+                    hip_check(hipEventRecord(c->join_ev, c->dense_s), "join");
+                }
                 hip_check(launch_filter(a, c->comp_s), "tuning launch");
                 hip_check(launch_resolve(a, c->comp_s), "tuning launch");
-                hip_check(launch_dense(a, c->comp_s), "tuning launch");
+                if (side)
+                    hip_check(hipStreamWaitEvent(c->comp_s, c->join_ev, 0), "join");
+                else
+                    hip_check(launch_dense(a, c->comp_s), "tuning launch");
             };
             for (;;) {
                 a.work = scratch_work.p;
