@@ -796,11 +796,12 @@ void scan_filter_mfma3_kernel(ScanArgs a)
     const uint32_t n_waves = (a.w_end - a.w_begin + 31u) >> 5;
     const uint32_t stride = gridDim.x * (WG / 64u);
     const ifa_v16f zero = {};
-    // tiles of the batch that run both K steps / the first alone (bit nt)
-    uint32_t full_tiles = 0, half_tiles = 0;
+    // tiles of the batch that run the first K step alone: none, or all
+    bool all_full = true, all_half = true;
     for (uint32_t i = 0; i < tn; i++) {
-        if ((sw[i] >> 8) != 0u) half_tiles |= 1u << i;
-        else full_tiles |= 1u << i;
+        const bool hf = (sw[i] >> 8) != 0u;
+        all_full = all_full && !hf;
+        all_half = all_half && hf;
     }
     // Lane j < kBlocks / 4 holds plane word j of a wave's stream (its four
     // 8-base blocks). A window filtered on NW prefix words reads the words of
@@ -868,13 +869,13 @@ void scan_filter_mfma3_kernel(ScanArgs a)
                                          (int)f[8 * t + 3], 0, 0, 0, 0};
             }
         uint32_t pending = 0;   // wave-uniform
-        // One-word batches: a software pipeline over two sets of
-        // accumulators, once over the tiles that run both K steps and once
-        // over those that run the first alone (`tiles`: bit nt for tile nt).
-        // The p1 MFMAs of a tile run while its p0 counts are folded, and the
-        // p0 MFMAs of the next tile while its p1 counts are folded, so that
-        // each wave keeps the matrix core busy during its own fold.
-        auto pipeline = [&](auto half_tag, uint32_t tiles) {
+        // One-word batches whose tiles all run both K steps, or all the
+        // first alone: a software pipeline over two sets of accumulators. The
+        // p1 MFMAs of tile nt run while the p0 counts of tile nt are folded,
+        // and the p0 MFMAs of tile nt + 1 while the p1 counts of tile nt are
+        // folded, so that each wave keeps the matrix core busy during its own
+        // fold.
+        auto pipeline = [&](auto half_tag) {
             constexpr bool kHalf = decltype(half_tag)::value;
             auto ldB = [&](uint32_t nt, ifa_v8i &B0, ifa_v8i &B1, float &nd) {
                 const uint4 v0 = sb[(4u * nt) * 64u + l];
@@ -901,18 +902,13 @@ void scan_filter_mfma3_kernel(ScanArgs a)
                 for (uint32_t q = 0; q < 4; q++)
                     if (m & (0x000000ff000000ffull << (8u * q))) pending |= 1u << (4u * nt + q);
             };
-            if (tiles == 0u) return;
             ifa_v8i cB0 = {}, cB1 = {}, nB0 = {}, nB1 = {};
             float cneed, nneed;
             ifa_v16f a0, a1, b0, b1;
-            uint32_t nt = (uint32_t)__builtin_ctz(tiles);
-            tiles &= tiles - 1u;
-            ldB(nt, cB0, cB1, cneed);
+            ldB(0, cB0, cB1, cneed);
             counts(0, cB0, cB1, a0, a1);
-            while (tiles != 0u) {
-                const uint32_t nn = (uint32_t)__builtin_ctz(tiles);
-                tiles &= tiles - 1u;
-                ldB(nn, nB0, nB1, nneed);
+            for (uint32_t nt = 0; nt + 1u < tn; nt++) {
+                ldB(nt + 1u, nB0, nB1, nneed);
                 counts(1, cB0, cB1, b0, b1);
                 float mx = -1e30f;
 #pragma unroll
@@ -924,7 +920,6 @@ void scan_filter_mfma3_kernel(ScanArgs a)
                 cB0 = nB0;
                 cB1 = nB1;
                 cneed = nneed;
-                nt = nn;
                 // the order above, interleaved: each MFMA followed by VALU
                 // instructions of the fold that does not wait on it
                 constexpr int kMfma = kHalf ? 4 : 8;
@@ -941,11 +936,12 @@ void scan_filter_mfma3_kernel(ScanArgs a)
             for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(a0[i], a1[i]), mx);
 #pragma unroll
             for (int i = 0; i < 16; i++) mx = fmaxf(fmaxf(b0[i], b1[i]), mx);
-            mark(nt, mx, cneed);
+            mark(tn - 1u, mx, cneed);
         };
-        if (NW == 1) {
-            pipeline(std::false_type{}, full_tiles);
-            pipeline(std::true_type{}, half_tiles);
+        if (NW == 1 && all_full) {
+            pipeline(std::false_type{});
+        } else if (NW == 1 && all_half) {
+            pipeline(std::true_type{});
         } else
         for (uint32_t nt = 0; nt < tn; nt++) {
             const uint4 v0 = sb[(4u * nt) * 64u + l], v1 = sb[(4u * nt + 1u) * 64u + l];
