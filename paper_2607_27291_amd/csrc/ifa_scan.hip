@@ -1052,7 +1052,6 @@ __device__ __forceinline__ bool wave_is_clean(const ScanArgs &a, uint32_t w0)
 
 // LDS state of a dense matrix workgroup (one batch of kDmTiles column tiles).
 struct DmShared {
-    const float *need;              // [tile][32 columns] need of the column's strand
     const uint32_t *kq;             // [32] k | strand << 16 per strand of the batch
     const uint32_t *qid;            // [32] caller's query index per strand
     uint32_t *cnt;                  // [32][kDmReps] hit counts
@@ -1060,10 +1059,12 @@ struct DmShared {
 };
 
 // Hash (or write out as records) the `total` hits listed in a wave's list,
-// with every lane. An entry is D | lane << 8 | register << 14 | row tile << 18
-// | tile << 21: the lane that held the value gives its column (strand
-// 4 tile + column / 8 of the batch, shift column % 8), and the mismatches are
-// k - (D - need). Counts and digests go to one of kDmReps copies of the
+// with every lane. An entry is (D - need) | lane << 8 | register << 14 | row
+// tile << 18 | tile << 21: the lane that held the value gives its column
+// (strand 4 tile + column / 8 of the batch, shift column % 8), and the
+// mismatches are k - (D - need). (D and need may be negative: D counts an A
+// of the query as -1 where the reference base is not A; D - need of a hit is
+// in [0, k].) Counts and digests go to one of kDmReps copies of the
 // strand's sums (by lane), so that lanes hashing hits of one strand do not
 // queue on one LDS address. Called by all 64 lanes of the wave.
 __device__ __forceinline__ void dm_flush(const ScanArgs &a, const uint32_t *list, uint32_t total,
@@ -1088,7 +1089,7 @@ __device__ __forceinline__ void dm_flush(const ScanArgs &a, const uint32_t *list
         const uint32_t kq = sh.kq[qb];
         // window of register i: row tile u, group 8 (i / 4) + 4 h + i % 4
         const uint32_t win = 256u * u + 8u * (8u * (i >> 2) + 4u * eh + (i & 3u)) + (col & 7u);
-        const uint32_t m = (kq & 0xffffu) + (uint32_t)sh.need[32u * nt + col] - (ent & 0xffu);
+        const uint32_t m = (kq & 0xffffu) - (ent & 0xffu);
         if (a.sink == kSinkRecords) {
             if (base + e < a.hit_cap)
                 a.hits[base + e] = make_uint4(sh.qid[qb], contig, pos0 + win, (kq >> 16) | (m << 16));
@@ -1136,7 +1137,7 @@ __global__ __launch_bounds__(WG) void scan_dense_mfma3_kernel(ScanArgs a)
     }
     for (uint32_t i = threadIdx.x; i < 256u; i += WG) sp[i] = kSpread.v[i];
     __syncthreads();
-    const DmShared sh{st, skq, sqid, scnt, sdig};
+    const DmShared sh{skq, sqid, scnt, sdig};
 
     const uint32_t l = threadIdx.x & 63u;
     const uint32_t g = l & 31u, h = l >> 5;
@@ -1234,7 +1235,8 @@ __global__ __launch_bounds__(WG) void scan_dense_mfma3_kernel(ScanArgs a)
                             const uint32_t slot = __builtin_amdgcn_mbcnt_hi(
                                 (uint32_t)(mb[j] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb[j], total));
                             list[slot] = __builtin_amdgcn_cvt_pk_u8_f32(
-                                v, 0u, lane_ent | ((uint32_t)(r & 15) << 14) | ((uint32_t)(2 * p + (r >> 4)) << 18));
+                                v - need, 0u,
+                                lane_ent | ((uint32_t)(r & 15) << 14) | ((uint32_t)(2 * p + (r >> 4)) << 18));
                         }
                         total += (uint32_t)__popcll(mb[j]);
                     }

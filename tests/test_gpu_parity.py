@@ -858,14 +858,16 @@ def test_filter_launch_split_past_65535_batches(ifa, orc):
 @pytest.mark.parametrize("sink", [0, 1])
 def test_dense_strands_on_matrix_cores(ifa, orc, sink):
     """Dense strands of at most 32 bases with a random-window hit rate of at
-    most 2 % are counted on the matrix cores on clean waves (no N or contig
+    most 5 % are counted on the matrix cores on clean waves (no N or contig
     end among the words their windows read) and by the VALU kernels
     elsewhere; the other dense strands always by the VALU kernels, which run
     the two groups (each by L descending) in launches of their own. Short
     high-threshold queries (hit rates from 1e-4 to ~1) against contigs with N
     runs and many contig ends, in small chunks (carried prefixes), records
     with a small hit buffer (re-scans) and count+digest: every three-class
-    variant and a VALU variant equal the oracle."""
+    variant and a VALU variant equal the oracle. A-rich and T-rich queries
+    give strands whose required count L - k - nA is negative (the three-class
+    value of a window is negative where the reference misses query A bases)."""
     rng = random.Random(4422)
     contigs = []
     for i in range(10):
@@ -880,6 +882,14 @@ def test_dense_strands_on_matrix_cores(ifa, orc, sink):
                  (32, 16), (32, 13), (36, 16), (37, 17), (19, 11), (22, 8), (26, 10)):
         for _ in range(3):
             qs.append(rand_dna(rng, L, b"ACGT" if rng.random() < 0.9 else b"ACGTN"))
+            ks.append(k)
+    # matrix-core strands (hit rate at most 5 %) with more A bases than L - k
+    for L, k, base in ((20, 11, b"A"), (26, 15, b"A"), (18, 9, b"T"), (28, 15, b"T")):
+        for _ in range(2):
+            q = bytearray(rand_dna(rng, L))
+            for i in rng.sample(range(L), L - k + 2):
+                q[i] = base[0]
+            qs.append(bytes(q))
             ks.append(k)
     if sink == 0:
         want = orc.scan(qs, contigs, ks)

@@ -80,10 +80,23 @@ def test_c2_full_size_every_threshold(ifa):
             assert np.array_equal(gc, gold[k][0]) and np.array_equal(gd, gold[k][1]), k
 
 
-def test_c3_all_queries_10mbp_of_the_1gbp_reference(ifa):
+def matrix_dense_variant(ifa):
+    """The variant that counts the low-hit-rate dense strands on the matrix
+    cores with 256-thread filter workgroups (the batched workload's choice
+    of the autotuner when the dense kernels run beside the filter)."""
+    for v in range(ifa.ifa_variant_count()):
+        info = ifa.ifa_variant_info(v)
+        if info["encoding"] == 3 and info["workgroup"] == 256:
+            return v
+    raise AssertionError("no such variant")
+
+
+@pytest.mark.parametrize("kind", ["default", "matrix_dense"])
+def test_c3_all_queries_10mbp_of_the_1gbp_reference(ifa, kind):
     """All 10,000 batched queries (L 18-50, maxSubs 0-16) against a 10 Mbp
     sample of whole contigs of the batched workload's 1 Gbp reference:
-    per-query count and digest equal the oracle's (fixture)."""
+    per-query count and digest equal the oracle's (fixture), with the
+    context's default variant and with the matrix-core dense variant."""
     import re
     import synth
     w = synth.c3_batched(total=1_000_000_000)
@@ -91,8 +104,10 @@ def test_c3_all_queries_10mbp_of_the_1gbp_reference(ifa):
     check_fingerprint(head, w.ref)
     pick = [int(x) for x in re.search(r"whole contigs ([0-9,]+)", " ".join(head)).group(1).split(",")]
     sub = w.ref.subset(pick)
-    say(f"c3 all queries x {sub.total / 1e6:.1f} Mbp ({len(pick)} contigs), count+digest")
+    say(f"c3 all queries x {sub.total / 1e6:.1f} Mbp ({len(pick)} contigs), count+digest, {kind}")
     with ifa.Scanner(sink=ifa.IFA_SINK_COUNT_DIGEST) as s:
+        if kind == "matrix_dense":
+            ifa.ifa_set_variant(s.ctx, matrix_dense_variant(ifa))
         s.load_queries(w.queries, w.max_subs)
         s.scan_chunk(sub)
         gc, gd = s.query_stats()
@@ -103,10 +118,12 @@ def test_c3_all_queries_10mbp_of_the_1gbp_reference(ifa):
     assert int(want_c.sum()) > 10 ** 9
 
 
-def test_c3_stratified_queries_full_1gbp(ifa):
+@pytest.mark.parametrize("kind", ["default", "matrix_dense"])
+def test_c3_stratified_queries_full_1gbp(ifa, kind):
     """100 batched queries stratified over (L, maxSubs), leaving out pairs
     expected to hit more than 1e7 times, against the whole 1 Gbp batched
-    reference: per-query count and digest equal the oracle's (fixture)."""
+    reference: per-query count and digest equal the oracle's (fixture), with
+    the context's default variant and with the matrix-core dense variant."""
     import synth
     w = synth.c3_batched(total=1_000_000_000)
     head, rows = load_golden("c3_100q_1gbp_count_digest.txt")
@@ -115,8 +132,10 @@ def test_c3_stratified_queries_full_1gbp(ifa):
     qs = [w.queries[i] for i in idx]
     ks = [w.max_subs[i] for i in idx]
     assert ks == [r[1] for r in rows]
-    say(f"c3 stratified: {len(qs)} queries x 1 Gbp, count+digest")
+    say(f"c3 stratified: {len(qs)} queries x 1 Gbp, count+digest, {kind}")
     with ifa.Scanner(sink=ifa.IFA_SINK_COUNT_DIGEST) as s:
+        if kind == "matrix_dense":
+            ifa.ifa_set_variant(s.ctx, matrix_dense_variant(ifa))
         s.ref_load(w.ref)
         s.load_queries(qs, ks)
         s.scan_resident()
