@@ -720,9 +720,10 @@ bool forks(const ifa_ctx *c, const ScanArgs &a, bool dense)
 // kernels and (with IFA_FLAG_OVERHANG) the overhanging windows. Counters are
 // cleared by kernels on the stream first. With both parts, the dense kernels
 // run on the side stream, forked after the clear and joined before the
-// overhanging windows: the filter keeps the matrix cores busy and the dense
-// kernels the vector ALUs, so the two overlap on each CU. They share only
-// the pass counters and query sums, which both update atomically.
+// overhanging windows, so that the device's workgroup slots are shared
+// between the filter (mostly matrix-core work) and the dense kernels (vector
+// ALU work) and neither's tail leaves it idle. They share only the pass
+// counters and query sums, which both update atomically.
 // (A null event in ev is not recorded.)
 void enqueue_pass(ifa_ctx *c, const ScanArgs &a, bool clear_hits, bool dense, PassEvents &ev)
 {
