@@ -1031,10 +1031,12 @@ static uint32_t mq3_lds_bytes(uint32_t tiles, uint32_t wg, int nw)
 // Grid: x = workgroups walking waves (XCD-aware), y = batch of column tiles.
 // ---------------------------------------------------------------------------
 
-constexpr uint32_t kDmTiles = 8;     // column tiles per batch (32 strands)
+constexpr uint32_t kDmTiles = 4;     // column tiles per batch (16 strands)
 constexpr uint32_t kDmBlock = 8;     // accumulator registers listed per block
 constexpr uint32_t kDmList = 64u * kDmBlock;   // hit-list entries per wave
 constexpr uint32_t kDmReps = 8;      // copies of each strand's sums in LDS
+// the per-strand LDS arrays below hold 32 strands
+static_assert(4u * kDmTiles <= 32u, "dense matrix batch too large");
 
 // Is the 1024-window wave whose window starts begin at word w0 clean (see
 // above) for strands of at most 32 bases? Windows start in words w0 ..
@@ -2086,7 +2088,7 @@ hipError_t launch_dense(const ScanArgs &a, hipStream_t s, std::vector<ScanLaunch
     e = go(v.dense_cold, grid, dim3(256), 0, s, a, rec);
     if (e != hipSuccess || a.dm_first >= a.n_qs) return e;
     // one-word dense strands on the matrix cores, clean waves only: one
-    // batch of kDmTiles column tiles (32 strands) per grid row, about 2^15
+    // batch of kDmTiles column tiles (4 kDmTiles strands) per grid row, about 2^15
     // waves in all
     const uint32_t tiles = (a.n_qs - a.dm_first + 3u) / 4u;
     const uint32_t batches = (tiles + kDmTiles - 1u) / kDmTiles;
